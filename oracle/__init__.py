@@ -1,0 +1,412 @@
+"""Python face of the double-precision CPU oracle (ctypes over libpvoracle.so).
+
+TEST INFRASTRUCTURE ONLY.  The oracle is the checker the HIP path is held to;
+only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import it.  It shares no code with the product package.
+
+Arrays are numpy; coordinates and pose DOFs are binary64.  Receptor
+coordinates are binary32, the interface precision of the receptor, so that
+the map cutoff test can be taken in binary32 exactly as the map kernel takes
+it (see ``or_build_maps`` in pvoracle.c).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.LIB
+        if not os.path.exists(path):
+            _build.build()
+        _lib = C.CDLL(path)
+        _declare(_lib)
+    return _lib
+
+
+_dp = C.POINTER(C.c_double)
+_fp = C.POINTER(C.c_float)
+_ip = C.POINTER(C.c_int32)
+_i64p = C.POINTER(C.c_int64)
+_u64p = C.POINTER(C.c_uint64)
+_u8p = C.POINTER(C.c_uint8)
+
+
+class Flags(C.Structure):
+    _fields_ = [("min_face", C.c_double), ("min_cut", C.c_double),
+                ("min_kink", C.c_double), ("pairs_in", C.c_int64)]
+
+
+class _Grid(C.Structure):
+    _fields_ = [("maps", _dp), ("dims", C.c_int * 3), ("origin", C.c_float * 3),
+                ("h", C.c_float), ("kappa", C.c_double)]
+
+
+class BfgsParams(C.Structure):
+    _fields_ = [("max_iter", C.c_int32), ("m", C.c_int32), ("ls_max", C.c_int32),
+                ("pad", C.c_int32), ("rho", C.c_double), ("sigma", C.c_double),
+                ("eps_g", C.c_double), ("eps_c", C.c_double)]
+
+
+class McParams(C.Structure):
+    _fields_ = [("chains", C.c_int32), ("steps", C.c_int32), ("bfgs", BfgsParams),
+                ("refine_max_iter", C.c_int32), ("pad", C.c_int32),
+                ("temperature", C.c_double), ("mut_pos_amp", C.c_double),
+                ("mut_rot_amp", C.c_double), ("seed", C.c_uint64)]
+
+
+EVAL_FN = C.CFUNCTYPE(None, C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                      C.POINTER(C.c_double))
+
+
+def _declare(L):
+    L.or_terms.argtypes = [C.c_double, _dp, _dp]
+    L.or_pair.argtypes = [C.c_int, C.c_int, C.c_double, _dp]
+    L.or_pair.restype = C.c_double
+    L.or_type_params.argtypes = [C.c_int, _dp, _ip, _ip, _ip]
+    L.or_weights.argtypes = [_dp]
+    L.or_lattice.argtypes = [_dp, _dp, C.c_double, _ip, _fp]
+    L.or_build_maps.argtypes = [C.c_int, _fp, _ip, _ip, _fp, C.c_float, _dp]
+    L.or_map_point.argtypes = [C.c_int, _fp, _ip, _ip, _fp, C.c_float,
+                               C.c_int, C.c_int, C.c_int, _dp]
+    L.or_trilinear.argtypes = [_dp, _ip, _fp, C.c_float, C.c_double, _dp, _dp, _dp]
+    L.or_trilinear.restype = C.c_double
+    L.or_ligand_build.argtypes = [C.c_int, _dp, _ip, C.c_int, _ip, _u8p, C.POINTER(C.c_void_p)]
+    L.or_ligand_free.argtypes = [C.c_void_p]
+    L.or_ligand_info.argtypes = [C.c_void_p, _ip]
+    L.or_ligand_pairs.argtypes = [C.c_void_p, _ip]
+    L.or_ligand_frag.argtypes = [C.c_void_p, _ip]
+    L.or_ligand_torsions.argtypes = [C.c_void_p, _ip]
+    L.or_ligand_rg.argtypes = [C.c_void_p]
+    L.or_ligand_rg.restype = C.c_double
+    L.or_ligand_anchor.argtypes = [C.c_void_p, _dp]
+    L.or_fk.argtypes = [C.c_void_p, _dp, _dp]
+    L.or_score_grad.argtypes = [C.c_void_p, C.POINTER(_Grid), _dp, _dp, _dp, _dp, _dp, _dp,
+                                C.POINTER(Flags)]
+    L.or_score_xyz.argtypes = [C.c_void_p, C.POINTER(_Grid), _dp, _dp, _dp, C.POINTER(Flags)]
+    L.or_inter_pairwise.argtypes = [C.c_int, _fp, _ip, C.c_int, _dp, _ip]
+    L.or_inter_pairwise.restype = C.c_double
+    L.or_philox4x64_10.argtypes = [_u64p, _u64p, _u64p]
+    L.or_bfgs.argtypes = [C.c_void_p, C.POINTER(_Grid), C.POINTER(BfgsParams), _dp, _dp, _dp,
+                          _i64p, _ip]
+    L.or_bfgs_generic.argtypes = [C.c_int, EVAL_FN, C.c_void_p, C.POINTER(BfgsParams), _dp, _dp,
+                                  _dp, _i64p, _ip]
+    L.or_init_pose.argtypes = [C.c_void_p, C.POINTER(_Grid), C.c_uint64, C.c_int, C.c_int, _dp]
+    L.or_mc_chain.argtypes = [C.c_void_p, C.POINTER(_Grid), C.POINTER(McParams), C.c_int,
+                              C.c_int, _dp, _dp, _i64p]
+    L.or_dock.argtypes = [C.c_int, C.POINTER(C.c_void_p), C.c_int, C.POINTER(_Grid), C.c_int,
+                          _ip, C.POINTER(McParams), C.c_int, C.c_int, _dp, _dp, _i64p, _dp, _ip]
+
+
+def _p(a, t):
+    return a.ctypes.data_as(t)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+# ---------------------------------------------------------------- terms
+def terms(d: float):
+    v = np.zeros(5)
+    dv = np.zeros(5)
+    lib().or_terms(float(d), _p(v, _dp), _p(dv, _dp))
+    return v, dv
+
+
+def pair(ta: int, tb: int, r: float):
+    de = C.c_double()
+    e = lib().or_pair(int(ta), int(tb), float(r), C.byref(de))
+    return e, de.value
+
+
+def type_params(t: int):
+    r = C.c_double()
+    h, d, a = C.c_int32(), C.c_int32(), C.c_int32()
+    lib().or_type_params(int(t), C.byref(r), C.byref(h), C.byref(d), C.byref(a))
+    return r.value, h.value, d.value, a.value
+
+
+def weights():
+    w = np.zeros(5)
+    lib().or_weights(_p(w, _dp))
+    return w
+
+
+# ---------------------------------------------------------------- lattice / maps
+def lattice(center, size, h):
+    c = _f64(center)
+    s = _f64(np.broadcast_to(np.asarray(size, dtype=np.float64), (3,)))
+    dims = np.zeros(3, np.int32)
+    org = np.zeros(3, np.float32)
+    rc = lib().or_lattice(_p(c, _dp), _p(s, _dp), float(h), _p(dims, _ip), _p(org, _fp))
+    if rc != 0:
+        raise ValueError("invalid box (code %d)" % rc)
+    return dims, org
+
+
+def build_maps(rec_xyz, rec_type, dims, origin, h):
+    x = _f32(rec_xyz)
+    t = _i32(rec_type)
+    d = _i32(dims)
+    o = _f32(origin)
+    out = np.zeros((8, int(d[2]), int(d[1]), int(d[0])), np.float64)
+    rc = lib().or_build_maps(len(t), _p(x, _fp), _p(t, _ip), _p(d, _ip), _p(o, _fp),
+                             float(np.float32(h)), _p(out, _dp))
+    if rc != 0:
+        raise ValueError("invalid receptor (code %d)" % rc)
+    return out
+
+
+def map_point(rec_xyz, rec_type, dims, origin, h, i, j, k):
+    x = _f32(rec_xyz)
+    t = _i32(rec_type)
+    d = _i32(dims)
+    o = _f32(origin)
+    out = np.zeros(8)
+    rc = lib().or_map_point(len(t), _p(x, _fp), _p(t, _ip), _p(d, _ip), _p(o, _fp),
+                            float(np.float32(h)), int(i), int(j), int(k), _p(out, _dp))
+    if rc != 0:
+        raise ValueError("invalid point (code %d)" % rc)
+    return out
+
+
+class Grid:
+    """Maps of one box in binary64 plus its lattice and penalty slope."""
+
+    def __init__(self, maps, dims, origin, h, kappa=1000.0):
+        self.maps = _f64(maps)
+        self.dims = _i32(dims)
+        self.origin = _f32(origin)
+        self.h = float(np.float32(h))
+        self.kappa = float(kappa)
+        self._s = _Grid()
+        self._s.maps = _p(self.maps, _dp)
+        for a in range(3):
+            self._s.dims[a] = int(self.dims[a])
+            self._s.origin[a] = float(self.origin[a])
+        self._s.h = self.h
+        self._s.kappa = self.kappa
+
+    @classmethod
+    def build(cls, rec_xyz, rec_type, center, size, h, kappa=1000.0):
+        dims, org = lattice(center, size, h)
+        return cls(build_maps(rec_xyz, rec_type, dims, org, h), dims, org, h, kappa)
+
+    @property
+    def struct(self):
+        return self._s
+
+    def trilinear(self, t, x):
+        g = np.zeros(3)
+        fd = C.c_double()
+        xx = _f64(x)
+        msz = int(np.prod(self.dims))
+        sub = self.maps.reshape(8, msz)[int(t)]
+        v = lib().or_trilinear(_p(sub, _dp), _p(self.dims, _ip), _p(self.origin, _fp),
+                               self.h, self.kappa, _p(xx, _dp), _p(g, _dp), C.byref(fd))
+        return v, g, fd.value
+
+
+# ---------------------------------------------------------------- ligand
+class Ligand:
+    def __init__(self, ref_xyz, types, bonds, rotatable):
+        self.ref = _f64(ref_xyz).reshape(-1, 3)
+        self.types = _i32(types)
+        self.bonds = _i32(bonds).reshape(-1, 2)
+        self.rot = np.ascontiguousarray(rotatable, dtype=np.uint8)
+        h = C.c_void_p()
+        rc = lib().or_ligand_build(len(self.types), _p(self.ref, _dp), _p(self.types, _ip),
+                                   len(self.bonds), _p(self.bonds, _ip), _p(self.rot, _u8p),
+                                   C.byref(h))
+        if rc != 0:
+            raise ValueError("invalid ligand (code %d)" % rc)
+        self.h = h
+        info = np.zeros(8, np.int32)
+        lib().or_ligand_info(self.h, _p(info, _ip))
+        self.n_atoms, self.n_frag, self.n_tors, self.n_pairs, self.root, self.depth = \
+            [int(v) for v in info[:6]]
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.or_ligand_free(self.h)
+            self.h = None
+
+    @property
+    def ndof(self):
+        return 7 + self.n_tors
+
+    def pairs(self):
+        p = np.zeros((self.n_pairs, 2), np.int32)
+        lib().or_ligand_pairs(self.h, _p(p, _ip))
+        return p
+
+    def frag(self):
+        f = np.zeros(self.n_atoms, np.int32)
+        lib().or_ligand_frag(self.h, _p(f, _ip))
+        return f
+
+    def torsions(self):
+        t = np.zeros((self.n_tors, 3), np.int32)
+        lib().or_ligand_torsions(self.h, _p(t, _ip))
+        return t
+
+    def rg(self):
+        return lib().or_ligand_rg(self.h)
+
+    def anchor(self):
+        a = np.zeros(3)
+        lib().or_ligand_anchor(self.h, _p(a, _dp))
+        return a
+
+    def fk(self, dof):
+        d = _f64(dof)
+        x = np.zeros((self.n_atoms, 3))
+        lib().or_fk(self.h, _p(d, _dp), _p(x, _dp))
+        return x
+
+    def score_grad(self, grid: Grid, dof):
+        d = _f64(dof)
+        e3 = np.zeros(3)
+        gd = np.zeros(self.ndof)
+        gt = np.zeros(6 + self.n_tors)
+        x = np.zeros((self.n_atoms, 3))
+        gx = np.zeros((self.n_atoms, 3))
+        fl = Flags()
+        lib().or_score_grad(self.h, C.byref(grid.struct), _p(d, _dp), _p(e3, _dp), _p(gd, _dp),
+                            _p(gt, _dp), _p(x, _dp), _p(gx, _dp), C.byref(fl))
+        return dict(e=e3[0], e_inter=e3[1], e_intra=e3[2], grad_dof=gd, grad_tan=gt, xyz=x,
+                    grad_xyz=gx, min_face=fl.min_face, min_cut=fl.min_cut,
+                    min_kink=fl.min_kink, pairs_in=fl.pairs_in)
+
+    def score_xyz(self, grid: Grid, xyz):
+        x = _f64(xyz).reshape(-1, 3)
+        e3 = np.zeros(3)
+        gx = np.zeros((self.n_atoms, 3))
+        fl = Flags()
+        lib().or_score_xyz(self.h, C.byref(grid.struct), _p(x, _dp), _p(e3, _dp), _p(gx, _dp),
+                           C.byref(fl))
+        return dict(e=e3[0], e_inter=e3[1], e_intra=e3[2], grad_xyz=gx, min_face=fl.min_face,
+                    min_cut=fl.min_cut, min_kink=fl.min_kink, pairs_in=fl.pairs_in)
+
+
+def inter_pairwise(rec_xyz, rec_type, xyz, types):
+    r = _f32(rec_xyz)
+    rt = _i32(rec_type)
+    x = _f64(xyz)
+    t = _i32(types)
+    return lib().or_inter_pairwise(len(rt), _p(r, _fp), _p(rt, _ip), len(t), _p(x, _dp),
+                                   _p(t, _ip))
+
+
+# ---------------------------------------------------------------- RNG
+def philox4x64_10(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint64)
+    k = np.ascontiguousarray(key, dtype=np.uint64)
+    out = np.zeros(4, np.uint64)
+    lib().or_philox4x64_10(_p(c, _u64p), _p(k, _u64p), _p(out, _u64p))
+    return out
+
+
+# ---------------------------------------------------------------- search
+def bfgs_params(max_iter=30, m=5, ls_max=10, rho=1e-4, sigma=0.1, eps_g=1e-3, eps_c=1e-6):
+    return BfgsParams(int(max_iter), int(m), int(ls_max), 0, float(rho), float(sigma),
+                      float(eps_g), float(eps_c))
+
+
+def mc_params(chains, steps, seed, bfgs=None, refine_max_iter=None, temperature=1.2,
+              mut_pos_amp=2.0, mut_rot_amp=2.0):
+    b = bfgs if bfgs is not None else bfgs_params()
+    return McParams(int(chains), int(steps), b,
+                    int(b.max_iter if refine_max_iter is None else refine_max_iter), 0,
+                    float(temperature), float(mut_pos_amp), float(mut_rot_amp),
+                    int(seed) & 0xFFFFFFFFFFFFFFFF)
+
+
+def bfgs(lig: Ligand, grid: Grid, x0, params: BfgsParams | None = None):
+    P = params if params is not None else bfgs_params()
+    x = _f64(x0)
+    xo = np.zeros(lig.ndof)
+    f = C.c_double()
+    ne = C.c_int64()
+    it = C.c_int32()
+    lib().or_bfgs(lig.h, C.byref(grid.struct), C.byref(P), _p(x, _dp), _p(xo, _dp), C.byref(f),
+                  C.byref(ne), C.byref(it))
+    return xo, f.value, ne.value, it.value
+
+
+def bfgs_generic(fun, x0, params: BfgsParams | None = None):
+    """The oracle's BFGS on a flat objective: fun(x) -> (f, grad)."""
+    P = params if params is not None else bfgs_params()
+    x0 = _f64(x0)
+    n = len(x0)
+
+    def cb(_user, xp, fp, gp):
+        x = np.ctypeslib.as_array(xp, shape=(n,)).copy()
+        f, g = fun(x)
+        fp[0] = float(f)
+        for i in range(n):
+            gp[i] = float(g[i])
+
+    cfun = EVAL_FN(cb)
+    xo = np.zeros(n)
+    f = C.c_double()
+    ne = C.c_int64()
+    it = C.c_int32()
+    lib().or_bfgs_generic(n, cfun, None, C.byref(P), _p(x0, _dp), _p(xo, _dp), C.byref(f),
+                          C.byref(ne), C.byref(it))
+    return xo, f.value, ne.value, it.value
+
+
+def init_pose(lig: Ligand, grid: Grid, seed, job, chain):
+    d = np.zeros(lig.ndof)
+    lib().or_init_pose(lig.h, C.byref(grid.struct), int(seed) & 0xFFFFFFFFFFFFFFFF, int(job),
+                       int(chain), _p(d, _dp))
+    return d
+
+
+def mc_chain(lig: Ligand, grid: Grid, params: McParams, job, chain):
+    d = np.zeros(lig.ndof)
+    e = C.c_double()
+    ne = C.c_int64()
+    lib().or_mc_chain(lig.h, C.byref(grid.struct), C.byref(params), int(job), int(chain),
+                      _p(d, _dp), C.byref(e), C.byref(ne))
+    return d, e.value, ne.value
+
+
+def dock(ligands, grids, jobs, params: McParams, dof_stride=None, n_threads=0):
+    """Every (job, chain) of Supplementary Algorithm 2; jobs = [(ligand, grid)]."""
+    jobs = _i32(jobs).reshape(-1, 2)
+    nj = len(jobs)
+    stride = dof_stride or max(l.ndof for l in ligands)
+    hs = (C.c_void_p * len(ligands))(*[l.h for l in ligands])
+    gs = (_Grid * len(grids))(*[g.struct for g in grids])
+    ch = params.chains
+    cbe = np.zeros(nj * ch)
+    cbd = np.zeros((nj * ch, stride))
+    cev = np.zeros(nj * ch, np.int64)
+    jbe = np.zeros(nj)
+    jbc = np.zeros(nj, np.int32)
+    rc = lib().or_dock(len(ligands), hs, len(grids), gs, nj, _p(jobs, _ip), C.byref(params),
+                       int(stride), int(n_threads), _p(cbe, _dp), _p(cbd, _dp), _p(cev, _i64p),
+                       _p(jbe, _dp), _p(jbc, _ip))
+    if rc != 0:
+        raise ValueError("invalid dock input (code %d)" % rc)
+    return dict(chain_best_e=cbe.reshape(nj, ch), chain_best_dof=cbd.reshape(nj, ch, stride),
+                chain_evals=cev.reshape(nj, ch), job_best_e=jbe, job_best_chain=jbc)

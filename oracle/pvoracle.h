@@ -1,0 +1,134 @@
+/*
+ * pvoracle.h -- plain double-precision CPU oracle of the PocketVina docking
+ * hot path (arXiv 2506.20043: Methods, "Accelerated Docking with QuickVina
+ * 2-GPU 2.1", Eqs. qvina_eq_1 .. qvina_eq_13, and Supplementary Algorithm 2).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is the checker the GPU path is held to.
+ * It is not part of the product: only the test suite, the smoke entry and
+ * the CPU-baseline leg of the benchmark load it.  It shares no code, header
+ * or table with the HIP library.
+ *
+ * All arithmetic is IEEE binary64, with one documented exception: when a
+ * grid map is built, the 8 A cutoff test is taken on binary32 distances
+ * (see or_build_maps), so that it is decided in the same precision as the
+ * kernel that builds the maps.
+ *
+ * Return codes: 0 = OK; negative = invalid input (nothing written).
+ */
+#ifndef PVORACLE_H
+#define PVORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OR_NTYPES 8
+
+/* ---- scoring terms (Eq. qvina_eq_3; Vina functional form, see oracle.c) */
+void   or_terms(double d, double v[5], double dv[5]);
+double or_pair(int ta, int tb, double r, double* dphi_dr);
+void   or_type_params(int t, double* radius, int* hydrophobic, int* donor, int* acceptor);
+void   or_weights(double w[5]);
+
+/* ---- lattice of one search box */
+int or_lattice(const double center[3], const double size[3], double h,
+               int dims[3], float origin[3]);
+
+/* ---- grid maps: maps[t][k][j][i], t < 8 (Kernel 1) */
+int or_build_maps(int n_rec, const float* rec_xyz, const int32_t* rec_type,
+                  const int dims[3], const float origin[3], float h,
+                  double* maps);
+int or_map_point(int n_rec, const float* rec_xyz, const int32_t* rec_type,
+                 const int dims[3], const float origin[3], float h,
+                 int i, int j, int k, double out[8]);
+
+/* ---- trilinear lookup with out-of-box penalty */
+double or_trilinear(const double* map, const int dims[3], const float origin[3],
+                    float h, double kappa, const double x[3], double grad[3],
+                    double* face_dist);
+
+/* ---- ligand model: rigid fragments, torsion tree, intra pair list */
+typedef struct or_ligand or_ligand;
+int  or_ligand_build(int n_atoms, const double* ref_xyz, const int32_t* type,
+                     int n_bonds, const int32_t* bonds, const uint8_t* rotatable,
+                     or_ligand** out);
+void or_ligand_free(or_ligand* L);
+/* info[0..7] = n_atoms, n_frag, n_tors, n_pairs, root_frag, depth, 0, 0 */
+void or_ligand_info(const or_ligand* L, int32_t info[8]);
+void or_ligand_pairs(const or_ligand* L, int32_t* pairs /* [n_pairs][2] */);
+void or_ligand_frag(const or_ligand* L, int32_t* frag /* [n_atoms] */);
+/* per torsion: bond index, parent-side atom, child-side atom */
+void or_ligand_torsions(const or_ligand* L, int32_t* tors /* [T][3] */);
+double or_ligand_rg(const or_ligand* L);
+void or_ligand_anchor(const or_ligand* L, double anchor[3]);
+
+/* ---- pose evaluation */
+typedef struct {
+    double min_face;   /* smallest distance (A) of an atom to a lattice plane or box face */
+    double min_cut;    /* smallest |r - 8| over intra pairs */
+    double min_kink;   /* smallest |d - kink| over intra pairs with an active hyd / hbond kink */
+    int64_t pairs_in;  /* intra pairs inside the cutoff */
+} or_flags;
+
+/* grid of one box: 8 maps in double, lattice and penalty slope */
+typedef struct {
+    const double* maps;   /* [8][nz][ny][nx] */
+    int dims[3];
+    float origin[3];
+    float h;
+    double kappa;
+} or_grid;
+
+void or_fk(const or_ligand* L, const double* dof, double* xyz);
+/* e3 = {E, e_inter, e_intra}; grad_dof [7+T]; grad_tan [6+T] = (dE/dt, torque, dE/dpsi) */
+int or_score_grad(const or_ligand* L, const or_grid* G, const double* dof,
+                  double e3[3], double* grad_dof, double* grad_tan,
+                  double* xyz, double* grad_xyz, or_flags* flags);
+int or_score_xyz(const or_ligand* L, const or_grid* G, const double* xyz,
+                 double e3[3], double* grad_xyz, or_flags* flags);
+double or_inter_pairwise(int n_rec, const float* rec_xyz, const int32_t* rec_type,
+                         int n, const double* xyz, const int32_t* type);
+
+/* ---- counter-based RNG: Philox4x64-10 (Salmon et al., SC'11) */
+void or_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+
+/* ---- RILC-BFGS (Eqs. qvina_eq_6 .. qvina_eq_12) */
+typedef struct {
+    int32_t max_iter, m, ls_max, pad;
+    double rho, sigma, eps_g, eps_c;
+} or_bfgs_params;
+int or_bfgs(const or_ligand* L, const or_grid* G, const or_bfgs_params* P,
+            const double* x0, double* xout, double* fout,
+            int64_t* n_evals, int32_t* n_iters);
+
+/* the same BFGS on a flat R^n objective with an additive update */
+typedef void (*or_eval_fn)(void* user, const double* x, double* f, double* g);
+int or_bfgs_generic(int n, or_eval_fn fn, void* user, const or_bfgs_params* P,
+                    const double* x0, double* xout, double* fout, int64_t* n_evals,
+                    int32_t* n_iters);
+
+/* ---- Monte Carlo chains (Supplementary Algorithm 2) */
+typedef struct {
+    int32_t chains, steps;
+    or_bfgs_params bfgs;
+    int32_t refine_max_iter, pad;
+    double temperature, mut_pos_amp, mut_rot_amp;
+    uint64_t seed;
+} or_mc_params;
+int or_init_pose(const or_ligand* L, const or_grid* G, uint64_t seed,
+                 int job, int chain, double* dof);
+int or_mc_chain(const or_ligand* L, const or_grid* G, const or_mc_params* P,
+                int job, int chain, double* best_dof, double* best_e,
+                int64_t* n_evals);
+/* jobs [n_jobs][2] = (ligand, grid); chain outputs [n_jobs*chains(*stride)] */
+int or_dock(int n_lig, or_ligand* const* ligs, int n_grids, const or_grid* grids,
+            int n_jobs, const int32_t* jobs, const or_mc_params* P, int dof_stride,
+            int n_threads, double* chain_best_e, double* chain_best_dof,
+            int64_t* chain_evals, double* job_best_e, int32_t* job_best_chain);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

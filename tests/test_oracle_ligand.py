@@ -1,0 +1,282 @@
+"""Pins of the oracle's ligand model, forward kinematics and gradient
+(the POT of Eq. qvina_eq_1 and the derivatives the optimiser of
+Eqs. qvina_eq_6 .. qvina_eq_12 consumes)."""
+import numpy as np
+import pytest
+from scipy.spatial.transform import Rotation
+
+from paper_2506_20043_amd import synth as S
+
+
+def _chain(n, rot_bonds):
+    """Zig-zag chain of n atoms, bonds (i, i+1), the given bonds rotatable."""
+    x = np.array([[1.5 * i * np.cos(0.3), (i % 2) * 0.8, 0.1 * i] for i in range(n)])
+    bonds = np.array([(i, i + 1) for i in range(n - 1)], np.int32)
+    rot = np.zeros(n - 1, np.uint8)
+    rot[list(rot_bonds)] = 1
+    return x, np.zeros(n, np.int32), bonds, rot
+
+
+def test_model_hand_counted(oracle):
+    # 0-1-2 | 3-4-5 with bond 2-3 rotatable: two fragments, pairs in different
+    # fragments and >= 4 bonds apart: (0,4), (0,5), (1,5)
+    x, t, b, r = _chain(6, [2])
+    L = oracle.Ligand(x, t, b, r)
+    assert (L.n_frag, L.n_tors, L.root) == (2, 1, 0)
+    np.testing.assert_array_equal(L.pairs(), [[0, 4], [0, 5], [1, 5]])
+    np.testing.assert_array_equal(L.frag(), [0, 0, 0, 1, 1, 1])
+    np.testing.assert_array_equal(L.torsions(), [[2, 2, 3]])
+    # root = largest fragment: 0-1 | 2-3-4-5 with bond 1-2 rotatable
+    x, t, b, r = _chain(6, [1])
+    L = oracle.Ligand(x, t, b, r)
+    assert L.root == 1
+    np.testing.assert_array_equal(L.torsions(), [[1, 2, 1]])   # parent atom 2, child atom 1
+    np.testing.assert_array_equal(L.pairs(), [[0, 4], [0, 5], [1, 5]])
+    # a rigid chain has no intra pairs at all
+    x, t, b, r = _chain(7, [])
+    L = oracle.Ligand(x, t, b, r)
+    assert (L.n_frag, L.n_tors, L.n_pairs) == (1, 0, 0)
+
+
+def test_model_star_depth(oracle):
+    # 0-1-2-3-4-5-6 with every inner bond rotatable: depth of the fragment tree
+    x, t, b, r = _chain(7, [1, 2, 3, 4])
+    L = oracle.Ligand(x, t, b, r)
+    assert L.n_tors == 4 and L.n_frag == 5
+    # fragments {0,1} {2} {3} {4} {5,6}: the root is the lowest-id largest one
+    assert L.root == 0 and L.depth == 4
+
+
+def test_model_rejects(oracle):
+    x, t, b, r = _chain(5, [1])
+    with pytest.raises(ValueError):   # disconnected
+        oracle.Ligand(x, t, b[:-1], r[:-1])
+    with pytest.raises(ValueError):   # bad type
+        oracle.Ligand(x, np.full(5, 9, np.int32), b, r)
+    with pytest.raises(ValueError):   # self bond
+        bb = b.copy()
+        bb[0] = (2, 2)
+        oracle.Ligand(x, t, bb, r)
+    # a ring whose bond is rotatable: 0-1-2-3-0 with (3,0) rotatable
+    ring_b = np.array([(0, 1), (1, 2), (2, 3), (3, 0)], np.int32)
+    with pytest.raises(ValueError):
+        oracle.Ligand(x[:4], t[:4], ring_b, np.array([0, 0, 0, 1], np.uint8))
+    # the same ring with no rotatable bond is one rigid fragment
+    L = oracle.Ligand(x[:4], t[:4], ring_b, np.zeros(4, np.uint8))
+    assert L.n_frag == 1
+
+
+def _lig(seed=0, n=24, t=6):
+    g = np.random.default_rng(seed)
+    m = S.tree_ligand(g, n, t)
+    return oracle_ligand(m), m
+
+
+def oracle_ligand(m):
+    import oracle as O
+    return O.Ligand(m.xyz, m.types, m.bonds, m.rotatable)
+
+
+def _identity(L):
+    return np.concatenate([L.anchor(), [1.0, 0, 0, 0], np.zeros(L.n_tors)])
+
+
+def test_fk_identity_and_invariants(oracle):
+    L, m = _lig(1)
+    np.testing.assert_allclose(L.fk(_identity(L)), m.xyz, atol=1e-12)
+    g = np.random.default_rng(2)
+    frag = L.frag()
+    for _ in range(20):
+        dof = np.concatenate([g.normal(size=3) * 4, g.normal(size=4), g.uniform(-np.pi, np.pi, L.n_tors)])
+        x = L.fk(dof)
+        for a, b in m.bonds:
+            assert np.linalg.norm(x[a] - x[b]) == pytest.approx(np.linalg.norm(m.xyz[a] - m.xyz[b]), abs=1e-12)
+        for f in range(L.n_frag):
+            idx = np.nonzero(frag == f)[0]
+            d0 = np.linalg.norm(m.xyz[idx, None] - m.xyz[None, idx], axis=-1)
+            d1 = np.linalg.norm(x[idx, None] - x[None, idx], axis=-1)
+            np.testing.assert_allclose(d1, d0, atol=1e-12)
+        # root centroid sits at t
+        root = np.nonzero(frag == L.root)[0]
+        np.testing.assert_allclose(x[root].mean(axis=0), dof[:3], atol=1e-12)
+        # q == -q, q == 3q, psi + 2 pi == psi
+        d2 = dof.copy()
+        d2[3:7] *= -3.0
+        d2[7:] += 2 * np.pi
+        np.testing.assert_allclose(L.fk(d2), x, atol=1e-11)
+
+
+def test_fk_rotation_matches_scipy(oracle):
+    L, m = _lig(3, 15, 0)
+    g = np.random.default_rng(4)
+    for _ in range(10):
+        q = S.random_quaternions(g, 1)[0]
+        t = g.normal(size=3)
+        x = L.fk(np.concatenate([t, q]))
+        R = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()   # scipy is scalar-last
+        np.testing.assert_allclose(x, (m.xyz - L.anchor()) @ R.T + t, atol=1e-12)
+
+
+def test_torsion_sense_matches_scipy(oracle):
+    """psi turns the child side right-handedly about parent atom -> child atom."""
+    L, m = _lig(5, 18, 3)
+    frag = L.frag()
+    tors = L.torsions()
+    for k in range(L.n_tors):
+        psi = 0.7 + 0.3 * k
+        dof = _identity(L)
+        dof[7 + k] = psi
+        x = L.fk(dof)
+        _, a_atom, c_atom = tors[k]
+        axis = m.xyz[c_atom] - m.xyz[a_atom]
+        axis /= np.linalg.norm(axis)
+        R = Rotation.from_rotvec(axis * psi).as_matrix()
+        moved = np.linalg.norm(x - m.xyz, axis=1) > 1e-9
+        # the child-side atoms rotate about the axis through the child atom
+        want = (m.xyz - m.xyz[c_atom]) @ R.T + m.xyz[c_atom]
+        np.testing.assert_allclose(x[moved], want[moved], atol=1e-12)
+        # the root fragment never moves
+        assert not moved[frag == L.root].any()
+
+
+def _zero_grid(oracle, center, edge=60.0):
+    dims, org = oracle.lattice(center, [edge] * 3, 2.0)
+    return oracle.Grid(np.zeros((8, dims[2], dims[1], dims[0])), dims, org, 2.0)
+
+
+def test_intra_newton_third_law(oracle):
+    """With empty maps only e_intra acts: zero net force and zero net torque."""
+    L, m = _lig(6, 30, 8)
+    G = _zero_grid(oracle, [0, 0, 0])
+    g = np.random.default_rng(7)
+    for _ in range(10):
+        dof = np.concatenate([g.normal(size=3), g.normal(size=4), g.uniform(-np.pi, np.pi, L.n_tors)])
+        r = L.score_grad(G, dof)
+        assert r["e_inter"] == 0.0 and r["pairs_in"] > 0
+        gx, x = r["grad_xyz"], r["xyz"]
+        scale = np.abs(gx).sum()
+        np.testing.assert_allclose(gx.sum(axis=0), 0, atol=1e-12 * max(scale, 1))
+        np.testing.assert_allclose(np.cross(x, gx).sum(axis=0), 0, atol=1e-11 * max(scale, 1))
+        np.testing.assert_allclose(r["grad_dof"][:7], 0, atol=1e-10 * max(scale, 1))
+
+
+def test_intra_invariant_under_root_motion(oracle):
+    L, m = _lig(8, 30, 8)
+    G = _zero_grid(oracle, [0, 0, 0])
+    g = np.random.default_rng(9)
+    psi = g.uniform(-np.pi, np.pi, L.n_tors)
+    e0 = L.score_grad(G, np.concatenate([[0, 0, 0], [1, 0, 0, 0], psi]))["e_intra"]
+    for _ in range(10):
+        dof = np.concatenate([g.normal(size=3) * 3, g.normal(size=4), psi])
+        assert L.score_grad(G, dof)["e_intra"] == pytest.approx(e0, rel=1e-12, abs=1e-13)
+
+
+def _c1_grid(oracle):
+    cfg = S.CONFIGS["c1"]
+    rx, rt, bxs = S.make_receptor(cfg)
+    b = bxs[0]
+    return oracle.Grid.build(rx, rt, b.center, b.size, b.spacing)
+
+
+@pytest.fixture(scope="module")
+def c1_grid(oracle):
+    return _c1_grid(oracle)
+
+
+def test_gradient_fd_dofs(oracle, c1_grid):
+    """Analytic dE/dPOT against central differences (h = 1e-6) on every DOF,
+    away from the non-smooth points (cell faces, term kinks, cutoff)."""
+    G = c1_grid
+    L, m = _lig(10, 26, 7)
+    g = np.random.default_rng(11)
+    lo, hi = G.origin.astype(np.float64), G.origin + G.h * (G.dims - 1)
+    checked = skipped = 0
+    for _ in range(40):
+        dof = np.concatenate([g.uniform(lo + 3, hi - 3), g.normal(size=4), g.uniform(-np.pi, np.pi, L.n_tors)])
+        r = L.score_grad(G, dof)
+        if min(r["min_face"], r["min_cut"], r["min_kink"]) < 1e-4:
+            skipped += 1
+            continue
+        h = 1e-6
+        for i in range(L.ndof):
+            dp, dm = dof.copy(), dof.copy()
+            dp[i] += h
+            dm[i] -= h
+            fd = (L.score_grad(G, dp)["e"] - L.score_grad(G, dm)["e"]) / (2 * h)
+            assert r["grad_dof"][i] == pytest.approx(fd, rel=1e-5, abs=1e-5 * (1 + abs(r["e"]))), i
+        # the raw-quaternion gradient is orthogonal to q
+        q = dof[3:7] / np.linalg.norm(dof[3:7])
+        assert abs(q @ r["grad_dof"][3:7]) < 1e-9 * (1 + np.abs(r["grad_dof"][3:7]).max())
+        checked += 1
+    assert checked >= 25, (checked, skipped)
+
+
+def test_gradient_fd_tangent(oracle, c1_grid):
+    """The tangent gradient (dE/dt, torque, dE/dpsi) against differences along
+    the retraction the optimiser uses: t + h e, exp(h e) q, psi + h e."""
+    G = c1_grid
+    L, m = _lig(12, 22, 5)
+    g = np.random.default_rng(13)
+    lo, hi = G.origin.astype(np.float64), G.origin + G.h * (G.dims - 1)
+    checked = 0
+    for _ in range(30):
+        dof = np.concatenate([g.uniform(lo + 3, hi - 3), S.random_quaternions(g, 1)[0],
+                              g.uniform(-np.pi, np.pi, L.n_tors)])
+        r = L.score_grad(G, dof)
+        if min(r["min_face"], r["min_cut"], r["min_kink"]) < 1e-4:
+            continue
+        h = 1e-6
+        for i in range(6 + L.n_tors):
+            vals = []
+            for s in (h, -h):
+                d = dof.copy()
+                if i < 3:
+                    d[i] += s
+                elif i < 6:
+                    rv = np.zeros(3)
+                    rv[i - 3] = s
+                    Rq = Rotation.from_rotvec(rv) * Rotation.from_quat([d[4], d[5], d[6], d[3]])
+                    xq = Rq.as_quat()
+                    d[3:7] = [xq[3], xq[0], xq[1], xq[2]]
+                else:
+                    d[7 + i - 6] += s
+                vals.append(L.score_grad(G, d)["e"])
+            fd = (vals[0] - vals[1]) / (2 * h)
+            assert r["grad_tan"][i] == pytest.approx(fd, rel=1e-5, abs=1e-5 * (1 + abs(r["e"]))), i
+        checked += 1
+    assert checked >= 18
+
+
+def test_gradient_fd_coordinates(oracle, c1_grid):
+    G = c1_grid
+    L, m = _lig(14, 20, 4)
+    g = np.random.default_rng(15)
+    lo, hi = G.origin.astype(np.float64), G.origin + G.h * (G.dims - 1)
+    checked = 0
+    for _ in range(20):
+        dof = np.concatenate([g.uniform(lo + 3, hi - 3), g.normal(size=4), g.uniform(-np.pi, np.pi, L.n_tors)])
+        x = L.fk(dof)
+        r = L.score_xyz(G, x)
+        if min(r["min_face"], r["min_cut"], r["min_kink"]) < 1e-4:
+            continue
+        h = 1e-6
+        for i in range(L.n_atoms):
+            for a in range(3):
+                xp, xm = x.copy(), x.copy()
+                xp[i, a] += h
+                xm[i, a] -= h
+                fd = (L.score_xyz(G, xp)["e"] - L.score_xyz(G, xm)["e"]) / (2 * h)
+                assert r["grad_xyz"][i, a] == pytest.approx(fd, rel=1e-5, abs=1e-6 * (1 + abs(r["e"])))
+        checked += 1
+    assert checked >= 12
+
+
+def test_score_grad_consistent_with_xyz(oracle, c1_grid):
+    L, m = _lig(16, 30, 9)
+    g = np.random.default_rng(17)
+    for _ in range(5):
+        dof = np.concatenate([g.uniform(8, 20, 3), g.normal(size=4), g.uniform(-np.pi, np.pi, L.n_tors)])
+        a = L.score_grad(c1_grid, dof)
+        b = L.score_xyz(c1_grid, a["xyz"])
+        assert a["e"] == b["e"]
+        np.testing.assert_array_equal(a["grad_xyz"], b["grad_xyz"])

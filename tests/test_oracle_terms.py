@@ -1,0 +1,90 @@
+"""Pins of the oracle's empirical terms (Eq. qvina_eq_3, Vina functional form).
+
+Closed forms from tests/golden, derivatives against central differences, and
+the 8 A hard cutoff on a one-atom receptor.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2506_20043_amd.synth import XS_NAMES
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+TERM_INDEX = {"gauss1": 0, "gauss2": 1, "repulsion": 2, "hydrophobic": 3, "hbond": 4}
+
+
+def _rows(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                yield line.split(None, 3 if name == "vina_pairs.txt" else 2)
+
+
+def test_terms_closed_forms(oracle):
+    n = 0
+    for term, d, expr in _rows("vina_terms.txt"):
+        v, _ = oracle.terms(float(d))
+        assert v[TERM_INDEX[term]] == pytest.approx(eval(expr, {"math": math}), abs=1e-15), (term, d)
+        n += 1
+    assert n >= 20
+
+
+def test_pair_closed_forms(oracle):
+    for ta, tb, r, expr in _rows("vina_pairs.txt"):
+        e, _ = oracle.pair(XS_NAMES.index(ta), XS_NAMES.index(tb), float(r))
+        assert e == pytest.approx(eval(expr, {"math": math}), rel=1e-13, abs=1e-15), (ta, tb, r)
+
+
+def test_pair_symmetric(oracle):
+    for a in range(8):
+        for b in range(8):
+            for r in (2.9, 3.4, 4.1, 5.5, 7.9):
+                assert oracle.pair(a, b, r)[0] == pytest.approx(oracle.pair(b, a, r)[0], rel=1e-14)
+
+
+@pytest.mark.parametrize("d", [-2.3, -1.1, -0.4, 0.2, 0.9, 1.2, 2.2, 3.7, 4.1])
+def test_term_derivatives_fd(oracle, d):
+    h = 1e-6
+    _, dv = oracle.terms(d)
+    vp, _ = oracle.terms(d + h)
+    vm, _ = oracle.terms(d - h)
+    np.testing.assert_allclose(dv, (vp - vm) / (2 * h), rtol=1e-7, atol=1e-9)
+
+
+def test_pair_derivative_fd(oracle):
+    h = 1e-6
+    for a in range(8):
+        for b in range(8):
+            for r in (3.05, 3.77, 4.66, 6.01, 7.3):
+                _, de = oracle.pair(a, b, r)
+                fd = (oracle.pair(a, b, r + h)[0] - oracle.pair(a, b, r - h)[0]) / (2 * h)
+                assert de == pytest.approx(fd, rel=1e-6, abs=1e-9)
+
+
+def test_type_table(oracle):
+    # X-Score radii by element and the XS donor / acceptor / hydrophobic sets
+    radii = [oracle.type_params(t)[0] for t in range(8)]
+    assert radii == [1.9, 1.9, 1.8, 1.8, 1.8, 1.7, 1.7, 2.0]
+    assert [oracle.type_params(t)[1] for t in range(8)] == [1, 0, 0, 0, 0, 0, 0, 0]
+    assert [oracle.type_params(t)[2] for t in range(8)] == [0, 0, 0, 1, 0, 0, 1, 0]
+    assert [oracle.type_params(t)[3] for t in range(8)] == [0, 0, 0, 0, 1, 1, 1, 0]
+    np.testing.assert_array_equal(oracle.weights(), [-0.0356, -0.00516, 0.840, -0.0351, -0.587])
+
+
+def test_cutoff_on_map(oracle):
+    """A one-atom receptor: the map is phi inside 8 A and exactly 0 outside."""
+    h = 0.375
+    dims, org = oracle.lattice([0.0, 0.0, 0.0], [6.0, 6.0, 6.0], h)
+    # put the atom on the lattice x axis line so that distances are exact
+    for gap, inside in ((8.0 - 1e-3, True), (8.0 + 1e-3, False), (7.0, True), (9.0, False)):
+        atom = np.array([[org[0] + gap, org[1], org[2]]], np.float32)
+        out = oracle.map_point(atom, [0], dims, org, h, 0, 0, 0)
+        r = float(np.float64(atom[0, 0]) - np.float64(org[0]))
+        for t in range(8):
+            want = oracle.pair(t, 0, r)[0] if inside else 0.0
+            assert out[t] == pytest.approx(want, rel=1e-12, abs=1e-300)
+        if inside:
+            assert np.all(out != 0.0)
