@@ -1,0 +1,258 @@
+/*
+ * pvdock.h -- C ABI of the MI355X (gfx950) docking hot path of PocketVina
+ * (arXiv 2506.20043): grid maps over the pocket boxes of one receptor, score
+ * and analytic gradient of ligand poses, and Monte Carlo + RILC-BFGS search.
+ *
+ * Conventions shared by every call
+ *   - Status: 0 = PV_OK; negative = error.  Nothing throws or aborts across
+ *     the ABI.  pv_last_error() returns a thread-local message for the last
+ *     failure on the calling thread.
+ *   - Host validation happens before anything is enqueued: an invalid call
+ *     returns an error and enqueues nothing.
+ *   - "host" pointers are read during the call only; "device" pointers must
+ *     stay valid until the work enqueued on `stream` has completed.
+ *   - Every call is asynchronous and ordered on `stream` (a hipStream_t;
+ *     NULL = the null stream).  Results are valid after synchronisation.
+ *   - Opaque handles are owned by the library until their *_free call.
+ *   - Output buffers are caller-allocated device memory.
+ *   - Arithmetic is IEEE binary32.
+ *
+ * Atom types are the Vina XS types: 0 C_H, 1 C_P, 2 N_P, 3 N_D, 4 N_A,
+ * 5 O_A, 6 O_DA, 7 S_P.
+ */
+#ifndef PVDOCK_H
+#define PVDOCK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PV_OK = 0,
+    PV_E_INVALID = -1,     /* malformed argument (NULL, bad type, bad bond, ...) */
+    PV_E_RANGE = -2,       /* size beyond a documented limit */
+    PV_E_NOMEM = -3,       /* device or host allocation failed */
+    PV_E_DEVICE = -4,      /* a HIP call failed */
+    PV_E_UNSUPPORTED = -5, /* request the library does not implement */
+    PV_E_STATE = -6        /* handles from different contexts, freed handle, ... */
+} pv_status;
+
+#define PV_NTYPES 8
+#define PV_MAX_ATOMS 128   /* heavy atoms per ligand */
+#define PV_MAX_TORS 32     /* rotatable bonds per ligand */
+#define PV_MAX_PAIRS 8128  /* intra pairs per ligand (128 choose 2) */
+
+/* message of the last failure on this thread ("" if none) */
+const char* pv_last_error(void);
+/* ABI version: major * 100 + minor */
+int32_t pv_version(void);
+
+/* ------------------------------------------------------------------ context */
+typedef struct pv_ctx pv_ctx;
+/* Binds a context to HIP device `device`.  Every later call on the context
+ * makes that device current. */
+pv_status pv_create(int32_t device, pv_ctx** out);
+void pv_destroy(pv_ctx* ctx);
+
+/* ---------------------------------------------------------------- grid maps
+ * Grid cache of the paper's "Kernel 1" (Methods, Accelerated Docking;
+ * Supplementary Algorithm 2, first step): for every search box and every
+ * ligand atom type t, the lattice map
+ *     M_t(g) = sum over receptor atoms r with |g - x_r| < 8 A of phi_{t,type_r}(|g - x_r|)
+ * where phi is the Vina-form pair energy (gauss1, gauss2, repulsion,
+ * hydrophobic, hydrogen bond of the surface distance).  The 8 A test is the
+ * binary32 comparison fma(dx,dx,fma(dy,dy,dz*dz)) < 64 with g = fma(i,h,origin).
+ *
+ * Lattice of a box: n = ceil(size/spacing) + 1 points per axis, origin =
+ * binary32(center - (n-1) * spacing / 2) rounded once from binary64, points
+ * origin + spacing * (i, j, k).  Maps are [box][type][z][y][x] binary32,
+ * resident in device memory and owned by the handle.
+ *
+ * rec_xyz: host [n_rec][3]; rec_type: host [n_rec], values < 8.
+ * boxes: host [n_boxes]; size > 0, spacing > 0, at most 2048 points per axis.
+ * penalty_slope: kcal/mol per A added for each atom coordinate outside a box
+ * (its lookups clamp to the box face); must be >= 0.
+ * n_rec may be 0 (all maps zero). */
+typedef struct {
+    float center[3];
+    float size[3];
+    float spacing;
+} pv_box;
+
+/* Host only (no device needed): the lattice of one box as pv_build_grids
+ * defines it. */
+pv_status pv_box_lattice(const pv_box* box, int32_t dims[3], float origin[3]);
+
+typedef struct pv_grids pv_grids;
+pv_status pv_build_grids(pv_ctx* ctx, int32_t n_rec, const float* rec_xyz, const uint8_t* rec_type,
+                         const pv_box* boxes, int32_t n_boxes, float penalty_slope,
+                         void* stream, pv_grids** out);
+/* dims, origin and the device address of the 8 maps of one box */
+pv_status pv_grids_info(const pv_grids* g, int32_t box, int32_t dims[3], float origin[3],
+                        const float** dev_maps);
+/* copies the 8 maps of one box ([8][nz][ny][nx] binary32) into the caller's
+ * device buffer `dst`, ordered on `stream` */
+pv_status pv_grids_copy(const pv_grids* g, int32_t box, float* dst, void* stream);
+void pv_grids_free(pv_grids* g);
+
+/* ------------------------------------------------------------------ ligands
+ * Ligand model of the POT conformation (Eq. qvina_eq_1): rigid fragments
+ * are the components left after cutting the rotatable bonds and form a tree;
+ * torsion k is the k-th rotatable bond in input order; the root fragment is
+ * the largest (ties: the one holding the lowest atom index); the translation
+ * is the world position of the root fragment's centroid; psi = 0 is the input
+ * geometry and positive psi turns the child (away-from-root) side right-
+ * handedly about the axis parent atom -> child atom.  Intra pairs (the
+ * e_intra of Eq. qvina_eq_3) are atoms in different fragments at least four
+ * bonds apart.
+ *
+ * Arrays are host, concatenated over ligands: atom_off [n_lig+1], ref_xyz
+ * [atoms][3], type [atoms]; bond_off [n_lig+1], bonds [bonds][2] with
+ * ligand-local atom indices, rotatable [bonds] (0/1).  Each ligand must be
+ * connected, every rotatable bond must be a bridge, and n_atoms <= 128,
+ * rotatable bonds <= 32.  Rings are allowed inside fragments. */
+typedef struct pv_ligands pv_ligands;
+pv_status pv_ligands_create(pv_ctx* ctx, int32_t n_lig, const int32_t* atom_off, const float* ref_xyz,
+                            const uint8_t* type, const int32_t* bond_off, const int32_t* bonds,
+                            const uint8_t* rotatable, pv_ligands** out);
+/* info = {n_atoms, n_frag, n_tors, n_pairs, root_size, depth, dof (7+T), 0} */
+pv_status pv_ligands_info(const pv_ligands* l, int32_t lig, int32_t info[8]);
+void pv_ligands_free(pv_ligands* l);
+
+/* Host only (no device needed): checks one ligand and describes the model
+ * pv_ligands_create would build.  info as pv_ligands_info.  pairs (may be
+ * NULL): the intra pairs as [n_pairs][2] input atom indices, lower index
+ * first, at most max_pairs of them (PV_E_RANGE if more).  frag (may be NULL):
+ * [n_atoms] fragment of each input atom, 0 = root, in the depth-first order
+ * of the torsion tree. */
+pv_status pv_ligand_describe(int32_t n_atoms, const float* ref_xyz, const uint8_t* type, int32_t n_bonds,
+                             const int32_t* bonds, const uint8_t* rotatable, int32_t info[8], int32_t* pairs,
+                             int32_t max_pairs, int32_t* frag);
+
+/* --------------------------------------------------------------- score+grad
+ * Score SF = e_inter + e_intra (Eq. qvina_eq_3) of B poses and its analytic
+ * gradient.  e_inter is the trilinear interpolation of the box's map of each
+ * atom's type plus the out-of-box penalty; e_intra sums the pair energy over
+ * the ligand's intra pairs closer than 8 A.
+ *
+ * dof: device [B][dof_stride], row = [tx, ty, tz, qw, qx, qy, qz, psi_0 ..
+ * psi_{T-1}] (the quaternion need not be unit; a zero quaternion gives NaN).
+ * lig_of_pose, box_of_pose: device [B]; an out-of-range index sets that
+ * pose's outputs to NaN.
+ * grad_energy: device [B] upstream factor for a backward pass, or NULL (= 1).
+ * Outputs (device, any may be NULL):
+ *   energy [B]; e_parts [B][2] = (e_inter, e_intra);
+ *   grad_dof [B][dof_stride]: grad_energy * dSF/d(t, q, psi), where the
+ *   quaternion part is the derivative with respect to the raw input q;
+ *   xyz_out, grad_xyz [B][xyz_stride][3]: atom coordinates and
+ *   grad_energy * dSF/dx in the caller's atom order.
+ * dof_stride >= 7 + max T; xyz_stride >= max atoms when xyz outputs are used. */
+pv_status pv_score_grad(pv_ctx* ctx, const pv_grids* grids, const pv_ligands* ligs, int32_t n_poses,
+                        const int32_t* lig_of_pose, const int32_t* box_of_pose, const float* dof,
+                        int32_t dof_stride, const float* grad_energy, float* energy, float* e_parts,
+                        float* grad_dof, float* xyz_out, float* grad_xyz, int32_t xyz_stride,
+                        void* stream);
+
+/* The same score on given world coordinates xyz [B][xyz_stride][3] (caller's
+ * atom order): energy, e_parts and grad_energy * dSF/dx. */
+pv_status pv_score_grad_xyz(pv_ctx* ctx, const pv_grids* grids, const pv_ligands* ligs, int32_t n_poses,
+                            const int32_t* lig_of_pose, const int32_t* box_of_pose, const float* xyz,
+                            int32_t xyz_stride, const float* grad_energy, float* energy, float* e_parts,
+                            float* grad_xyz, void* stream);
+
+/* -------------------------------------------------------------------- search
+ * Parameters of RILC-BFGS (Eqs. qvina_eq_6 .. qvina_eq_12) and of the Monte
+ * Carlo chains (Supplementary Algorithm 2).  BFGS runs in the 6+T tangent
+ * space (translation, rotation vector, torsions) with the orientation moved
+ * by a left rotation; Lewis-Overton line search with Armijo parameter ls_rho
+ * and weak-Wolfe parameter ls_sigma, at most ls_max_trials trials starting
+ * from step 1; cautious update when y.s/s.s > eps_curv * |g|; history of
+ * bfgs_m pairs; stop when |g| <= eps_grad, when the direction is not a
+ * descent direction, or after bfgs_max_iter iterations.
+ * MC step: mutate one entity (position by a uniform point of a ball of
+ * radius mut_pos_amp; orientation by a uniform rotation vector of a ball of
+ * radius mut_rot_amp / R_g; or one torsion redrawn), BFGS, Metropolis
+ * acceptance exp((e_cur - e_new) / temperature), and a new best refined by a
+ * second BFGS of at most refine_max_iter iterations.
+ * Random numbers: Philox4x64-10 keyed (seed, 0) with counter (block, step,
+ * chain, job). */
+typedef struct {
+    int32_t chains;          /* MC chains per job, >= 1 */
+    int32_t steps;           /* MC steps per chain, >= 0 */
+    int32_t bfgs_max_iter;   /* >= 0 */
+    int32_t bfgs_m;          /* 1 .. 8 */
+    int32_t ls_max_trials;   /* 1 .. 64 */
+    int32_t refine_max_iter; /* >= 0 */
+    float ls_rho, ls_sigma, eps_grad, eps_curv;
+    float temperature, mut_pos_amp, mut_rot_amp;
+    uint32_t flags;          /* PV_DOCK_* */
+    uint64_t seed;
+    int32_t workgroups;      /* persistent launch width; 0 = chosen by the library */
+    int32_t reserved;
+} pv_dock_params;
+
+#define PV_DOCK_TIMESTAMPS 1u /* write per-job device timestamps */
+#define PV_DOCK_GRAPH 2u      /* pv_dock_run captures its launches in a hipGraph once and replays it */
+
+/* fills the defaults: 30 BFGS iterations, m = 5, 10 trials, rho 1e-4,
+ * sigma 0.1, eps_grad 1e-3, eps_curv 1e-6, temperature 1.2, amplitudes 2 A */
+void pv_dock_params_default(pv_dock_params* p);
+
+typedef struct { int32_t ligand, box; } pv_job;
+
+/* Outputs of a dock (device arrays; any may be NULL):
+ *   chain_best_e [jobs*chains], chain_best_dof [jobs*chains][dof_stride],
+ *   chain_evals [jobs*chains] (score+grad evaluations, line-search trials
+ *   and refinements included), chain_pairs [jobs*chains] (intra pairs
+ *   evaluated inside the cutoff, for the roofline),
+ *   job_best_e [jobs], job_best_chain [jobs] (ties: lowest chain),
+ *   job_evals [jobs], job_status [jobs] (0 ok, 1 non-finite best energy),
+ *   job_t_start, job_t_end [jobs] (device clock, 100 MHz; with
+ *   PV_DOCK_TIMESTAMPS). */
+typedef struct {
+    float* chain_best_e;
+    float* chain_best_dof;
+    int64_t* chain_evals;
+    int64_t* chain_pairs;
+    float* job_best_e;
+    int32_t* job_best_chain;
+    int64_t* job_evals;
+    int32_t* job_status;
+    uint64_t* job_t_start;
+    uint64_t* job_t_end;
+    int32_t dof_stride;
+} pv_dock_out;
+
+/* A dock plan: the job table uploaded once and the parameters checked.
+ * jobs: host [n_jobs]; every ligand and box index must exist. */
+typedef struct pv_plan pv_plan;
+pv_status pv_dock_plan(pv_ctx* ctx, const pv_grids* grids, const pv_ligands* ligs, const pv_job* jobs,
+                       int32_t n_jobs, const pv_dock_params* params, pv_plan** out);
+/* Batched form: every (job, chain) of the plan in one persistent launch
+ * whose waves pull work from a device queue (plus a reset and a per-job
+ * reduction).  Captured in a hipGraph when the plan's flags ask for it. */
+pv_status pv_dock_run(pv_plan* plan, const pv_dock_out* out, void* stream);
+/* Plain form: one launch per job, in job order, on `stream`
+ * (the per-ligand loop of Supplementary Algorithm 2). */
+pv_status pv_dock_run_plain(pv_plan* plan, const pv_dock_out* out, void* stream);
+void pv_plan_free(pv_plan* plan);
+
+/* plan + batched run + free in one call; it synchronises `stream` before
+ * it releases the plan, so it returns after the dock has completed */
+pv_status pv_dock(pv_ctx* ctx, const pv_grids* grids, const pv_ligands* ligs, const pv_job* jobs,
+                  int32_t n_jobs, const pv_dock_params* params, const pv_dock_out* out, void* stream);
+
+/* Local optimisation only: one BFGS run (the parameters' bfgs_* and ls_*
+ * fields) from each of B poses.  dof_in, dof_out: device [B][dof_stride];
+ * energy [B]; n_evals [B] (may be NULL).  dof_out quaternions are unit. */
+pv_status pv_local_opt(pv_ctx* ctx, const pv_grids* grids, const pv_ligands* ligs, int32_t n_poses,
+                       const int32_t* lig_of_pose, const int32_t* box_of_pose, const float* dof_in,
+                       int32_t dof_stride, const pv_dock_params* params, float* dof_out, float* energy,
+                       int64_t* n_evals, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,823 @@
+// pv_api.cpp -- the C ABI of include/pvdock.h: argument checks, device
+// tables of grids, ligands and dock plans, and the launch sequences.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/pvdock.h"
+#include "pv_internal.h"
+
+using namespace pv;
+
+namespace {
+
+thread_local std::string g_err;
+
+pv_status fail(pv_status s, const std::string& msg)
+{
+    g_err = msg;
+    return s;
+}
+
+pv_status hip_fail(hipError_t e, const char* what)
+{
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? PV_E_NOMEM : PV_E_DEVICE;
+}
+
+#define HIP_TRY(expr, what)                                 \
+    do {                                                    \
+        hipError_t _e = (expr);                             \
+        if (_e != hipSuccess) return hip_fail(_e, what);    \
+    } while (0)
+
+template <class T>
+pv_status upload(T** dst, const T* src, size_t n, const char* what)
+{
+    *dst = nullptr;
+    if (n == 0) n = 1;  // keep a valid pointer for empty tables
+    hipError_t e = hipMalloc((void**)dst, n * sizeof(T));
+    if (e != hipSuccess) return hip_fail(e, what);
+    if (src) {
+        e = hipMemcpy(*dst, src, n * sizeof(T), hipMemcpyHostToDevice);
+        if (e != hipSuccess) { (void)hipFree(*dst); *dst = nullptr; return hip_fail(e, what); }
+    }
+    return PV_OK;
+}
+
+void dfree(void* p)
+{
+    if (p) (void)hipFree(p);
+}
+
+}  // namespace
+
+struct pv_ctx {
+    int device;
+    int n_cu;
+    uint32_t magic;
+};
+
+struct pv_grids {
+    pv_ctx* ctx;
+    int32_t n_boxes;
+    float kappa;
+    float* maps;
+    int32_t* dims;
+    float* geom;
+    int64_t* map_off;
+    float4* atoms;
+    int32_t* atom_off;
+    int32_t* tile_off;
+    std::vector<int32_t> h_dims;
+    std::vector<float> h_geom;
+    std::vector<int64_t> h_off;
+};
+
+struct pv_ligands {
+    pv_ctx* ctx;
+    int32_t n_lig;
+    int32_t max_atoms, max_pairs, max_tors;
+    DevLig* ligs;
+    float4* atoms;
+    int16_t* perm;
+    DevFrag* frags;
+    int8_t* tors_frag;
+    uint32_t* pairs;
+    std::vector<std::array<int32_t, 8>>* info;
+};
+
+struct pv_plan {
+    pv_ctx* ctx;
+    const pv_grids* grids;
+    const pv_ligands* ligs;
+    SearchParams sp;
+    int32_t n_jobs;
+    int2* jobs;
+    std::vector<int2> h_jobs;
+    uint32_t* queue;
+    float* scratch_best;      // chain_best_e when the caller does not want it
+    int64_t* scratch_evals;   // chain_evals when only job_evals is wanted
+    int32_t workgroups;
+    hipStream_t cap_stream;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    pv_dock_out cached;
+    bool have_graph;
+};
+
+namespace {
+
+bool ctx_ok(const pv_ctx* c) { return c && c->magic == 0x70766378u; }
+
+pv_status set_device(const pv_ctx* c)
+{
+    HIP_TRY(hipSetDevice(c->device), "hipSetDevice");
+    return PV_OK;
+}
+
+GridDev grid_view(const pv_grids* g)
+{
+    GridDev v;
+    v.maps = g->maps;
+    v.dims = g->dims;
+    v.geom = g->geom;
+    v.map_off = g->map_off;
+    v.n_boxes = g->n_boxes;
+    v.kappa = g->kappa;
+    return v;
+}
+
+LigDev lig_view(const pv_ligands* l)
+{
+    LigDev v;
+    v.ligs = l->ligs;
+    v.atoms = l->atoms;
+    v.perm = l->perm;
+    v.frags = l->frags;
+    v.tors_frag = l->tors_frag;
+    v.pairs = l->pairs;
+    v.n_lig = l->n_lig;
+    v.max_atoms = l->max_atoms;
+    v.max_pairs = l->max_pairs;
+    v.max_tors = l->max_tors;
+    return v;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pv_last_error(void) { return g_err.c_str(); }
+
+int32_t pv_version(void) { return 100; }
+
+pv_status pv_create(int32_t device, pv_ctx** out)
+{
+    if (!out) return fail(PV_E_INVALID, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+    if (device < 0 || device >= n) return fail(PV_E_INVALID, "no such HIP device");
+    HIP_TRY(hipSetDevice(device), "hipSetDevice");
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties");
+    pv_ctx* c = new (std::nothrow) pv_ctx;
+    if (!c) return fail(PV_E_NOMEM, "host allocation");
+    c->device = device;
+    c->n_cu = prop.multiProcessorCount;
+    c->magic = 0x70766378u;
+    *out = c;
+    return PV_OK;
+}
+
+void pv_destroy(pv_ctx* c)
+{
+    if (!ctx_ok(c)) return;
+    c->magic = 0;
+    delete c;
+}
+
+// ------------------------------------------------------------------ grids
+static pv_status lattice(const pv_box& B, int32_t dims[3], float origin[3], float ext[3])
+{
+    const double h = B.spacing;
+    if (!(h > 0.0) || !std::isfinite(h)) return fail(PV_E_INVALID, "box spacing must be > 0");
+    for (int a = 0; a < 3; ++a) {
+        if (!(B.size[a] > 0.f) || !std::isfinite(B.size[a]) || !std::isfinite(B.center[a]))
+            return fail(PV_E_INVALID, "box size must be > 0 and finite");
+        const double n = std::ceil((double)B.size[a] / h) + 1.0;
+        if (n > 2048.0) return fail(PV_E_RANGE, "more than 2048 lattice points on an axis");
+        dims[a] = (int32_t)n;
+        origin[a] = (float)((double)B.center[a] - 0.5 * (n - 1.0) * h);
+        if (ext) ext[a] = (float)((n - 1.0) * h);
+    }
+    return PV_OK;
+}
+
+pv_status pv_box_lattice(const pv_box* box, int32_t dims[3], float origin[3])
+{
+    if (!box || !dims || !origin) return fail(PV_E_INVALID, "NULL argument");
+    return lattice(*box, dims, origin, nullptr);
+}
+
+pv_status pv_build_grids(pv_ctx* ctx, int32_t n_rec, const float* rec_xyz, const uint8_t* rec_type,
+                         const pv_box* boxes, int32_t n_boxes, float penalty_slope, void* stream,
+                         pv_grids** out)
+{
+    if (!out) return fail(PV_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!ctx_ok(ctx)) return fail(PV_E_STATE, "invalid context");
+    if (n_rec < 0) return fail(PV_E_INVALID, "n_rec < 0");
+    if (n_rec > 0 && (!rec_xyz || !rec_type)) return fail(PV_E_INVALID, "receptor arrays are NULL");
+    if (n_boxes < 1 || !boxes) return fail(PV_E_INVALID, "need at least one box");
+    if (!(penalty_slope >= 0.f) || !std::isfinite(penalty_slope)) return fail(PV_E_INVALID, "penalty_slope must be finite and >= 0");
+    for (int32_t r = 0; r < n_rec; ++r) {
+        if (rec_type[r] >= kNTypes) return fail(PV_E_INVALID, "receptor atom type out of range");
+        for (int a = 0; a < 3; ++a)
+            if (!std::isfinite(rec_xyz[3 * r + a])) return fail(PV_E_INVALID, "non-finite receptor coordinate");
+    }
+    std::vector<int32_t> dims(4 * (size_t)n_boxes);
+    std::vector<float> geom(8 * (size_t)n_boxes);
+    std::vector<int64_t> off(n_boxes);
+    std::vector<int32_t> tile_off(n_boxes + 1);
+    int64_t total = 0, tiles = 0;
+    for (int32_t b = 0; b < n_boxes; ++b) {
+        const pv_box& B = boxes[b];
+        int32_t d3[3];
+        float o3[3], e3[3];
+        pv_status ls = lattice(B, d3, o3, e3);
+        if (ls != PV_OK) return ls;
+        const double h = B.spacing;
+        int64_t msz = 1;
+        for (int a = 0; a < 3; ++a) {
+            dims[4 * b + a] = d3[a];
+            geom[8 * b + a] = o3[a];
+            geom[8 * b + 5 + a] = e3[a];
+            msz *= (int64_t)d3[a];
+        }
+        dims[4 * b + 3] = 0;
+        geom[8 * b + 3] = B.spacing;
+        geom[8 * b + 4] = (float)(1.0 / h);
+        off[b] = total;
+        total += 8 * msz;
+        tile_off[b] = (int32_t)tiles;
+        tiles += (int64_t)((dims[4 * b] + kTileX - 1) / kTileX) * ((dims[4 * b + 1] + kTileY - 1) / kTileY) *
+                 ((dims[4 * b + 2] + kTileZ - 1) / kTileZ);
+        if (tiles > INT32_MAX) return fail(PV_E_RANGE, "too many lattice tiles");
+    }
+    tile_off[n_boxes] = (int32_t)tiles;
+    // receptor atoms that can reach each box (8 A plus a margin)
+    std::vector<float4> atoms;
+    std::vector<int32_t> atom_off(n_boxes + 1, 0);
+    for (int32_t b = 0; b < n_boxes; ++b) {
+        atom_off[b] = (int32_t)atoms.size();
+        double lo[3], hi[3];
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = (double)geom[8 * b + a] - 8.05;
+            hi[a] = (double)geom[8 * b + a] + (double)geom[8 * b + 5 + a] + 8.05;
+        }
+        for (int32_t r = 0; r < n_rec; ++r) {
+            const float* x = rec_xyz + 3 * r;
+            if (x[0] < lo[0] || x[0] > hi[0] || x[1] < lo[1] || x[1] > hi[1] || x[2] < lo[2] || x[2] > hi[2]) continue;
+            float w;
+            uint32_t t = rec_type[r];
+            std::memcpy(&w, &t, 4);
+            atoms.push_back(make_float4(x[0], x[1], x[2], w));
+        }
+    }
+    atom_off[n_boxes] = (int32_t)atoms.size();
+    pv_status st = set_device(ctx);
+    if (st != PV_OK) return st;
+    pv_grids* g = new (std::nothrow) pv_grids();
+    if (!g) return fail(PV_E_NOMEM, "host allocation");
+    g->ctx = ctx;
+    g->n_boxes = n_boxes;
+    g->kappa = penalty_slope;
+    g->h_dims = dims;
+    g->h_geom = geom;
+    g->h_off = off;
+    if ((st = upload(&g->maps, (const float*)nullptr, (size_t)total, "map allocation")) != PV_OK ||
+        (st = upload(&g->dims, dims.data(), dims.size(), "grid tables")) != PV_OK ||
+        (st = upload(&g->geom, geom.data(), geom.size(), "grid tables")) != PV_OK ||
+        (st = upload(&g->map_off, off.data(), off.size(), "grid tables")) != PV_OK ||
+        (st = upload(&g->atoms, atoms.data(), atoms.size(), "receptor upload")) != PV_OK ||
+        (st = upload(&g->atom_off, atom_off.data(), atom_off.size(), "receptor upload")) != PV_OK ||
+        (st = upload(&g->tile_off, tile_off.data(), tile_off.size(), "grid tables")) != PV_OK) {
+        pv_grids_free(g);
+        return st;
+    }
+    GridBuildArgs a;
+    a.atoms = g->atoms;
+    a.atom_off = g->atom_off;
+    a.maps = g->maps;
+    a.map_off = g->map_off;
+    a.dims = g->dims;
+    a.geom = g->geom;
+    a.tile_off = g->tile_off;
+    a.n_boxes = n_boxes;
+    hipError_t e = launch_build_grids(a, tiles, (hipStream_t)stream);
+    if (e != hipSuccess) {
+        pv_grids_free(g);
+        return hip_fail(e, "grid-map launch");
+    }
+    *out = g;
+    return PV_OK;
+}
+
+pv_status pv_grids_info(const pv_grids* g, int32_t box, int32_t dims[3], float origin[3], const float** dev_maps)
+{
+    if (!g) return fail(PV_E_INVALID, "grids is NULL");
+    if (box < 0 || box >= g->n_boxes) return fail(PV_E_INVALID, "no such box");
+    for (int a = 0; a < 3; ++a) {
+        if (dims) dims[a] = g->h_dims[4 * box + a];
+        if (origin) origin[a] = g->h_geom[8 * box + a];
+    }
+    if (dev_maps) *dev_maps = g->maps + g->h_off[box];
+    return PV_OK;
+}
+
+pv_status pv_grids_copy(const pv_grids* g, int32_t box, float* dst, void* stream)
+{
+    if (!g || !dst) return fail(PV_E_INVALID, "NULL argument");
+    if (box < 0 || box >= g->n_boxes) return fail(PV_E_INVALID, "no such box");
+    pv_status st = set_device(g->ctx);
+    if (st != PV_OK) return st;
+    const size_t n = 8 * (size_t)g->h_dims[4 * box] * g->h_dims[4 * box + 1] * g->h_dims[4 * box + 2];
+    HIP_TRY(hipMemcpyAsync(dst, g->maps + g->h_off[box], n * sizeof(float), hipMemcpyDeviceToDevice,
+                           (hipStream_t)stream),
+            "hipMemcpyAsync");
+    return PV_OK;
+}
+
+void pv_grids_free(pv_grids* g)
+{
+    if (!g) return;
+    if (ctx_ok(g->ctx)) (void)hipSetDevice(g->ctx->device);
+    dfree(g->maps); dfree(g->dims); dfree(g->geom); dfree(g->map_off);
+    dfree(g->atoms); dfree(g->atom_off); dfree(g->tile_off);
+    delete g;
+}
+
+// ------------------------------------------------------------------ ligands
+pv_status pv_ligands_create(pv_ctx* ctx, int32_t n_lig, const int32_t* atom_off, const float* ref_xyz,
+                            const uint8_t* type, const int32_t* bond_off, const int32_t* bonds,
+                            const uint8_t* rotatable, pv_ligands** out)
+{
+    if (!out) return fail(PV_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!ctx_ok(ctx)) return fail(PV_E_STATE, "invalid context");
+    if (n_lig < 1) return fail(PV_E_INVALID, "need at least one ligand");
+    if (!atom_off || !ref_xyz || !type || !bond_off) return fail(PV_E_INVALID, "ligand arrays are NULL");
+    if (atom_off[0] != 0 || bond_off[0] != 0) return fail(PV_E_INVALID, "offsets must start at 0");
+    std::vector<DevLig> H(n_lig);
+    std::vector<float> atoms;
+    std::vector<int16_t> perm;
+    std::vector<DevFrag> frags;
+    std::vector<int8_t> tors_frag;
+    std::vector<uint32_t> pairs;
+    auto* info = new (std::nothrow) std::vector<std::array<int32_t, 8>>(n_lig);
+    if (!info) return fail(PV_E_NOMEM, "host allocation");
+    int max_atoms = 0, max_pairs = 0, max_tors = 0;
+    for (int32_t i = 0; i < n_lig; ++i) {
+        const int32_t a0 = atom_off[i], a1 = atom_off[i + 1], b0 = bond_off[i], b1 = bond_off[i + 1];
+        if (a1 < a0 || b1 < b0) { delete info; return fail(PV_E_INVALID, "offsets must not decrease"); }
+        if (b1 > b0 && (!bonds || !rotatable)) { delete info; return fail(PV_E_INVALID, "bond arrays are NULL"); }
+        LigModel M;
+        std::string err;
+        int rc = build_ligand_model(a1 - a0, ref_xyz + 3 * (size_t)a0, type + a0, b1 - b0,
+                                    bonds ? bonds + 2 * (size_t)b0 : nullptr, rotatable ? rotatable + b0 : nullptr, M, err);
+        if (rc != PV_OK) { delete info; return fail((pv_status)rc, "ligand " + std::to_string(i) + ": " + err); }
+        DevLig& D = H[i];
+        std::memset(&D, 0, sizeof(D));
+        D.atom_base = (int32_t)perm.size();
+        D.n_atoms = M.n;
+        D.frag_base = (int32_t)frags.size();
+        D.n_frag = M.nf;
+        D.pair_base = (int32_t)pairs.size();
+        D.n_pairs = M.np;
+        D.tors_base = (int32_t)tors_frag.size();
+        D.n_tors = M.nt;
+        D.rounds = M.rounds;
+        for (int a = 0; a < 3; ++a) D.anchor[a] = M.anchor[a];
+        D.rot_amp_scale = (float)(1.0 / std::max((double)M.rg, 1e-3));
+        atoms.insert(atoms.end(), M.ref.begin(), M.ref.end());
+        for (int v : M.perm) perm.push_back((int16_t)v);
+        frags.insert(frags.end(), M.frags.begin(), M.frags.end());
+        for (int v : M.tors_frag) tors_frag.push_back((int8_t)v);
+        pairs.insert(pairs.end(), M.pairs.begin(), M.pairs.end());
+        (*info)[i] = {M.n, M.nf, M.nt, M.np, M.root_size, M.depth, 7 + M.nt, 0};
+        max_atoms = std::max(max_atoms, M.n);
+        max_pairs = std::max(max_pairs, M.np);
+        max_tors = std::max(max_tors, M.nt);
+    }
+    pv_status st = set_device(ctx);
+    if (st != PV_OK) { delete info; return st; }
+    pv_ligands* L = new (std::nothrow) pv_ligands();
+    if (!L) { delete info; return fail(PV_E_NOMEM, "host allocation"); }
+    L->ctx = ctx;
+    L->n_lig = n_lig;
+    L->max_atoms = max_atoms;
+    L->max_pairs = max_pairs;
+    L->max_tors = max_tors;
+    L->info = info;
+    if ((st = upload(&L->ligs, H.data(), H.size(), "ligand upload")) != PV_OK ||
+        (st = upload(&L->atoms, (const float4*)atoms.data(), atoms.size() / 4, "ligand upload")) != PV_OK ||
+        (st = upload(&L->perm, perm.data(), perm.size(), "ligand upload")) != PV_OK ||
+        (st = upload(&L->frags, frags.data(), frags.size(), "ligand upload")) != PV_OK ||
+        (st = upload(&L->tors_frag, tors_frag.data(), tors_frag.size(), "ligand upload")) != PV_OK ||
+        (st = upload(&L->pairs, pairs.data(), pairs.size(), "ligand upload")) != PV_OK) {
+        pv_ligands_free(L);
+        return st;
+    }
+    *out = L;
+    return PV_OK;
+}
+
+pv_status pv_ligands_info(const pv_ligands* l, int32_t lig, int32_t info[8])
+{
+    if (!l || !info) return fail(PV_E_INVALID, "NULL argument");
+    if (lig < 0 || lig >= l->n_lig) return fail(PV_E_INVALID, "no such ligand");
+    for (int k = 0; k < 8; ++k) info[k] = (*l->info)[lig][k];
+    return PV_OK;
+}
+
+pv_status pv_ligand_describe(int32_t n_atoms, const float* ref_xyz, const uint8_t* type, int32_t n_bonds,
+                             const int32_t* bonds, const uint8_t* rotatable, int32_t info[8], int32_t* pairs,
+                             int32_t max_pairs, int32_t* frag)
+{
+    if (!info || !ref_xyz || !type || n_atoms < 0 || n_bonds < 0) return fail(PV_E_INVALID, "NULL or negative argument");
+    if (n_bonds > 0 && (!bonds || !rotatable)) return fail(PV_E_INVALID, "bond arrays are NULL");
+    LigModel M;
+    std::string err;
+    int rc = build_ligand_model(n_atoms, ref_xyz, type, n_bonds, bonds, rotatable, M, err);
+    if (rc != PV_OK) return fail((pv_status)rc, err);
+    const int32_t v[8] = {M.n, M.nf, M.nt, M.np, M.root_size, M.depth, 7 + M.nt, 0};
+    for (int k = 0; k < 8; ++k) info[k] = v[k];
+    if (pairs) {
+        if (M.np > max_pairs) return fail(PV_E_RANGE, "more pairs than max_pairs");
+        std::vector<std::pair<int, int>> pl;
+        for (uint32_t pk : M.pairs) {
+            int a = M.perm[pk & 0xff], b = M.perm[(pk >> 8) & 0xff];
+            pl.push_back({std::min(a, b), std::max(a, b)});
+        }
+        std::sort(pl.begin(), pl.end());
+        for (size_t i = 0; i < pl.size(); ++i) { pairs[2 * i] = pl[i].first; pairs[2 * i + 1] = pl[i].second; }
+    }
+    if (frag)
+        for (int i = 0; i < M.n; ++i) {
+            uint32_t w;
+            std::memcpy(&w, &M.ref[4 * i + 3], 4);
+            frag[M.perm[i]] = (int32_t)(w >> 8);
+        }
+    return PV_OK;
+}
+
+void pv_ligands_free(pv_ligands* l)
+{
+    if (!l) return;
+    if (ctx_ok(l->ctx)) (void)hipSetDevice(l->ctx->device);
+    dfree(l->ligs); dfree(l->atoms); dfree(l->perm); dfree(l->frags); dfree(l->tors_frag); dfree(l->pairs);
+    delete l->info;
+    delete l;
+}
+
+// ------------------------------------------------------------------ score
+static pv_status check_pair(pv_ctx* ctx, const pv_grids* g, const pv_ligands* l)
+{
+    if (!ctx_ok(ctx)) return fail(PV_E_STATE, "invalid context");
+    if (!g || !l) return fail(PV_E_INVALID, "grids or ligands are NULL");
+    if (g->ctx != ctx || l->ctx != ctx) return fail(PV_E_STATE, "handles belong to another context");
+    return PV_OK;
+}
+
+pv_status pv_score_grad(pv_ctx* ctx, const pv_grids* grids, const pv_ligands* ligs, int32_t n_poses,
+                        const int32_t* lig_of_pose, const int32_t* box_of_pose, const float* dof,
+                        int32_t dof_stride, const float* grad_energy, float* energy, float* e_parts,
+                        float* grad_dof, float* xyz_out, float* grad_xyz, int32_t xyz_stride, void* stream)
+{
+    pv_status st = check_pair(ctx, grids, ligs);
+    if (st != PV_OK) return st;
+    if (n_poses < 0) return fail(PV_E_INVALID, "n_poses < 0");
+    if (n_poses == 0) return PV_OK;
+    if (!lig_of_pose || !box_of_pose || !dof) return fail(PV_E_INVALID, "input arrays are NULL");
+    if (dof_stride < 7 + ligs->max_tors) return fail(PV_E_INVALID, "dof_stride < 7 + max torsions");
+    if (dof_stride > 64) return fail(PV_E_RANGE, "dof_stride > 64");
+    if ((xyz_out || grad_xyz) && xyz_stride < ligs->max_atoms) return fail(PV_E_INVALID, "xyz_stride < max atoms");
+    if ((st = set_device(ctx)) != PV_OK) return st;
+    ScoreArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.g = grid_view(grids);
+    a.l = lig_view(ligs);
+    a.n_poses = n_poses;
+    a.lig_of_pose = lig_of_pose;
+    a.box_of_pose = box_of_pose;
+    a.dof = dof;
+    a.dof_stride = dof_stride;
+    a.from_xyz = 0;
+    a.grad_energy = grad_energy;
+    a.energy = energy;
+    a.e_parts = e_parts;
+    a.grad_dof = grad_dof;
+    a.xyz_out = xyz_out;
+    a.grad_xyz = grad_xyz;
+    a.xyz_stride = xyz_stride;
+    hipError_t e = launch_score(a, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "score launch");
+    return PV_OK;
+}
+
+pv_status pv_score_grad_xyz(pv_ctx* ctx, const pv_grids* grids, const pv_ligands* ligs, int32_t n_poses,
+                            const int32_t* lig_of_pose, const int32_t* box_of_pose, const float* xyz,
+                            int32_t xyz_stride, const float* grad_energy, float* energy, float* e_parts,
+                            float* grad_xyz, void* stream)
+{
+    pv_status st = check_pair(ctx, grids, ligs);
+    if (st != PV_OK) return st;
+    if (n_poses < 0) return fail(PV_E_INVALID, "n_poses < 0");
+    if (n_poses == 0) return PV_OK;
+    if (!lig_of_pose || !box_of_pose || !xyz) return fail(PV_E_INVALID, "input arrays are NULL");
+    if (xyz_stride < ligs->max_atoms) return fail(PV_E_INVALID, "xyz_stride < max atoms");
+    if ((st = set_device(ctx)) != PV_OK) return st;
+    ScoreArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.g = grid_view(grids);
+    a.l = lig_view(ligs);
+    a.n_poses = n_poses;
+    a.lig_of_pose = lig_of_pose;
+    a.box_of_pose = box_of_pose;
+    a.dof = xyz;
+    a.dof_stride = 0;
+    a.from_xyz = 1;
+    a.grad_energy = grad_energy;
+    a.energy = energy;
+    a.e_parts = e_parts;
+    a.grad_xyz = grad_xyz;
+    a.xyz_stride = xyz_stride;
+    hipError_t e = launch_score(a, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "score launch");
+    return PV_OK;
+}
+
+// ------------------------------------------------------------------ search
+void pv_dock_params_default(pv_dock_params* p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->chains = 8;
+    p->steps = 100;
+    p->bfgs_max_iter = 30;
+    p->bfgs_m = 5;
+    p->ls_max_trials = 10;
+    p->refine_max_iter = 30;
+    p->ls_rho = 1e-4f;
+    p->ls_sigma = 0.1f;
+    p->eps_grad = 1e-3f;
+    p->eps_curv = 1e-6f;
+    p->temperature = 1.2f;
+    p->mut_pos_amp = 2.0f;
+    p->mut_rot_amp = 2.0f;
+    p->seed = 20043;
+}
+
+static pv_status check_search(const pv_dock_params* p, bool mc)
+{
+    if (!p) return fail(PV_E_INVALID, "params is NULL");
+    if (mc && p->chains < 1) return fail(PV_E_INVALID, "chains < 1");
+    if (mc && p->steps < 0) return fail(PV_E_INVALID, "steps < 0");
+    if (p->bfgs_max_iter < 0 || (mc && p->refine_max_iter < 0)) return fail(PV_E_INVALID, "iteration caps must be >= 0");
+    if (p->bfgs_m < 1 || p->bfgs_m > 8) return fail(PV_E_RANGE, "bfgs_m must be 1..8");
+    if (p->ls_max_trials < 1 || p->ls_max_trials > 64) return fail(PV_E_RANGE, "ls_max_trials must be 1..64");
+    if (!(p->ls_rho > 0.f && p->ls_rho < p->ls_sigma && p->ls_sigma < 1.f))
+        return fail(PV_E_INVALID, "need 0 < ls_rho < ls_sigma < 1");
+    if (!(p->eps_grad >= 0.f) || !(p->eps_curv >= 0.f)) return fail(PV_E_INVALID, "epsilons must be >= 0");
+    if (mc && !(p->temperature > 0.f)) return fail(PV_E_INVALID, "temperature must be > 0");
+    if (mc && (!(p->mut_pos_amp >= 0.f) || !(p->mut_rot_amp >= 0.f))) return fail(PV_E_INVALID, "amplitudes must be >= 0");
+    return PV_OK;
+}
+
+static SearchParams to_sp(const pv_dock_params* p)
+{
+    SearchParams s;
+    s.chains = p->chains;
+    s.steps = p->steps;
+    s.max_iter = p->bfgs_max_iter;
+    s.m = p->bfgs_m;
+    s.ls_max = p->ls_max_trials;
+    s.refine_max_iter = p->refine_max_iter;
+    s.rho = p->ls_rho;
+    s.sigma = p->ls_sigma;
+    s.eps_g = p->eps_grad;
+    s.eps_c = p->eps_curv;
+    s.temperature = p->temperature;
+    s.pos_amp = p->mut_pos_amp;
+    s.rot_amp = p->mut_rot_amp;
+    s.flags = p->flags;
+    s.seed = p->seed;
+    return s;
+}
+
+pv_status pv_dock_plan(pv_ctx* ctx, const pv_grids* grids, const pv_ligands* ligs, const pv_job* jobs,
+                       int32_t n_jobs, const pv_dock_params* params, pv_plan** out)
+{
+    if (!out) return fail(PV_E_INVALID, "out is NULL");
+    *out = nullptr;
+    pv_status st = check_pair(ctx, grids, ligs);
+    if (st != PV_OK) return st;
+    if ((st = check_search(params, true)) != PV_OK) return st;
+    if (n_jobs < 0) return fail(PV_E_INVALID, "n_jobs < 0");
+    if (n_jobs > 0 && !jobs) return fail(PV_E_INVALID, "jobs is NULL");
+    if ((int64_t)n_jobs * params->chains > (int64_t)INT32_MAX) return fail(PV_E_RANGE, "jobs * chains too large");
+    std::vector<int2> hj(n_jobs);
+    for (int32_t j = 0; j < n_jobs; ++j) {
+        if (jobs[j].ligand < 0 || jobs[j].ligand >= ligs->n_lig) return fail(PV_E_INVALID, "job names an unknown ligand");
+        if (jobs[j].box < 0 || jobs[j].box >= grids->n_boxes) return fail(PV_E_INVALID, "job names an unknown box");
+        hj[j] = make_int2(jobs[j].ligand, jobs[j].box);
+    }
+    if ((st = set_device(ctx)) != PV_OK) return st;
+    pv_plan* P = new (std::nothrow) pv_plan();
+    if (!P) return fail(PV_E_NOMEM, "host allocation");
+    P->ctx = ctx;
+    P->grids = grids;
+    P->ligs = ligs;
+    P->sp = to_sp(params);
+    P->n_jobs = n_jobs;
+    P->h_jobs = hj;
+    const size_t nchain = (size_t)n_jobs * params->chains;
+    if ((st = upload(&P->jobs, hj.data(), hj.size(), "job table")) != PV_OK ||
+        (st = upload(&P->queue, (const uint32_t*)nullptr, 1, "queue")) != PV_OK ||
+        (st = upload(&P->scratch_best, (const float*)nullptr, nchain, "scratch")) != PV_OK ||
+        (st = upload(&P->scratch_evals, (const int64_t*)nullptr, nchain, "scratch")) != PV_OK) {
+        pv_plan_free(P);
+        return st;
+    }
+    int per_cu = 0;
+    hipError_t e = dock_occupancy(ligs->max_atoms, ligs->max_pairs, &per_cu);
+    if (e != hipSuccess || per_cu < 1) per_cu = 1;
+    int64_t wg = params->workgroups > 0 ? params->workgroups : (int64_t)per_cu * ctx->n_cu;
+    wg = std::min<int64_t>(wg, std::max<int64_t>((int64_t)nchain, 1));
+    P->workgroups = (int32_t)wg;
+    e = hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) { pv_plan_free(P); return hip_fail(e, "hipStreamCreate"); }
+    *out = P;
+    return PV_OK;
+}
+
+static DockArgs dock_args(pv_plan* P, const pv_dock_out* o, float* cbe, int64_t* cev)
+{
+    DockArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.g = grid_view(P->grids);
+    a.l = lig_view(P->ligs);
+    a.sp = P->sp;
+    a.jobs = P->jobs;
+    a.n_jobs = P->n_jobs;
+    a.queue = P->queue;
+    a.chain_best_e = cbe;
+    a.chain_best_dof = o->chain_best_dof;
+    a.chain_evals = cev;
+    a.chain_pairs = o->chain_pairs;
+    a.job_t_start = o->job_t_start;
+    a.job_t_end = o->job_t_end;
+    a.dof_stride = o->dof_stride;
+    return a;
+}
+
+static pv_status check_out(const pv_plan* P, const pv_dock_out* o)
+{
+    if (!o) return fail(PV_E_INVALID, "out is NULL");
+    if (o->chain_best_dof && (o->dof_stride < 7 + P->ligs->max_tors || o->dof_stride > 64))
+        return fail(PV_E_INVALID, "dof_stride must be 7 + max torsions .. 64");
+    if ((P->sp.flags & PV_DOCK_TIMESTAMPS) && (!o->job_t_start || !o->job_t_end))
+        return fail(PV_E_INVALID, "timestamps requested without job_t_start / job_t_end");
+    return PV_OK;
+}
+
+static hipError_t enqueue_batched(pv_plan* P, const pv_dock_out* o, hipStream_t s)
+{
+    float* cbe = o->chain_best_e ? o->chain_best_e : P->scratch_best;
+    int64_t* cev = o->chain_evals ? o->chain_evals : P->scratch_evals;
+    DockArgs a = dock_args(P, o, cbe, cev);
+    a.job_begin = 0;
+    a.n_items = (int64_t)P->n_jobs * P->sp.chains;
+    a.persistent = 1;
+    hipError_t e = launch_reset_queue(P->queue, s);
+    if (e != hipSuccess) return e;
+    if (P->sp.flags & PV_DOCK_TIMESTAMPS) {
+        e = launch_reset_times(o->job_t_start, o->job_t_end, P->n_jobs, s);
+        if (e != hipSuccess) return e;
+    }
+    e = launch_dock(a, P->workgroups, s);
+    if (e != hipSuccess) return e;
+    if (o->job_best_e || o->job_best_chain || o->job_evals || o->job_status)
+        e = launch_job_reduce(cbe, cev, P->n_jobs, P->sp.chains, o->job_best_e, o->job_best_chain, o->job_evals,
+                              o->job_status, s);
+    return e;
+}
+
+pv_status pv_dock_run(pv_plan* P, const pv_dock_out* o, void* stream)
+{
+    if (!P) return fail(PV_E_INVALID, "plan is NULL");
+    pv_status st = check_out(P, o);
+    if (st != PV_OK) return st;
+    if ((st = set_device(P->ctx)) != PV_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if (!(P->sp.flags & PV_DOCK_GRAPH)) {
+        hipError_t e = enqueue_batched(P, o, s);
+        if (e != hipSuccess) return hip_fail(e, "dock launch");
+        return PV_OK;
+    }
+    if (!P->have_graph || std::memcmp(&P->cached, o, sizeof(*o)) != 0) {
+        if (P->have_graph) {
+            (void)hipGraphExecDestroy(P->exec);
+            (void)hipGraphDestroy(P->graph);
+            P->have_graph = false;
+        }
+        HIP_TRY(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        hipError_t e = enqueue_batched(P, o, P->cap_stream);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(P->cap_stream, &g);
+        if (e != hipSuccess) { if (g) (void)hipGraphDestroy(g); return hip_fail(e, "dock launch (capture)"); }
+        if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+        hipGraphExec_t x = nullptr;
+        e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) { (void)hipGraphDestroy(g); return hip_fail(e, "hipGraphInstantiate"); }
+        P->graph = g;
+        P->exec = x;
+        P->cached = *o;
+        P->have_graph = true;
+    }
+    HIP_TRY(hipGraphLaunch(P->exec, s), "hipGraphLaunch");
+    return PV_OK;
+}
+
+pv_status pv_dock_run_plain(pv_plan* P, const pv_dock_out* o, void* stream)
+{
+    if (!P) return fail(PV_E_INVALID, "plan is NULL");
+    pv_status st = check_out(P, o);
+    if (st != PV_OK) return st;
+    if ((st = set_device(P->ctx)) != PV_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    float* cbe = o->chain_best_e ? o->chain_best_e : P->scratch_best;
+    int64_t* cev = o->chain_evals ? o->chain_evals : P->scratch_evals;
+    if (P->sp.flags & PV_DOCK_TIMESTAMPS) HIP_TRY(launch_reset_times(o->job_t_start, o->job_t_end, P->n_jobs, s), "reset");
+    for (int32_t j = 0; j < P->n_jobs; ++j) {
+        DockArgs a = dock_args(P, o, cbe, cev);
+        a.job_begin = j;
+        a.n_items = P->sp.chains;
+        a.persistent = 0;
+        HIP_TRY(launch_dock(a, 0, s), "dock launch");
+    }
+    if (o->job_best_e || o->job_best_chain || o->job_evals || o->job_status)
+        HIP_TRY(launch_job_reduce(cbe, cev, P->n_jobs, P->sp.chains, o->job_best_e, o->job_best_chain, o->job_evals,
+                                  o->job_status, s),
+                "job reduce");
+    return PV_OK;
+}
+
+void pv_plan_free(pv_plan* P)
+{
+    if (!P) return;
+    if (ctx_ok(P->ctx)) (void)hipSetDevice(P->ctx->device);
+    if (P->have_graph) {
+        (void)hipGraphExecDestroy(P->exec);
+        (void)hipGraphDestroy(P->graph);
+    }
+    if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
+    dfree(P->jobs); dfree(P->queue); dfree(P->scratch_best); dfree(P->scratch_evals);
+    delete P;
+}
+
+pv_status pv_dock(pv_ctx* ctx, const pv_grids* grids, const pv_ligands* ligs, const pv_job* jobs, int32_t n_jobs,
+                  const pv_dock_params* params, const pv_dock_out* out, void* stream)
+{
+    pv_plan* P = nullptr;
+    pv_status st = pv_dock_plan(ctx, grids, ligs, jobs, n_jobs, params, &P);
+    if (st != PV_OK) return st;
+    st = pv_dock_run(P, out, stream);
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    pv_plan_free(P);
+    if (st != PV_OK) return st;
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return PV_OK;
+}
+
+pv_status pv_local_opt(pv_ctx* ctx, const pv_grids* grids, const pv_ligands* ligs, int32_t n_poses,
+                       const int32_t* lig_of_pose, const int32_t* box_of_pose, const float* dof_in,
+                       int32_t dof_stride, const pv_dock_params* params, float* dof_out, float* energy,
+                       int64_t* n_evals, void* stream)
+{
+    pv_status st = check_pair(ctx, grids, ligs);
+    if (st != PV_OK) return st;
+    if ((st = check_search(params, false)) != PV_OK) return st;
+    if (n_poses < 0) return fail(PV_E_INVALID, "n_poses < 0");
+    if (n_poses == 0) return PV_OK;
+    if (!lig_of_pose || !box_of_pose || !dof_in || !dof_out) return fail(PV_E_INVALID, "pose arrays are NULL");
+    if (dof_stride < 7 + ligs->max_tors || dof_stride > 64) return fail(PV_E_INVALID, "dof_stride must be 7 + max torsions .. 64");
+    if ((st = set_device(ctx)) != PV_OK) return st;
+    OptArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.g = grid_view(grids);
+    a.l = lig_view(ligs);
+    a.sp = to_sp(params);
+    a.n_poses = n_poses;
+    a.lig_of_pose = lig_of_pose;
+    a.box_of_pose = box_of_pose;
+    a.dof_in = dof_in;
+    a.dof_stride = dof_stride;
+    a.dof_out = dof_out;
+    a.energy = energy;
+    a.n_evals = n_evals;
+    hipError_t e = launch_local_opt(a, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "local-opt launch");
+    return PV_OK;
+}
+
+}  // extern "C"

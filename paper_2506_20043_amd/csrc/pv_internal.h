@@ -1,0 +1,171 @@
+// pv_internal.h -- device-side data layouts shared by the host library and
+// the gfx950 kernels of the docking hot path.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+namespace pv {
+
+constexpr int kNTypes = 8;
+constexpr int kMaxAtoms = 128;
+constexpr int kMaxTors = 32;
+constexpr int kMaxFrag = kMaxTors + 1;
+constexpr int kWave = 64;
+
+// Per-ligand header in device memory.  Atoms are stored in depth-first
+// fragment order (each torsion moves one contiguous atom range); fragments
+// in depth-first preorder with the root first.
+struct alignas(16) DevLig {
+    int32_t atom_base, n_atoms, frag_base, n_frag;
+    int32_t pair_base, n_pairs, tors_base, n_tors;
+    int32_t rounds;      // pointer-doubling rounds to compose the frame tree
+    int32_t pad0, pad1, pad2;
+    float anchor[3];     // reference centroid of the root fragment
+    float rot_amp_scale; // 1 / max(R_g, 1e-3)
+};
+
+// One rigid fragment.  Fragment 0 is the root (parent -1).
+struct alignas(16) DevFrag {
+    int32_t parent;      // parent fragment (local index), -1 at the root
+    int32_t tors;        // torsion joining it to its parent (input order), -1 at the root
+    int32_t child_atom;  // child-side atom of that torsion (local, new order)
+    int32_t a0;          // first atom of the fragment (local, new order)
+    int32_t sub_end;     // one past the last atom of its subtree
+    int32_t pad0, pad1, pad2;
+    float axis[4];       // unit axis parent atom -> child atom, reference frame
+    float xc[4];         // reference position of the child-side atom
+};
+
+// Intra pair packed as i | j << 8 | type_pair << 16 (new atom order).
+// Atom record: x, y, z and w = bits(type | fragment << 8).
+
+// Host model of one ligand (built by build_ligand_model).
+struct LigModel {
+    int n = 0, nf = 0, nt = 0, np = 0, depth = 0, rounds = 0, root_size = 0;
+    std::vector<int> perm;          // new -> input atom index
+    std::vector<float> ref;         // [n][4] new order: x, y, z, w-bits
+    std::vector<DevFrag> frags;     // preorder
+    std::vector<int> tors_frag;     // torsion k -> fragment
+    std::vector<uint32_t> pairs;    // packed, lane-interleaved order
+    float anchor[3] = {0, 0, 0};
+    float rg = 0.f;
+};
+
+// Returns 0 or a negative pv_status; `err` names the problem.
+int build_ligand_model(int n, const float* xyz, const uint8_t* type, int nb, const int32_t* bonds,
+                       const uint8_t* rot, LigModel& out, std::string& err);
+
+// Type-pair table: Rsum = R_a + R_b, flags bit0 hydrophobic pair, bit1 hbond pair.
+void type_pair_table(float rsum[64], uint32_t flags[64]);
+
+// ------------------------------------------------------------ launchers
+struct GridDev {
+    const float* maps;    // [box][8][nz][ny][nx]
+    const int32_t* dims;  // [box][4] nx, ny, nz, pad
+    const float* geom;    // [box][8] ox, oy, oz, h, inv_h, ext_x, ext_y, ext_z
+    const int64_t* map_off; // [box] offset of the box's first map
+    int32_t n_boxes;
+    float kappa;
+};
+
+struct LigDev {
+    const DevLig* ligs;
+    const float4* atoms;
+    const int16_t* perm;
+    const DevFrag* frags;
+    const int8_t* tors_frag;
+    const uint32_t* pairs;
+    int32_t n_lig;
+    int32_t max_atoms, max_pairs, max_tors;
+};
+
+struct ScoreArgs {
+    GridDev g;
+    LigDev l;
+    int32_t n_poses;
+    const int32_t* lig_of_pose;
+    const int32_t* box_of_pose;
+    const float* dof;      // or xyz when from_xyz
+    int32_t dof_stride;
+    int32_t from_xyz;
+    const float* grad_energy;
+    float* energy;
+    float* e_parts;
+    float* grad_dof;
+    float* xyz_out;
+    float* grad_xyz;
+    int32_t xyz_stride;
+};
+
+struct SearchParams {
+    int32_t chains, steps, max_iter, m, ls_max, refine_max_iter;
+    float rho, sigma, eps_g, eps_c, temperature, pos_amp, rot_amp;
+    uint32_t flags;
+    uint64_t seed;
+};
+
+struct DockArgs {
+    GridDev g;
+    LigDev l;
+    SearchParams sp;
+    const int2* jobs;         // (ligand, box)
+    int32_t n_jobs;
+    int32_t job_begin;        // first job of this launch
+    int64_t n_items;          // (job, chain) items of this launch
+    uint32_t* queue;          // work counter (persistent launch)
+    int32_t persistent;
+    // outputs
+    float* chain_best_e;
+    float* chain_best_dof;
+    int64_t* chain_evals;
+    int64_t* chain_pairs;
+    uint64_t* job_t_start;
+    uint64_t* job_t_end;
+    int32_t dof_stride;
+};
+
+struct OptArgs {
+    GridDev g;
+    LigDev l;
+    SearchParams sp;
+    int32_t n_poses;
+    const int32_t* lig_of_pose;
+    const int32_t* box_of_pose;
+    const float* dof_in;
+    int32_t dof_stride;
+    float* dof_out;
+    float* energy;
+    int64_t* n_evals;
+};
+
+struct GridBuildArgs {
+    const float4* atoms;      // per box: receptor atoms near the box (x, y, z, w = type bits)
+    const int32_t* atom_off;  // [box+1]
+    float* maps;
+    const int64_t* map_off;
+    const int32_t* dims;
+    const float* geom;
+    const int32_t* tile_off;  // [box+1] first tile of each box
+    int32_t n_boxes;
+};
+
+hipError_t launch_build_grids(const GridBuildArgs& a, int64_t n_tiles, hipStream_t s);
+hipError_t launch_score(const ScoreArgs& a, hipStream_t s);
+hipError_t launch_dock(const DockArgs& a, int32_t workgroups, hipStream_t s);
+hipError_t launch_reset_queue(uint32_t* q, hipStream_t s);
+hipError_t launch_job_reduce(const float* chain_best_e, const int64_t* chain_evals, int32_t n_jobs,
+                             int32_t chains, float* job_best_e, int32_t* job_best_chain, int64_t* job_evals,
+                             int32_t* job_status, hipStream_t s);
+hipError_t launch_local_opt(const OptArgs& a, hipStream_t s);
+hipError_t launch_reset_times(uint64_t* t0, uint64_t* t1, int n, hipStream_t s);
+hipError_t dock_occupancy(int max_atoms, int max_pairs, int* blocks_per_cu);
+int dock_lds_bytes(int max_atoms, int max_pairs);
+
+// Tiles of the grid-map kernel.
+constexpr int kTileX = 8, kTileY = 8, kTileZ = 4;
+
+}  // namespace pv

@@ -1,0 +1,1131 @@
+// pv_kernels.hip -- gfx950 kernels of the docking hot path.
+//
+//  * grid maps ("Kernel 1" of the paper: one map per ligand atom type over
+//    each pocket box, Methods "Accelerated Docking" and Supplementary
+//    Algorithm 2, first step): FP32 VALU, lattice tiles of 8x8x4 points per
+//    workgroup, receptor atoms culled per tile into LDS;
+//  * pose evaluation (Eq. qvina_eq_1 forward kinematics, Eq. qvina_eq_3
+//    score): one wave64 per pose, lanes over fragments for the frame tree,
+//    over atoms for the trilinear gathers and over intra pairs, LDS force
+//    accumulation and a wave scan that carries force and torque back to the
+//    torsions;
+//  * RILC-BFGS (Eqs. qvina_eq_6 .. qvina_eq_12) with the tangent-space
+//    vectors spread one component per lane;
+//  * Monte Carlo chains (Supplementary Algorithm 2, Eq. qvina_eq_13) in a
+//    persistent launch whose waves pull (job, chain) items from a device
+//    queue, with Philox4x64-10 draws.
+//
+// Every workgroup is one wave of 64 lanes; all arithmetic is binary32.
+#include <hip/hip_runtime.h>
+
+#include "pv_internal.h"
+
+namespace pv {
+
+// Vina-form weights: gauss1, gauss2, repulsion, hydrophobic, hydrogen bond.
+constexpr float kW1 = -0.0356f, kW2 = -0.00516f, kW3 = 0.840f, kW4 = -0.0351f, kW5 = -0.587f;
+constexpr float kCut2 = 64.0f;
+constexpr float kPi = 3.14159265358979323846f;
+
+// ---------------------------------------------------------------- wave helpers
+__device__ __forceinline__ float wsum(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x; }
+
+// ---------------------------------------------------------------- Philox4x64-10
+__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1)
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) { k0 += W0; k1 += W1; }
+        uint64_t h0 = __umul64hi(M0, c[0]), l0 = M0 * c[0];
+        uint64_t h1 = __umul64hi(M1, c[2]), l1 = M1 * c[2];
+        uint64_t n0 = h1 ^ c[1] ^ k0, n2 = h0 ^ c[3] ^ k1;
+        c[0] = n0; c[1] = l1; c[2] = n2; c[3] = l0;
+    }
+}
+
+__device__ __forceinline__ float u01(uint64_t w) { return (float)(uint32_t)(w >> 40) * 0x1p-24f; }
+
+// counter = (block, step, chain, job), key = (seed, 0)
+__device__ __forceinline__ uint64_t philox_word(uint64_t seed, int job, int chain, uint64_t step,
+                                                uint64_t block, int word)
+{
+    uint64_t c[4] = {block, step, (uint64_t)chain, (uint64_t)job};
+    philox4x64_10(c, seed, 0);
+    return word == 0 ? c[0] : word == 1 ? c[1] : word == 2 ? c[2] : c[3];
+}
+
+// ---------------------------------------------------------------- small rotations
+__device__ __forceinline__ void quat_mul(const float a[4], const float b[4], float o[4])
+{
+    float r0 = a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+    float r1 = a[0] * b[1] + a[1] * b[0] + a[2] * b[3] - a[3] * b[2];
+    float r2 = a[0] * b[2] - a[1] * b[3] + a[2] * b[0] + a[3] * b[1];
+    float r3 = a[0] * b[3] + a[1] * b[2] - a[2] * b[1] + a[3] * b[0];
+    o[0] = r0; o[1] = r1; o[2] = r2; o[3] = r3;
+}
+
+__device__ __forceinline__ void rotvec_quat(float tx, float ty, float tz, float q[4])
+{
+    float a = sqrtf(tx * tx + ty * ty + tz * tz);
+    if (a == 0.0f) { q[0] = 1.f; q[1] = q[2] = q[3] = 0.f; return; }
+    float s, c;
+    sincosf(0.5f * a, &s, &c);
+    float k = s / a;
+    q[0] = c; q[1] = k * tx; q[2] = k * ty; q[3] = k * tz;
+}
+
+__device__ __forceinline__ void quat_normalize(float q[4])
+{
+    float n = rsqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    q[0] *= n; q[1] *= n; q[2] *= n; q[3] *= n;
+}
+
+// ---------------------------------------------------------------- per-box grid view
+struct BoxView {
+    const float* maps;  // 8 maps of the box
+    int nx, ny, nz;
+    int64_t msz;
+    float ox, oy, oz, h, inv_h, ex, ey, ez, kappa;
+};
+
+__device__ __forceinline__ BoxView box_view(const GridDev& g, int box)
+{
+    BoxView v;
+    v.maps = g.maps + g.map_off[box];
+    v.nx = g.dims[4 * box]; v.ny = g.dims[4 * box + 1]; v.nz = g.dims[4 * box + 2];
+    v.msz = (int64_t)v.nx * v.ny * v.nz;
+    const float* ge = g.geom + 8 * box;
+    v.ox = ge[0]; v.oy = ge[1]; v.oz = ge[2]; v.h = ge[3]; v.inv_h = ge[4];
+    v.ex = ge[5]; v.ey = ge[6]; v.ez = ge[7];
+    v.kappa = g.kappa;
+    return v;
+}
+
+// One axis of the lookup: fractional coordinate clamped to [0, n-1], cell
+// i0 = min(floor f, n-2), the out-of-box penalty and whether the axis is
+// clamped (its interpolant gradient is then zero).
+__device__ __forceinline__ void axis_setup(float x, float o, float inv_h, float ext, int n, float kappa,
+                                           int& i0, float& u, float& pen, float& dpen, bool& clamped)
+{
+    float rel = x - o;
+    float f = rel * inv_h;
+    pen = 0.f; dpen = 0.f; clamped = false;
+    if (x < o) { pen = kappa * (o - x); dpen = -kappa; f = 0.f; clamped = true; }
+    else if (rel > ext) { pen = kappa * (rel - ext); dpen = kappa; f = (float)(n - 1); clamped = true; }
+    int c = (int)floorf(f);
+    c = max(0, min(c, n - 2));  // also keeps a NaN coordinate inside the map
+    i0 = c;
+    u = f - (float)c;
+}
+
+// trilinear value + gradient of map `t` at x, plus the penalty
+__device__ __forceinline__ float trilinear(const BoxView& B, int t, float x, float y, float z, float& gx,
+                                           float& gy, float& gz)
+{
+    int ix, iy, iz;
+    float ux, uy, uz, px, py, pz, dx, dy, dz;
+    bool cx, cy, cz;
+    axis_setup(x, B.ox, B.inv_h, B.ex, B.nx, B.kappa, ix, ux, px, dx, cx);
+    axis_setup(y, B.oy, B.inv_h, B.ey, B.ny, B.kappa, iy, uy, py, dy, cy);
+    axis_setup(z, B.oz, B.inv_h, B.ez, B.nz, B.kappa, iz, uz, pz, dz, cz);
+    const float* m = B.maps + (int64_t)t * B.msz + ((int64_t)iz * B.ny + iy) * B.nx + ix;
+    const int sy = B.nx;
+    const int64_t sz = (int64_t)B.nx * B.ny;
+    float m000 = m[0], m100 = m[1];
+    float m010 = m[sy], m110 = m[sy + 1];
+    float m001 = m[sz], m101 = m[sz + 1];
+    float m011 = m[sz + sy], m111 = m[sz + sy + 1];
+    // along x
+    float a00 = m000 + ux * (m100 - m000), a10 = m010 + ux * (m110 - m010);
+    float a01 = m001 + ux * (m101 - m001), a11 = m011 + ux * (m111 - m011);
+    float b0 = a00 + uy * (a10 - a00), b1 = a01 + uy * (a11 - a01);
+    float v = b0 + uz * (b1 - b0);
+    // derivatives of the interpolant in the cell
+    float d00 = m100 - m000, d10 = m110 - m010, d01 = m101 - m001, d11 = m111 - m011;
+    float e0 = d00 + uy * (d10 - d00), e1 = d01 + uy * (d11 - d01);
+    float dvx = e0 + uz * (e1 - e0);
+    float dvy = (a10 - a00) + uz * ((a11 - a01) - (a10 - a00));
+    float dvz = b1 - b0;
+    gx = (cx ? 0.f : dvx * B.inv_h) + dx;
+    gy = (cy ? 0.f : dvy * B.inv_h) + dy;
+    gz = (cz ? 0.f : dvz * B.inv_h) + dz;
+    return v + px + py + pz;
+}
+
+// ---------------------------------------------------------------- LDS carving
+// Pose slots hold [t(3), q(4), psi(T)] = up to 39 floats; 40 with padding.
+constexpr int kSlot = 40;
+enum { SLOT_X = 0, SLOT_XT = 1, SLOT_XA = 2, SLOT_CUR = 3, SLOT_BEST = 4, kNSlots = 5 };
+
+struct Lds {
+    float2* tp;        // [64] (Rsum, flags-as-bits)
+    float* pose;       // [kNSlots][kSlot]
+    float* frame;      // [kMaxFrag][12]
+    float4* pos;       // [max_atoms]
+    float4* frc;       // [max_atoms]
+    float* pre;        // [6][max_atoms]
+    uint32_t* pairs;   // [max_pairs]
+    int ma;
+};
+
+__host__ __device__ inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+__host__ __device__ inline int lds_bytes(int max_atoms, int max_pairs)
+{
+    int ma = round_up(max_atoms < 1 ? 1 : max_atoms, 64);
+    return 64 * 8 + kNSlots * kSlot * 4 + kMaxFrag * 12 * 4 + ma * 16 * 2 + 6 * ma * 4 +
+           round_up(max_pairs, 4) * 4;
+}
+
+__device__ __forceinline__ Lds carve(char* base, int max_atoms, int max_pairs)
+{
+    Lds s;
+    int ma = round_up(max_atoms < 1 ? 1 : max_atoms, 64);
+    char* p = base;
+    s.tp = (float2*)p; p += 64 * 8;
+    s.pos = (float4*)p; p += ma * 16;
+    s.frc = (float4*)p; p += ma * 16;
+    s.pose = (float*)p; p += kNSlots * kSlot * 4;
+    s.frame = (float*)p; p += kMaxFrag * 12 * 4;
+    s.pre = (float*)p; p += 6 * ma * 4;
+    s.pairs = (uint32_t*)p;
+    s.ma = ma;
+    return s;
+}
+
+__device__ __forceinline__ void stage_tp(const Lds& S, const float* rsum, const uint32_t* flags)
+{
+    int l = lane_id();
+    S.tp[l] = make_float2(rsum[l], __uint_as_float(flags[l]));
+}
+
+// ---------------------------------------------------------------- staged ligand
+// Topology lives in registers: atoms blocked A per lane (atom = lane*A + a),
+// fragments one per lane, and for lane 6+k the fragment of torsion k.
+template <int A>
+struct Topo {
+    int n, nf, nt, np, rounds, lig;
+    float anc_x, anc_y, anc_z, rot_scale;
+    float4 ref[A];
+    int f_parent, f_tors, f_child, f_a0, f_end;
+    float ax, ay, az, cx, cy, cz;
+    int dof_frag;
+};
+
+template <int A>
+__device__ void stage_ligand(Topo<A>& T, const LigDev& L, int lig, const Lds& S)
+{
+    const int l = lane_id();
+    const DevLig d = L.ligs[lig];
+    T.lig = lig;
+    T.n = d.n_atoms; T.nf = d.n_frag; T.nt = d.n_tors; T.np = d.n_pairs; T.rounds = d.rounds;
+    T.anc_x = d.anchor[0]; T.anc_y = d.anchor[1]; T.anc_z = d.anchor[2]; T.rot_scale = d.rot_amp_scale;
+#pragma unroll
+    for (int a = 0; a < A; ++a) {
+        int i = l * A + a;
+        T.ref[a] = i < T.n ? L.atoms[d.atom_base + i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    if (l < T.nf) {
+        const DevFrag F = L.frags[d.frag_base + l];
+        T.f_parent = F.parent; T.f_tors = F.tors; T.f_child = F.child_atom; T.f_a0 = F.a0; T.f_end = F.sub_end;
+        T.ax = F.axis[0]; T.ay = F.axis[1]; T.az = F.axis[2];
+        T.cx = F.xc[0]; T.cy = F.xc[1]; T.cz = F.xc[2];
+    } else {
+        T.f_parent = -1; T.f_tors = -1; T.f_child = 0; T.f_a0 = 0; T.f_end = 0;
+        T.ax = T.ay = T.az = T.cx = T.cy = T.cz = 0.f;
+    }
+    T.dof_frag = (l >= 6 && l < 6 + T.nt) ? (int)L.tors_frag[d.tors_base + l - 6] : 0;
+    for (int p = l; p < T.np; p += kWave) S.pairs[p] = L.pairs[d.pair_base + p];
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------- evaluation
+struct Eval {
+    float e, e_inter, e_intra;
+    float g;          // this lane's tangent component (lane < 6 + T)
+    int pairs_in;
+};
+
+// Frame of every fragment: x = R X + b on reference coordinates.  Lane f
+// starts from its local map (the root's pose map, or the rotation by psi
+// about its torsion axis) and composes with its ancestors by pointer
+// doubling; after `rounds` rounds every frame is world-absolute.
+template <int A>
+__device__ __forceinline__ void frames(const Topo<A>& T, const float* pose, float R[9], float b[3])
+{
+    const int l = lane_id();
+    const float tx = pose[0], ty = pose[1], tz = pose[2];
+    int anc = -1;
+    if (l == 0) {
+        float q[4] = {pose[3], pose[4], pose[5], pose[6]};
+        quat_normalize(q);
+        float w = q[0], x = q[1], y = q[2], z = q[3];
+        R[0] = 1.f - 2.f * (y * y + z * z); R[1] = 2.f * (x * y - w * z); R[2] = 2.f * (x * z + w * y);
+        R[3] = 2.f * (x * y + w * z); R[4] = 1.f - 2.f * (x * x + z * z); R[5] = 2.f * (y * z - w * x);
+        R[6] = 2.f * (x * z - w * y); R[7] = 2.f * (y * z + w * x); R[8] = 1.f - 2.f * (x * x + y * y);
+        b[0] = tx - (R[0] * T.anc_x + R[1] * T.anc_y + R[2] * T.anc_z);
+        b[1] = ty - (R[3] * T.anc_x + R[4] * T.anc_y + R[5] * T.anc_z);
+        b[2] = tz - (R[6] * T.anc_x + R[7] * T.anc_y + R[8] * T.anc_z);
+    } else if (l < T.nf) {
+        float s, c;
+        sincosf(pose[7 + T.f_tors], &s, &c);
+        float t = 1.f - c, ux = T.ax, uy = T.ay, uz = T.az;
+        R[0] = c + t * ux * ux;      R[1] = t * ux * uy - s * uz; R[2] = t * ux * uz + s * uy;
+        R[3] = t * uy * ux + s * uz; R[4] = c + t * uy * uy;      R[5] = t * uy * uz - s * ux;
+        R[6] = t * uz * ux - s * uy; R[7] = t * uz * uy + s * ux; R[8] = c + t * uz * uz;
+        b[0] = T.cx - (R[0] * T.cx + R[1] * T.cy + R[2] * T.cz);
+        b[1] = T.cy - (R[3] * T.cx + R[4] * T.cy + R[5] * T.cz);
+        b[2] = T.cz - (R[6] * T.cx + R[7] * T.cy + R[8] * T.cz);
+        anc = T.f_parent;
+    } else {
+        R[0] = R[4] = R[8] = 1.f; R[1] = R[2] = R[3] = R[5] = R[6] = R[7] = 0.f; b[0] = b[1] = b[2] = 0.f;
+    }
+    for (int r = 0; r < T.rounds; ++r) {
+        const int src = anc < 0 ? l : anc;
+        float P[9], pb[3];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) P[k] = __shfl(R[k], src);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) pb[k] = __shfl(b[k], src);
+        const int panc = __shfl(anc, src);
+        if (anc >= 0) {
+            float N[9], nb[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+                    N[3 * i + j] = P[3 * i] * R[j] + P[3 * i + 1] * R[3 + j] + P[3 * i + 2] * R[6 + j];
+                nb[i] = P[3 * i] * b[0] + P[3 * i + 1] * b[1] + P[3 * i + 2] * b[2] + pb[i];
+            }
+#pragma unroll
+            for (int k = 0; k < 9; ++k) R[k] = N[k];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) b[k] = nb[k];
+            anc = panc;
+        }
+    }
+}
+
+// Intra pairs: the Vina-form pair energy inside 8 A, forces added to both
+// atoms in LDS.  Returns this lane's energy; counts pairs inside the cutoff.
+__device__ __forceinline__ float pair_loop(const Lds& S, int np, int& cnt)
+{
+    const int l = lane_id();
+    float e = 0.f;
+    for (int p = l; p < np; p += kWave) {
+        const uint32_t pk = S.pairs[p];
+        const int i = pk & 0xff, j = (pk >> 8) & 0xff, tp = pk >> 16;
+        const float4 xi = S.pos[i], xj = S.pos[j];
+        const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 < kCut2) {
+            const float2 tpe = S.tp[tp];
+            const uint32_t fl = __float_as_uint(tpe.y);
+            const float r = sqrtf(r2);
+            const float d = r - tpe.x;
+            const float g1 = __expf(-4.f * d * d);
+            const float dm3 = d - 3.f;
+            const float g2 = __expf(-0.25f * dm3 * dm3);
+            float en = kW1 * g1 + kW2 * g2;
+            float de = kW1 * g1 * (-8.f * d) + kW2 * g2 * (-0.5f * dm3);
+            if (d < 0.f) { en += kW3 * d * d; de += kW3 * 2.f * d; }
+            if (fl & 1u) {
+                if (d < 0.5f) en += kW4;
+                else if (d < 1.5f) { en += kW4 * (1.5f - d); de -= kW4; }
+            }
+            if (fl & 2u) {
+                if (d < -0.7f) en += kW5;
+                else if (d < 0.f) { en += kW5 * (-d * (1.f / 0.7f)); de -= kW5 * (1.f / 0.7f); }
+            }
+            e += en;
+            ++cnt;
+            const float c = r2 > 0.f ? de / r : 0.f;
+            const float fx = c * dx, fy = c * dy, fz = c * dz;
+            atomicAdd(&S.frc[i].x, fx); atomicAdd(&S.frc[i].y, fy); atomicAdd(&S.frc[i].z, fz);
+            atomicAdd(&S.frc[j].x, -fx); atomicAdd(&S.frc[j].y, -fy); atomicAdd(&S.frc[j].z, -fz);
+        }
+    }
+    return e;
+}
+
+// Score and tangent gradient of the pose in `pose` (an LDS slot).  Leaves
+// atom positions in S.pos and dE/dx in S.frc.
+template <int A>
+__device__ Eval evaluate(const Topo<A>& T, const BoxView& B, const Lds& S, const float* pose)
+{
+    const int l = lane_id();
+    Eval out;
+    float R[9], b[3];
+    frames(T, pose, R, b);
+    if (l < T.nf) {
+        float* fr = S.frame + 12 * l;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) fr[k] = R[k];
+        fr[9] = b[0]; fr[10] = b[1]; fr[11] = b[2];
+    }
+    __syncthreads();
+    float e_in = 0.f;
+#pragma unroll
+    for (int a = 0; a < A; ++a) {
+        const int i = l * A + a;
+        if (i < T.n) {
+            const uint32_t w = __float_as_uint(T.ref[a].w);
+            const int ty = w & 0xff, f = w >> 8;
+            const float4* fr = (const float4*)(S.frame + 12 * f);
+            const float4 r0 = fr[0], r1 = fr[1], r2 = fr[2];
+            const float X = T.ref[a].x, Y = T.ref[a].y, Z = T.ref[a].z;
+            const float x = r0.x * X + r0.y * Y + r0.z * Z + r2.y;
+            const float y = r0.w * X + r1.x * Y + r1.y * Z + r2.z;
+            const float z = r1.z * X + r1.w * Y + r2.x * Z + r2.w;
+            S.pos[i] = make_float4(x, y, z, 0.f);
+            float gx, gy, gz;
+            e_in += trilinear(B, ty, x, y, z, gx, gy, gz);
+            S.frc[i] = make_float4(gx, gy, gz, 0.f);
+        }
+    }
+    __syncthreads();
+    int cnt = 0;
+    const float e_ia = pair_loop(S, T.np, cnt);
+    __syncthreads();
+    // per-atom force and torque about t, blocked inclusive scan over atoms
+    const float tx = pose[0], ty = pose[1], tz = pose[2];
+    float v[A][6];
+    float run[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < A; ++a) {
+        const int i = l * A + a;
+        float G[3] = {0, 0, 0}, rx = 0, ry = 0, rz = 0;
+        if (i < T.n) {
+            const float4 f = S.frc[i], p = S.pos[i];
+            G[0] = f.x; G[1] = f.y; G[2] = f.z;
+            rx = p.x - tx; ry = p.y - ty; rz = p.z - tz;
+        }
+        run[0] += G[0]; run[1] += G[1]; run[2] += G[2];
+        run[3] += ry * G[2] - rz * G[1];
+        run[4] += rz * G[0] - rx * G[2];
+        run[5] += rx * G[1] - ry * G[0];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) v[a][c] = run[c];
+    }
+    float incl[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        float s = run[c];
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const float u = __shfl_up(s, o);
+            if (l >= o) s += u;
+        }
+        incl[c] = s;
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        const float excl = incl[c] - run[c];
+#pragma unroll
+        for (int a = 0; a < A; ++a) {
+            const int i = l * A + a;
+            if (i < T.n) S.pre[c * S.ma + i] = excl + v[a][c];
+        }
+    }
+    __syncthreads();
+    // torsion derivative: world axis . sum over the moved atoms of (x - x_c) x G
+    float dpsi = 0.f;
+    if (l >= 1 && l < T.nf) {
+        const int e = T.f_end - 1, s0 = T.f_a0 - 1;
+        float Sg[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) Sg[c] = S.pre[c * S.ma + e] - S.pre[c * S.ma + s0];
+        const float4 pc = S.pos[T.f_child];
+        const float cx = pc.x - tx, cy = pc.y - ty, cz = pc.z - tz;
+        const float mx = Sg[3] - (cy * Sg[2] - cz * Sg[1]);
+        const float my = Sg[4] - (cz * Sg[0] - cx * Sg[2]);
+        const float mz = Sg[5] - (cx * Sg[1] - cy * Sg[0]);
+        const float awx = R[0] * T.ax + R[1] * T.ay + R[2] * T.az;
+        const float awy = R[3] * T.ax + R[4] * T.ay + R[5] * T.az;
+        const float awz = R[6] * T.ax + R[7] * T.ay + R[8] * T.az;
+        dpsi = awx * mx + awy * my + awz * mz;
+    }
+    const float dsel = __shfl(dpsi, T.dof_frag);
+    const int last = T.n - 1;
+    float g = 0.f;
+    if (l < 6) g = S.pre[l * S.ma + last];
+    else if (l < 6 + T.nt) g = dsel;
+    out.g = g;
+    out.e_inter = wsum(e_in);
+    out.e_intra = wsum(e_ia);
+    out.e = out.e_inter + out.e_intra;
+    out.pairs_in = (int)wsum((float)cnt);
+    return out;
+}
+
+// Score on given coordinates already in S.pos: forces in S.frc.
+template <int A>
+__device__ Eval evaluate_xyz(const Topo<A>& T, const BoxView& B, const Lds& S)
+{
+    const int l = lane_id();
+    Eval out;
+    float e_in = 0.f;
+#pragma unroll
+    for (int a = 0; a < A; ++a) {
+        const int i = l * A + a;
+        if (i < T.n) {
+            const int ty = __float_as_uint(T.ref[a].w) & 0xff;
+            const float4 p = S.pos[i];
+            float gx, gy, gz;
+            e_in += trilinear(B, ty, p.x, p.y, p.z, gx, gy, gz);
+            S.frc[i] = make_float4(gx, gy, gz, 0.f);
+        }
+    }
+    __syncthreads();
+    int cnt = 0;
+    const float e_ia = pair_loop(S, T.np, cnt);
+    __syncthreads();
+    out.g = 0.f;
+    out.e_inter = wsum(e_in);
+    out.e_intra = wsum(e_ia);
+    out.e = out.e_inter + out.e_intra;
+    out.pairs_in = (int)wsum((float)cnt);
+    return out;
+}
+
+// ---------------------------------------------------------------- pose slots
+__device__ __forceinline__ void slot_copy(const Lds& S, int dst, int src, int len)
+{
+    const int l = lane_id();
+    if (l < len) S.pose[dst * kSlot + l] = S.pose[src * kSlot + l];
+    __syncthreads();
+}
+
+// x (+) lam d : t + lam d_t, exp(lam d_theta) q, psi + lam d_psi.  d is the
+// lane-distributed tangent vector.
+__device__ __forceinline__ void retract(const Lds& S, int dst, int src, float d, float lam, int nt)
+{
+    const int l = lane_id();
+    const float* x = S.pose + src * kSlot;
+    float* o = S.pose + dst * kSlot;
+    const float th0 = __shfl(d, 3) * lam, th1 = __shfl(d, 4) * lam, th2 = __shfl(d, 5) * lam;
+    float dq[4], q[4] = {x[3], x[4], x[5], x[6]}, nq[4];
+    rotvec_quat(th0, th1, th2, dq);
+    quat_mul(dq, q, nq);
+    quat_normalize(nq);
+    float vt = 0.f, vpsi = 0.f;
+    if (l < 3) vt = x[l] + lam * d;
+    if (l >= 6 && l < 6 + nt) vpsi = x[l + 1] + lam * d;
+    __syncthreads();
+    if (l < 3) o[l] = vt;
+    else if (l < 7) o[l] = nq[l - 3];
+    if (l >= 6 && l < 6 + nt) o[l + 1] = vpsi;
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------- RILC-BFGS
+constexpr int kMaxM = 8;
+
+struct BfgsOut {
+    float f;
+    int evals;
+    int64_t pairs;
+};
+
+// Minimises from the pose in SLOT_X; the result is left in SLOT_X.
+template <int A>
+__device__ BfgsOut bfgs(const Topo<A>& T, const BoxView& B, const Lds& S, const SearchParams& P, int max_iter)
+{
+    const int l = lane_id();
+    const int nd = 6 + T.nt;
+    const bool act = l < nd;
+    BfgsOut out;
+    out.evals = 0;
+    out.pairs = 0;
+    Eval ev = evaluate(T, B, S, S.pose + SLOT_X * kSlot);
+    ++out.evals;
+    out.pairs += ev.pairs_in;
+    float f = ev.e, g = act ? ev.g : 0.f;
+    float Sh[kMaxM], Yh[kMaxM], rh[kMaxM];
+#pragma unroll
+    for (int h = 0; h < kMaxM; ++h) { Sh[h] = 0.f; Yh[h] = 0.f; rh[h] = 0.f; }
+    int hn = 0;
+    const int m = P.m;
+    for (int it = 0; it < max_iter; ++it) {
+        const float gn = sqrtf(wsum(g * g));
+        if (gn <= P.eps_g) break;
+        // two-loop recursion
+        float q = g, al[kMaxM];
+#pragma unroll
+        for (int h = kMaxM - 1; h >= 0; --h) {
+            al[h] = 0.f;
+            if (h < hn) {
+                al[h] = rh[h] * wsum(Sh[h] * q);
+                q -= al[h] * Yh[h];
+            }
+        }
+        if (hn > 0) {
+            float sy = 0.f, yy = 0.f;
+#pragma unroll
+            for (int h = 0; h < kMaxM; ++h)
+                if (h == hn - 1) { sy = Sh[h] * Yh[h]; yy = Yh[h] * Yh[h]; }
+            q *= wsum(sy) / wsum(yy);
+        }
+#pragma unroll
+        for (int h = 0; h < kMaxM; ++h) {
+            if (h < hn) {
+                const float bb = rh[h] * wsum(Yh[h] * q);
+                q += Sh[h] * (al[h] - bb);
+            }
+        }
+        const float d = -q;
+        const float gd = wsum(g * d);
+        if (!(gd < 0.f)) break;
+        // Lewis-Overton line search
+        float lo = 0.f, lam = 1.f, beta = 0.f, lam_ok = -1.f;
+        bool beta_inf = true, accepted = false;
+        float ft = 0.f, gt = 0.f, fa = 0.f, ga = 0.f;
+        for (int tr = 0; tr < P.ls_max; ++tr) {
+            retract(S, SLOT_XT, SLOT_X, d, lam, T.nt);
+            Eval et = evaluate(T, B, S, S.pose + SLOT_XT * kSlot);
+            ++out.evals;
+            out.pairs += et.pairs_in;
+            ft = et.e;
+            gt = act ? et.g : 0.f;
+            if (ft > f + P.rho * lam * gd) {
+                beta = lam; beta_inf = false;
+            } else if (wsum(gt * d) < P.sigma * gd) {
+                lo = lam;
+                slot_copy(S, SLOT_XA, SLOT_XT, 7 + T.nt);
+                fa = ft; ga = gt;
+            } else {
+                accepted = true; lam_ok = lam;
+                break;
+            }
+            lam = beta_inf ? 2.f * lam : 0.5f * (lo + beta);
+        }
+        if (!accepted) {
+            if (lo > 0.f) {
+                lam_ok = lo;
+                slot_copy(S, SLOT_XT, SLOT_XA, 7 + T.nt);
+                ft = fa; gt = ga;
+            } else {
+                break;
+            }
+        }
+        const float s = lam_ok * d, y = gt - g;
+        const float ys = wsum(y * s), ss = wsum(s * s);
+        if (ys / ss > P.eps_c * gn) {
+            if (hn == m) {
+#pragma unroll
+                for (int h = 0; h < kMaxM - 1; ++h) { Sh[h] = Sh[h + 1]; Yh[h] = Yh[h + 1]; rh[h] = rh[h + 1]; }
+                --hn;
+            }
+#pragma unroll
+            for (int h = 0; h < kMaxM; ++h)
+                if (h == hn) { Sh[h] = s; Yh[h] = y; rh[h] = 1.f / ys; }
+            ++hn;
+        }
+        slot_copy(S, SLOT_X, SLOT_XT, 7 + T.nt);
+        f = ft;
+        g = gt;
+    }
+    out.f = f;
+    return out;
+}
+
+// ---------------------------------------------------------------- Monte Carlo
+struct ChainOut {
+    float best_e;
+    int64_t evals, pairs;
+};
+
+template <int A>
+__device__ void init_pose(const Topo<A>& T, const BoxView& B, const Lds& S, int slot, uint64_t seed, int job,
+                          int chain)
+{
+    const int l = lane_id();
+    // lane l draws uniform l (block l/4, word l%4) of step 0
+    const float u = u01(philox_word(seed, job, chain, 0, (uint64_t)(l >> 2), l & 3));
+    const float u3 = __shfl(u, 3), u4 = __shfl(u, 4), u5 = __shfl(u, 5);
+    const float s1 = sqrtf(1.f - u3), s2 = sqrtf(u3);
+    float sa, ca, sb, cb;
+    sincosf(2.f * kPi * u4, &sa, &ca);
+    sincosf(2.f * kPi * u5, &sb, &cb);
+    float* o = S.pose + slot * kSlot;
+    if (l < 3) {
+        const float lo = l == 0 ? B.ox : l == 1 ? B.oy : B.oz;
+        const float ext = l == 0 ? B.ex : l == 1 ? B.ey : B.ez;
+        o[l] = lo + u * ext;
+    }
+    if (l == 3) o[3] = s2 * cb;
+    if (l == 4) o[4] = s1 * sa;
+    if (l == 5) o[5] = s1 * ca;
+    if (l == 6) o[6] = s2 * sb;
+    if (l >= 6 && l < 6 + T.nt) o[l + 1] = -kPi + 2.f * kPi * u;
+    __syncthreads();
+}
+
+// Mutation of one POT entity (Eq. qvina_eq_2) from the 8 words w of the step.
+template <int A>
+__device__ void mutate(const Topo<A>& T, const Lds& S, int slot, const SearchParams& P, const uint64_t w[8])
+{
+    const int l = lane_id();
+    float* x = S.pose + slot * kSlot;
+    const uint64_t n_ent = (uint64_t)(2 + T.nt);
+    const int ent = (int)(((w[0] >> 32) * n_ent) >> 32);
+    const float u1 = u01(w[1]), u2 = u01(w[2]), u3 = u01(w[3]), u4 = u01(w[4]);
+    const float ur = u01(w[5]), ua = u01(w[6]);
+    const float r12 = sqrtf(-2.f * logf(1.f - u1)), r34 = sqrtf(-2.f * logf(1.f - u3));
+    float s2, c2, s4, c4;
+    sincosf(2.f * kPi * u2, &s2, &c2);
+    sincosf(2.f * kPi * u4, &s4, &c4);
+    const float vx = r12 * c2, vy = r12 * s2, vz = r34 * c4;
+    const float vn2 = vx * vx + vy * vy + vz * vz;
+    float dx = 0.f, dy = 0.f, dz = 1.f;
+    if (vn2 > 0.f) { const float inv = 1.f / sqrtf(vn2); dx = vx * inv; dy = vy * inv; dz = vz * inv; }
+    const float rad = cbrtf(ur);
+    float nv = 0.f;
+    bool wr = false;
+    if (ent == 0) {
+        if (l < 3) { nv = x[l] + P.pos_amp * rad * (l == 0 ? dx : l == 1 ? dy : dz); wr = true; }
+    } else if (ent == 1) {
+        const float amp = P.rot_amp * T.rot_scale * rad;
+        float dq[4], q[4] = {x[3], x[4], x[5], x[6]}, nq[4];
+        rotvec_quat(amp * dx, amp * dy, amp * dz, dq);
+        quat_mul(dq, q, nq);
+        quat_normalize(nq);
+        if (l >= 3 && l < 7) { nv = nq[l - 3]; wr = true; }
+    } else {
+        if (l == 7 + (ent - 2)) { nv = -kPi + 2.f * kPi * ua; wr = true; }
+    }
+    __syncthreads();
+    if (wr) x[l] = nv;
+    __syncthreads();
+}
+
+template <int A>
+__device__ ChainOut mc_chain(const Topo<A>& T, const BoxView& B, const Lds& S, const SearchParams& P, int job,
+                             int chain)
+{
+    const int l = lane_id();
+    ChainOut out;
+    out.evals = 0;
+    out.pairs = 0;
+    init_pose(T, B, S, SLOT_CUR, P.seed, job, chain);
+    Eval e0 = evaluate(T, B, S, S.pose + SLOT_CUR * kSlot);
+    out.evals += 1;
+    out.pairs += e0.pairs_in;
+    float e_cur = e0.e, e_best = e0.e;
+    slot_copy(S, SLOT_BEST, SLOT_CUR, 7 + T.nt);
+    for (int s = 0; s < P.steps; ++s) {
+        // lanes 0-3 hold block 0, lanes 4-7 block 1 of step s + 1; broadcast
+        const uint64_t mine = philox_word(P.seed, job, chain, (uint64_t)s + 1, (uint64_t)((l >> 2) & 1), l & 3);
+        uint64_t w[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const uint32_t lo = __shfl((uint32_t)mine, k), hi = __shfl((uint32_t)(mine >> 32), k);
+            w[k] = ((uint64_t)hi << 32) | lo;
+        }
+        slot_copy(S, SLOT_X, SLOT_CUR, 7 + T.nt);
+        mutate(T, S, SLOT_X, P, w);
+        BfgsOut bo = bfgs(T, B, S, P, P.max_iter);
+        out.evals += bo.evals;
+        out.pairs += bo.pairs;
+        const float e_o = bo.f;
+        const float um = u01(w[7]);
+        if (e_o < e_cur || um < __expf((e_cur - e_o) / P.temperature)) {
+            slot_copy(S, SLOT_CUR, SLOT_X, 7 + T.nt);
+            e_cur = e_o;
+        }
+        if (e_o < e_best) {
+            BfgsOut br = bfgs(T, B, S, P, P.refine_max_iter);
+            out.evals += br.evals;
+            out.pairs += br.pairs;
+            slot_copy(S, SLOT_BEST, SLOT_X, 7 + T.nt);
+            slot_copy(S, SLOT_CUR, SLOT_X, 7 + T.nt);
+            e_best = br.f;
+            e_cur = br.f;
+        }
+    }
+    out.best_e = e_best;
+    return out;
+}
+
+// ---------------------------------------------------------------- kernels
+__constant__ float c_rsum[64];
+__constant__ uint32_t c_tpflags[64];
+
+template <int A>
+__global__ __launch_bounds__(64) void dock_kernel(DockArgs a)
+{
+    extern __shared__ __align__(16) char smem[];
+    const Lds S = carve(smem, a.l.max_atoms, a.l.max_pairs);
+    const int l = lane_id();
+    stage_tp(S, c_rsum, c_tpflags);
+    Topo<A> T;
+    T.lig = -1;
+    const int chains = a.sp.chains;
+    int64_t item = a.persistent ? -1 : (int64_t)blockIdx.x;
+    while (true) {
+        if (a.persistent) {
+            uint32_t v = 0;
+            if (l == 0) v = atomicAdd(a.queue, 1u);
+            item = (int64_t)__shfl(v, 0);
+        }
+        if (item >= a.n_items) break;
+        const int job = a.job_begin + (int)(item / chains);
+        const int chain = (int)(item % chains);
+        const int2 jb = a.jobs[job];
+        if (jb.x != T.lig) stage_ligand(T, a.l, jb.x, S);
+        const BoxView B = box_view(a.g, jb.y);
+        uint64_t t0 = 0;
+        if (a.sp.flags & 1u) t0 = wall_clock64();
+        ChainOut co = mc_chain(T, B, S, a.sp, job, chain);
+        const int64_t ci = (int64_t)job * chains + chain;
+        if (a.chain_best_dof && l < a.dof_stride)
+            a.chain_best_dof[ci * a.dof_stride + l] = l < 7 + T.nt ? S.pose[SLOT_BEST * kSlot + l] : 0.f;
+        if (l == 0) {
+            if (a.chain_best_e) a.chain_best_e[ci] = co.best_e;
+            if (a.chain_evals) a.chain_evals[ci] = co.evals;
+            if (a.chain_pairs) a.chain_pairs[ci] = co.pairs;
+            if (a.sp.flags & 1u) {
+                const uint64_t t1 = wall_clock64();
+                atomicMin((unsigned long long*)&a.job_t_start[job], (unsigned long long)t0);
+                atomicMax((unsigned long long*)&a.job_t_end[job], (unsigned long long)t1);
+            }
+        }
+        __syncthreads();
+        if (!a.persistent) break;
+    }
+}
+
+__global__ void reset_queue_kernel(uint32_t* q) { if (threadIdx.x == 0) *q = 0u; }
+
+__global__ void reset_times_kernel(uint64_t* t0, uint64_t* t1, int n)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) { t0[i] = ~0ull; t1[i] = 0ull; }
+}
+
+__global__ void job_reduce_kernel(const float* cbe, const int64_t* cev, int n_jobs, int chains, float* jbe,
+                                  int32_t* jbc, int64_t* jev, int32_t* jst)
+{
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n_jobs) return;
+    int bc = 0;
+    float be = cbe[(int64_t)j * chains];
+    int64_t ev = cev ? cev[(int64_t)j * chains] : 0;
+    for (int c = 1; c < chains; ++c) {
+        const float e = cbe[(int64_t)j * chains + c];
+        if (e < be || (be != be && e == e)) { be = e; bc = c; }
+        if (cev) ev += cev[(int64_t)j * chains + c];
+    }
+    if (jbe) jbe[j] = be;
+    if (jbc) jbc[j] = bc;
+    if (jev) jev[j] = ev;
+    if (jst) jst[j] = isfinite(be) ? 0 : 1;
+}
+
+template <int A>
+__global__ __launch_bounds__(64) void score_kernel(ScoreArgs a)
+{
+    extern __shared__ __align__(16) char smem[];
+    const Lds S = carve(smem, a.l.max_atoms, a.l.max_pairs);
+    const int l = lane_id();
+    stage_tp(S, c_rsum, c_tpflags);
+    Topo<A> T;
+    T.lig = -1;
+    const float nanv = __int_as_float(0x7fc00000);
+    for (int pose = blockIdx.x; pose < a.n_poses; pose += gridDim.x) {
+        const int lig = a.lig_of_pose[pose], box = a.box_of_pose[pose];
+        if (lig < 0 || lig >= a.l.n_lig || box < 0 || box >= a.g.n_boxes) {
+            if (l == 0 && a.energy) a.energy[pose] = nanv;
+            if (l < 2 && a.e_parts) a.e_parts[2 * (int64_t)pose + l] = nanv;
+            if (a.grad_dof && l < a.dof_stride) a.grad_dof[(int64_t)pose * a.dof_stride + l] = nanv;
+            continue;
+        }
+        if (lig != T.lig) stage_ligand(T, a.l, lig, S);
+        const BoxView B = box_view(a.g, box);
+        const float scale = a.grad_energy ? a.grad_energy[pose] : 1.f;
+        const int16_t* perm = a.l.perm + a.l.ligs[lig].atom_base;
+        Eval ev;
+        if (!a.from_xyz) {
+            if (l < 7 + T.nt) S.pose[SLOT_X * kSlot + l] = a.dof[(int64_t)pose * a.dof_stride + l];
+            __syncthreads();
+            ev = evaluate(T, B, S, S.pose + SLOT_X * kSlot);
+        } else {
+            for (int i = l; i < T.n; i += kWave) {
+                const float* src = a.dof + ((int64_t)pose * a.xyz_stride + perm[i]) * 3;
+                S.pos[i] = make_float4(src[0], src[1], src[2], 0.f);
+            }
+            __syncthreads();
+            ev = evaluate_xyz(T, B, S);
+        }
+        if (l == 0 && a.energy) a.energy[pose] = ev.e;
+        if (a.e_parts && l < 2) a.e_parts[2 * (int64_t)pose + l] = l == 0 ? ev.e_inter : ev.e_intra;
+        if (a.grad_dof && !a.from_xyz) {
+            // dE/dt, dE/d(raw q) = 2 ((0, torque) (x) q)/|p|, dE/dpsi
+            const float* x = S.pose + SLOT_X * kSlot;
+            const float tq0 = __shfl(ev.g, 3), tq1 = __shfl(ev.g, 4), tq2 = __shfl(ev.g, 5);
+            const float dpsi = __shfl(ev.g, l - 1 < 0 ? 0 : (l - 1 > 63 ? 63 : l - 1));
+            float p[4] = {x[3], x[4], x[5], x[6]};
+            const float pn = sqrtf(p[0] * p[0] + p[1] * p[1] + p[2] * p[2] + p[3] * p[3]);
+            float qh[4] = {p[0] / pn, p[1] / pn, p[2] / pn, p[3] / pn};
+            float t4[4] = {0.f, tq0, tq1, tq2}, gq[4];
+            quat_mul(t4, qh, gq);
+            float v = 0.f;
+            if (l < 3) v = ev.g;
+            else if (l < 7) v = 2.f * gq[l - 3] / pn;
+            else if (l < 7 + T.nt) v = dpsi;
+            if (l < a.dof_stride) a.grad_dof[(int64_t)pose * a.dof_stride + l] = l < 7 + T.nt ? v * scale : 0.f;
+        }
+        if (a.xyz_out || a.grad_xyz) {
+            for (int i = l; i < T.n; i += kWave) {
+                const int64_t o = ((int64_t)pose * a.xyz_stride + perm[i]) * 3;
+                if (a.xyz_out) {
+                    const float4 p = S.pos[i];
+                    a.xyz_out[o] = p.x; a.xyz_out[o + 1] = p.y; a.xyz_out[o + 2] = p.z;
+                }
+                if (a.grad_xyz) {
+                    const float4 f = S.frc[i];
+                    a.grad_xyz[o] = f.x * scale; a.grad_xyz[o + 1] = f.y * scale; a.grad_xyz[o + 2] = f.z * scale;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int A>
+__global__ __launch_bounds__(64) void local_opt_kernel(OptArgs a)
+{
+    extern __shared__ __align__(16) char smem[];
+    const Lds S = carve(smem, a.l.max_atoms, a.l.max_pairs);
+    const int l = lane_id();
+    stage_tp(S, c_rsum, c_tpflags);
+    Topo<A> T;
+    T.lig = -1;
+    for (int pose = blockIdx.x; pose < a.n_poses; pose += gridDim.x) {
+        const int lig = a.lig_of_pose[pose], box = a.box_of_pose[pose];
+        if (lig < 0 || lig >= a.l.n_lig || box < 0 || box >= a.g.n_boxes) {
+            if (l == 0 && a.energy) a.energy[pose] = __int_as_float(0x7fc00000);
+            continue;
+        }
+        if (lig != T.lig) stage_ligand(T, a.l, lig, S);
+        const BoxView B = box_view(a.g, box);
+        float v = l < 7 + T.nt ? a.dof_in[(int64_t)pose * a.dof_stride + l] : 0.f;
+        // normalise the quaternion once so the run starts from a unit q
+        float q0 = __shfl(v, 3), q1 = __shfl(v, 4), q2 = __shfl(v, 5), q3 = __shfl(v, 6);
+        const float qn = rsqrtf(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+        if (l >= 3 && l < 7) v *= qn;
+        if (l < 7 + T.nt) S.pose[SLOT_X * kSlot + l] = v;
+        __syncthreads();
+        BfgsOut bo = bfgs(T, B, S, a.sp, a.sp.max_iter);
+        if (l < a.dof_stride) a.dof_out[(int64_t)pose * a.dof_stride + l] = l < 7 + T.nt ? S.pose[SLOT_X * kSlot + l] : 0.f;
+        if (l == 0) {
+            if (a.energy) a.energy[pose] = bo.f;
+            if (a.n_evals) a.n_evals[pose] = bo.evals;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- grid maps
+// One workgroup per 8x8x4 tile of one box.  Receptor atoms near the box are
+// streamed in chunks of 256; those within reach of the tile's bounding box
+// are compacted into LDS and every lane adds their terms to its point's 8
+// accumulators (one per ligand type).
+constexpr int kGridThreads = kTileX * kTileY * kTileZ;  // 256
+
+__global__ __launch_bounds__(256) void gridmap_kernel(GridBuildArgs a)
+{
+    __shared__ float4 cand[kGridThreads];
+    __shared__ int n_cand;
+    // which box and which tile of it
+    const int tile = blockIdx.x;
+    int box = 0;
+    while (box + 1 < a.n_boxes && a.tile_off[box + 1] <= tile) ++box;
+    const int nx = a.dims[4 * box], ny = a.dims[4 * box + 1], nz = a.dims[4 * box + 2];
+    const float ox = a.geom[8 * box], oy = a.geom[8 * box + 1], oz = a.geom[8 * box + 2], h = a.geom[8 * box + 3];
+    const int tx = (nx + kTileX - 1) / kTileX, ty = (ny + kTileY - 1) / kTileY;
+    const int t = tile - a.tile_off[box];
+    const int bx = t % tx, by = (t / tx) % ty, bz = t / (tx * ty);
+    const int li = threadIdx.x % kTileX, lj = (threadIdx.x / kTileX) % kTileY, lk = threadIdx.x / (kTileX * kTileY);
+    const int i = bx * kTileX + li, j = by * kTileY + lj, k = bz * kTileZ + lk;
+    const bool valid = i < nx && j < ny && k < nz;
+    // the lattice point exactly as the cutoff test defines it
+    const float gx = fmaf((float)i, h, ox), gy = fmaf((float)j, h, oy), gz = fmaf((float)k, h, oz);
+    // tile bounding box (points that exist)
+    const float lox = fmaf((float)(bx * kTileX), h, ox), loy = fmaf((float)(by * kTileY), h, oy),
+                loz = fmaf((float)(bz * kTileZ), h, oz);
+    const float hix = fmaf((float)min(bx * kTileX + kTileX - 1, nx - 1), h, ox);
+    const float hiy = fmaf((float)min(by * kTileY + kTileY - 1, ny - 1), h, oy);
+    const float hiz = fmaf((float)min(bz * kTileZ + kTileZ - 1, nz - 1), h, oz);
+    const float reach2 = 8.01f * 8.01f;
+    float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int abeg = a.atom_off[box], aend = a.atom_off[box + 1];
+    // element radii C N O S and the receptor-type table
+    const float Rel[4] = {1.9f, 1.8f, 1.7f, 2.0f};
+    for (int base = abeg; base < aend; base += kGridThreads) {
+        if (threadIdx.x == 0) n_cand = 0;
+        __syncthreads();
+        const int ai = base + threadIdx.x;
+        if (ai < aend) {
+            const float4 at = a.atoms[ai];
+            const float ddx = fmaxf(fmaxf(lox - at.x, at.x - hix), 0.f);
+            const float ddy = fmaxf(fmaxf(loy - at.y, at.y - hiy), 0.f);
+            const float ddz = fmaxf(fmaxf(loz - at.z, at.z - hiz), 0.f);
+            if (ddx * ddx + ddy * ddy + ddz * ddz < reach2) {
+                const int slot = atomicAdd(&n_cand, 1);
+                cand[slot] = at;
+            }
+        }
+        __syncthreads();
+        const int nc = n_cand;
+        for (int c = 0; c < nc; ++c) {
+            const float4 at = cand[c];
+            const float dx = gx - at.x, dy = gy - at.y, dz = gz - at.z;
+            const float dz2 = dz * dz;
+            const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz2));
+            if (!(r2 < kCut2)) continue;
+            const float r = sqrtf(r2);
+            const int rt = __float_as_uint(at.w) & 0xff;
+            const float Rr = rt <= 1 ? 1.9f : rt <= 4 ? 1.8f : rt <= 6 ? 1.7f : 2.0f;
+            const bool r_hyd = rt == 0, r_don = rt == 3 || rt == 6, r_acc = rt == 4 || rt == 5 || rt == 6;
+            float base_e[4], hbv[4];
+            float hyd_c = 0.f;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float d = r - (Rel[e] + Rr);
+                const float g1 = __expf(-4.f * d * d);
+                const float dm3 = d - 3.f;
+                const float g2 = __expf(-0.25f * dm3 * dm3);
+                float v = kW1 * g1 + kW2 * g2;
+                if (d < 0.f) v += kW3 * d * d;
+                base_e[e] = v;
+                hbv[e] = d < -0.7f ? 1.f : (d < 0.f ? -d * (1.f / 0.7f) : 0.f);
+                if (e == 0) hyd_c = d < 0.5f ? 1.f : (d < 1.5f ? 1.5f - d : 0.f);
+            }
+            acc[0] += base_e[0] + (r_hyd ? kW4 * hyd_c : 0.f);           // C_H
+            acc[1] += base_e[0];                                         // C_P
+            acc[2] += base_e[1];                                         // N_P
+            acc[3] += base_e[1] + (r_acc ? kW5 * hbv[1] : 0.f);          // N_D
+            acc[4] += base_e[1] + (r_don ? kW5 * hbv[1] : 0.f);          // N_A
+            acc[5] += base_e[2] + (r_don ? kW5 * hbv[2] : 0.f);          // O_A
+            acc[6] += base_e[2] + ((r_don || r_acc) ? kW5 * hbv[2] : 0.f); // O_DA
+            acc[7] += base_e[3];                                         // S_P
+        }
+        __syncthreads();
+    }
+    if (valid) {
+        const int64_t msz = (int64_t)nx * ny * nz;
+        const int64_t idx = ((int64_t)k * ny + j) * nx + i;
+        float* out = a.maps + a.map_off[box];
+#pragma unroll
+        for (int tt = 0; tt < 8; ++tt) out[tt * msz + idx] = acc[tt];
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+int dock_lds_bytes(int max_atoms, int max_pairs) { return lds_bytes(max_atoms, max_pairs); }
+
+static bool tables_ready = false;
+
+static hipError_t ensure_tables()
+{
+    if (tables_ready) return hipSuccess;
+    float rsum[64];
+    uint32_t fl[64];
+    type_pair_table(rsum, fl);
+    hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_rsum), rsum, sizeof(rsum));
+    if (e != hipSuccess) return e;
+    e = hipMemcpyToSymbol(HIP_SYMBOL(c_tpflags), fl, sizeof(fl));
+    if (e == hipSuccess) tables_ready = true;
+    return e;
+}
+
+hipError_t launch_build_grids(const GridBuildArgs& a, int64_t n_tiles, hipStream_t s)
+{
+    if (n_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gridmap_kernel, dim3((unsigned)n_tiles), dim3(kGridThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_score(const ScoreArgs& a, hipStream_t s)
+{
+    hipError_t e = ensure_tables();
+    if (e != hipSuccess) return e;
+    if (a.n_poses <= 0) return hipSuccess;
+    const int lds = lds_bytes(a.l.max_atoms, a.l.max_pairs);
+    const int grid = a.n_poses < 65536 ? a.n_poses : 65536;
+    if (a.l.max_atoms <= 64)
+        hipLaunchKernelGGL(score_kernel<1>, dim3(grid), dim3(64), lds, s, a);
+    else
+        hipLaunchKernelGGL(score_kernel<2>, dim3(grid), dim3(64), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_dock(const DockArgs& a, int32_t workgroups, hipStream_t s)
+{
+    hipError_t e = ensure_tables();
+    if (e != hipSuccess) return e;
+    if (a.n_items <= 0) return hipSuccess;
+    const int lds = lds_bytes(a.l.max_atoms, a.l.max_pairs);
+    const unsigned grid = a.persistent ? (unsigned)workgroups : (unsigned)a.n_items;
+    if (a.l.max_atoms <= 64)
+        hipLaunchKernelGGL(dock_kernel<1>, dim3(grid), dim3(64), lds, s, a);
+    else
+        hipLaunchKernelGGL(dock_kernel<2>, dim3(grid), dim3(64), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_queue(uint32_t* q, hipStream_t s)
+{
+    hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, s, q);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_times(uint64_t* t0, uint64_t* t1, int n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(reset_times_kernel, dim3((n + 255) / 256), dim3(256), 0, s, t0, t1, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_job_reduce(const float* cbe, const int64_t* cev, int32_t n_jobs, int32_t chains, float* jbe,
+                             int32_t* jbc, int64_t* jev, int32_t* jst, hipStream_t s)
+{
+    if (n_jobs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(job_reduce_kernel, dim3((n_jobs + 255) / 256), dim3(256), 0, s, cbe, cev, n_jobs, chains,
+                       jbe, jbc, jev, jst);
+    return hipGetLastError();
+}
+
+hipError_t launch_local_opt(const OptArgs& a, hipStream_t s)
+{
+    hipError_t e = ensure_tables();
+    if (e != hipSuccess) return e;
+    if (a.n_poses <= 0) return hipSuccess;
+    const int lds = lds_bytes(a.l.max_atoms, a.l.max_pairs);
+    const int grid = a.n_poses < 65536 ? a.n_poses : 65536;
+    if (a.l.max_atoms <= 64)
+        hipLaunchKernelGGL(local_opt_kernel<1>, dim3(grid), dim3(64), lds, s, a);
+    else
+        hipLaunchKernelGGL(local_opt_kernel<2>, dim3(grid), dim3(64), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t dock_occupancy(int max_atoms, int max_pairs, int* blocks_per_cu)
+{
+    const int lds = lds_bytes(max_atoms, max_pairs);
+    if (max_atoms <= 64)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, dock_kernel<1>, 64, lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, dock_kernel<2>, 64, lds);
+}
+
+}  // namespace pv

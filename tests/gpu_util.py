@@ -1,0 +1,32 @@
+"""Shared set-up of the GPU parity tests: seeded inputs handed to both the HIP
+path and the oracle, and the tolerances the comparisons use.
+
+Tolerances (binary32 kernels against the binary64 oracle):
+  energy:   |E_gpu - E_ref| <= 1e-3 + 1e-4 |E_ref|          (kcal/mol)
+  gradient: max_k |g_gpu,k - g_ref,k| <= 1e-3 + 1e-4 max_k |g_ref,k|
+            (per pose: relative to the largest component of the pose's
+            gradient, since each component is a sum of contributions of
+            that size)
+Poses with an atom within 1e-3 A of a lattice plane, or an intra pair within
+1e-3 A of the cutoff or of a term kink, sit where the two sides may take
+different one-sided derivatives; they are counted and must stay few.
+"""
+import numpy as np
+
+KINK = 1e-3
+
+
+def e_tol(ref):
+    return 1e-3 + 1e-4 * np.abs(ref)
+
+
+def g_tol(ref):
+    return 1e-3 + 1e-4 * np.max(np.abs(ref))
+
+
+def near_kink(r):
+    return min(r["min_face"], r["min_cut"], r["min_kink"]) < KINK
+
+
+def cpu_dof(dof):
+    return np.asarray(dof, np.float64)

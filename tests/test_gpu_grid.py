@@ -1,0 +1,96 @@
+"""GPU parity of the grid-map kernel ("Kernel 1" grid cache) against the
+oracle's maps: every value of the tiny configuration, sampled values of the
+five 24 A pockets at full size, and ragged or degenerate boxes."""
+import numpy as np
+import pytest
+
+from paper_2506_20043_amd import synth as S
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pv_ctx():
+    import paper_2506_20043_amd as pv
+    return pv.Context(0)
+
+
+def _gpu_maps(pv_ctx, rx, rt, boxes):
+    import paper_2506_20043_amd as pv
+    grids = pv.build_grids(pv_ctx, rx, rt, boxes)
+    return grids, [grids.maps(b).cpu().numpy() for b in range(len(boxes))]
+
+
+def _assert_maps_close(gpu, ref, what):
+    err = np.abs(gpu.astype(np.float64) - ref)
+    tol = 1e-3 + 1e-4 * np.abs(ref)
+    bad = err > tol
+    assert not bad.any(), "%s: %d of %d values off, worst %.3g at %s" % (
+        what, int(bad.sum()), bad.size, float(err.max()), np.unravel_index(np.argmax(err - tol), err.shape))
+
+
+def test_tiny_config_every_value(oracle, pv_ctx):
+    cfg = S.CONFIGS["c1"]
+    rx, rt, bxs = S.make_receptor(cfg)
+    grids, maps = _gpu_maps(pv_ctx, rx, rt, bxs)
+    dims, org = grids.info(0)
+    odims, oorg = oracle.lattice(bxs[0].center.astype(np.float64), bxs[0].size.astype(np.float64), bxs[0].spacing)
+    np.testing.assert_array_equal(dims, odims)
+    np.testing.assert_array_equal(org, oorg)
+    ref = oracle.build_maps(rx, rt, dims, org, bxs[0].spacing)
+    assert maps[0].shape == ref.shape == (8, 55, 55, 55)
+    _assert_maps_close(maps[0], ref, "c1")
+
+
+def test_five_pockets_sampled(oracle, pv_ctx):
+    cfg = S.CONFIGS["c2"]
+    rx, rt, bxs = S.make_receptor(cfg)
+    grids, maps = _gpu_maps(pv_ctx, rx, rt, bxs)
+    g = np.random.default_rng(0)
+    for b, box in enumerate(bxs):
+        dims, org = grids.info(b)
+        assert list(dims) == [65, 65, 65]
+        pts = [(0, 0, 0), (64, 64, 64), (64, 0, 32)] + [tuple(int(v) for v in g.integers(0, 65, 3)) for _ in range(300)]
+        for i, j, k in pts:
+            ref = oracle.map_point(rx, rt, dims, org, box.spacing, i, j, k)
+            _assert_maps_close(maps[b][:, k, j, i], ref, "box %d point %s" % (b, (i, j, k)))
+
+
+def test_ragged_and_degenerate_boxes(oracle, pv_ctx):
+    g = np.random.default_rng(1)
+    rx, rt = S.receptor(g, 400, 20.0)
+    boxes = [S.Box(np.array([10.0, 10.0, 10.0], np.float32), np.array([7.3, 4.1, 9.9], np.float32), 0.375),
+             S.Box(np.array([3.0, 17.0, 9.0], np.float32), np.array([0.3, 0.3, 0.3], np.float32), 0.375),
+             S.Box(np.array([-5.0, 25.0, 10.0], np.float32), np.array([6.0, 6.0, 6.0], np.float32), 0.5)]
+    grids, maps = _gpu_maps(pv_ctx, rx, rt, boxes)
+    for b, box in enumerate(boxes):
+        dims, org = grids.info(b)
+        ref = oracle.build_maps(rx, rt, dims, org, box.spacing)
+        _assert_maps_close(maps[b], ref, "box %d dims %s" % (b, dims))
+    assert list(grids.info(1)[0]) == [2, 2, 2]
+
+
+def test_empty_receptor_gives_zero_maps(pv_ctx):
+    box = S.Box(np.zeros(3, np.float32), np.full(3, 5.0, np.float32), 0.375)
+    _, maps = _gpu_maps(pv_ctx, np.zeros((0, 3), np.float32), np.zeros(0, np.uint8), [box])
+    assert maps[0].shape == (8, 15, 15, 15) and np.all(maps[0] == 0.0)
+
+
+def test_receptor_far_from_box_gives_zero_maps(pv_ctx):
+    rx = np.array([[100.0, 0, 0], [0, 100.0, 0]], np.float32)
+    box = S.Box(np.zeros(3, np.float32), np.full(3, 10.0, np.float32), 0.375)
+    _, maps = _gpu_maps(pv_ctx, rx, np.array([0, 5], np.uint8), [box])
+    assert np.all(maps[0] == 0.0)
+
+
+def test_build_grids_rejects(pv_ctx):
+    import paper_2506_20043_amd as pv
+    rx = np.zeros((1, 3), np.float32)
+    box = S.Box(np.zeros(3, np.float32), np.full(3, 5.0, np.float32), 0.375)
+    with pytest.raises(pv.PvError, match="type"):
+        pv.build_grids(pv_ctx, rx, np.array([8], np.uint8), [box])
+    with pytest.raises(pv.PvError, match="penalty"):
+        pv.build_grids(pv_ctx, rx, np.array([0], np.uint8), [box], penalty_slope=-1.0)
+    bad = S.Box(np.zeros(3, np.float32), np.array([5.0, 0.0, 5.0], np.float32), 0.375)
+    with pytest.raises(pv.PvError, match="size"):
+        pv.build_grids(pv_ctx, rx, np.array([0], np.uint8), [bad])

@@ -1,0 +1,226 @@
+"""GPU parity of score + analytic gradient (Eq. qvina_eq_3 and the chain rule
+through the torsion tree of Eq. qvina_eq_1) against the oracle, on the tiny
+configuration, on the full 16,384-pose differentiation workload (sampled),
+on degenerate ligands and poses, and through the autograd Function."""
+import numpy as np
+import pytest
+
+from gpu_util import cpu_dof, e_tol, g_tol, near_kink
+from paper_2506_20043_amd import synth as S
+
+pytestmark = pytest.mark.gpu
+KAPPA = 10.0
+
+
+@pytest.fixture(scope="module")
+def pv_ctx():
+    import paper_2506_20043_amd as pv
+    return pv.Context(0)
+
+
+class Setup:
+    def __init__(self, oracle, pv_ctx, rx, rt, boxes, mols):
+        import paper_2506_20043_amd as pv
+        self.grids = pv.build_grids(pv_ctx, rx, rt, boxes, penalty_slope=KAPPA)
+        self.ligs = pv.Ligands(pv_ctx, mols)
+        self.og = [oracle.Grid.build(rx, rt, b.center.astype(np.float64), b.size.astype(np.float64), b.spacing,
+                                     kappa=KAPPA) for b in boxes]
+        self.ol = [oracle.Ligand(m.xyz, m.types, m.bonds, m.rotatable) for m in mols]
+        self.mols, self.boxes, self.ctx = mols, boxes, pv_ctx
+
+    def lohi(self, b):
+        G = self.og[b]
+        return G.origin.astype(np.float64), G.origin + G.h * (G.dims - 1)
+
+
+def compare(st, lig, box, dof, out, idx, strict_frac=0.8):
+    """Compares GPU outputs at pose rows idx with the oracle; returns counts."""
+    e = out["energy"].cpu().numpy()
+    parts = out["e_parts"].cpu().numpy() if "e_parts" in out else None
+    gd = out["grad_dof"].cpu().numpy()
+    xyz = out["xyz"].cpu().numpy() if "xyz" in out else None
+    gx = out["grad_xyz"].cpu().numpy() if "grad_xyz" in out else None
+    n_kink = 0
+    for b in idx:
+        L, G = st.ol[lig[b]], st.og[box[b]]
+        r = L.score_grad(G, cpu_dof(dof[b, :L.ndof]))
+        kink = near_kink(r)
+        slack = 0.01 if r["min_cut"] < 1e-3 else 0.0
+        assert abs(e[b] - r["e"]) <= e_tol(r["e"]) + slack, (b, e[b], r["e"])
+        if parts is not None:
+            assert abs(parts[b, 0] - r["e_inter"]) <= e_tol(r["e_inter"]), (b, parts[b], r["e_inter"])
+            assert abs(parts[b, 1] - r["e_intra"]) <= e_tol(r["e_intra"]) + slack, (b, parts[b], r["e_intra"])
+        if xyz is not None:
+            assert np.abs(xyz[b, :L.n_atoms] - r["xyz"]).max() <= 1e-4, b
+        if kink:
+            n_kink += 1
+            continue
+        gref = r["grad_dof"]
+        assert np.abs(gd[b, :L.ndof] - gref).max() <= g_tol(gref), (b, gd[b, :L.ndof], gref)
+        assert np.all(gd[b, L.ndof:] == 0.0)
+        if gx is not None:
+            assert np.abs(gx[b, :L.n_atoms] - r["grad_xyz"]).max() <= g_tol(r["grad_xyz"]), b
+    assert n_kink <= (1 - strict_frac) * len(idx), (n_kink, len(idx))
+    return n_kink
+
+
+def test_tiny_config_poses(oracle, pv_ctx):
+    import paper_2506_20043_amd as pv
+    cfg = S.CONFIGS["c1"]
+    rx, rt, bxs = S.make_receptor(cfg)
+    mols = S.make_ligands(cfg)
+    st = Setup(oracle, pv_ctx, rx, rt, bxs, mols)
+    g = np.random.default_rng(0)
+    lo, hi = st.lohi(0)
+    B = 300
+    dof = S.poses(g, B, lo - 1.0, hi + 1.0, st.ol[0].n_tors)  # some poses leave the box
+    z = np.zeros(B, np.int32)
+    out = pv.score_grad(pv_ctx, st.grids, st.ligs, z, z, dof, parts=True, xyz=True)
+    compare(st, z, z, dof, out, range(B))
+
+
+def test_differentiation_workload_full_size(oracle, pv_ctx):
+    """16,384 poses of 64 ligands (40 atoms, 10 torsions) in one 24 A pocket,
+    the launch the benchmark times; the oracle checks a sample."""
+    import paper_2506_20043_amd as pv
+    cfg = S.CONFIGS["c4"]
+    rx, rt, bxs = S.make_receptor(cfg)
+    mols = S.make_ligands(cfg)
+    st = Setup(oracle, pv_ctx, rx, rt, bxs[:1], mols)
+    g = S.rng(cfg.index, S.STREAM_POSES)
+    lo, hi = st.lohi(0)
+    per = cfg.n_poses // cfg.n_ligands
+    dof = S.poses(g, cfg.n_poses, lo, hi, 10)
+    lig = np.repeat(np.arange(cfg.n_ligands, dtype=np.int32), per)
+    box = np.zeros(cfg.n_poses, np.int32)
+    out = pv.score_grad(pv_ctx, st.grids, st.ligs, lig, box, dof, parts=True)
+    assert np.isfinite(out["energy"].cpu().numpy()).all()
+    idx = np.random.default_rng(1).choice(cfg.n_poses, 400, replace=False)
+    compare(st, lig, box, dof, out, np.sort(idx))
+
+
+def test_degenerate_ligands(oracle, pv_ctx):
+    """One atom, no torsion, and the largest ligand (128 atoms, 32 torsions)."""
+    import paper_2506_20043_amd as pv
+    g = np.random.default_rng(2)
+    rx, rt = S.receptor(g, 1500, 40.0)
+    box = S.Box(np.full(3, 20.0, np.float32), np.full(3, 30.0, np.float32), 0.375)
+    one = S.Molecule(np.zeros((1, 3)), np.array([4], np.int32), np.zeros((0, 2), np.int32), np.zeros(0, np.uint8))
+    rigid = S.tree_ligand(g, 12, 0)
+    big = S.tree_ligand(g, 128, 32)
+    mols = [one, rigid, big]
+    st = Setup(oracle, pv_ctx, rx, rt, [box], mols)
+    lo, hi = st.lohi(0)
+    B = 60
+    lig = np.repeat(np.arange(3, dtype=np.int32), B // 3)
+    dof = np.zeros((B, 7 + 32), np.float32)
+    for b in range(B):
+        nt = st.ol[lig[b]].n_tors
+        dof[b, :7 + nt] = S.poses(g, 1, lo + 2, hi - 2, nt)[0]
+    out = pv.score_grad(pv_ctx, st.grids, st.ligs, lig, np.zeros(B, np.int32), dof, parts=True, xyz=True)
+    compare(st, lig, np.zeros(B, np.int32), dof, out, range(B), strict_frac=0.6)
+
+
+def test_invalid_rows_and_empty_batch(oracle, pv_ctx):
+    import paper_2506_20043_amd as pv
+    g = np.random.default_rng(3)
+    rx, rt = S.receptor(g, 300, 20.0)
+    box = S.Box(np.full(3, 10.0, np.float32), np.full(3, 12.0, np.float32), 0.375)
+    mol = S.tree_ligand(g, 10, 2)
+    st = Setup(oracle, pv_ctx, rx, rt, [box], [mol])
+    dof = np.tile(np.array([10, 10, 10, 1, 0, 0, 0, 0.1, 0.2], np.float32), (4, 1))
+    dof[3, 3:7] = 0.0   # zero quaternion
+    out = pv.score_grad(pv_ctx, st.grids, st.ligs, [0, 5, 0, 0], [0, 0, -1, 0], dof)
+    e = out["energy"].cpu().numpy()
+    assert np.isfinite(e[0]) and np.isnan(e[1]) and np.isnan(e[2]) and np.isnan(e[3])
+    assert np.isnan(out["grad_dof"].cpu().numpy()[1]).all()
+    empty = pv.score_grad(pv_ctx, st.grids, st.ligs, np.zeros(0, np.int32), np.zeros(0, np.int32),
+                          np.zeros((0, 9), np.float32))
+    assert empty["energy"].numel() == 0
+    with pytest.raises(pv.PvError, match="dof_stride"):
+        pv.score_grad(pv_ctx, st.grids, st.ligs, [0], [0], np.zeros((1, 8), np.float32))
+
+
+def test_score_on_coordinates(oracle, pv_ctx):
+    import paper_2506_20043_amd as pv
+    cfg = S.CONFIGS["c1"]
+    rx, rt, bxs = S.make_receptor(cfg)
+    mols = S.make_ligands(S.CONFIGS["c3"], count=6)
+    st = Setup(oracle, pv_ctx, rx, rt, bxs, mols)
+    g = np.random.default_rng(4)
+    lo, hi = st.lohi(0)
+    B = 60
+    lig = np.arange(B, dtype=np.int32) % 6
+    ma = st.ligs.max_atoms
+    xyz = np.zeros((B, ma, 3), np.float32)
+    for b in range(B):
+        L = st.ol[lig[b]]
+        d = S.poses(g, 1, lo, hi, L.n_tors)[0]
+        xyz[b, :L.n_atoms] = L.fk(d.astype(np.float64)).astype(np.float32)
+    out = pv.score_grad_xyz(pv_ctx, st.grids, st.ligs, lig, np.zeros(B, np.int32), xyz, parts=True)
+    e = out["energy"].cpu().numpy()
+    gx = out["grad_xyz"].cpu().numpy()
+    kinks = 0
+    for b in range(B):
+        L = st.ol[lig[b]]
+        r = L.score_xyz(st.og[0], xyz[b, :L.n_atoms].astype(np.float64))
+        slack = 0.01 if r["min_cut"] < 1e-3 else 0.0
+        assert abs(e[b] - r["e"]) <= e_tol(r["e"]) + slack
+        if near_kink(r):
+            kinks += 1
+            continue
+        assert np.abs(gx[b, :L.n_atoms] - r["grad_xyz"]).max() <= g_tol(r["grad_xyz"])
+    assert kinks < B // 4
+
+
+def test_autograd_backward(oracle, pv_ctx):
+    """ScoreGrad's backward equals grad_energy times the gradient kernel's
+    output, and both agree with central differences (h = 1e-4) of the oracle."""
+    import torch
+
+    import paper_2506_20043_amd as pv
+    cfg = S.CONFIGS["c1"]
+    rx, rt, bxs = S.make_receptor(cfg)
+    mols = S.make_ligands(cfg)
+    st = Setup(oracle, pv_ctx, rx, rt, bxs, mols)
+    g = np.random.default_rng(5)
+    lo, hi = st.lohi(0)
+    B = 64
+    L = st.ol[0]
+    dof_np = S.poses(g, B, lo + 2, hi - 2, L.n_tors)
+    z = torch.zeros(B, dtype=torch.int32, device="cuda")
+    handles = (pv_ctx, st.grids, st.ligs, z, z)
+    dof = torch.tensor(dof_np, device="cuda", requires_grad=True)
+    e = pv.ScoreGrad.apply(dof, handles)
+    w = torch.tensor(g.normal(size=B), dtype=torch.float32, device="cuda")
+    (e * w).sum().backward()
+    grad = dof.grad.cpu().numpy()
+    plain = pv.score_grad(pv_ctx, st.grids, st.ligs, z, z, dof_np)["grad_dof"].cpu().numpy()
+    wn = w.cpu().numpy()
+    np.testing.assert_allclose(grad, plain * wn[:, None], rtol=1e-6, atol=1e-6)
+    checked = 0
+    for b in range(B):
+        x = dof_np[b].astype(np.float64)
+        r = L.score_grad(st.og[0], x)
+        if near_kink(r):
+            continue
+        h = 1e-4
+        fd = np.zeros(L.ndof)
+        for i in range(L.ndof):
+            xp, xm = x.copy(), x.copy()
+            xp[i] += h
+            xm[i] -= h
+            fd[i] = (L.score_grad(st.og[0], xp)["e"] - L.score_grad(st.og[0], xm)["e"]) / (2 * h)
+        # a difference quotient may straddle a cell face; skip those rows
+        if np.abs(fd - r["grad_dof"]).max() > 1e-3 * (1 + np.abs(r["grad_dof"]).max()):
+            continue
+        assert np.abs(plain[b] - fd).max() <= 2e-3 + 1e-4 * np.abs(fd).max(), b
+        checked += 1
+    assert checked >= B // 2
+    # coordinates form
+    xyz = torch.tensor(np.stack([L.fk(d.astype(np.float64)) for d in dof_np]).astype(np.float32), device="cuda",
+                       requires_grad=True)
+    ex = pv.ScoreGradXYZ.apply(xyz, handles)
+    ex.sum().backward()
+    ref = pv.score_grad(pv_ctx, st.grids, st.ligs, z, z, dof_np, xyz=True)["grad_xyz"].cpu().numpy()
+    np.testing.assert_allclose(xyz.grad.cpu().numpy(), ref[:, :L.n_atoms], rtol=1e-3, atol=1e-3)

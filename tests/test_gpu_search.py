@@ -1,0 +1,208 @@
+"""GPU parity of the search: initial poses and Philox draws, Monte Carlo
+without local optimisation (decision by decision), RILC-BFGS from fixed
+starts, full Monte Carlo + BFGS docks checked for validity and compared with
+the oracle statistically, and the batched, plain and graph-replayed forms
+against each other (Supplementary Algorithm 2, Eqs. qvina_eq_6 .. qvina_eq_13)."""
+import numpy as np
+import pytest
+from scipy import stats
+
+from gpu_util import cpu_dof, e_tol
+from paper_2506_20043_amd import synth as S
+
+pytestmark = pytest.mark.gpu
+KAPPA = 10.0
+
+
+@pytest.fixture(scope="module")
+def pv_ctx():
+    import paper_2506_20043_amd as pv
+    return pv.Context(0)
+
+
+@pytest.fixture(scope="module")
+def c1(oracle, pv_ctx):
+    import paper_2506_20043_amd as pv
+    cfg = S.CONFIGS["c1"]
+    rx, rt, bxs = S.make_receptor(cfg)
+    mols = S.make_ligands(cfg)
+    b = bxs[0]
+    return dict(
+        grids=pv.build_grids(pv_ctx, rx, rt, bxs, penalty_slope=KAPPA),
+        ligs=pv.Ligands(pv_ctx, mols),
+        og=oracle.Grid.build(rx, rt, b.center.astype(np.float64), b.size.astype(np.float64), b.spacing, kappa=KAPPA),
+        ol=oracle.Ligand(mols[0].xyz, mols[0].types, mols[0].bonds, mols[0].rotatable),
+        seed=S.philox_seed(cfg))
+
+
+def _params(pv, **kw):
+    return pv.dock_params(**kw)
+
+
+def _oparams(oracle, p):
+    bp = oracle.bfgs_params(max_iter=p.bfgs_max_iter, m=p.bfgs_m, ls_max=p.ls_max_trials, rho=p.ls_rho,
+                            sigma=p.ls_sigma, eps_g=p.eps_grad, eps_c=p.eps_curv)
+    return oracle.mc_params(chains=p.chains, steps=p.steps, seed=p.seed, bfgs=bp,
+                            refine_max_iter=p.refine_max_iter, temperature=p.temperature,
+                            mut_pos_amp=p.mut_pos_amp, mut_rot_amp=p.mut_rot_amp)
+
+
+def test_initial_poses_match_oracle_draws(oracle, pv_ctx, c1):
+    """steps = 0: each chain's best is its Philox-drawn initial pose."""
+    import paper_2506_20043_amd as pv
+    p = _params(pv, chains=64, steps=0, seed=c1["seed"])
+    res = pv.dock(pv_ctx, c1["grids"], c1["ligs"], [(0, 0), (0, 0)], p)
+    cbd = res["chain_best_dof"].cpu().numpy().reshape(2, 64, -1)
+    cbe = res["chain_best_e"].cpu().numpy().reshape(2, 64)
+    ev = res["chain_evals"].cpu().numpy()
+    assert np.all(ev == 1)
+    L, G = c1["ol"], c1["og"]
+    for j in range(2):
+        for c in range(64):
+            ref = oracle.init_pose(L, G, p.seed, j, c)
+            assert np.abs(cbd[j, c, :3] - ref[:3]).max() < 1e-4
+            assert np.abs(cbd[j, c, 3:L.ndof] - ref[3:]).max() < 2e-6
+            r = L.score_grad(G, ref)
+            assert abs(cbe[j, c] - r["e"]) <= e_tol(r["e"]) + (0.01 if r["min_cut"] < 1e-3 else 0.0)
+    # jobs draw different streams
+    assert not np.allclose(cbd[0], cbd[1])
+
+
+def test_mc_without_bfgs_replays_oracle(oracle, pv_ctx, c1):
+    """With no BFGS iterations the chain is mutate + Metropolis only: the same
+    Philox draws give the same trajectory, so the best pose and energy match
+    the oracle's unless a Metropolis test lands within rounding of its
+    threshold (rare)."""
+    import paper_2506_20043_amd as pv
+    p = _params(pv, chains=64, steps=40, seed=c1["seed"] + 1, bfgs_max_iter=0, refine_max_iter=0)
+    res = pv.dock(pv_ctx, c1["grids"], c1["ligs"], [(0, 0)], p)
+    cbd = res["chain_best_dof"].cpu().numpy()
+    cbe = res["chain_best_e"].cpu().numpy()
+    ev = res["chain_evals"].cpu().numpy()
+    L, G = c1["ol"], c1["og"]
+    same = 0
+    for c in range(64):
+        d, e, ne = oracle.mc_chain(L, G, _oparams(oracle, p), 0, c)
+        if ne == ev[c] and abs(cbe[c] - e) <= e_tol(e) and np.abs(cbd[c, :3] - d[:3]).max() < 1e-3:
+            same += 1
+    assert same >= 58, same
+
+
+def test_local_opt_matches_oracle_on_smooth_objective(oracle, pv_ctx):
+    """Intra-only objective (no receptor), C_P atoms and ligands at most 5
+    bonds across, so it is smooth: from the same starts the GPU's FP32 BFGS
+    and the oracle's FP64 BFGS reach the same minimum within 1e-3 kcal/mol."""
+    import paper_2506_20043_amd as pv
+    from test_oracle_search import _diameter
+    g = np.random.default_rng(6)
+    mols = []
+    while len(mols) < 24:
+        m = S.tree_ligand(g, 9, 4)
+        if m.n_tors >= 3 and _diameter(9, m.bonds) <= 5:
+            mols.append(S.Molecule(m.xyz, np.full(9, 1, np.int32), m.bonds, m.rotatable, m.n_tors))
+    box = S.Box(np.zeros(3, np.float32), np.full(3, 40.0, np.float32), 1.0)
+    grids = pv.build_grids(pv_ctx, np.zeros((0, 3), np.float32), np.zeros(0, np.uint8), [box], penalty_slope=KAPPA)
+    ligs = pv.Ligands(pv_ctx, mols)
+    dims, org = grids.info(0)
+    og = oracle.Grid(np.zeros((8, dims[2], dims[1], dims[0])), dims, org, 1.0, kappa=KAPPA)
+    stride = ligs.dof_stride
+    dof = np.zeros((len(mols), stride), np.float32)
+    for i, m in enumerate(mols):
+        dof[i, :7 + m.n_tors] = S.poses(g, 1, [-1, -1, -1], [1, 1, 1], m.n_tors)[0]
+    p = _params(pv, bfgs_max_iter=300, eps_grad=1e-4)
+    out, e, ne = pv.local_opt(pv_ctx, grids, ligs, np.arange(len(mols)), np.zeros(len(mols)), dof, p)
+    e = e.cpu().numpy()
+    bp = oracle.bfgs_params(max_iter=300, eps_g=1e-4)
+    agree = 0
+    for i, m in enumerate(mols):
+        L = oracle.Ligand(m.xyz, m.types, m.bonds, m.rotatable)
+        _, f, _, _ = oracle.bfgs(L, og, cpu_dof(dof[i, :L.ndof]), bp)
+        agree += abs(e[i] - f) <= 1e-3
+        # the GPU's end point is a stationary point of the oracle's objective
+        r = L.score_grad(og, cpu_dof(out[i, :L.ndof].cpu().numpy()))
+        assert abs(r["e"] - e[i]) <= 1e-3
+        assert np.abs(r["grad_tan"]).max() < 2e-2
+    assert agree >= 20, agree
+
+
+def test_local_opt_decreases_and_is_valid(oracle, pv_ctx, c1):
+    import paper_2506_20043_amd as pv
+    L, G = c1["ol"], c1["og"]
+    g = np.random.default_rng(7)
+    lo, hi = G.origin.astype(np.float64), G.origin + G.h * (G.dims - 1)
+    B = 128
+    dof = S.poses(g, B, lo + 2, hi - 2, L.n_tors)
+    out, e, ne = pv.local_opt(pv_ctx, c1["grids"], c1["ligs"], np.zeros(B), np.zeros(B), dof, _params(pv))
+    out, e, ne = out.cpu().numpy(), e.cpu().numpy(), ne.cpu().numpy()
+    assert np.all(ne >= 1) and np.all(np.abs(np.linalg.norm(out[:, 3:7], axis=1) - 1) < 1e-5)
+    close = 0
+    for b in range(B):
+        r0 = L.score_grad(G, cpu_dof(dof[b]))
+        r1 = L.score_grad(G, cpu_dof(out[b]))
+        assert abs(r1["e"] - e[b]) <= e_tol(r1["e"]) + 0.01
+        assert e[b] <= r0["e"] + e_tol(r0["e"])
+        _, f, _, _ = oracle.bfgs(L, G, cpu_dof(dof[b]))
+        close += abs(f - e[b]) <= 1e-3 + 1e-4 * abs(f)
+    # trajectories of a non-smooth landscape may part ways; most do not
+    assert close >= B // 2, close
+
+
+def test_dock_valid_and_statistically_like_oracle(oracle, pv_ctx, c1):
+    """Full MC + BFGS on the tiny configuration with 64 chains: every GPU
+    chain best re-scores to its reported energy under the oracle, never
+    exceeds its initial energy, and the distribution of chain bests matches
+    the oracle's run on the same Philox streams."""
+    import paper_2506_20043_amd as pv
+    p = _params(pv, chains=64, steps=200, seed=c1["seed"])
+    res = pv.dock(pv_ctx, c1["grids"], c1["ligs"], [(0, 0)], p)
+    cbd = res["chain_best_dof"].cpu().numpy()
+    cbe = res["chain_best_e"].cpu().numpy()
+    L, G = c1["ol"], c1["og"]
+    for c in range(64):
+        r = L.score_grad(G, cpu_dof(cbd[c, :L.ndof]))
+        assert abs(r["e"] - cbe[c]) <= e_tol(r["e"]) + 0.01, (c, cbe[c], r["e"])
+        assert cbe[c] <= L.score_grad(G, oracle.init_pose(L, G, p.seed, 0, c))["e"] + 1e-3
+    ref = oracle.dock([L], [G], [(0, 0)], _oparams(oracle, p))
+    oe = ref["chain_best_e"][0]
+    ks = stats.ks_2samp(cbe, oe)
+    assert ks.pvalue > 0.01, (ks, np.median(cbe), np.median(oe))
+    assert res["job_best_e"].cpu().numpy()[0] == cbe.min()
+    assert res["job_best_chain"].cpu().numpy()[0] == int(np.argmin(cbe))
+
+
+def test_batched_plain_graph_agree(pv_ctx, c1):
+    import torch
+
+    import paper_2506_20043_amd as pv
+    jobs = [(0, 0)] * 6
+    p = _params(pv, chains=16, steps=30, seed=c1["seed"] + 7)
+    plan = pv.Plan(pv_ctx, c1["grids"], c1["ligs"], jobs, p)
+    a = {k: v.clone() for k, v in plan.run().items()}
+    b = {k: v.clone() for k, v in plan.run(plain=True).items()}
+    torch.cuda.synchronize()
+    for k in ("chain_best_e", "chain_best_dof", "chain_evals", "job_best_e"):
+        assert torch.equal(a[k], b[k]), k
+    gp = _params(pv, chains=16, steps=30, seed=c1["seed"] + 7, flags=pv.PV_DOCK_GRAPH | pv.PV_DOCK_TIMESTAMPS)
+    gplan = pv.Plan(pv_ctx, c1["grids"], c1["ligs"], jobs, gp)
+    for rep in range(3):
+        out = gplan.run()
+        torch.cuda.synchronize()
+        for k in ("chain_best_e", "chain_best_dof", "chain_evals"):
+            assert torch.equal(out[k], a[k]), (rep, k)
+        t0, t1 = out["job_t_start"].cpu().numpy(), out["job_t_end"].cpu().numpy()
+        assert np.all(t1 > t0)
+        torch.zeros(1000, device="cuda").sum().item()  # eager work between replays
+    plan.close()
+    gplan.close()
+
+
+def test_dock_rejects(pv_ctx, c1):
+    import paper_2506_20043_amd as pv
+    with pytest.raises(pv.PvError, match="ligand"):
+        pv.Plan(pv_ctx, c1["grids"], c1["ligs"], [(1, 0)], _params(pv))
+    with pytest.raises(pv.PvError, match="box"):
+        pv.Plan(pv_ctx, c1["grids"], c1["ligs"], [(0, 3)], _params(pv))
+    with pytest.raises(pv.PvError, match="chains"):
+        pv.Plan(pv_ctx, c1["grids"], c1["ligs"], [(0, 0)], _params(pv, chains=0))
+    with pytest.raises(pv.PvError, match="ls_rho"):
+        pv.Plan(pv_ctx, c1["grids"], c1["ligs"], [(0, 0)], _params(pv, ls_rho=0.5, ls_sigma=0.1))
