@@ -96,6 +96,9 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise PvError("native library %s is missing: build it with "
                           "`python -c 'import __graft_entry__ as g; g.build()'`" % LIB_PATH)
+        # torch carries its own HIP runtime; loading it first makes the
+        # library bind to that same runtime (one runtime, one set of streams)
+        _torch()
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)

@@ -7,13 +7,15 @@ Tolerances (binary32 kernels against the binary64 oracle):
             (per pose: relative to the largest component of the pose's
             gradient, since each component is a sum of contributions of
             that size)
-Poses with an atom within 1e-3 A of a lattice plane, or an intra pair within
-1e-3 A of the cutoff or of a term kink, sit where the two sides may take
-different one-sided derivatives; they are counted and must stay few.
+A pose with an atom within 1e-4 A of a lattice plane, or an intra pair within
+1e-4 A of the cutoff or of a term kink, sits where binary32 and binary64 may
+pick different one-sided derivatives (coordinates differ by ~1e-5 A): a
+gradient mismatch there is excused, counted, and must stay rare.  A mismatch
+anywhere else fails.
 """
 import numpy as np
 
-KINK = 1e-3
+KINK = 1e-4
 
 
 def e_tol(ref):

@@ -5,7 +5,7 @@ on degenerate ligands and poses, and through the autograd Function."""
 import numpy as np
 import pytest
 
-from gpu_util import cpu_dof, e_tol, g_tol, near_kink
+from gpu_util import KINK, cpu_dof, e_tol, g_tol, near_kink
 from paper_2506_20043_amd import synth as S
 
 pytestmark = pytest.mark.gpu
@@ -33,35 +33,35 @@ class Setup:
         return G.origin.astype(np.float64), G.origin + G.h * (G.dims - 1)
 
 
-def compare(st, lig, box, dof, out, idx, strict_frac=0.8):
-    """Compares GPU outputs at pose rows idx with the oracle; returns counts."""
+def compare(st, lig, box, dof, out, idx, max_excused=0.05):
+    """Compares GPU outputs at pose rows idx with the oracle; returns the
+    number of gradient mismatches excused by a nearby kink."""
     e = out["energy"].cpu().numpy()
     parts = out["e_parts"].cpu().numpy() if "e_parts" in out else None
     gd = out["grad_dof"].cpu().numpy()
     xyz = out["xyz"].cpu().numpy() if "xyz" in out else None
     gx = out["grad_xyz"].cpu().numpy() if "grad_xyz" in out else None
-    n_kink = 0
+    excused = 0
     for b in idx:
         L, G = st.ol[lig[b]], st.og[box[b]]
         r = L.score_grad(G, cpu_dof(dof[b, :L.ndof]))
-        kink = near_kink(r)
-        slack = 0.01 if r["min_cut"] < 1e-3 else 0.0
+        slack = 0.01 if r["min_cut"] < KINK else 0.0
         assert abs(e[b] - r["e"]) <= e_tol(r["e"]) + slack, (b, e[b], r["e"])
         if parts is not None:
             assert abs(parts[b, 0] - r["e_inter"]) <= e_tol(r["e_inter"]), (b, parts[b], r["e_inter"])
             assert abs(parts[b, 1] - r["e_intra"]) <= e_tol(r["e_intra"]) + slack, (b, parts[b], r["e_intra"])
         if xyz is not None:
             assert np.abs(xyz[b, :L.n_atoms] - r["xyz"]).max() <= 1e-4, b
-        if kink:
-            n_kink += 1
-            continue
-        gref = r["grad_dof"]
-        assert np.abs(gd[b, :L.ndof] - gref).max() <= g_tol(gref), (b, gd[b, :L.ndof], gref)
         assert np.all(gd[b, L.ndof:] == 0.0)
+        gref = r["grad_dof"]
+        ok = np.abs(gd[b, :L.ndof] - gref).max() <= g_tol(gref)
         if gx is not None:
-            assert np.abs(gx[b, :L.n_atoms] - r["grad_xyz"]).max() <= g_tol(r["grad_xyz"]), b
-    assert n_kink <= (1 - strict_frac) * len(idx), (n_kink, len(idx))
-    return n_kink
+            ok = ok and np.abs(gx[b, :L.n_atoms] - r["grad_xyz"]).max() <= g_tol(r["grad_xyz"])
+        if not ok:
+            assert near_kink(r), (b, gd[b, :L.ndof], gref)
+            excused += 1
+    assert excused <= max_excused * len(idx), (excused, len(idx))
+    return excused
 
 
 def test_tiny_config_poses(oracle, pv_ctx):
@@ -118,7 +118,7 @@ def test_degenerate_ligands(oracle, pv_ctx):
         nt = st.ol[lig[b]].n_tors
         dof[b, :7 + nt] = S.poses(g, 1, lo + 2, hi - 2, nt)[0]
     out = pv.score_grad(pv_ctx, st.grids, st.ligs, lig, np.zeros(B, np.int32), dof, parts=True, xyz=True)
-    compare(st, lig, np.zeros(B, np.int32), dof, out, range(B), strict_frac=0.6)
+    compare(st, lig, np.zeros(B, np.int32), dof, out, range(B), max_excused=0.2)
 
 
 def test_invalid_rows_and_empty_batch(oracle, pv_ctx):
@@ -160,17 +160,16 @@ def test_score_on_coordinates(oracle, pv_ctx):
     out = pv.score_grad_xyz(pv_ctx, st.grids, st.ligs, lig, np.zeros(B, np.int32), xyz, parts=True)
     e = out["energy"].cpu().numpy()
     gx = out["grad_xyz"].cpu().numpy()
-    kinks = 0
+    excused = 0
     for b in range(B):
         L = st.ol[lig[b]]
         r = L.score_xyz(st.og[0], xyz[b, :L.n_atoms].astype(np.float64))
-        slack = 0.01 if r["min_cut"] < 1e-3 else 0.0
+        slack = 0.01 if r["min_cut"] < KINK else 0.0
         assert abs(e[b] - r["e"]) <= e_tol(r["e"]) + slack
-        if near_kink(r):
-            kinks += 1
-            continue
-        assert np.abs(gx[b, :L.n_atoms] - r["grad_xyz"]).max() <= g_tol(r["grad_xyz"])
-    assert kinks < B // 4
+        if np.abs(gx[b, :L.n_atoms] - r["grad_xyz"]).max() > g_tol(r["grad_xyz"]):
+            assert near_kink(r), b
+            excused += 1
+    assert excused <= B // 10
 
 
 def test_autograd_backward(oracle, pv_ctx):
@@ -212,9 +211,13 @@ def test_autograd_backward(oracle, pv_ctx):
             xm[i] -= h
             fd[i] = (L.score_grad(st.og[0], xp)["e"] - L.score_grad(st.og[0], xm)["e"]) / (2 * h)
         # a difference quotient may straddle a cell face; skip those rows
-        if np.abs(fd - r["grad_dof"]).max() > 1e-3 * (1 + np.abs(r["grad_dof"]).max()):
+        fd_tol = 1e-3 * (1 + np.abs(r["grad_dof"]).max())
+        if np.abs(fd - r["grad_dof"]).max() > fd_tol:
             continue
-        assert np.abs(plain[b] - fd).max() <= 2e-3 + 1e-4 * np.abs(fd).max(), b
+        # against the quotient at its own accuracy (its truncation error is
+        # O(h^2)), and against the oracle's analytic gradient at parity
+        assert np.abs(plain[b] - fd).max() <= 2 * fd_tol, b
+        assert np.abs(plain[b] - r["grad_dof"]).max() <= g_tol(r["grad_dof"]), b
         checked += 1
     assert checked >= B // 2
     # coordinates form
