@@ -1,0 +1,229 @@
+#!/usr/bin/env python
+"""Benchmark of the docking hot path on one MI355X.
+
+One step = one pass of the whole hot path over the multi-pocket workload:
+grid maps of 5 pockets rebuilt (the grid-map kernel), then Monte Carlo +
+RILC-BFGS docking of one 35-atom, 8-torsion ligand into every pocket, 256
+chains x 1,000 MC steps each, as one persistent hipGraph-replayed launch.
+Inputs are seeded and synthetic and stay resident in HBM.
+
+Prints one JSON line: docks/s (value), score+grad evaluations/s, the plain
+per-job launch path, the roofline of the dominant kernel (measured with HIP
+events on the stream the kernels run on) and the oracle timed on the host.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_VECTOR = 157.3e12   # MI355X vector FP32, FLOP/s
+PEAK_HBM = 8.0e12             # MI355X HBM3E, B/s
+
+# Algorithmic work of one score + gradient evaluation, counted from the
+# operations the method needs ("Roofline"): per intra pair
+# tested (difference, squared distance), per pair inside the cutoff (terms,
+# derivative, force on both atoms), per atom (frame transform, trilinear
+# value and gradient, force/torque accumulation), per torsion (local
+# rotation, frame composition, torsion derivative), per evaluation (root
+# frame) and BFGS vector work per evaluation.
+FLOP_PAIR_TEST = 8
+FLOP_PAIR_IN = 36
+FLOP_ATOM = 91
+FLOP_TORS = 141
+FLOP_EVAL = 50
+
+
+def flops_per_launch(n_evals, pairs_in, n_atoms, n_tors, n_pairs, m=5):
+    per_eval = FLOP_PAIR_TEST * n_pairs + FLOP_ATOM * n_atoms + FLOP_TORS * n_tors + FLOP_EVAL
+    per_eval += (4 * m + 10) * (6 + n_tors)
+    return float(n_evals) * per_eval + float(pairs_in) * FLOP_PAIR_IN
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--chains", type=int, default=256)
+    ap.add_argument("--mc-steps", type=int, default=1000)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-score", action="store_true")
+    ap.add_argument("--cpu-chains", type=int, default=128)
+    ap.add_argument("--workgroups", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
+              "(the work shards by pocket across GPUs, see DESIGN.md)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2506_20043_amd as pv
+    from paper_2506_20043_amd import synth as S
+
+    cfg = S.CONFIGS["c2"]
+    rx, rt, bxs = S.make_receptor(cfg)
+    mols = S.make_ligands(cfg)
+    seed = S.philox_seed(cfg)
+    ctx = pv.Context(0)
+    stream = torch.cuda.current_stream()
+    grids = pv.build_grids(ctx, rx, rt, bxs, penalty_slope=10.0)
+    ligs = pv.Ligands(ctx, mols)
+    n_atoms, n_frag, n_tors, n_pairs = ligs.info(0)[:4]
+    jobs = [(0, b) for b in range(len(bxs))]
+    params = pv.dock_params(chains=args.chains, steps=args.mc_steps, seed=seed,
+                            flags=pv.PV_DOCK_GRAPH, workgroups=args.workgroups)
+    plan = pv.Plan(ctx, grids, ligs, jobs, params)
+    torch.cuda.synchronize()
+
+    def step():
+        grids.rebuild()
+        plan.run()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        grids.rebuild()
+        ev[k][1].record(stream)
+        plan.run()
+        ev[k][2].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    out = plan.outputs()
+    n_evals = int(out["job_evals"].sum().item())
+    pairs_in = int(out["chain_pairs"].sum().item())
+    grid_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+    dock_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+    ms_per_step = wall * 1e3 / args.steps
+    docks = len(jobs) * args.steps
+    docks_per_s = docks / wall
+    evals_per_s = n_evals * args.steps / wall
+    flops = flops_per_launch(n_evals, pairs_in, n_atoms, n_tors, n_pairs)
+    achieved = flops / (dock_ms * 1e-3)
+    result = {
+        "metric": "ligand-pocket docks/s and score+grad evals/s, batched vs plain on 1 MI355X",
+        "value": docks_per_s,
+        "unit": "docks/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded receptor, pockets and ligand; no datasets)",
+        "config": {
+            "workload": "multi-pocket single ligand: 5,000-atom receptor in a 50 A cube, 5 pockets of 24 A "
+                        "at 0.375 A (65^3 x 8 FP32 maps each), one %d-atom ligand with %d torsions "
+                        "(%d intra pairs), %d chains x %d MC steps per pocket, BFGS <= 30 iterations; "
+                        "step = grid-map rebuild + batched persistent dock (hipGraph)"
+                        % (n_atoms, n_tors, n_pairs, args.chains, args.mc_steps),
+            "jobs": len(jobs), "chains": args.chains, "mc_steps": args.mc_steps,
+            "parallelism": "single GPU",
+        },
+        "evals_per_s": evals_per_s,
+        "evals_per_step": n_evals,
+        "grid_ms": grid_ms,
+        "dock_ms": dock_ms,
+        "workgroups": plan_workgroups(plan),
+    }
+    # plain path: one launch per job, same kernel and draws
+    if not args.no_plain:
+        plan.run(plain=True)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        plan.run(plain=True)
+        b.record(stream)
+        torch.cuda.synchronize()
+        plain_ms = a.elapsed_time(b)
+        result["plain"] = {"docks_per_s": len(jobs) / (plain_ms * 1e-3),
+                           "evals_per_s": n_evals / (plain_ms * 1e-3), "dock_ms": plain_ms}
+        result["batched_over_plain"] = plain_ms / dock_ms
+    result["roofline"] = {
+        "bound": "alu",
+        "kernel": "dock_kernel (persistent MC + BFGS)",
+        "achieved": achieved / 1e12,
+        "peak": PEAK_FP32_VECTOR / 1e12,
+        "unit": "TFLOP/s",
+        "frac": achieved / PEAK_FP32_VECTOR,
+        "traffic": None,
+        "flops_per_launch": flops,
+        "launch_ms": dock_ms,
+    }
+    if not args.no_score:
+        result["score_grad"] = bench_score(pv, S, ctx, stream)
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(S, cfg, rx, rt, bxs, mols, seed, args)
+    print(json.dumps(result), flush=True)
+
+
+def plan_workgroups(plan):
+    return int(plan.params.workgroups) if plan.params.workgroups else None
+
+
+def bench_score(pv, S, ctx, stream):
+    """score+grad of the differentiation workload: 16,384 poses of 64
+    ligands (40 atoms, 10 torsions) in one 24 A pocket, timed over 20 calls."""
+    import torch
+    cfg = S.CONFIGS["c4"]
+    rx, rt, bxs = S.make_receptor(cfg)
+    mols = S.make_ligands(cfg)
+    grids = pv.build_grids(ctx, rx, rt, bxs[:1], penalty_slope=10.0)
+    ligs = pv.Ligands(ctx, mols)
+    dims, org = grids.info(0)
+    lo, hi = org.astype(np.float64), org + 0.375 * (dims - 1)
+    dof = torch.tensor(S.poses(S.rng(cfg.index, S.STREAM_POSES), cfg.n_poses, lo, hi, 10), device="cuda")
+    lig = torch.tensor(np.repeat(np.arange(64, dtype=np.int32), 256), device="cuda")
+    box = torch.zeros(cfg.n_poses, dtype=torch.int32, device="cuda")
+    for _ in range(3):
+        pv.score_grad(ctx, grids, ligs, lig, box, dof)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    a.record(stream)
+    for _ in range(reps):
+        pv.score_grad(ctx, grids, ligs, lig, box, dof)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    return {"workload": "16,384 poses, 64 ligands of 40 atoms / 10 torsions, one 24 A pocket",
+            "ms_per_call": ms, "evals_per_s": cfg.n_poses / (ms * 1e-3)}
+
+
+def cpu_baseline(S, cfg, rx, rt, bxs, mols, seed, args):
+    """The FP64 oracle on the host: a bounded sample of the same dock (the
+    first --cpu-chains chains of pocket 0, all MC steps), scaled to docks/s."""
+    import oracle as O
+    b = bxs[0]
+    G = O.Grid.build(rx, rt, b.center.astype(np.float64), b.size.astype(np.float64), b.spacing, kappa=10.0)
+    m = mols[0]
+    L = O.Ligand(m.xyz, m.types, m.bonds, m.rotatable)
+    P = O.mc_params(args.cpu_chains, args.mc_steps, seed)
+    threads = len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    res = O.dock([L], [G], [(0, 0)], P, n_threads=threads)
+    dt = time.perf_counter() - t0
+    evals = int(res["chain_evals"].sum())
+    frac = args.cpu_chains / args.chains
+    return {"value": frac / dt, "unit": "docks/s", "cores": threads, "kind": "oracle",
+            "sample": "pocket 0, %d of %d chains x %d MC steps (%.3f of one dock), %.1f s wall"
+                      % (args.cpu_chains, args.chains, args.mc_steps, frac, dt),
+            "evals_per_s": evals / dt}
+
+
+if __name__ == "__main__":
+    main()

@@ -92,6 +92,9 @@ pv_status pv_build_grids(pv_ctx* ctx, int32_t n_rec, const float* rec_xyz, const
 /* dims, origin and the device address of the 8 maps of one box */
 pv_status pv_grids_info(const pv_grids* g, int32_t box, int32_t dims[3], float origin[3],
                         const float** dev_maps);
+/* recomputes every map from the receptor the handle was built with (the
+ * same kernel as pv_build_grids, no allocation), ordered on `stream` */
+pv_status pv_grids_rebuild(pv_grids* g, void* stream);
 /* copies the 8 maps of one box ([8][nz][ny][nx] binary32) into the caller's
  * device buffer `dst`, ordered on `stream` */
 pv_status pv_grids_copy(const pv_grids* g, int32_t box, float* dst, void* stream);

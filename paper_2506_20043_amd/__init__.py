@@ -72,6 +72,7 @@ SIGNATURES = {
     "pv_build_grids": (C.c_int, [_vp, _i32, _vp, _vp, C.POINTER(Box), _i32, C.c_float, _vp, C.POINTER(_vp)]),
     "pv_grids_info": (C.c_int, [_vp, _i32, _ip, C.POINTER(C.c_float), C.POINTER(_vp)]),
     "pv_grids_copy": (C.c_int, [_vp, _i32, _vp, _vp]),
+    "pv_grids_rebuild": (C.c_int, [_vp, _vp]),
     "pv_grids_free": (None, [_vp]),
     "pv_ligands_create": (C.c_int, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(_vp)]),
     "pv_ligands_info": (C.c_int, [_vp, _i32, _ip]),
@@ -222,6 +223,10 @@ class Grids:
                           device=self.ctx.torch_device)
         _check(lib().pv_grids_copy(self.h, int(box), _ptr(out), _stream(stream)), "pv_grids_copy")
         return out
+
+    def rebuild(self, stream=None):
+        """Recompute every map in place (same kernel, no allocation)."""
+        _check(lib().pv_grids_rebuild(self.h, _stream(stream)), "pv_grids_rebuild")
 
     def close(self):
         if self.h:

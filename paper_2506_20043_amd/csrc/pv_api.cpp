@@ -75,6 +75,7 @@ struct pv_grids {
     float4* atoms;
     int32_t* atom_off;
     int32_t* tile_off;
+    int64_t n_tiles;
     std::vector<int32_t> h_dims;
     std::vector<float> h_geom;
     std::vector<int64_t> h_off;
@@ -90,6 +91,8 @@ struct pv_ligands {
     DevFrag* frags;
     int8_t* tors_frag;
     uint32_t* pairs;
+    uint32_t* ell;
+    int32_t max_ell;
     std::vector<std::array<int32_t, 8>>* info;
 };
 
@@ -143,6 +146,8 @@ LigDev lig_view(const pv_ligands* l)
     v.frags = l->frags;
     v.tors_frag = l->tors_frag;
     v.pairs = l->pairs;
+    v.ell = l->ell;
+    v.max_ell = l->max_ell;
     v.n_lig = l->n_lig;
     v.max_atoms = l->max_atoms;
     v.max_pairs = l->max_pairs;
@@ -169,6 +174,7 @@ pv_status pv_create(int32_t device, pv_ctx** out)
     HIP_TRY(hipSetDevice(device), "hipSetDevice");
     hipDeviceProp_t prop;
     HIP_TRY(hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties");
+    HIP_TRY(init_device_tables(device), "constant tables");
     pv_ctx* c = new (std::nothrow) pv_ctx;
     if (!c) return fail(PV_E_NOMEM, "host allocation");
     c->device = device;
@@ -303,12 +309,31 @@ pv_status pv_build_grids(pv_ctx* ctx, int32_t n_rec, const float* rec_xyz, const
     a.geom = g->geom;
     a.tile_off = g->tile_off;
     a.n_boxes = n_boxes;
+    g->n_tiles = tiles;
     hipError_t e = launch_build_grids(a, tiles, (hipStream_t)stream);
     if (e != hipSuccess) {
         pv_grids_free(g);
         return hip_fail(e, "grid-map launch");
     }
     *out = g;
+    return PV_OK;
+}
+
+pv_status pv_grids_rebuild(pv_grids* g, void* stream)
+{
+    if (!g) return fail(PV_E_INVALID, "grids is NULL");
+    pv_status st = set_device(g->ctx);
+    if (st != PV_OK) return st;
+    GridBuildArgs a;
+    a.atoms = g->atoms;
+    a.atom_off = g->atom_off;
+    a.maps = g->maps;
+    a.map_off = g->map_off;
+    a.dims = g->dims;
+    a.geom = g->geom;
+    a.tile_off = g->tile_off;
+    a.n_boxes = g->n_boxes;
+    HIP_TRY(launch_build_grids(a, g->n_tiles, (hipStream_t)stream), "grid-map launch");
     return PV_OK;
 }
 
@@ -363,9 +388,10 @@ pv_status pv_ligands_create(pv_ctx* ctx, int32_t n_lig, const int32_t* atom_off,
     std::vector<DevFrag> frags;
     std::vector<int8_t> tors_frag;
     std::vector<uint32_t> pairs;
+    std::vector<uint32_t> ell;
     auto* info = new (std::nothrow) std::vector<std::array<int32_t, 8>>(n_lig);
     if (!info) return fail(PV_E_NOMEM, "host allocation");
-    int max_atoms = 0, max_pairs = 0, max_tors = 0;
+    int max_atoms = 0, max_pairs = 0, max_tors = 0, max_ell = 0;
     for (int32_t i = 0; i < n_lig; ++i) {
         const int32_t a0 = atom_off[i], a1 = atom_off[i + 1], b0 = bond_off[i], b1 = bond_off[i + 1];
         if (a1 < a0 || b1 < b0) { delete info; return fail(PV_E_INVALID, "offsets must not decrease"); }
@@ -386,6 +412,8 @@ pv_status pv_ligands_create(pv_ctx* ctx, int32_t n_lig, const int32_t* atom_off,
         D.tors_base = (int32_t)tors_frag.size();
         D.n_tors = M.nt;
         D.rounds = M.rounds;
+        D.ell_base = (int32_t)ell.size();
+        D.ell_w = M.ell_w;
         for (int a = 0; a < 3; ++a) D.anchor[a] = M.anchor[a];
         D.rot_amp_scale = (float)(1.0 / std::max((double)M.rg, 1e-3));
         atoms.insert(atoms.end(), M.ref.begin(), M.ref.end());
@@ -393,6 +421,8 @@ pv_status pv_ligands_create(pv_ctx* ctx, int32_t n_lig, const int32_t* atom_off,
         frags.insert(frags.end(), M.frags.begin(), M.frags.end());
         for (int v : M.tors_frag) tors_frag.push_back((int8_t)v);
         pairs.insert(pairs.end(), M.pairs.begin(), M.pairs.end());
+        ell.insert(ell.end(), M.ell.begin(), M.ell.end());
+        max_ell = std::max(max_ell, M.ell_w * M.n);
         (*info)[i] = {M.n, M.nf, M.nt, M.np, M.root_size, M.depth, 7 + M.nt, 0};
         max_atoms = std::max(max_atoms, M.n);
         max_pairs = std::max(max_pairs, M.np);
@@ -407,13 +437,15 @@ pv_status pv_ligands_create(pv_ctx* ctx, int32_t n_lig, const int32_t* atom_off,
     L->max_atoms = max_atoms;
     L->max_pairs = max_pairs;
     L->max_tors = max_tors;
+    L->max_ell = max_ell;
     L->info = info;
     if ((st = upload(&L->ligs, H.data(), H.size(), "ligand upload")) != PV_OK ||
         (st = upload(&L->atoms, (const float4*)atoms.data(), atoms.size() / 4, "ligand upload")) != PV_OK ||
         (st = upload(&L->perm, perm.data(), perm.size(), "ligand upload")) != PV_OK ||
         (st = upload(&L->frags, frags.data(), frags.size(), "ligand upload")) != PV_OK ||
         (st = upload(&L->tors_frag, tors_frag.data(), tors_frag.size(), "ligand upload")) != PV_OK ||
-        (st = upload(&L->pairs, pairs.data(), pairs.size(), "ligand upload")) != PV_OK) {
+        (st = upload(&L->pairs, pairs.data(), pairs.size(), "ligand upload")) != PV_OK ||
+        (st = upload(&L->ell, ell.data(), ell.size(), "ligand upload")) != PV_OK) {
         pv_ligands_free(L);
         return st;
     }
@@ -465,6 +497,7 @@ void pv_ligands_free(pv_ligands* l)
     if (!l) return;
     if (ctx_ok(l->ctx)) (void)hipSetDevice(l->ctx->device);
     dfree(l->ligs); dfree(l->atoms); dfree(l->perm); dfree(l->frags); dfree(l->tors_frag); dfree(l->pairs);
+    dfree(l->ell);
     delete l->info;
     delete l;
 }
@@ -639,7 +672,7 @@ pv_status pv_dock_plan(pv_ctx* ctx, const pv_grids* grids, const pv_ligands* lig
         return st;
     }
     int per_cu = 0;
-    hipError_t e = dock_occupancy(ligs->max_atoms, ligs->max_pairs, &per_cu);
+    hipError_t e = dock_occupancy(ligs->max_atoms, ligs->max_pairs, ligs->max_ell, &per_cu);
     if (e != hipSuccess || per_cu < 1) per_cu = 1;
     int64_t wg = params->workgroups > 0 ? params->workgroups : (int64_t)per_cu * ctx->n_cu;
     wg = std::min<int64_t>(wg, std::max<int64_t>((int64_t)nchain, 1));

@@ -23,7 +23,9 @@ struct alignas(16) DevLig {
     int32_t atom_base, n_atoms, frag_base, n_frag;
     int32_t pair_base, n_pairs, tors_base, n_tors;
     int32_t rounds;      // pointer-doubling rounds to compose the frame tree
-    int32_t pad0, pad1, pad2;
+    int32_t ell_base;    // first word of the atom -> pair table
+    int32_t ell_w;       // entries per atom row (the largest row)
+    int32_t pad0;
     float anchor[3];     // reference centroid of the root fragment
     float rot_amp_scale; // 1 / max(R_g, 1e-3)
 };
@@ -42,6 +44,10 @@ struct alignas(16) DevFrag {
 
 // Intra pair packed as i | j << 8 | type_pair << 16 (new atom order).
 // Atom record: x, y, z and w = bits(type | fragment << 8).
+// Atom -> pair table (ELL, [ell_w][n] words): entry k of atom i is
+// p | j << 16, the k-th pair p (index into the pair list) that holds atom i
+// and its partner j; rows shorter than ell_w are padded with p = n_pairs
+// (a zero coefficient) and j = i.
 
 // Host model of one ligand (built by build_ligand_model).
 struct LigModel {
@@ -51,6 +57,8 @@ struct LigModel {
     std::vector<DevFrag> frags;     // preorder
     std::vector<int> tors_frag;     // torsion k -> fragment
     std::vector<uint32_t> pairs;    // packed, lane-interleaved order
+    std::vector<uint32_t> ell;      // [ell_w][n]
+    int ell_w = 0;
     float anchor[3] = {0, 0, 0};
     float rg = 0.f;
 };
@@ -79,8 +87,10 @@ struct LigDev {
     const DevFrag* frags;
     const int8_t* tors_frag;
     const uint32_t* pairs;
+    const uint32_t* ell;
     int32_t n_lig;
     int32_t max_atoms, max_pairs, max_tors;
+    int32_t max_ell;   // largest ell_w * n_atoms
 };
 
 struct ScoreArgs {
@@ -162,8 +172,9 @@ hipError_t launch_job_reduce(const float* chain_best_e, const int64_t* chain_eva
                              int32_t* job_status, hipStream_t s);
 hipError_t launch_local_opt(const OptArgs& a, hipStream_t s);
 hipError_t launch_reset_times(uint64_t* t0, uint64_t* t1, int n, hipStream_t s);
-hipError_t dock_occupancy(int max_atoms, int max_pairs, int* blocks_per_cu);
-int dock_lds_bytes(int max_atoms, int max_pairs);
+hipError_t dock_occupancy(int max_atoms, int max_pairs, int max_ell, int* blocks_per_cu);
+int dock_lds_bytes(int max_atoms, int max_pairs, int max_ell);
+hipError_t init_device_tables(int device);
 
 // Tiles of the grid-map kernel.
 constexpr int kTileX = 8, kTileY = 8, kTileZ = 4;

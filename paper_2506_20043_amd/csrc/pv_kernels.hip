@@ -28,14 +28,56 @@ constexpr float kCut2 = 64.0f;
 constexpr float kPi = 3.14159265358979323846f;
 
 // ---------------------------------------------------------------- wave helpers
+// Cross-lane sums use DPP row permutations inside each 16-lane row and
+// readlane across rows: a few VALU cycles instead of LDS round trips, and
+// every lane ends with bit-identical results (the control flow that depends
+// on them stays uniform).
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ float dpp0(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
+}
+
+__device__ __forceinline__ float lane_f(float v, int lane)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+__device__ __forceinline__ int lane_i(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
+
+// sum over the 64 lanes, identical in every lane
 __device__ __forceinline__ float wsum(float v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    v += dpp0<0xB1>(v);   // quad_perm(1,0,3,2): lane ^ 1
+    v += dpp0<0x4E>(v);   // quad_perm(2,3,0,1): lane ^ 2
+    v += dpp0<0x141>(v);  // row_half_mirror: the other quad of each 8 lanes
+    v += dpp0<0x140>(v);  // row_mirror: the other half of each row
+    return (lane_f(v, 0) + lane_f(v, 16)) + (lane_f(v, 32) + lane_f(v, 48));
+}
+
+// inclusive prefix sum over the 64 lanes in lane order
+__device__ __forceinline__ float wscan(float v)
+{
+    v += dpp0<0x111>(v);        // row_shr:1
+    v += dpp0<0x112>(v);        // row_shr:2
+    v += dpp0<0x114>(v);        // row_shr:4
+    v += dpp0<0x118>(v);        // row_shr:8
+    v += dpp0<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+    v += dpp0<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
     return v;
 }
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x; }
+
+// Synchronisation of a one-wave workgroup.  The LDS executes the requests of
+// one wave in order, so ordering the compiler is enough: no wait for
+// outstanding global loads (which may stay in flight across it).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 
 // ---------------------------------------------------------------- Philox4x64-10
 __device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1)
@@ -75,11 +117,11 @@ __device__ __forceinline__ void quat_mul(const float a[4], const float b[4], flo
 
 __device__ __forceinline__ void rotvec_quat(float tx, float ty, float tz, float q[4])
 {
-    float a = sqrtf(tx * tx + ty * ty + tz * tz);
-    if (a == 0.0f) { q[0] = 1.f; q[1] = q[2] = q[3] = 0.f; return; }
+    // (cos(a/2), sin(a/2)/a * theta); sin(a/2)/a -> 1/2 as a -> 0
+    const float a = sqrtf(tx * tx + ty * ty + tz * tz);
     float s, c;
     sincosf(0.5f * a, &s, &c);
-    float k = s / a;
+    const float k = a > 0.f ? s / a : 0.5f;
     q[0] = c; q[1] = k * tx; q[2] = k * ty; q[3] = k * tz;
 }
 
@@ -127,24 +169,37 @@ __device__ __forceinline__ void axis_setup(float x, float o, float inv_h, float 
     u = f - (float)c;
 }
 
-// trilinear value + gradient of map `t` at x, plus the penalty
-__device__ __forceinline__ float trilinear(const BoxView& B, int t, float x, float y, float z, float& gx,
-                                           float& gy, float& gz)
+// Trilinear lookup in two halves: tri_issue computes the cell and starts the
+// 8 corner loads; tri_finish interpolates (value, gradient, penalty) once
+// they are needed, so other work can hide the memory latency in between.
+struct TriLoad {
+    float m[8];
+    float ux, uy, uz, pen, dx, dy, dz;
+    bool cx, cy, cz;
+};
+
+__device__ __forceinline__ void tri_issue(const BoxView& B, int t, float x, float y, float z, TriLoad& L)
 {
     int ix, iy, iz;
-    float ux, uy, uz, px, py, pz, dx, dy, dz;
-    bool cx, cy, cz;
-    axis_setup(x, B.ox, B.inv_h, B.ex, B.nx, B.kappa, ix, ux, px, dx, cx);
-    axis_setup(y, B.oy, B.inv_h, B.ey, B.ny, B.kappa, iy, uy, py, dy, cy);
-    axis_setup(z, B.oz, B.inv_h, B.ez, B.nz, B.kappa, iz, uz, pz, dz, cz);
+    float px, py, pz;
+    axis_setup(x, B.ox, B.inv_h, B.ex, B.nx, B.kappa, ix, L.ux, px, L.dx, L.cx);
+    axis_setup(y, B.oy, B.inv_h, B.ey, B.ny, B.kappa, iy, L.uy, py, L.dy, L.cy);
+    axis_setup(z, B.oz, B.inv_h, B.ez, B.nz, B.kappa, iz, L.uz, pz, L.dz, L.cz);
+    L.pen = px + py + pz;
     const float* m = B.maps + (int64_t)t * B.msz + ((int64_t)iz * B.ny + iy) * B.nx + ix;
     const int sy = B.nx;
     const int64_t sz = (int64_t)B.nx * B.ny;
-    float m000 = m[0], m100 = m[1];
-    float m010 = m[sy], m110 = m[sy + 1];
-    float m001 = m[sz], m101 = m[sz + 1];
-    float m011 = m[sz + sy], m111 = m[sz + sy + 1];
-    // along x
+    L.m[0] = m[0]; L.m[1] = m[1];
+    L.m[2] = m[sy]; L.m[3] = m[sy + 1];
+    L.m[4] = m[sz]; L.m[5] = m[sz + 1];
+    L.m[6] = m[sz + sy]; L.m[7] = m[sz + sy + 1];
+}
+
+__device__ __forceinline__ float tri_finish(const BoxView& B, const TriLoad& L, float& gx, float& gy, float& gz)
+{
+    const float m000 = L.m[0], m100 = L.m[1], m010 = L.m[2], m110 = L.m[3];
+    const float m001 = L.m[4], m101 = L.m[5], m011 = L.m[6], m111 = L.m[7];
+    const float ux = L.ux, uy = L.uy, uz = L.uz;
     float a00 = m000 + ux * (m100 - m000), a10 = m010 + ux * (m110 - m010);
     float a01 = m001 + ux * (m101 - m001), a11 = m011 + ux * (m111 - m011);
     float b0 = a00 + uy * (a10 - a00), b1 = a01 + uy * (a11 - a01);
@@ -155,10 +210,19 @@ __device__ __forceinline__ float trilinear(const BoxView& B, int t, float x, flo
     float dvx = e0 + uz * (e1 - e0);
     float dvy = (a10 - a00) + uz * ((a11 - a01) - (a10 - a00));
     float dvz = b1 - b0;
-    gx = (cx ? 0.f : dvx * B.inv_h) + dx;
-    gy = (cy ? 0.f : dvy * B.inv_h) + dy;
-    gz = (cz ? 0.f : dvz * B.inv_h) + dz;
-    return v + px + py + pz;
+    gx = (L.cx ? 0.f : dvx * B.inv_h) + L.dx;
+    gy = (L.cy ? 0.f : dvy * B.inv_h) + L.dy;
+    gz = (L.cz ? 0.f : dvz * B.inv_h) + L.dz;
+    return v + L.pen;
+}
+
+// trilinear value + gradient of map `t` at x, plus the penalty
+__device__ __forceinline__ float trilinear(const BoxView& B, int t, float x, float y, float z, float& gx,
+                                           float& gy, float& gz)
+{
+    TriLoad L;
+    tri_issue(B, t, x, y, z, L);
+    return tri_finish(B, L, gx, gy, gz);
 }
 
 // ---------------------------------------------------------------- LDS carving
@@ -169,24 +233,33 @@ enum { SLOT_X = 0, SLOT_XT = 1, SLOT_XA = 2, SLOT_CUR = 3, SLOT_BEST = 4, kNSlot
 struct Lds {
     float2* tp;        // [64] (Rsum, flags-as-bits)
     float* pose;       // [kNSlots][kSlot]
-    float* frame;      // [kMaxFrag][12]
+    float* frame;      // [kMaxFrag][12] frames, then [kMaxFrag] ancestor links
     float4* pos;       // [max_atoms]
     float4* frc;       // [max_atoms]
     float* pre;        // [6][max_atoms]
     uint32_t* pairs;   // [max_pairs]
+    float* cp;         // [max_pairs + 1] per-pair force coefficient (last = 0)
+    uint32_t* ell;     // [max_ell] atom -> pair table of the staged ligand
     int ma;
 };
 
 __host__ __device__ inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
-__host__ __device__ inline int lds_bytes(int max_atoms, int max_pairs)
+// Ligands of at most 64 atoms (one atom per lane) stage their pair list and
+// atom -> pair table in LDS; larger ones read both from global memory
+// (coalesced, L1/L2 resident) and keep only the per-pair coefficients here.
+__host__ __device__ inline bool tables_in_lds(int max_atoms) { return max_atoms <= 64; }
+
+__host__ __device__ inline int lds_bytes(int max_atoms, int max_pairs, int max_ell)
 {
     int ma = round_up(max_atoms < 1 ? 1 : max_atoms, 64);
-    return 64 * 8 + kNSlots * kSlot * 4 + kMaxFrag * 12 * 4 + ma * 16 * 2 + 6 * ma * 4 +
-           round_up(max_pairs, 4) * 4;
+    int b = 64 * 8 + kNSlots * kSlot * 4 + kMaxFrag * 13 * 4 + 12 + ma * 16 * 2 + 6 * ma * 4 +
+            round_up(max_pairs + 1, 4) * 4;
+    if (tables_in_lds(max_atoms)) b += round_up(max_pairs, 4) * 4 + round_up(max_ell, 4) * 4;
+    return b;
 }
 
-__device__ __forceinline__ Lds carve(char* base, int max_atoms, int max_pairs)
+__device__ __forceinline__ Lds carve(char* base, int max_atoms, int max_pairs, int max_ell)
 {
     Lds s;
     int ma = round_up(max_atoms < 1 ? 1 : max_atoms, 64);
@@ -195,10 +268,13 @@ __device__ __forceinline__ Lds carve(char* base, int max_atoms, int max_pairs)
     s.pos = (float4*)p; p += ma * 16;
     s.frc = (float4*)p; p += ma * 16;
     s.pose = (float*)p; p += kNSlots * kSlot * 4;
-    s.frame = (float*)p; p += kMaxFrag * 12 * 4;
+    s.frame = (float*)p; p += kMaxFrag * 13 * 4 + 12;
     s.pre = (float*)p; p += 6 * ma * 4;
-    s.pairs = (uint32_t*)p;
+    s.cp = (float*)p; p += round_up(max_pairs + 1, 4) * 4;
+    s.pairs = (uint32_t*)p; p += round_up(max_pairs, 4) * 4;
+    s.ell = (uint32_t*)p;
     s.ma = ma;
+    (void)max_ell;
     return s;
 }
 
@@ -213,12 +289,14 @@ __device__ __forceinline__ void stage_tp(const Lds& S, const float* rsum, const 
 // fragments one per lane, and for lane 6+k the fragment of torsion k.
 template <int A>
 struct Topo {
-    int n, nf, nt, np, rounds, lig;
+    int n, nf, nt, np, rounds, lig, ell_w;
     float anc_x, anc_y, anc_z, rot_scale;
     float4 ref[A];
     int f_parent, f_tors, f_child, f_a0, f_end;
     float ax, ay, az, cx, cy, cz;
     int dof_frag;
+    const uint32_t* gpairs;   // pair list and atom -> pair table in global
+    const uint32_t* gell;     // memory (read from there when A > 1)
 };
 
 template <int A>
@@ -228,6 +306,7 @@ __device__ void stage_ligand(Topo<A>& T, const LigDev& L, int lig, const Lds& S)
     const DevLig d = L.ligs[lig];
     T.lig = lig;
     T.n = d.n_atoms; T.nf = d.n_frag; T.nt = d.n_tors; T.np = d.n_pairs; T.rounds = d.rounds;
+    T.ell_w = d.ell_w;
     T.anc_x = d.anchor[0]; T.anc_y = d.anchor[1]; T.anc_z = d.anchor[2]; T.rot_scale = d.rot_amp_scale;
 #pragma unroll
     for (int a = 0; a < A; ++a) {
@@ -244,8 +323,15 @@ __device__ void stage_ligand(Topo<A>& T, const LigDev& L, int lig, const Lds& S)
         T.ax = T.ay = T.az = T.cx = T.cy = T.cz = 0.f;
     }
     T.dof_frag = (l >= 6 && l < 6 + T.nt) ? (int)L.tors_frag[d.tors_base + l - 6] : 0;
-    for (int p = l; p < T.np; p += kWave) S.pairs[p] = L.pairs[d.pair_base + p];
-    __syncthreads();
+    T.gpairs = L.pairs + d.pair_base;
+    T.gell = L.ell + d.ell_base;
+    if (A == 1) {
+        for (int p = l; p < T.np; p += kWave) S.pairs[p] = T.gpairs[p];
+        const int ne = T.ell_w * T.n;
+        for (int k = l; k < ne; k += kWave) S.ell[k] = T.gell[k];
+    }
+    if (l == 0) S.cp[T.np] = 0.f;
+    wave_sync();
 }
 
 // ---------------------------------------------------------------- evaluation
@@ -260,7 +346,7 @@ struct Eval {
 // about its torsion axis) and composes with its ancestors by pointer
 // doubling; after `rounds` rounds every frame is world-absolute.
 template <int A>
-__device__ __forceinline__ void frames(const Topo<A>& T, const float* pose, float R[9], float b[3])
+__device__ __forceinline__ void frames(const Topo<A>& T, const Lds& S, const float* pose, float R[9], float b[3])
 {
     const int l = lane_id();
     const float tx = pose[0], ty = pose[1], tz = pose[2];
@@ -277,7 +363,7 @@ __device__ __forceinline__ void frames(const Topo<A>& T, const float* pose, floa
         b[2] = tz - (R[6] * T.anc_x + R[7] * T.anc_y + R[8] * T.anc_z);
     } else if (l < T.nf) {
         float s, c;
-        sincosf(pose[7 + T.f_tors], &s, &c);
+        __sincosf(pose[7 + T.f_tors], &s, &c);
         float t = 1.f - c, ux = T.ax, uy = T.ay, uz = T.az;
         R[0] = c + t * ux * ux;      R[1] = t * ux * uy - s * uz; R[2] = t * ux * uz + s * uy;
         R[3] = t * uy * ux + s * uz; R[4] = c + t * uy * uy;      R[5] = t * uy * uz - s * ux;
@@ -289,15 +375,24 @@ __device__ __forceinline__ void frames(const Topo<A>& T, const float* pose, floa
     } else {
         R[0] = R[4] = R[8] = 1.f; R[1] = R[2] = R[3] = R[5] = R[6] = R[7] = 0.f; b[0] = b[1] = b[2] = 0.f;
     }
+    // pointer doubling through LDS: every round each fragment reads the
+    // partial frame and ancestor link of its current ancestor
+    float* fr = S.frame + 12 * l;
+    int* lk = (int*)(S.frame + 12 * kMaxFrag);
     for (int r = 0; r < T.rounds; ++r) {
-        const int src = anc < 0 ? l : anc;
-        float P[9], pb[3];
+        if (l < T.nf) {
 #pragma unroll
-        for (int k = 0; k < 9; ++k) P[k] = __shfl(R[k], src);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) pb[k] = __shfl(b[k], src);
-        const int panc = __shfl(anc, src);
+            for (int k = 0; k < 9; ++k) fr[k] = R[k];
+            fr[9] = b[0]; fr[10] = b[1]; fr[11] = b[2];
+            lk[l] = anc;
+        }
+        wave_sync();
         if (anc >= 0) {
+            const float4* pf = (const float4*)(S.frame + 12 * anc);
+            const float4 q0 = pf[0], q1 = pf[1], q2 = pf[2];
+            const float P[9] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, q2.x};
+            const float pb[3] = {q2.y, q2.z, q2.w};
+            const int panc = lk[anc];
             float N[9], nb[3];
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
@@ -312,49 +407,94 @@ __device__ __forceinline__ void frames(const Topo<A>& T, const float* pose, floa
             for (int k = 0; k < 3; ++k) b[k] = nb[k];
             anc = panc;
         }
+        wave_sync();
     }
 }
 
-// Intra pairs: the Vina-form pair energy inside 8 A, forces added to both
-// atoms in LDS.  Returns this lane's energy; counts pairs inside the cutoff.
-__device__ __forceinline__ float pair_loop(const Lds& S, int np, int& cnt)
+// One intra pair: the Vina-form energy inside 8 A and the force
+// coefficient c = (dphi/dr) / r (0 outside the cutoff).
+__device__ __forceinline__ void pair_term(const Lds& S, uint32_t pk, float& en_out, float& c_out, bool& inside)
+{
+    const int i = pk & 0xff, j = (pk >> 8) & 0xff, tp = pk >> 16;
+    const float4 xi = S.pos[i], xj = S.pos[j];
+    const float2 tpe = S.tp[tp];
+    const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
+    const float r2 = dx * dx + dy * dy + dz * dz;
+    inside = r2 < kCut2;
+    const uint32_t fl = __float_as_uint(tpe.y);
+    // one v_rsq_f32: r = r2 / sqrt(r2) and c = de / r = de * rsq; a zero
+    // distance gets a tiny finite r and its zero direction zeroes the force
+    const float r2c = fmaxf(r2, 1e-12f);
+    const float rinv = __builtin_amdgcn_rsqf(r2c);
+    const float r = r2c * rinv;
+    const float d = r - tpe.x;
+    const float g1 = __expf(-4.f * d * d);
+    const float dm3 = d - 3.f;
+    const float g2 = __expf(-0.25f * dm3 * dm3);
+    const float dn = fminf(d, 0.f);                                  // repulsion d^2 for d < 0
+    float en = kW1 * g1 + kW2 * g2 + kW3 * dn * dn;
+    float de = kW1 * g1 * (-8.f * d) + kW2 * g2 * (-0.5f * dm3) + kW3 * 2.f * dn;
+    const float hyf = (fl & 1u) ? 1.f : 0.f, hbf = (fl & 2u) ? 1.f : 0.f;
+    const float hv = fminf(fmaxf(1.5f - d, 0.f), 1.f);              // 1 below 0.5, 0 above 1.5
+    const float hs = (d >= 0.5f && d < 1.5f) ? -1.f : 0.f;
+    const float bv = fminf(fmaxf(-d * (1.f / 0.7f), 0.f), 1.f);     // 1 below -0.7, 0 above 0
+    const float bs = (d >= -0.7f && d < 0.f) ? -(1.f / 0.7f) : 0.f;
+    en += hyf * kW4 * hv + hbf * kW5 * bv;
+    de += hyf * kW4 * hs + hbf * kW5 * bs;
+    en_out = inside ? en : 0.f;
+    c_out = inside ? de * rinv : 0.f;
+}
+
+// Intra pairs, lanes over pairs, two pairs per lane and pass: energies
+// summed, coefficients stored in S.cp (no atomics: forces are gathered per
+// atom afterwards).  Returns this lane's energy; counts pairs inside.
+template <int A>
+__device__ __forceinline__ float pair_loop(const Topo<A>& T, const Lds& S, int& cnt)
 {
     const int l = lane_id();
+    const int np = T.np;
     float e = 0.f;
-    for (int p = l; p < np; p += kWave) {
-        const uint32_t pk = S.pairs[p];
-        const int i = pk & 0xff, j = (pk >> 8) & 0xff, tp = pk >> 16;
-        const float4 xi = S.pos[i], xj = S.pos[j];
-        const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
-        const float r2 = dx * dx + dy * dy + dz * dz;
-        if (r2 < kCut2) {
-            const float2 tpe = S.tp[tp];
-            const uint32_t fl = __float_as_uint(tpe.y);
-            const float r = sqrtf(r2);
-            const float d = r - tpe.x;
-            const float g1 = __expf(-4.f * d * d);
-            const float dm3 = d - 3.f;
-            const float g2 = __expf(-0.25f * dm3 * dm3);
-            float en = kW1 * g1 + kW2 * g2;
-            float de = kW1 * g1 * (-8.f * d) + kW2 * g2 * (-0.5f * dm3);
-            if (d < 0.f) { en += kW3 * d * d; de += kW3 * 2.f * d; }
-            if (fl & 1u) {
-                if (d < 0.5f) en += kW4;
-                else if (d < 1.5f) { en += kW4 * (1.5f - d); de -= kW4; }
-            }
-            if (fl & 2u) {
-                if (d < -0.7f) en += kW5;
-                else if (d < 0.f) { en += kW5 * (-d * (1.f / 0.7f)); de -= kW5 * (1.f / 0.7f); }
-            }
-            e += en;
-            ++cnt;
-            const float c = r2 > 0.f ? de / r : 0.f;
-            const float fx = c * dx, fy = c * dy, fz = c * dz;
-            atomicAdd(&S.frc[i].x, fx); atomicAdd(&S.frc[i].y, fy); atomicAdd(&S.frc[i].z, fz);
-            atomicAdd(&S.frc[j].x, -fx); atomicAdd(&S.frc[j].y, -fy); atomicAdd(&S.frc[j].z, -fz);
-        }
+    for (int p0 = l; p0 - l < np; p0 += 2 * kWave) {
+        const int p1 = p0 + kWave;
+        const bool v0 = p0 < np, v1 = p1 < np;
+        const uint32_t pk0 = v0 ? (A == 1 ? S.pairs[p0] : T.gpairs[p0]) : 0u;
+        const uint32_t pk1 = v1 ? (A == 1 ? S.pairs[p1] : T.gpairs[p1]) : 0u;
+        float e0, c0, e1, c1;
+        bool in0, in1;
+        pair_term(S, pk0, e0, c0, in0);
+        pair_term(S, pk1, e1, c1, in1);
+        in0 = in0 && v0;
+        in1 = in1 && v1;
+        e += (v0 ? e0 : 0.f) + (v1 ? e1 : 0.f);
+        cnt += __popcll(__ballot(in0)) + __popcll(__ballot(in1));
+        if (v0) S.cp[p0] = c0;
+        if (v1) S.cp[p1] = c1;
     }
     return e;
+}
+
+// dE/dx_i of the intra term: sum over the pairs holding atom i of
+// c_p (x_i - x_j); rows are padded to a multiple of four entries.
+template <int A>
+__device__ __forceinline__ void gather_pair_forces(const Topo<A>& T, const Lds& S, int i, float4 xi, float& gx,
+                                                   float& gy, float& gz)
+{
+    const int n = T.n;
+    for (int k = 0; k < T.ell_w; k += 4) {
+        uint32_t e[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) e[u] = A == 1 ? S.ell[(k + u) * n + i] : T.gell[(k + u) * n + i];
+        float c[4];
+        float4 xj[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) { c[u] = S.cp[e[u] & 0xffff]; xj[u] = S.pos[e[u] >> 16]; }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            gx += c[u] * (xi.x - xj[u].x);
+            gy += c[u] * (xi.y - xj[u].y);
+            gz += c[u] * (xi.z - xj[u].z);
+        }
+    }
 }
 
 // Score and tangent gradient of the pose in `pose` (an LDS slot).  Leaves
@@ -365,18 +505,23 @@ __device__ Eval evaluate(const Topo<A>& T, const BoxView& B, const Lds& S, const
     const int l = lane_id();
     Eval out;
     float R[9], b[3];
-    frames(T, pose, R, b);
+    frames(T, S, pose, R, b);
     if (l < T.nf) {
         float* fr = S.frame + 12 * l;
 #pragma unroll
         for (int k = 0; k < 9; ++k) fr[k] = R[k];
         fr[9] = b[0]; fr[10] = b[1]; fr[11] = b[2];
     }
-    __syncthreads();
+    wave_sync();
     float e_in = 0.f;
+    float4 X4[A];
+    float G[A][3];
+    TriLoad TL[A];
 #pragma unroll
     for (int a = 0; a < A; ++a) {
         const int i = l * A + a;
+        X4[a] = make_float4(0.f, 0.f, 0.f, 0.f);
+        G[a][0] = G[a][1] = G[a][2] = 0.f;
         if (i < T.n) {
             const uint32_t w = __float_as_uint(T.ref[a].w);
             const int ty = w & 0xff, f = w >> 8;
@@ -386,47 +531,41 @@ __device__ Eval evaluate(const Topo<A>& T, const BoxView& B, const Lds& S, const
             const float x = r0.x * X + r0.y * Y + r0.z * Z + r2.y;
             const float y = r0.w * X + r1.x * Y + r1.y * Z + r2.z;
             const float z = r1.z * X + r1.w * Y + r2.x * Z + r2.w;
-            S.pos[i] = make_float4(x, y, z, 0.f);
-            float gx, gy, gz;
-            e_in += trilinear(B, ty, x, y, z, gx, gy, gz);
-            S.frc[i] = make_float4(gx, gy, gz, 0.f);
+            X4[a] = make_float4(x, y, z, 0.f);
+            S.pos[i] = X4[a];
+            tri_issue(B, ty, x, y, z, TL[a]);
         }
     }
-    __syncthreads();
+    wave_sync();
     int cnt = 0;
-    const float e_ia = pair_loop(S, T.np, cnt);
-    __syncthreads();
-    // per-atom force and torque about t, blocked inclusive scan over atoms
+    const float e_ia = pair_loop(T, S, cnt);   // hides the map loads
+    wave_sync();
+#pragma unroll
+    for (int a = 0; a < A; ++a)
+        if (l * A + a < T.n) e_in += tri_finish(B, TL[a], G[a][0], G[a][1], G[a][2]);
+    // per-atom force (inter + intra) and torque about t, blocked scan over atoms
     const float tx = pose[0], ty = pose[1], tz = pose[2];
     float v[A][6];
     float run[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
     for (int a = 0; a < A; ++a) {
         const int i = l * A + a;
-        float G[3] = {0, 0, 0}, rx = 0, ry = 0, rz = 0;
+        float rx = 0, ry = 0, rz = 0;
         if (i < T.n) {
-            const float4 f = S.frc[i], p = S.pos[i];
-            G[0] = f.x; G[1] = f.y; G[2] = f.z;
-            rx = p.x - tx; ry = p.y - ty; rz = p.z - tz;
+            gather_pair_forces(T, S, i, X4[a], G[a][0], G[a][1], G[a][2]);
+            S.frc[i] = make_float4(G[a][0], G[a][1], G[a][2], 0.f);
+            rx = X4[a].x - tx; ry = X4[a].y - ty; rz = X4[a].z - tz;
         }
-        run[0] += G[0]; run[1] += G[1]; run[2] += G[2];
-        run[3] += ry * G[2] - rz * G[1];
-        run[4] += rz * G[0] - rx * G[2];
-        run[5] += rx * G[1] - ry * G[0];
+        run[0] += G[a][0]; run[1] += G[a][1]; run[2] += G[a][2];
+        run[3] += ry * G[a][2] - rz * G[a][1];
+        run[4] += rz * G[a][0] - rx * G[a][2];
+        run[5] += rx * G[a][1] - ry * G[a][0];
 #pragma unroll
         for (int c = 0; c < 6; ++c) v[a][c] = run[c];
     }
     float incl[6];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-        float s = run[c];
-#pragma unroll
-        for (int o = 1; o < kWave; o <<= 1) {
-            const float u = __shfl_up(s, o);
-            if (l >= o) s += u;
-        }
-        incl[c] = s;
-    }
+    for (int c = 0; c < 6; ++c) incl[c] = wscan(run[c]);
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
         const float excl = incl[c] - run[c];
@@ -436,7 +575,7 @@ __device__ Eval evaluate(const Topo<A>& T, const BoxView& B, const Lds& S, const
             if (i < T.n) S.pre[c * S.ma + i] = excl + v[a][c];
         }
     }
-    __syncthreads();
+    wave_sync();
     // torsion derivative: world axis . sum over the moved atoms of (x - x_c) x G
     float dpsi = 0.f;
     if (l >= 1 && l < T.nf) {
@@ -454,16 +593,19 @@ __device__ Eval evaluate(const Topo<A>& T, const BoxView& B, const Lds& S, const
         const float awz = R[6] * T.ax + R[7] * T.ay + R[8] * T.az;
         dpsi = awx * mx + awy * my + awz * mz;
     }
-    const float dsel = __shfl(dpsi, T.dof_frag);
+    float* dps = S.frame + 12 * kMaxFrag;   // reuse the link area
+    if (l >= 1 && l < T.nf) dps[l] = dpsi;
+    wave_sync();
     const int last = T.n - 1;
     float g = 0.f;
     if (l < 6) g = S.pre[l * S.ma + last];
-    else if (l < 6 + T.nt) g = dsel;
+    else if (l < 6 + T.nt) g = dps[T.dof_frag];
     out.g = g;
     out.e_inter = wsum(e_in);
     out.e_intra = wsum(e_ia);
     out.e = out.e_inter + out.e_intra;
-    out.pairs_in = (int)wsum((float)cnt);
+    out.pairs_in = cnt;
+    wave_sync();
     return out;
 }
 
@@ -474,6 +616,9 @@ __device__ Eval evaluate_xyz(const Topo<A>& T, const BoxView& B, const Lds& S)
     const int l = lane_id();
     Eval out;
     float e_in = 0.f;
+    int cnt = 0;
+    const float e_ia = pair_loop(T, S, cnt);
+    wave_sync();
 #pragma unroll
     for (int a = 0; a < A; ++a) {
         const int i = l * A + a;
@@ -482,18 +627,16 @@ __device__ Eval evaluate_xyz(const Topo<A>& T, const BoxView& B, const Lds& S)
             const float4 p = S.pos[i];
             float gx, gy, gz;
             e_in += trilinear(B, ty, p.x, p.y, p.z, gx, gy, gz);
+            gather_pair_forces(T, S, i, p, gx, gy, gz);
             S.frc[i] = make_float4(gx, gy, gz, 0.f);
         }
     }
-    __syncthreads();
-    int cnt = 0;
-    const float e_ia = pair_loop(S, T.np, cnt);
-    __syncthreads();
+    wave_sync();
     out.g = 0.f;
     out.e_inter = wsum(e_in);
     out.e_intra = wsum(e_ia);
     out.e = out.e_inter + out.e_intra;
-    out.pairs_in = (int)wsum((float)cnt);
+    out.pairs_in = cnt;
     return out;
 }
 
@@ -502,7 +645,7 @@ __device__ __forceinline__ void slot_copy(const Lds& S, int dst, int src, int le
 {
     const int l = lane_id();
     if (l < len) S.pose[dst * kSlot + l] = S.pose[src * kSlot + l];
-    __syncthreads();
+    wave_sync();
 }
 
 // x (+) lam d : t + lam d_t, exp(lam d_theta) q, psi + lam d_psi.  d is the
@@ -512,7 +655,7 @@ __device__ __forceinline__ void retract(const Lds& S, int dst, int src, float d,
     const int l = lane_id();
     const float* x = S.pose + src * kSlot;
     float* o = S.pose + dst * kSlot;
-    const float th0 = __shfl(d, 3) * lam, th1 = __shfl(d, 4) * lam, th2 = __shfl(d, 5) * lam;
+    const float th0 = lane_f(d, 3) * lam, th1 = lane_f(d, 4) * lam, th2 = lane_f(d, 5) * lam;
     float dq[4], q[4] = {x[3], x[4], x[5], x[6]}, nq[4];
     rotvec_quat(th0, th1, th2, dq);
     quat_mul(dq, q, nq);
@@ -520,11 +663,15 @@ __device__ __forceinline__ void retract(const Lds& S, int dst, int src, float d,
     float vt = 0.f, vpsi = 0.f;
     if (l < 3) vt = x[l] + lam * d;
     if (l >= 6 && l < 6 + nt) vpsi = x[l + 1] + lam * d;
-    __syncthreads();
+    wave_sync();
     if (l < 3) o[l] = vt;
-    else if (l < 7) o[l] = nq[l - 3];
+    // one fixed-address store per quaternion component (no per-lane select)
+    if (l == 3) o[3] = nq[0];
+    if (l == 4) o[4] = nq[1];
+    if (l == 5) o[5] = nq[2];
+    if (l == 6) o[6] = nq[3];
     if (l >= 6 && l < 6 + nt) o[l + 1] = vpsi;
-    __syncthreads();
+    wave_sync();
 }
 
 // ---------------------------------------------------------------- RILC-BFGS
@@ -536,7 +683,9 @@ struct BfgsOut {
     int64_t pairs;
 };
 
-// Minimises from the pose in SLOT_X; the result is left in SLOT_X.
+// Minimises from the pose in SLOT_X; the result is left in SLOT_X.  Written
+// as one loop around a single evaluation (the first at x0, then one per
+// line-search trial) so the kernel carries one copy of the evaluation code.
 template <int A>
 __device__ BfgsOut bfgs(const Topo<A>& T, const BoxView& B, const Lds& S, const SearchParams& P, int max_iter)
 {
@@ -546,56 +695,25 @@ __device__ BfgsOut bfgs(const Topo<A>& T, const BoxView& B, const Lds& S, const 
     BfgsOut out;
     out.evals = 0;
     out.pairs = 0;
-    Eval ev = evaluate(T, B, S, S.pose + SLOT_X * kSlot);
-    ++out.evals;
-    out.pairs += ev.pairs_in;
-    float f = ev.e, g = act ? ev.g : 0.f;
     float Sh[kMaxM], Yh[kMaxM], rh[kMaxM];
 #pragma unroll
     for (int h = 0; h < kMaxM; ++h) { Sh[h] = 0.f; Yh[h] = 0.f; rh[h] = 0.f; }
-    int hn = 0;
+    int hn = 0, it = 0, tr = 0;
     const int m = P.m;
-    for (int it = 0; it < max_iter; ++it) {
-        const float gn = sqrtf(wsum(g * g));
-        if (gn <= P.eps_g) break;
-        // two-loop recursion
-        float q = g, al[kMaxM];
-#pragma unroll
-        for (int h = kMaxM - 1; h >= 0; --h) {
-            al[h] = 0.f;
-            if (h < hn) {
-                al[h] = rh[h] * wsum(Sh[h] * q);
-                q -= al[h] * Yh[h];
-            }
-        }
-        if (hn > 0) {
-            float sy = 0.f, yy = 0.f;
-#pragma unroll
-            for (int h = 0; h < kMaxM; ++h)
-                if (h == hn - 1) { sy = Sh[h] * Yh[h]; yy = Yh[h] * Yh[h]; }
-            q *= wsum(sy) / wsum(yy);
-        }
-#pragma unroll
-        for (int h = 0; h < kMaxM; ++h) {
-            if (h < hn) {
-                const float bb = rh[h] * wsum(Yh[h] * q);
-                q += Sh[h] * (al[h] - bb);
-            }
-        }
-        const float d = -q;
-        const float gd = wsum(g * d);
-        if (!(gd < 0.f)) break;
-        // Lewis-Overton line search
-        float lo = 0.f, lam = 1.f, beta = 0.f, lam_ok = -1.f;
-        bool beta_inf = true, accepted = false;
-        float ft = 0.f, gt = 0.f, fa = 0.f, ga = 0.f;
-        for (int tr = 0; tr < P.ls_max; ++tr) {
-            retract(S, SLOT_XT, SLOT_X, d, lam, T.nt);
-            Eval et = evaluate(T, B, S, S.pose + SLOT_XT * kSlot);
-            ++out.evals;
-            out.pairs += et.pairs_in;
-            ft = et.e;
-            gt = act ? et.g : 0.f;
+    float f = 0.f, g = 0.f, d = 0.f, gd = 0.f, gn = 0.f;
+    float lo = 0.f, lam = 1.f, beta = 0.f, fa = 0.f, ga = 0.f;
+    bool beta_inf = true, initial = true;
+    while (true) {
+        const Eval ev = evaluate(T, B, S, S.pose + (initial ? SLOT_X : SLOT_XT) * kSlot);
+        ++out.evals;
+        out.pairs += ev.pairs_in;
+        const float ft = ev.e, gt = act ? ev.g : 0.f;
+        bool begin = false;
+        if (initial) {
+            f = ft; g = gt; initial = false; begin = true;
+        } else {
+            // Lewis-Overton trial at step lam (Eqs. qvina_eq_7 and qvina_eq_8)
+            bool accepted = false;
             if (ft > f + P.rho * lam * gd) {
                 beta = lam; beta_inf = false;
             } else if (wsum(gt * d) < P.sigma * gd) {
@@ -603,36 +721,75 @@ __device__ BfgsOut bfgs(const Topo<A>& T, const BoxView& B, const Lds& S, const 
                 slot_copy(S, SLOT_XA, SLOT_XT, 7 + T.nt);
                 fa = ft; ga = gt;
             } else {
-                accepted = true; lam_ok = lam;
-                break;
+                accepted = true;
             }
-            lam = beta_inf ? 2.f * lam : 0.5f * (lo + beta);
-        }
-        if (!accepted) {
-            if (lo > 0.f) {
+            float lam_ok = lam, fn = ft, gnw = gt;
+            if (!accepted) {
+                ++tr;
+                if (tr < P.ls_max) {
+                    lam = beta_inf ? 2.f * lam : 0.5f * (lo + beta);
+                    retract(S, SLOT_XT, SLOT_X, d, lam, T.nt);
+                    continue;
+                }
+                if (!(lo > 0.f)) break;
                 lam_ok = lo;
                 slot_copy(S, SLOT_XT, SLOT_XA, 7 + T.nt);
-                ft = fa; gt = ga;
-            } else {
-                break;
+                fn = fa; gnw = ga;
             }
-        }
-        const float s = lam_ok * d, y = gt - g;
-        const float ys = wsum(y * s), ss = wsum(s * s);
-        if (ys / ss > P.eps_c * gn) {
-            if (hn == m) {
+            // s = lam d, y = g+ - g; cautious update (Eqs. qvina_eq_10, qvina_eq_11)
+            const float sv = lam_ok * d, yv = gnw - g;
+            const float ys = wsum(yv * sv), ss = wsum(sv * sv);
+            if (ys / ss > P.eps_c * gn) {
+                if (hn == m) {
 #pragma unroll
-                for (int h = 0; h < kMaxM - 1; ++h) { Sh[h] = Sh[h + 1]; Yh[h] = Yh[h + 1]; rh[h] = rh[h + 1]; }
-                --hn;
+                    for (int h = 0; h < kMaxM - 1; ++h) { Sh[h] = Sh[h + 1]; Yh[h] = Yh[h + 1]; rh[h] = rh[h + 1]; }
+                    --hn;
+                }
+#pragma unroll
+                for (int h = 0; h < kMaxM; ++h)
+                    if (h == hn) { Sh[h] = sv; Yh[h] = yv; rh[h] = 1.f / ys; }
+                ++hn;
+            }
+            slot_copy(S, SLOT_X, SLOT_XT, 7 + T.nt);   // Eq. qvina_eq_9
+            f = fn;
+            g = gnw;
+            ++it;
+            begin = true;
+        }
+        if (begin) {
+            if (it >= max_iter) break;
+            gn = sqrtf(wsum(g * g));
+            if (gn <= P.eps_g) break;                 // Eq. qvina_eq_12
+            // two-loop recursion: d = -H g (d = -g with no pairs, Eq. qvina_eq_6)
+            float q = g, al[kMaxM];
+#pragma unroll
+            for (int h = kMaxM - 1; h >= 0; --h) {
+                al[h] = 0.f;
+                if (h < hn) {
+                    al[h] = rh[h] * wsum(Sh[h] * q);
+                    q -= al[h] * Yh[h];
+                }
+            }
+            if (hn > 0) {
+                float sy = 0.f, yy = 0.f;
+#pragma unroll
+                for (int h = 0; h < kMaxM; ++h)
+                    if (h == hn - 1) { sy = Sh[h] * Yh[h]; yy = Yh[h] * Yh[h]; }
+                q *= wsum(sy) / wsum(yy);
             }
 #pragma unroll
-            for (int h = 0; h < kMaxM; ++h)
-                if (h == hn) { Sh[h] = s; Yh[h] = y; rh[h] = 1.f / ys; }
-            ++hn;
+            for (int h = 0; h < kMaxM; ++h) {
+                if (h < hn) {
+                    const float bb = rh[h] * wsum(Yh[h] * q);
+                    q += Sh[h] * (al[h] - bb);
+                }
+            }
+            d = -q;
+            gd = wsum(g * d);
+            if (!(gd < 0.f)) break;                   // not a descent direction
+            lo = 0.f; lam = 1.f; beta = 0.f; beta_inf = true; tr = 0;
+            retract(S, SLOT_XT, SLOT_X, d, lam, T.nt);
         }
-        slot_copy(S, SLOT_X, SLOT_XT, 7 + T.nt);
-        f = ft;
-        g = gt;
     }
     out.f = f;
     return out;
@@ -651,23 +808,21 @@ __device__ void init_pose(const Topo<A>& T, const BoxView& B, const Lds& S, int 
     const int l = lane_id();
     // lane l draws uniform l (block l/4, word l%4) of step 0
     const float u = u01(philox_word(seed, job, chain, 0, (uint64_t)(l >> 2), l & 3));
-    const float u3 = __shfl(u, 3), u4 = __shfl(u, 4), u5 = __shfl(u, 5);
+    const float u3 = lane_f(u, 3), u4 = lane_f(u, 4), u5 = lane_f(u, 5);
     const float s1 = sqrtf(1.f - u3), s2 = sqrtf(u3);
     float sa, ca, sb, cb;
     sincosf(2.f * kPi * u4, &sa, &ca);
     sincosf(2.f * kPi * u5, &sb, &cb);
     float* o = S.pose + slot * kSlot;
-    if (l < 3) {
-        const float lo = l == 0 ? B.ox : l == 1 ? B.oy : B.oz;
-        const float ext = l == 0 ? B.ex : l == 1 ? B.ey : B.ez;
-        o[l] = lo + u * ext;
-    }
+    if (l == 0) o[0] = B.ox + u * B.ex;
+    if (l == 1) o[1] = B.oy + u * B.ey;
+    if (l == 2) o[2] = B.oz + u * B.ez;
     if (l == 3) o[3] = s2 * cb;
     if (l == 4) o[4] = s1 * sa;
     if (l == 5) o[5] = s1 * ca;
     if (l == 6) o[6] = s2 * sb;
     if (l >= 6 && l < 6 + T.nt) o[l + 1] = -kPi + 2.f * kPi * u;
-    __syncthreads();
+    wave_sync();
 }
 
 // Mutation of one POT entity (Eq. qvina_eq_2) from the 8 words w of the step.
@@ -689,23 +844,27 @@ __device__ void mutate(const Topo<A>& T, const Lds& S, int slot, const SearchPar
     float dx = 0.f, dy = 0.f, dz = 1.f;
     if (vn2 > 0.f) { const float inv = 1.f / sqrtf(vn2); dx = vx * inv; dy = vy * inv; dz = vz * inv; }
     const float rad = cbrtf(ur);
-    float nv = 0.f;
-    bool wr = false;
+    wave_sync();
     if (ent == 0) {
-        if (l < 3) { nv = x[l] + P.pos_amp * rad * (l == 0 ? dx : l == 1 ? dy : dz); wr = true; }
+        const float a = P.pos_amp * rad;
+        if (l == 0) x[0] += a * dx;
+        if (l == 1) x[1] += a * dy;
+        if (l == 2) x[2] += a * dz;
     } else if (ent == 1) {
         const float amp = P.rot_amp * T.rot_scale * rad;
         float dq[4], q[4] = {x[3], x[4], x[5], x[6]}, nq[4];
         rotvec_quat(amp * dx, amp * dy, amp * dz, dq);
         quat_mul(dq, q, nq);
         quat_normalize(nq);
-        if (l >= 3 && l < 7) { nv = nq[l - 3]; wr = true; }
+        wave_sync();
+        if (l == 3) x[3] = nq[0];
+        if (l == 4) x[4] = nq[1];
+        if (l == 5) x[5] = nq[2];
+        if (l == 6) x[6] = nq[3];
     } else {
-        if (l == 7 + (ent - 2)) { nv = -kPi + 2.f * kPi * ua; wr = true; }
+        if (l == 7 + (ent - 2)) x[l] = -kPi + 2.f * kPi * ua;
     }
-    __syncthreads();
-    if (wr) x[l] = nv;
-    __syncthreads();
+    wave_sync();
 }
 
 template <int A>
@@ -716,41 +875,48 @@ __device__ ChainOut mc_chain(const Topo<A>& T, const BoxView& B, const Lds& S, c
     ChainOut out;
     out.evals = 0;
     out.pairs = 0;
-    init_pose(T, B, S, SLOT_CUR, P.seed, job, chain);
-    Eval e0 = evaluate(T, B, S, S.pose + SLOT_CUR * kSlot);
-    out.evals += 1;
-    out.pairs += e0.pairs_in;
-    float e_cur = e0.e, e_best = e0.e;
-    slot_copy(S, SLOT_BEST, SLOT_CUR, 7 + T.nt);
-    for (int s = 0; s < P.steps; ++s) {
-        // lanes 0-3 hold block 0, lanes 4-7 block 1 of step s + 1; broadcast
+    init_pose(T, B, S, SLOT_X, P.seed, job, chain);
+    float e_cur = 0.f, e_best = 0.f, um = 0.f;
+    int s = 0, mode = 0;   // 0 initial pose, 1 step optimisation, 2 refinement
+    while (true) {
+        const int iters = mode == 0 ? 0 : (mode == 1 ? P.max_iter : P.refine_max_iter);
+        const BfgsOut bo = bfgs(T, B, S, P, iters);
+        out.evals += bo.evals;
+        out.pairs += bo.pairs;
+        bool next = true;
+        if (mode == 0) {
+            e_cur = e_best = bo.f;
+            slot_copy(S, SLOT_CUR, SLOT_X, 7 + T.nt);
+            slot_copy(S, SLOT_BEST, SLOT_X, 7 + T.nt);
+        } else if (mode == 1) {
+            const float e_o = bo.f;
+            if (e_o < e_cur || um < __expf((e_cur - e_o) / P.temperature)) {   // Eq. qvina_eq_13
+                slot_copy(S, SLOT_CUR, SLOT_X, 7 + T.nt);
+                e_cur = e_o;
+            }
+            if (e_o < e_best) { mode = 2; next = false; }
+        } else {
+            slot_copy(S, SLOT_BEST, SLOT_X, 7 + T.nt);
+            slot_copy(S, SLOT_CUR, SLOT_X, 7 + T.nt);
+            e_best = bo.f;
+            e_cur = bo.f;
+        }
+        if (!next) continue;
+        if (s >= P.steps) break;
+        // the 8 draws of step s + 1: lanes 0-3 compute block 0, lanes 4-7 block 1
         const uint64_t mine = philox_word(P.seed, job, chain, (uint64_t)s + 1, (uint64_t)((l >> 2) & 1), l & 3);
         uint64_t w[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            const uint32_t lo = __shfl((uint32_t)mine, k), hi = __shfl((uint32_t)(mine >> 32), k);
+            const uint32_t lo = (uint32_t)lane_i((int)(uint32_t)mine, k);
+            const uint32_t hi = (uint32_t)lane_i((int)(uint32_t)(mine >> 32), k);
             w[k] = ((uint64_t)hi << 32) | lo;
         }
+        um = u01(w[7]);
         slot_copy(S, SLOT_X, SLOT_CUR, 7 + T.nt);
         mutate(T, S, SLOT_X, P, w);
-        BfgsOut bo = bfgs(T, B, S, P, P.max_iter);
-        out.evals += bo.evals;
-        out.pairs += bo.pairs;
-        const float e_o = bo.f;
-        const float um = u01(w[7]);
-        if (e_o < e_cur || um < __expf((e_cur - e_o) / P.temperature)) {
-            slot_copy(S, SLOT_CUR, SLOT_X, 7 + T.nt);
-            e_cur = e_o;
-        }
-        if (e_o < e_best) {
-            BfgsOut br = bfgs(T, B, S, P, P.refine_max_iter);
-            out.evals += br.evals;
-            out.pairs += br.pairs;
-            slot_copy(S, SLOT_BEST, SLOT_X, 7 + T.nt);
-            slot_copy(S, SLOT_CUR, SLOT_X, 7 + T.nt);
-            e_best = br.f;
-            e_cur = br.f;
-        }
+        ++s;
+        mode = 1;
     }
     out.best_e = e_best;
     return out;
@@ -764,7 +930,7 @@ template <int A>
 __global__ __launch_bounds__(64) void dock_kernel(DockArgs a)
 {
     extern __shared__ __align__(16) char smem[];
-    const Lds S = carve(smem, a.l.max_atoms, a.l.max_pairs);
+    const Lds S = carve(smem, a.l.max_atoms, a.l.max_pairs, a.l.max_ell);
     const int l = lane_id();
     stage_tp(S, c_rsum, c_tpflags);
     Topo<A> T;
@@ -775,7 +941,7 @@ __global__ __launch_bounds__(64) void dock_kernel(DockArgs a)
         if (a.persistent) {
             uint32_t v = 0;
             if (l == 0) v = atomicAdd(a.queue, 1u);
-            item = (int64_t)__shfl(v, 0);
+            item = (int64_t)(uint32_t)lane_i((int)v, 0);
         }
         if (item >= a.n_items) break;
         const int job = a.job_begin + (int)(item / chains);
@@ -799,7 +965,7 @@ __global__ __launch_bounds__(64) void dock_kernel(DockArgs a)
                 atomicMax((unsigned long long*)&a.job_t_end[job], (unsigned long long)t1);
             }
         }
-        __syncthreads();
+        wave_sync();
         if (!a.persistent) break;
     }
 }
@@ -835,7 +1001,7 @@ template <int A>
 __global__ __launch_bounds__(64) void score_kernel(ScoreArgs a)
 {
     extern __shared__ __align__(16) char smem[];
-    const Lds S = carve(smem, a.l.max_atoms, a.l.max_pairs);
+    const Lds S = carve(smem, a.l.max_atoms, a.l.max_pairs, a.l.max_ell);
     const int l = lane_id();
     stage_tp(S, c_rsum, c_tpflags);
     Topo<A> T;
@@ -856,14 +1022,14 @@ __global__ __launch_bounds__(64) void score_kernel(ScoreArgs a)
         Eval ev;
         if (!a.from_xyz) {
             if (l < 7 + T.nt) S.pose[SLOT_X * kSlot + l] = a.dof[(int64_t)pose * a.dof_stride + l];
-            __syncthreads();
+            wave_sync();
             ev = evaluate(T, B, S, S.pose + SLOT_X * kSlot);
         } else {
             for (int i = l; i < T.n; i += kWave) {
                 const float* src = a.dof + ((int64_t)pose * a.xyz_stride + perm[i]) * 3;
                 S.pos[i] = make_float4(src[0], src[1], src[2], 0.f);
             }
-            __syncthreads();
+            wave_sync();
             ev = evaluate_xyz(T, B, S);
         }
         if (l == 0 && a.energy) a.energy[pose] = ev.e;
@@ -871,7 +1037,7 @@ __global__ __launch_bounds__(64) void score_kernel(ScoreArgs a)
         if (a.grad_dof && !a.from_xyz) {
             // dE/dt, dE/d(raw q) = 2 ((0, torque) (x) q)/|p|, dE/dpsi
             const float* x = S.pose + SLOT_X * kSlot;
-            const float tq0 = __shfl(ev.g, 3), tq1 = __shfl(ev.g, 4), tq2 = __shfl(ev.g, 5);
+            const float tq0 = lane_f(ev.g, 3), tq1 = lane_f(ev.g, 4), tq2 = lane_f(ev.g, 5);
             const float dpsi = __shfl(ev.g, l - 1 < 0 ? 0 : (l - 1 > 63 ? 63 : l - 1));
             float p[4] = {x[3], x[4], x[5], x[6]};
             const float pn = sqrtf(p[0] * p[0] + p[1] * p[1] + p[2] * p[2] + p[3] * p[3]);
@@ -880,8 +1046,11 @@ __global__ __launch_bounds__(64) void score_kernel(ScoreArgs a)
             quat_mul(t4, qh, gq);
             float v = 0.f;
             if (l < 3) v = ev.g;
-            else if (l < 7) v = 2.f * gq[l - 3] / pn;
-            else if (l < 7 + T.nt) v = dpsi;
+            if (l == 3) v = 2.f * gq[0] / pn;
+            if (l == 4) v = 2.f * gq[1] / pn;
+            if (l == 5) v = 2.f * gq[2] / pn;
+            if (l == 6) v = 2.f * gq[3] / pn;
+            if (l >= 7 && l < 7 + T.nt) v = dpsi;
             if (l < a.dof_stride) a.grad_dof[(int64_t)pose * a.dof_stride + l] = l < 7 + T.nt ? v * scale : 0.f;
         }
         if (a.xyz_out || a.grad_xyz) {
@@ -897,7 +1066,7 @@ __global__ __launch_bounds__(64) void score_kernel(ScoreArgs a)
                 }
             }
         }
-        __syncthreads();
+        wave_sync();
     }
 }
 
@@ -905,7 +1074,7 @@ template <int A>
 __global__ __launch_bounds__(64) void local_opt_kernel(OptArgs a)
 {
     extern __shared__ __align__(16) char smem[];
-    const Lds S = carve(smem, a.l.max_atoms, a.l.max_pairs);
+    const Lds S = carve(smem, a.l.max_atoms, a.l.max_pairs, a.l.max_ell);
     const int l = lane_id();
     stage_tp(S, c_rsum, c_tpflags);
     Topo<A> T;
@@ -920,18 +1089,18 @@ __global__ __launch_bounds__(64) void local_opt_kernel(OptArgs a)
         const BoxView B = box_view(a.g, box);
         float v = l < 7 + T.nt ? a.dof_in[(int64_t)pose * a.dof_stride + l] : 0.f;
         // normalise the quaternion once so the run starts from a unit q
-        float q0 = __shfl(v, 3), q1 = __shfl(v, 4), q2 = __shfl(v, 5), q3 = __shfl(v, 6);
+        float q0 = lane_f(v, 3), q1 = lane_f(v, 4), q2 = lane_f(v, 5), q3 = lane_f(v, 6);
         const float qn = rsqrtf(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
         if (l >= 3 && l < 7) v *= qn;
         if (l < 7 + T.nt) S.pose[SLOT_X * kSlot + l] = v;
-        __syncthreads();
+        wave_sync();
         BfgsOut bo = bfgs(T, B, S, a.sp, a.sp.max_iter);
         if (l < a.dof_stride) a.dof_out[(int64_t)pose * a.dof_stride + l] = l < 7 + T.nt ? S.pose[SLOT_X * kSlot + l] : 0.f;
         if (l == 0) {
             if (a.energy) a.energy[pose] = bo.f;
             if (a.n_evals) a.n_evals[pose] = bo.evals;
         }
-        __syncthreads();
+        wave_sync();
     }
 }
 
@@ -1032,21 +1201,33 @@ __global__ __launch_bounds__(256) void gridmap_kernel(GridBuildArgs a)
 }
 
 // ---------------------------------------------------------------- launchers
-int dock_lds_bytes(int max_atoms, int max_pairs) { return lds_bytes(max_atoms, max_pairs); }
+int dock_lds_bytes(int max_atoms, int max_pairs, int max_ell) { return lds_bytes(max_atoms, max_pairs, max_ell); }
 
-static bool tables_ready = false;
+// The type-pair table lives in __constant__ memory of every device; it is
+// written once per device when a context is created on it (never during a
+// stream capture).
+static bool tables_ready[64] = {};
 
-static hipError_t ensure_tables()
+hipError_t init_device_tables(int device)
 {
-    if (tables_ready) return hipSuccess;
+    if (device < 0 || device >= 64) return hipErrorInvalidDevice;
+    if (tables_ready[device]) return hipSuccess;
     float rsum[64];
     uint32_t fl[64];
     type_pair_table(rsum, fl);
     hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_rsum), rsum, sizeof(rsum));
     if (e != hipSuccess) return e;
     e = hipMemcpyToSymbol(HIP_SYMBOL(c_tpflags), fl, sizeof(fl));
-    if (e == hipSuccess) tables_ready = true;
+    if (e == hipSuccess) tables_ready[device] = true;
     return e;
+}
+
+static hipError_t ensure_tables()
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    return tables_ready[dev] ? hipSuccess : hipErrorNotInitialized;
 }
 
 hipError_t launch_build_grids(const GridBuildArgs& a, int64_t n_tiles, hipStream_t s)
@@ -1061,7 +1242,7 @@ hipError_t launch_score(const ScoreArgs& a, hipStream_t s)
     hipError_t e = ensure_tables();
     if (e != hipSuccess) return e;
     if (a.n_poses <= 0) return hipSuccess;
-    const int lds = lds_bytes(a.l.max_atoms, a.l.max_pairs);
+    const int lds = lds_bytes(a.l.max_atoms, a.l.max_pairs, a.l.max_ell);
     const int grid = a.n_poses < 65536 ? a.n_poses : 65536;
     if (a.l.max_atoms <= 64)
         hipLaunchKernelGGL(score_kernel<1>, dim3(grid), dim3(64), lds, s, a);
@@ -1075,7 +1256,7 @@ hipError_t launch_dock(const DockArgs& a, int32_t workgroups, hipStream_t s)
     hipError_t e = ensure_tables();
     if (e != hipSuccess) return e;
     if (a.n_items <= 0) return hipSuccess;
-    const int lds = lds_bytes(a.l.max_atoms, a.l.max_pairs);
+    const int lds = lds_bytes(a.l.max_atoms, a.l.max_pairs, a.l.max_ell);
     const unsigned grid = a.persistent ? (unsigned)workgroups : (unsigned)a.n_items;
     if (a.l.max_atoms <= 64)
         hipLaunchKernelGGL(dock_kernel<1>, dim3(grid), dim3(64), lds, s, a);
@@ -1111,7 +1292,7 @@ hipError_t launch_local_opt(const OptArgs& a, hipStream_t s)
     hipError_t e = ensure_tables();
     if (e != hipSuccess) return e;
     if (a.n_poses <= 0) return hipSuccess;
-    const int lds = lds_bytes(a.l.max_atoms, a.l.max_pairs);
+    const int lds = lds_bytes(a.l.max_atoms, a.l.max_pairs, a.l.max_ell);
     const int grid = a.n_poses < 65536 ? a.n_poses : 65536;
     if (a.l.max_atoms <= 64)
         hipLaunchKernelGGL(local_opt_kernel<1>, dim3(grid), dim3(64), lds, s, a);
@@ -1120,9 +1301,9 @@ hipError_t launch_local_opt(const OptArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t dock_occupancy(int max_atoms, int max_pairs, int* blocks_per_cu)
+hipError_t dock_occupancy(int max_atoms, int max_pairs, int max_ell, int* blocks_per_cu)
 {
-    const int lds = lds_bytes(max_atoms, max_pairs);
+    const int lds = lds_bytes(max_atoms, max_pairs, max_ell);
     if (max_atoms <= 64)
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, dock_kernel<1>, 64, lds);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, dock_kernel<2>, 64, lds);

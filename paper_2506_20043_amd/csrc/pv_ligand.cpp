@@ -237,6 +237,21 @@ int build_ligand_model(int n, const float* xyz, const uint8_t* type, int nb, con
             int tp = type[perm[i]] * 8 + type[perm[j]];
             M.pairs.push_back((uint32_t)i | ((uint32_t)j << 8) | ((uint32_t)tp << 16));
         }
+    // atom -> pair rows (partners in ascending pair order), padded to the longest
+    std::vector<std::vector<uint32_t>> rows(n);
+    for (int q = 0; q < P; ++q) {
+        const uint32_t i = M.pairs[q] & 0xff, j = (M.pairs[q] >> 8) & 0xff;
+        rows[i].push_back((uint32_t)q | (j << 16));
+        rows[j].push_back((uint32_t)q | (i << 16));
+    }
+    int w = 0;
+    for (int i = 0; i < n; ++i) w = std::max(w, (int)rows[i].size());
+    w = (w + 3) / 4 * 4;   // the kernels read rows four entries at a time
+    M.ell_w = w;
+    M.ell.assign((size_t)w * n, 0u);
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k < w; ++k)
+            M.ell[(size_t)k * n + i] = k < (int)rows[i].size() ? rows[i][k] : ((uint32_t)P | ((uint32_t)i << 16));
     return PV_OK;
 }
 
