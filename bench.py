@@ -57,6 +57,8 @@ def main():
     ap.add_argument("--no-score", action="store_true")
     ap.add_argument("--cpu-chains", type=int, default=128)
     ap.add_argument("--workgroups", type=int, default=0)
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device-to-device (calibrates the HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
@@ -64,6 +66,16 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.copy_calib:
+        n = args.copy_calib * (1 << 20) // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calib_bytes": 4 * n}), flush=True)
+        return
 
     import paper_2506_20043_amd as pv
     from paper_2506_20043_amd import synth as S
@@ -160,7 +172,7 @@ def main():
         "peak": PEAK_FP32_VECTOR / 1e12,
         "unit": "TFLOP/s",
         "frac": achieved / PEAK_FP32_VECTOR,
-        "traffic": None,
+        "traffic": recorded_traffic(),
         "flops_per_launch": flops,
         "launch_ms": dock_ms,
     }
@@ -169,6 +181,26 @@ def main():
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(S, cfg, rx, rt, bxs, mols, seed, args)
     print(json.dumps(result), flush=True)
+
+
+def recorded_traffic():
+    """HBM bytes per dock launch from the committed rocprofv3 counter record,
+    or None when the kernel sources changed since the counters were taken."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", "dock_kernel_multipocket.md")
+    if not os.path.exists(prof):
+        return None
+    rec = None
+    for line in open(prof):
+        if line.startswith("traffic_record: "):
+            rec = json.loads(line[len("traffic_record: "):])
+    if rec is None:
+        return None
+    csrc = os.path.join(ROOT, "paper_2506_20043_amd", "csrc")
+    src = b"".join(open(os.path.join(csrc, f), "rb").read() for f in ("pv_kernels.hip", "pv_internal.h"))
+    if hashlib.sha256(src).hexdigest() != rec["kernel_source_sha256"]:
+        return None
+    return rec["dock_traffic_bytes_per_launch"]
 
 
 def plan_workgroups(plan):

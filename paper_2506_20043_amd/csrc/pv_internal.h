@@ -177,6 +177,6 @@ int dock_lds_bytes(int max_atoms, int max_pairs, int max_ell);
 hipError_t init_device_tables(int device);
 
 // Tiles of the grid-map kernel.
-constexpr int kTileX = 8, kTileY = 8, kTileZ = 4;
+constexpr int kTileX = 16, kTileY = 4, kTileZ = 4;
 
 }  // namespace pv

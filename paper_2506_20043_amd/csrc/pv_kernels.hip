@@ -2,7 +2,7 @@
 //
 //  * grid maps ("Kernel 1" of the paper: one map per ligand atom type over
 //    each pocket box, Methods "Accelerated Docking" and Supplementary
-//    Algorithm 2, first step): FP32 VALU, lattice tiles of 8x8x4 points per
+//    Algorithm 2, first step): FP32 VALU, lattice tiles of 16x4x4 points per
 //    workgroup, receptor atoms culled per tile into LDS;
 //  * pose evaluation (Eq. qvina_eq_1 forward kinematics, Eq. qvina_eq_3
 //    score): one wave64 per pose, lanes over fragments for the frame tree,
@@ -1105,7 +1105,8 @@ __global__ __launch_bounds__(64) void local_opt_kernel(OptArgs a)
 }
 
 // ---------------------------------------------------------------- grid maps
-// One workgroup per 8x8x4 tile of one box.  Receptor atoms near the box are
+// One workgroup per 16x4x4 tile of one box (a wave writes 16-float = 64 B
+// rows).  Receptor atoms near the box are
 // streamed in chunks of 256; those within reach of the tile's bounding box
 // are compacted into LDS and every lane adds their terms to its point's 8
 // accumulators (one per ligand type).
