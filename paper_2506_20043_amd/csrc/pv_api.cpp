@@ -92,6 +92,7 @@ struct pv_ligands {
     int8_t* tors_frag;
     uint32_t* pairs;
     uint32_t* ell;
+    uint32_t* pslot;
     int32_t max_ell;
     std::vector<std::array<int32_t, 8>>* info;
 };
@@ -147,6 +148,7 @@ LigDev lig_view(const pv_ligands* l)
     v.tors_frag = l->tors_frag;
     v.pairs = l->pairs;
     v.ell = l->ell;
+    v.pslot = l->pslot;
     v.max_ell = l->max_ell;
     v.n_lig = l->n_lig;
     v.max_atoms = l->max_atoms;
@@ -389,6 +391,7 @@ pv_status pv_ligands_create(pv_ctx* ctx, int32_t n_lig, const int32_t* atom_off,
     std::vector<int8_t> tors_frag;
     std::vector<uint32_t> pairs;
     std::vector<uint32_t> ell;
+    std::vector<uint32_t> pslot;
     auto* info = new (std::nothrow) std::vector<std::array<int32_t, 8>>(n_lig);
     if (!info) return fail(PV_E_NOMEM, "host allocation");
     int max_atoms = 0, max_pairs = 0, max_tors = 0, max_ell = 0;
@@ -422,7 +425,8 @@ pv_status pv_ligands_create(pv_ctx* ctx, int32_t n_lig, const int32_t* atom_off,
         for (int v : M.tors_frag) tors_frag.push_back((int8_t)v);
         pairs.insert(pairs.end(), M.pairs.begin(), M.pairs.end());
         ell.insert(ell.end(), M.ell.begin(), M.ell.end());
-        max_ell = std::max(max_ell, M.ell_w * M.n);
+        pslot.insert(pslot.end(), M.pslot.begin(), M.pslot.end());
+        max_ell = std::max(max_ell, M.ell_w * (M.n | 1));   // slot rows have an odd stride
         (*info)[i] = {M.n, M.nf, M.nt, M.np, M.root_size, M.depth, 7 + M.nt, 0};
         max_atoms = std::max(max_atoms, M.n);
         max_pairs = std::max(max_pairs, M.np);
@@ -445,7 +449,8 @@ pv_status pv_ligands_create(pv_ctx* ctx, int32_t n_lig, const int32_t* atom_off,
         (st = upload(&L->frags, frags.data(), frags.size(), "ligand upload")) != PV_OK ||
         (st = upload(&L->tors_frag, tors_frag.data(), tors_frag.size(), "ligand upload")) != PV_OK ||
         (st = upload(&L->pairs, pairs.data(), pairs.size(), "ligand upload")) != PV_OK ||
-        (st = upload(&L->ell, ell.data(), ell.size(), "ligand upload")) != PV_OK) {
+        (st = upload(&L->ell, ell.data(), ell.size(), "ligand upload")) != PV_OK ||
+        (st = upload(&L->pslot, pslot.data(), pslot.size(), "ligand upload")) != PV_OK) {
         pv_ligands_free(L);
         return st;
     }
@@ -497,7 +502,7 @@ void pv_ligands_free(pv_ligands* l)
     if (!l) return;
     if (ctx_ok(l->ctx)) (void)hipSetDevice(l->ctx->device);
     dfree(l->ligs); dfree(l->atoms); dfree(l->perm); dfree(l->frags); dfree(l->tors_frag); dfree(l->pairs);
-    dfree(l->ell);
+    dfree(l->ell); dfree(l->pslot);
     delete l->info;
     delete l;
 }

@@ -44,6 +44,8 @@ struct alignas(16) DevFrag {
 
 // Intra pair packed as i | j << 8 | type_pair << 16 (new atom order).
 // Atom record: x, y, z and w = bits(type | fragment << 8).
+// pslot (same index as the pair list): the slot the pair occupies in the
+// row of its first atom | in the row of its second atom << 16.
 // Atom -> pair table (ELL, [ell_w][n] words): entry k of atom i is
 // p | j << 16, the k-th pair p (index into the pair list) that holds atom i
 // and its partner j; rows shorter than ell_w are padded with p = n_pairs
@@ -56,8 +58,9 @@ struct LigModel {
     std::vector<float> ref;         // [n][4] new order: x, y, z, w-bits
     std::vector<DevFrag> frags;     // preorder
     std::vector<int> tors_frag;     // torsion k -> fragment
-    std::vector<uint32_t> pairs;    // packed, lane-interleaved order
+    std::vector<uint32_t> pairs;    // packed, grouped by interaction class
     std::vector<uint32_t> ell;      // [ell_w][n]
+    std::vector<uint32_t> pslot;    // per pair: slot in row i | slot in row j << 16
     int ell_w = 0;
     float anchor[3] = {0, 0, 0};
     float rg = 0.f;
@@ -88,6 +91,7 @@ struct LigDev {
     const int8_t* tors_frag;
     const uint32_t* pairs;
     const uint32_t* ell;
+    const uint32_t* pslot;   // indexed like pairs
     int32_t n_lig;
     int32_t max_atoms, max_pairs, max_tors;
     int32_t max_ell;   // largest ell_w * n_atoms

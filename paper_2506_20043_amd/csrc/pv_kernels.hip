@@ -120,8 +120,8 @@ __device__ __forceinline__ void rotvec_quat(float tx, float ty, float tz, float 
     // (cos(a/2), sin(a/2)/a * theta); sin(a/2)/a -> 1/2 as a -> 0
     const float a = sqrtf(tx * tx + ty * ty + tz * tz);
     float s, c;
-    sincosf(0.5f * a, &s, &c);
-    const float k = a > 0.f ? s / a : 0.5f;
+    __sincosf(0.5f * a, &s, &c);
+    const float k = a > 0.f ? __fdividef(s, a) : 0.5f;
     q[0] = c; q[1] = k * tx; q[2] = k * ty; q[3] = k * tz;
 }
 
@@ -238,24 +238,27 @@ struct Lds {
     float4* frc;       // [max_atoms]
     float* pre;        // [6][max_atoms]
     uint32_t* pairs;   // [max_pairs]
-    float* cp;         // [max_pairs + 1] per-pair force coefficient (last = 0)
-    uint32_t* ell;     // [max_ell] atom -> pair table of the staged ligand
+    float* cp;         // [max_pairs + 1] per-pair force coefficient (last = 0), global-table path
+    uint32_t* ell;     // unused in LDS (the global-table path reads the table from memory)
+    float4* fs;        // [max_ell] pair forces in atom-row slots (row stride n | 1), LDS-table path
     int ma;
 };
 
 __host__ __device__ inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
-// Ligands of at most 64 atoms (one atom per lane) stage their pair list and
-// atom -> pair table in LDS; larger ones read both from global memory
-// (coalesced, L1/L2 resident) and keep only the per-pair coefficients here.
+// Ligands of at most 64 atoms (one atom per lane) keep their pair list in
+// LDS, packed with the slots each pair owns in its two atoms' rows, and the
+// per-slot pair forces (so an atom's intra force is a stream of independent
+// reads).  Larger ligands read the pair list and the atom -> pair table from
+// global memory and keep per-pair coefficients in LDS.
 __host__ __device__ inline bool tables_in_lds(int max_atoms) { return max_atoms <= 64; }
 
 __host__ __device__ inline int lds_bytes(int max_atoms, int max_pairs, int max_ell)
 {
     int ma = round_up(max_atoms < 1 ? 1 : max_atoms, 64);
-    int b = 64 * 8 + kNSlots * kSlot * 4 + kMaxFrag * 13 * 4 + 12 + ma * 16 * 2 + 6 * ma * 4 +
-            round_up(max_pairs + 1, 4) * 4;
-    if (tables_in_lds(max_atoms)) b += round_up(max_pairs, 4) * 4 + round_up(max_ell, 4) * 4;
+    int b = 64 * 8 + kNSlots * kSlot * 4 + kMaxFrag * 13 * 4 + 12 + ma * 16 * 2 + 6 * ma * 4;
+    if (tables_in_lds(max_atoms)) b += round_up(max_pairs, 4) * 4 + max_ell * 16;
+    else b += round_up(max_pairs + 1, 4) * 4;
     return b;
 }
 
@@ -270,11 +273,17 @@ __device__ __forceinline__ Lds carve(char* base, int max_atoms, int max_pairs, i
     s.pose = (float*)p; p += kNSlots * kSlot * 4;
     s.frame = (float*)p; p += kMaxFrag * 13 * 4 + 12;
     s.pre = (float*)p; p += 6 * ma * 4;
-    s.cp = (float*)p; p += round_up(max_pairs + 1, 4) * 4;
-    s.pairs = (uint32_t*)p; p += round_up(max_pairs, 4) * 4;
-    s.ell = (uint32_t*)p;
+    s.ell = nullptr;
+    if (tables_in_lds(max_atoms)) {
+        s.pairs = (uint32_t*)p; p += round_up(max_pairs, 4) * 4;
+        s.fs = (float4*)p;
+        s.cp = nullptr;
+    } else {
+        s.cp = (float*)p;
+        s.pairs = nullptr;
+        s.fs = nullptr;
+    }
     s.ma = ma;
-    (void)max_ell;
     return s;
 }
 
@@ -289,7 +298,7 @@ __device__ __forceinline__ void stage_tp(const Lds& S, const float* rsum, const 
 // fragments one per lane, and for lane 6+k the fragment of torsion k.
 template <int A>
 struct Topo {
-    int n, nf, nt, np, rounds, lig, ell_w;
+    int n, nf, nt, np, rounds, lig, ell_w, fs_stride;
     float anc_x, anc_y, anc_z, rot_scale;
     float4 ref[A];
     int f_parent, f_tors, f_child, f_a0, f_end;
@@ -307,6 +316,9 @@ __device__ void stage_ligand(Topo<A>& T, const LigDev& L, int lig, const Lds& S)
     T.lig = lig;
     T.n = d.n_atoms; T.nf = d.n_frag; T.nt = d.n_tors; T.np = d.n_pairs; T.rounds = d.rounds;
     T.ell_w = d.ell_w;
+    // slot rows of an odd number of float4: lanes writing slots of one atom
+    // then fall in different LDS banks
+    T.fs_stride = T.n | 1;
     T.anc_x = d.anchor[0]; T.anc_y = d.anchor[1]; T.anc_z = d.anchor[2]; T.rot_scale = d.rot_amp_scale;
 #pragma unroll
     for (int a = 0; a < A; ++a) {
@@ -326,11 +338,18 @@ __device__ void stage_ligand(Topo<A>& T, const LigDev& L, int lig, const Lds& S)
     T.gpairs = L.pairs + d.pair_base;
     T.gell = L.ell + d.ell_base;
     if (A == 1) {
-        for (int p = l; p < T.np; p += kWave) S.pairs[p] = T.gpairs[p];
-        const int ne = T.ell_w * T.n;
-        for (int k = l; k < ne; k += kWave) S.ell[k] = T.gell[k];
+        // pair word: i | j << 6 | type pair << 12 | slot in row i << 18 | slot in row j << 24
+        const uint32_t* ps = L.pslot + d.pair_base;
+        for (int p = l; p < T.np; p += kWave) {
+            const uint32_t pk = T.gpairs[p], sl = ps[p];
+            S.pairs[p] = (pk & 0x3f) | (((pk >> 8) & 0x3f) << 6) | ((pk >> 16) << 12) | ((sl & 0x3f) << 18) |
+                         (((sl >> 16) & 0x3f) << 24);
+        }
+        const int nfs = T.ell_w * T.fs_stride;
+        for (int k = l; k < nfs; k += kWave) S.fs[k] = make_float4(0.f, 0.f, 0.f, 0.f);   // padding stays zero
+    } else {
+        if (l == 0) S.cp[T.np] = 0.f;
     }
-    if (l == 0) S.cp[T.np] = 0.f;
     wave_sync();
 }
 
@@ -413,12 +432,10 @@ __device__ __forceinline__ void frames(const Topo<A>& T, const Lds& S, const flo
 
 // One intra pair: the Vina-form energy inside 8 A and the force
 // coefficient c = (dphi/dr) / r (0 outside the cutoff).
-__device__ __forceinline__ void pair_term(const Lds& S, uint32_t pk, float& en_out, float& c_out, bool& inside)
+__device__ __forceinline__ void pair_term(float4 xi, float4 xj, float2 tpe, float& en_out, float& c_out, bool& inside,
+                                          float& dx, float& dy, float& dz)
 {
-    const int i = pk & 0xff, j = (pk >> 8) & 0xff, tp = pk >> 16;
-    const float4 xi = S.pos[i], xj = S.pos[j];
-    const float2 tpe = S.tp[tp];
-    const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
+    dx = xi.x - xj.x; dy = xi.y - xj.y; dz = xi.z - xj.z;
     const float r2 = dx * dx + dy * dy + dz * dz;
     inside = r2 < kCut2;
     const uint32_t fl = __float_as_uint(tpe.y);
@@ -432,58 +449,101 @@ __device__ __forceinline__ void pair_term(const Lds& S, uint32_t pk, float& en_o
     const float dm3 = d - 3.f;
     const float g2 = __expf(-0.25f * dm3 * dm3);
     const float dn = fminf(d, 0.f);                                  // repulsion d^2 for d < 0
-    float en = kW1 * g1 + kW2 * g2 + kW3 * dn * dn;
-    float de = kW1 * g1 * (-8.f * d) + kW2 * g2 * (-0.5f * dm3) + kW3 * 2.f * dn;
     const float hyf = (fl & 1u) ? 1.f : 0.f, hbf = (fl & 2u) ? 1.f : 0.f;
     const float hv = fminf(fmaxf(1.5f - d, 0.f), 1.f);              // 1 below 0.5, 0 above 1.5
     const float hs = (d >= 0.5f && d < 1.5f) ? -1.f : 0.f;
     const float bv = fminf(fmaxf(-d * (1.f / 0.7f), 0.f), 1.f);     // 1 below -0.7, 0 above 0
     const float bs = (d >= -0.7f && d < 0.f) ? -(1.f / 0.7f) : 0.f;
-    en += hyf * kW4 * hv + hbf * kW5 * bv;
-    de += hyf * kW4 * hs + hbf * kW5 * bs;
+    const float en = kW1 * g1 + kW2 * g2 + kW3 * dn * dn + hyf * kW4 * hv + hbf * kW5 * bv;
+    const float de = kW1 * g1 * (-8.f * d) + kW2 * g2 * (-0.5f * dm3) + kW3 * 2.f * dn + hyf * kW4 * hs + hbf * kW5 * bs;
     en_out = inside ? en : 0.f;
     c_out = inside ? de * rinv : 0.f;
 }
 
-// Intra pairs, lanes over pairs, two pairs per lane and pass: energies
-// summed, coefficients stored in S.cp (no atomics: forces are gathered per
-// atom afterwards).  Returns this lane's energy; counts pairs inside.
+// Intra pairs, lanes over pairs, kPairUnroll pairs per lane and pass: every
+// load of a pass (pair words, then both positions and the type-pair entry)
+// is issued before any of its arithmetic, so the LDS latency is paid once
+// per pass.  With the tables in LDS each pair writes its force +f / -f into
+// its slots of the two atoms' rows; otherwise it stores its coefficient c
+// for the table gather.  No atomics either way.  Returns this lane's energy;
+// counts pairs inside the cutoff.
+constexpr int kPairUnroll = 4;
+
 template <int A>
 __device__ __forceinline__ float pair_loop(const Topo<A>& T, const Lds& S, int& cnt)
 {
+    constexpr int U = kPairUnroll;
     const int l = lane_id();
-    const int np = T.np;
+    const int np = T.np, ns = T.fs_stride;
     float e = 0.f;
-    for (int p0 = l; p0 - l < np; p0 += 2 * kWave) {
-        const int p1 = p0 + kWave;
-        const bool v0 = p0 < np, v1 = p1 < np;
-        const uint32_t pk0 = v0 ? (A == 1 ? S.pairs[p0] : T.gpairs[p0]) : 0u;
-        const uint32_t pk1 = v1 ? (A == 1 ? S.pairs[p1] : T.gpairs[p1]) : 0u;
-        float e0, c0, e1, c1;
-        bool in0, in1;
-        pair_term(S, pk0, e0, c0, in0);
-        pair_term(S, pk1, e1, c1, in1);
-        in0 = in0 && v0;
-        in1 = in1 && v1;
-        e += (v0 ? e0 : 0.f) + (v1 ? e1 : 0.f);
-        cnt += __popcll(__ballot(in0)) + __popcll(__ballot(in1));
-        if (v0) S.cp[p0] = c0;
-        if (v1) S.cp[p1] = c1;
+    for (int p0 = l; p0 - l < np; p0 += U * kWave) {
+        uint32_t pk[U];
+        bool v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int p = p0 + u * kWave;
+            v[u] = p < np;
+            // a lane past the end reads pair 0 (np >= 1 here) and discards it
+            pk[u] = A == 1 ? S.pairs[v[u] ? p : 0] : T.gpairs[v[u] ? p : 0];
+        }
+        int ii[U], jj[U];
+        float4 xi[U], xj[U];
+        float2 tpe[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            int t;
+            if (A == 1) {
+                ii[u] = pk[u] & 0x3f; jj[u] = (pk[u] >> 6) & 0x3f; t = (pk[u] >> 12) & 0x3f;
+            } else {
+                ii[u] = pk[u] & 0xff; jj[u] = (pk[u] >> 8) & 0xff; t = pk[u] >> 16;
+            }
+            xi[u] = S.pos[ii[u]];
+            xj[u] = S.pos[jj[u]];
+            tpe[u] = S.tp[t];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            float eu, c, dx, dy, dz;
+            bool in;
+            pair_term(xi[u], xj[u], tpe[u], eu, c, in, dx, dy, dz);
+            e += v[u] ? eu : 0.f;
+            cnt += __popcll(__ballot(in && v[u]));
+            if (v[u]) {
+                if (A == 1) {
+                    const float fx = c * dx, fy = c * dy, fz = c * dz;
+                    S.fs[((pk[u] >> 18) & 0x3f) * ns + ii[u]] = make_float4(fx, fy, fz, 0.f);
+                    S.fs[((pk[u] >> 24) & 0x3f) * ns + jj[u]] = make_float4(-fx, -fy, -fz, 0.f);
+                } else {
+                    S.cp[p0 + u * kWave] = c;
+                }
+            }
+        }
     }
     return e;
 }
 
-// dE/dx_i of the intra term: sum over the pairs holding atom i of
-// c_p (x_i - x_j); rows are padded to a multiple of four entries.
+// dE/dx_i of the intra term.  LDS tables: the sum of atom i's row of pair
+// forces (independent reads, rows padded to a multiple of four with zeros).
+// Global tables: sum over the pairs holding atom i of c_p (x_i - x_j).
 template <int A>
 __device__ __forceinline__ void gather_pair_forces(const Topo<A>& T, const Lds& S, int i, float4 xi, float& gx,
                                                    float& gy, float& gz)
 {
     const int n = T.n;
+    if (A == 1) {
+        for (int k = 0; k < T.ell_w; k += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const float4 f = S.fs[(k + u) * T.fs_stride + i];
+                gx += f.x; gy += f.y; gz += f.z;
+            }
+        }
+        return;
+    }
     for (int k = 0; k < T.ell_w; k += 4) {
         uint32_t e[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) e[u] = A == 1 ? S.ell[(k + u) * n + i] : T.gell[(k + u) * n + i];
+        for (int u = 0; u < 4; ++u) e[u] = T.gell[(k + u) * n + i];
         float c[4];
         float4 xj[4];
 #pragma unroll

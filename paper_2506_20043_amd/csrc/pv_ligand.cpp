@@ -224,23 +224,32 @@ int build_ligand_model(int n, const float* xyz, const uint8_t* type, int nb, con
                 pl.push_back({std::min(i, j), std::max(i, j)});
             }
     }
-    std::sort(pl.begin(), pl.end());
+    // pairs grouped by interaction class (plain, hydrophobic, hydrogen bond)
+    // so that the class-specific terms are mostly wave-uniform branches
+    auto cls = [&](const std::pair<int, int>& q) {
+        const int a = type[perm[q.first]], b = type[perm[q.second]];
+        if (kHyd[a] && kHyd[b]) return 1;
+        if ((kDon[a] && kAcc[b]) || (kAcc[a] && kDon[b])) return 2;
+        return 0;
+    };
+    std::sort(pl.begin(), pl.end(), [&](const std::pair<int, int>& x, const std::pair<int, int>& y) {
+        const int cx = cls(x), cy = cls(y);
+        return cx != cy ? cx < cy : x < y;
+    });
     M.np = (int)pl.size();
-    // lane interleave: consecutive lanes take pairs from different rows
-    const int P = M.np, S = (P + kWave - 1) / kWave;
+    const int P = M.np;
     M.pairs.reserve(P);
-    for (int cc = 0; cc < S; ++cc)
-        for (int l = 0; l < kWave; ++l) {
-            int idx = l * S + cc;
-            if (idx >= P) continue;
-            int i = pl[idx].first, j = pl[idx].second;
-            int tp = type[perm[i]] * 8 + type[perm[j]];
-            M.pairs.push_back((uint32_t)i | ((uint32_t)j << 8) | ((uint32_t)tp << 16));
-        }
+    for (int idx = 0; idx < P; ++idx) {
+        int i = pl[idx].first, j = pl[idx].second;
+        int tp = type[perm[i]] * 8 + type[perm[j]];
+        M.pairs.push_back((uint32_t)i | ((uint32_t)j << 8) | ((uint32_t)tp << 16));
+    }
     // atom -> pair rows (partners in ascending pair order), padded to the longest
     std::vector<std::vector<uint32_t>> rows(n);
+    M.pslot.assign(P, 0u);
     for (int q = 0; q < P; ++q) {
         const uint32_t i = M.pairs[q] & 0xff, j = (M.pairs[q] >> 8) & 0xff;
+        M.pslot[q] = (uint32_t)rows[i].size() | ((uint32_t)rows[j].size() << 16);
         rows[i].push_back((uint32_t)q | (j << 16));
         rows[j].push_back((uint32_t)q | (i << 16));
     }
