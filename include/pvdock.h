@@ -255,6 +255,26 @@ pv_status pv_local_opt(pv_ctx* ctx, const pv_grids* grids, const pv_ligands* lig
                        int32_t dof_stride, const pv_dock_params* params, float* dof_out, float* energy,
                        int64_t* n_evals, void* stream);
 
+/* Launch shape diagnostics (host only, no device work): the kernel variant
+ * that a launch of `kind` over `items` waves (dock: jobs x chains; score and
+ * local-opt: poses) on these ligands uses, its dynamic LDS bytes per
+ * workgroup and how many of its workgroups one CU holds.  Variants:
+ *   PV_VARIANT_SLOTS    one atom per lane; each intra pair writes its force
+ *                       into slots of its two atoms' rows in LDS;
+ *   PV_VARIANT_GATHER   one atom per lane; per-pair coefficients in LDS, an
+ *                       atom -> pair table in global memory;
+ *   PV_VARIANT_GATHER2  two atoms per lane (ligands over 64 atoms), gather.
+ * Slots are chosen while they still let the CUs hold as many of the
+ * launch's waves as the gather layout would.  Any output may be NULL. */
+#define PV_KIND_DOCK 0
+#define PV_KIND_SCORE 1
+#define PV_KIND_LOCAL_OPT 2
+#define PV_VARIANT_SLOTS 0
+#define PV_VARIANT_GATHER 1
+#define PV_VARIANT_GATHER2 2
+pv_status pv_launch_info(pv_ctx* ctx, const pv_ligands* ligs, int32_t kind, int64_t items, int32_t* variant,
+                         int32_t* lds_bytes, int32_t* per_cu);
+
 #ifdef __cplusplus
 }
 #endif

@@ -87,6 +87,7 @@ SIGNATURES = {
     "pv_plan_free": (None, [_vp]),
     "pv_dock": (C.c_int, [_vp, _vp, _vp, C.POINTER(Job), _i32, C.POINTER(DockParams), C.POINTER(DockOut), _vp]),
     "pv_local_opt": (C.c_int, [_vp, _vp, _vp, _i32, _vp, _vp, _vp, _i32, C.POINTER(DockParams), _vp, _vp, _vp, _vp]),
+    "pv_launch_info": (C.c_int, [_vp, _vp, _i32, C.c_int64, _ip, _ip, _ip]),
 }
 
 
@@ -494,3 +495,16 @@ def local_opt(ctx: Context, grids: Grids, ligs: Ligands, lig_of_pose, box_of_pos
     _check(lib().pv_local_opt(ctx.h, grids.h, ligs.h, int(B), _ptr(lp), _ptr(bp), _ptr(dof), int(stride),
                               C.byref(p), _ptr(out), _ptr(e), _ptr(ne), _stream(stream)), "pv_local_opt")
     return out, e, ne
+
+
+KIND_DOCK, KIND_SCORE, KIND_LOCAL_OPT = 0, 1, 2
+VARIANT_SLOTS, VARIANT_GATHER, VARIANT_GATHER2 = 0, 1, 2
+
+
+def launch_info(ctx: Context, ligs: Ligands, kind: int, items: int):
+    """(variant, LDS bytes, workgroups per CU) of a launch of `kind` over
+    `items` waves on these ligands (host-side, no device work)."""
+    v, lds, occ = C.c_int32(), C.c_int32(), C.c_int32()
+    _check(lib().pv_launch_info(ctx.h, ligs.h, int(kind), int(items), C.byref(v), C.byref(lds), C.byref(occ)),
+           "pv_launch_info")
+    return v.value, lds.value, occ.value

@@ -109,6 +109,8 @@ struct pv_plan {
     float* scratch_best;      // chain_best_e when the caller does not want it
     int64_t* scratch_evals;   // chain_evals when only job_evals is wanted
     int32_t workgroups;
+    LaunchShape shape;        // batched launch
+    LaunchShape plain_shape;  // one launch per job
     hipStream_t cap_stream;
     hipGraph_t graph;
     hipGraphExec_t exec;
@@ -547,7 +549,7 @@ pv_status pv_score_grad(pv_ctx* ctx, const pv_grids* grids, const pv_ligands* li
     a.xyz_out = xyz_out;
     a.grad_xyz = grad_xyz;
     a.xyz_stride = xyz_stride;
-    hipError_t e = launch_score(a, (hipStream_t)stream);
+    hipError_t e = launch_score(a, ctx->n_cu, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "score launch");
     return PV_OK;
 }
@@ -579,7 +581,7 @@ pv_status pv_score_grad_xyz(pv_ctx* ctx, const pv_grids* grids, const pv_ligands
     a.e_parts = e_parts;
     a.grad_xyz = grad_xyz;
     a.xyz_stride = xyz_stride;
-    hipError_t e = launch_score(a, (hipStream_t)stream);
+    hipError_t e = launch_score(a, ctx->n_cu, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "score launch");
     return PV_OK;
 }
@@ -676,10 +678,11 @@ pv_status pv_dock_plan(pv_ctx* ctx, const pv_grids* grids, const pv_ligands* lig
         pv_plan_free(P);
         return st;
     }
-    int per_cu = 0;
-    hipError_t e = dock_occupancy(ligs->max_atoms, ligs->max_pairs, ligs->max_ell, &per_cu);
-    if (e != hipSuccess || per_cu < 1) per_cu = 1;
-    int64_t wg = params->workgroups > 0 ? params->workgroups : (int64_t)per_cu * ctx->n_cu;
+    const LigDev lv = lig_view(ligs);
+    hipError_t e = launch_shape(kKindDock, lv, (int64_t)nchain, ctx->n_cu, &P->shape);
+    if (e == hipSuccess) e = launch_shape(kKindDock, lv, params->chains, ctx->n_cu, &P->plain_shape);
+    if (e != hipSuccess) { pv_plan_free(P); return hip_fail(e, "dock launch shape"); }
+    int64_t wg = params->workgroups > 0 ? params->workgroups : (int64_t)P->shape.per_cu * ctx->n_cu;
     wg = std::min<int64_t>(wg, std::max<int64_t>((int64_t)nchain, 1));
     P->workgroups = (int32_t)wg;
     e = hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking);
@@ -732,7 +735,7 @@ static hipError_t enqueue_batched(pv_plan* P, const pv_dock_out* o, hipStream_t 
         e = launch_reset_times(o->job_t_start, o->job_t_end, P->n_jobs, s);
         if (e != hipSuccess) return e;
     }
-    e = launch_dock(a, P->workgroups, s);
+    e = launch_dock(a, P->shape, P->workgroups, s);
     if (e != hipSuccess) return e;
     if (o->job_best_e || o->job_best_chain || o->job_evals || o->job_status)
         e = launch_job_reduce(cbe, cev, P->n_jobs, P->sp.chains, o->job_best_e, o->job_best_chain, o->job_evals,
@@ -791,7 +794,7 @@ pv_status pv_dock_run_plain(pv_plan* P, const pv_dock_out* o, void* stream)
         a.job_begin = j;
         a.n_items = P->sp.chains;
         a.persistent = 0;
-        HIP_TRY(launch_dock(a, 0, s), "dock launch");
+        HIP_TRY(launch_dock(a, P->plain_shape, 0, s), "dock launch");
     }
     if (o->job_best_e || o->job_best_chain || o->job_evals || o->job_status)
         HIP_TRY(launch_job_reduce(cbe, cev, P->n_jobs, P->sp.chains, o->job_best_e, o->job_best_chain, o->job_evals,
@@ -853,8 +856,28 @@ pv_status pv_local_opt(pv_ctx* ctx, const pv_grids* grids, const pv_ligands* lig
     a.dof_out = dof_out;
     a.energy = energy;
     a.n_evals = n_evals;
-    hipError_t e = launch_local_opt(a, (hipStream_t)stream);
+    hipError_t e = launch_local_opt(a, ctx->n_cu, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "local-opt launch");
+    return PV_OK;
+}
+
+pv_status pv_launch_info(pv_ctx* ctx, const pv_ligands* ligs, int32_t kind, int64_t items, int32_t* variant,
+                         int32_t* lds_bytes, int32_t* per_cu)
+{
+    if (!ctx_ok(ctx)) return fail(PV_E_INVALID, "bad context");
+    if (!ligs) return fail(PV_E_INVALID, "ligands are NULL");
+    static_assert(PV_KIND_DOCK == kKindDock && PV_KIND_SCORE == kKindScore && PV_KIND_LOCAL_OPT == kKindOpt,
+                  "kernel kinds");
+    if (kind < PV_KIND_DOCK || kind > PV_KIND_LOCAL_OPT) return fail(PV_E_INVALID, "unknown kernel kind");
+    if (items < 0) return fail(PV_E_INVALID, "items < 0");
+    pv_status st = set_device(ctx);
+    if (st != PV_OK) return st;
+    LaunchShape sh;
+    hipError_t e = launch_shape(kind, lig_view(ligs), items, ctx->n_cu, &sh);
+    if (e != hipSuccess) return hip_fail(e, "launch shape");
+    if (variant) *variant = sh.variant;
+    if (lds_bytes) *lds_bytes = sh.lds;
+    if (per_cu) *per_cu = sh.per_cu;
     return PV_OK;
 }
 

@@ -168,16 +168,26 @@ struct GridBuildArgs {
 };
 
 hipError_t launch_build_grids(const GridBuildArgs& a, int64_t n_tiles, hipStream_t s);
-hipError_t launch_score(const ScoreArgs& a, hipStream_t s);
-hipError_t launch_dock(const DockArgs& a, int32_t workgroups, hipStream_t s);
+// Kernel variant of a launch: 0 = one atom per lane with LDS force slots,
+// 1 = one atom per lane with the coefficient gather, 2 = two atoms per lane
+// with the coefficient gather; lds = dynamic LDS bytes per workgroup and
+// per_cu = workgroups one CU holds at once.
+struct LaunchShape {
+    int variant;
+    int lds;
+    int per_cu;
+};
+enum KernelKind { kKindDock = 0, kKindScore = 1, kKindOpt = 2 };
+hipError_t launch_shape(int kind, const LigDev& l, int64_t items, int n_cu, LaunchShape* out);
+
+hipError_t launch_score(const ScoreArgs& a, int n_cu, hipStream_t s);
+hipError_t launch_dock(const DockArgs& a, const LaunchShape& sh, int32_t workgroups, hipStream_t s);
 hipError_t launch_reset_queue(uint32_t* q, hipStream_t s);
 hipError_t launch_job_reduce(const float* chain_best_e, const int64_t* chain_evals, int32_t n_jobs,
                              int32_t chains, float* job_best_e, int32_t* job_best_chain, int64_t* job_evals,
                              int32_t* job_status, hipStream_t s);
-hipError_t launch_local_opt(const OptArgs& a, hipStream_t s);
+hipError_t launch_local_opt(const OptArgs& a, int n_cu, hipStream_t s);
 hipError_t launch_reset_times(uint64_t* t0, uint64_t* t1, int n, hipStream_t s);
-hipError_t dock_occupancy(int max_atoms, int max_pairs, int max_ell, int* blocks_per_cu);
-int dock_lds_bytes(int max_atoms, int max_pairs, int max_ell);
 hipError_t init_device_tables(int device);
 
 // Tiles of the grid-map kernel.

@@ -246,23 +246,23 @@ struct Lds {
 
 __host__ __device__ inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
-// Ligands of at most 64 atoms (one atom per lane) keep their pair list in
-// LDS, packed with the slots each pair owns in its two atoms' rows, and the
-// per-slot pair forces (so an atom's intra force is a stream of independent
-// reads).  Larger ligands read the pair list and the atom -> pair table from
-// global memory and keep per-pair coefficients in LDS.
-__host__ __device__ inline bool tables_in_lds(int max_atoms) { return max_atoms <= 64; }
-
-__host__ __device__ inline int lds_bytes(int max_atoms, int max_pairs, int max_ell)
+// Two layouts of the intra-force tables.  Slots (ligands of at most 64
+// atoms, one atom per lane): the pair list sits in LDS, packed with the slots
+// each pair owns in its two atoms' rows, beside the per-slot pair forces, so
+// an atom's intra force is a stream of independent LDS reads.  Gather: the
+// pair list and the atom -> pair table are read from global memory and only
+// the per-pair coefficients live in LDS (a small footprint, for large
+// ligands or launches that need many resident waves).
+__host__ __device__ inline int lds_bytes(int max_atoms, int max_pairs, int max_ell, bool slots)
 {
     int ma = round_up(max_atoms < 1 ? 1 : max_atoms, 64);
     int b = 64 * 8 + kNSlots * kSlot * 4 + kMaxFrag * 13 * 4 + 12 + ma * 16 * 2 + 6 * ma * 4;
-    if (tables_in_lds(max_atoms)) b += round_up(max_pairs, 4) * 4 + max_ell * 16;
+    if (slots) b += round_up(max_pairs, 4) * 4 + max_ell * 16;
     else b += round_up(max_pairs + 1, 4) * 4;
     return b;
 }
 
-__device__ __forceinline__ Lds carve(char* base, int max_atoms, int max_pairs, int max_ell)
+__device__ __forceinline__ Lds carve(char* base, int max_atoms, int max_pairs, int max_ell, bool slots)
 {
     Lds s;
     int ma = round_up(max_atoms < 1 ? 1 : max_atoms, 64);
@@ -274,7 +274,7 @@ __device__ __forceinline__ Lds carve(char* base, int max_atoms, int max_pairs, i
     s.frame = (float*)p; p += kMaxFrag * 13 * 4 + 12;
     s.pre = (float*)p; p += 6 * ma * 4;
     s.ell = nullptr;
-    if (tables_in_lds(max_atoms)) {
+    if (slots) {
         s.pairs = (uint32_t*)p; p += round_up(max_pairs, 4) * 4;
         s.fs = (float4*)p;
         s.cp = nullptr;
@@ -296,7 +296,7 @@ __device__ __forceinline__ void stage_tp(const Lds& S, const float* rsum, const 
 // ---------------------------------------------------------------- staged ligand
 // Topology lives in registers: atoms blocked A per lane (atom = lane*A + a),
 // fragments one per lane, and for lane 6+k the fragment of torsion k.
-template <int A>
+template <int A, bool SL>
 struct Topo {
     int n, nf, nt, np, rounds, lig, ell_w, fs_stride;
     float anc_x, anc_y, anc_z, rot_scale;
@@ -308,8 +308,8 @@ struct Topo {
     const uint32_t* gell;     // memory (read from there when A > 1)
 };
 
-template <int A>
-__device__ void stage_ligand(Topo<A>& T, const LigDev& L, int lig, const Lds& S)
+template <int A, bool SL>
+__device__ void stage_ligand(Topo<A, SL>& T, const LigDev& L, int lig, const Lds& S)
 {
     const int l = lane_id();
     const DevLig d = L.ligs[lig];
@@ -337,7 +337,7 @@ __device__ void stage_ligand(Topo<A>& T, const LigDev& L, int lig, const Lds& S)
     T.dof_frag = (l >= 6 && l < 6 + T.nt) ? (int)L.tors_frag[d.tors_base + l - 6] : 0;
     T.gpairs = L.pairs + d.pair_base;
     T.gell = L.ell + d.ell_base;
-    if (A == 1) {
+    if (SL) {
         // pair word: i | j << 6 | type pair << 12 | slot in row i << 18 | slot in row j << 24
         const uint32_t* ps = L.pslot + d.pair_base;
         for (int p = l; p < T.np; p += kWave) {
@@ -364,8 +364,8 @@ struct Eval {
 // starts from its local map (the root's pose map, or the rotation by psi
 // about its torsion axis) and composes with its ancestors by pointer
 // doubling; after `rounds` rounds every frame is world-absolute.
-template <int A>
-__device__ __forceinline__ void frames(const Topo<A>& T, const Lds& S, const float* pose, float R[9], float b[3])
+template <int A, bool SL>
+__device__ __forceinline__ void frames(const Topo<A, SL>& T, const Lds& S, const float* pose, float R[9], float b[3])
 {
     const int l = lane_id();
     const float tx = pose[0], ty = pose[1], tz = pose[2];
@@ -469,8 +469,8 @@ __device__ __forceinline__ void pair_term(float4 xi, float4 xj, float2 tpe, floa
 // counts pairs inside the cutoff.
 constexpr int kPairUnroll = 4;
 
-template <int A>
-__device__ __forceinline__ float pair_loop(const Topo<A>& T, const Lds& S, int& cnt)
+template <int A, bool SL>
+__device__ __forceinline__ float pair_loop(const Topo<A, SL>& T, const Lds& S, int& cnt)
 {
     constexpr int U = kPairUnroll;
     const int l = lane_id();
@@ -484,7 +484,7 @@ __device__ __forceinline__ float pair_loop(const Topo<A>& T, const Lds& S, int& 
             const int p = p0 + u * kWave;
             v[u] = p < np;
             // a lane past the end reads pair 0 (np >= 1 here) and discards it
-            pk[u] = A == 1 ? S.pairs[v[u] ? p : 0] : T.gpairs[v[u] ? p : 0];
+            pk[u] = SL ? S.pairs[v[u] ? p : 0] : T.gpairs[v[u] ? p : 0];
         }
         int ii[U], jj[U];
         float4 xi[U], xj[U];
@@ -492,7 +492,7 @@ __device__ __forceinline__ float pair_loop(const Topo<A>& T, const Lds& S, int& 
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             int t;
-            if (A == 1) {
+            if (SL) {
                 ii[u] = pk[u] & 0x3f; jj[u] = (pk[u] >> 6) & 0x3f; t = (pk[u] >> 12) & 0x3f;
             } else {
                 ii[u] = pk[u] & 0xff; jj[u] = (pk[u] >> 8) & 0xff; t = pk[u] >> 16;
@@ -509,7 +509,7 @@ __device__ __forceinline__ float pair_loop(const Topo<A>& T, const Lds& S, int& 
             e += v[u] ? eu : 0.f;
             cnt += __popcll(__ballot(in && v[u]));
             if (v[u]) {
-                if (A == 1) {
+                if (SL) {
                     const float fx = c * dx, fy = c * dy, fz = c * dz;
                     S.fs[((pk[u] >> 18) & 0x3f) * ns + ii[u]] = make_float4(fx, fy, fz, 0.f);
                     S.fs[((pk[u] >> 24) & 0x3f) * ns + jj[u]] = make_float4(-fx, -fy, -fz, 0.f);
@@ -525,12 +525,12 @@ __device__ __forceinline__ float pair_loop(const Topo<A>& T, const Lds& S, int& 
 // dE/dx_i of the intra term.  LDS tables: the sum of atom i's row of pair
 // forces (independent reads, rows padded to a multiple of four with zeros).
 // Global tables: sum over the pairs holding atom i of c_p (x_i - x_j).
-template <int A>
-__device__ __forceinline__ void gather_pair_forces(const Topo<A>& T, const Lds& S, int i, float4 xi, float& gx,
+template <int A, bool SL>
+__device__ __forceinline__ void gather_pair_forces(const Topo<A, SL>& T, const Lds& S, int i, float4 xi, float& gx,
                                                    float& gy, float& gz)
 {
     const int n = T.n;
-    if (A == 1) {
+    if (SL) {
         for (int k = 0; k < T.ell_w; k += 4) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -559,8 +559,8 @@ __device__ __forceinline__ void gather_pair_forces(const Topo<A>& T, const Lds& 
 
 // Score and tangent gradient of the pose in `pose` (an LDS slot).  Leaves
 // atom positions in S.pos and dE/dx in S.frc.
-template <int A>
-__device__ Eval evaluate(const Topo<A>& T, const BoxView& B, const Lds& S, const float* pose)
+template <int A, bool SL>
+__device__ Eval evaluate(const Topo<A, SL>& T, const BoxView& B, const Lds& S, const float* pose)
 {
     const int l = lane_id();
     Eval out;
@@ -670,8 +670,8 @@ __device__ Eval evaluate(const Topo<A>& T, const BoxView& B, const Lds& S, const
 }
 
 // Score on given coordinates already in S.pos: forces in S.frc.
-template <int A>
-__device__ Eval evaluate_xyz(const Topo<A>& T, const BoxView& B, const Lds& S)
+template <int A, bool SL>
+__device__ Eval evaluate_xyz(const Topo<A, SL>& T, const BoxView& B, const Lds& S)
 {
     const int l = lane_id();
     Eval out;
@@ -746,8 +746,8 @@ struct BfgsOut {
 // Minimises from the pose in SLOT_X; the result is left in SLOT_X.  Written
 // as one loop around a single evaluation (the first at x0, then one per
 // line-search trial) so the kernel carries one copy of the evaluation code.
-template <int A>
-__device__ BfgsOut bfgs(const Topo<A>& T, const BoxView& B, const Lds& S, const SearchParams& P, int max_iter)
+template <int A, bool SL>
+__device__ BfgsOut bfgs(const Topo<A, SL>& T, const BoxView& B, const Lds& S, const SearchParams& P, int max_iter)
 {
     const int l = lane_id();
     const int nd = 6 + T.nt;
@@ -861,8 +861,8 @@ struct ChainOut {
     int64_t evals, pairs;
 };
 
-template <int A>
-__device__ void init_pose(const Topo<A>& T, const BoxView& B, const Lds& S, int slot, uint64_t seed, int job,
+template <int A, bool SL>
+__device__ void init_pose(const Topo<A, SL>& T, const BoxView& B, const Lds& S, int slot, uint64_t seed, int job,
                           int chain)
 {
     const int l = lane_id();
@@ -886,8 +886,8 @@ __device__ void init_pose(const Topo<A>& T, const BoxView& B, const Lds& S, int 
 }
 
 // Mutation of one POT entity (Eq. qvina_eq_2) from the 8 words w of the step.
-template <int A>
-__device__ void mutate(const Topo<A>& T, const Lds& S, int slot, const SearchParams& P, const uint64_t w[8])
+template <int A, bool SL>
+__device__ void mutate(const Topo<A, SL>& T, const Lds& S, int slot, const SearchParams& P, const uint64_t w[8])
 {
     const int l = lane_id();
     float* x = S.pose + slot * kSlot;
@@ -927,8 +927,8 @@ __device__ void mutate(const Topo<A>& T, const Lds& S, int slot, const SearchPar
     wave_sync();
 }
 
-template <int A>
-__device__ ChainOut mc_chain(const Topo<A>& T, const BoxView& B, const Lds& S, const SearchParams& P, int job,
+template <int A, bool SL>
+__device__ ChainOut mc_chain(const Topo<A, SL>& T, const BoxView& B, const Lds& S, const SearchParams& P, int job,
                              int chain)
 {
     const int l = lane_id();
@@ -986,14 +986,14 @@ __device__ ChainOut mc_chain(const Topo<A>& T, const BoxView& B, const Lds& S, c
 __constant__ float c_rsum[64];
 __constant__ uint32_t c_tpflags[64];
 
-template <int A>
+template <int A, bool SL>
 __global__ __launch_bounds__(64) void dock_kernel(DockArgs a)
 {
     extern __shared__ __align__(16) char smem[];
-    const Lds S = carve(smem, a.l.max_atoms, a.l.max_pairs, a.l.max_ell);
+    const Lds S = carve(smem, a.l.max_atoms, a.l.max_pairs, a.l.max_ell, SL);
     const int l = lane_id();
     stage_tp(S, c_rsum, c_tpflags);
-    Topo<A> T;
+    Topo<A, SL> T;
     T.lig = -1;
     const int chains = a.sp.chains;
     int64_t item = a.persistent ? -1 : (int64_t)blockIdx.x;
@@ -1057,17 +1057,21 @@ __global__ void job_reduce_kernel(const float* cbe, const int64_t* cev, int n_jo
     if (jst) jst[j] = isfinite(be) ? 0 : 1;
 }
 
-template <int A>
+template <int A, bool SL>
 __global__ __launch_bounds__(64) void score_kernel(ScoreArgs a)
 {
     extern __shared__ __align__(16) char smem[];
-    const Lds S = carve(smem, a.l.max_atoms, a.l.max_pairs, a.l.max_ell);
+    const Lds S = carve(smem, a.l.max_atoms, a.l.max_pairs, a.l.max_ell, SL);
     const int l = lane_id();
     stage_tp(S, c_rsum, c_tpflags);
-    Topo<A> T;
+    Topo<A, SL> T;
     T.lig = -1;
     const float nanv = __int_as_float(0x7fc00000);
-    for (int pose = blockIdx.x; pose < a.n_poses; pose += gridDim.x) {
+    // a contiguous run of poses per workgroup: runs of one ligand stage it once
+    const int chunk = (a.n_poses + (int)gridDim.x - 1) / (int)gridDim.x;
+    const int p_begin = (int)blockIdx.x * chunk;
+    const int p_end = min(a.n_poses, p_begin + chunk);
+    for (int pose = p_begin; pose < p_end; ++pose) {
         const int lig = a.lig_of_pose[pose], box = a.box_of_pose[pose];
         if (lig < 0 || lig >= a.l.n_lig || box < 0 || box >= a.g.n_boxes) {
             if (l == 0 && a.energy) a.energy[pose] = nanv;
@@ -1130,14 +1134,14 @@ __global__ __launch_bounds__(64) void score_kernel(ScoreArgs a)
     }
 }
 
-template <int A>
+template <int A, bool SL>
 __global__ __launch_bounds__(64) void local_opt_kernel(OptArgs a)
 {
     extern __shared__ __align__(16) char smem[];
-    const Lds S = carve(smem, a.l.max_atoms, a.l.max_pairs, a.l.max_ell);
+    const Lds S = carve(smem, a.l.max_atoms, a.l.max_pairs, a.l.max_ell, SL);
     const int l = lane_id();
     stage_tp(S, c_rsum, c_tpflags);
-    Topo<A> T;
+    Topo<A, SL> T;
     T.lig = -1;
     for (int pose = blockIdx.x; pose < a.n_poses; pose += gridDim.x) {
         const int lig = a.lig_of_pose[pose], box = a.box_of_pose[pose];
@@ -1262,8 +1266,6 @@ __global__ __launch_bounds__(256) void gridmap_kernel(GridBuildArgs a)
 }
 
 // ---------------------------------------------------------------- launchers
-int dock_lds_bytes(int max_atoms, int max_pairs, int max_ell) { return lds_bytes(max_atoms, max_pairs, max_ell); }
-
 // The type-pair table lives in __constant__ memory of every device; it is
 // written once per device when a context is created on it (never during a
 // stream capture).
@@ -1298,31 +1300,77 @@ hipError_t launch_build_grids(const GridBuildArgs& a, int64_t n_tiles, hipStream
     return hipGetLastError();
 }
 
-hipError_t launch_score(const ScoreArgs& a, hipStream_t s)
+template <typename K>
+static int occupancy(K kernel, int lds)
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, 64, lds) != hipSuccess) return 0;
+    return n;
+}
+
+template <int A, bool SL>
+static int kind_occupancy(int kind, int lds)
+{
+    if (kind == kKindDock) return occupancy(dock_kernel<A, SL>, lds);
+    if (kind == kKindScore) return occupancy(score_kernel<A, SL>, lds);
+    return occupancy(local_opt_kernel<A, SL>, lds);
+}
+
+// Slots are faster per evaluation but take 16 B per pair end in LDS; they
+// are used while the CUs can still hold as many of the launch's waves as the
+// gather layout would (a persistent launch over few chains, or small
+// ligands), else the gather layout keeps the occupancy.
+hipError_t launch_shape(int kind, const LigDev& l, int64_t items, int n_cu, LaunchShape* out)
+{
+    const int64_t cus = n_cu > 0 ? n_cu : 1;
+    if (l.max_atoms > 64) {
+        const int lds = lds_bytes(l.max_atoms, l.max_pairs, l.max_ell, false);
+        *out = {2, lds, kind_occupancy<2, false>(kind, lds)};
+        return out->per_cu > 0 ? hipSuccess : hipErrorInvalidConfiguration;
+    }
+    const int lds_s = lds_bytes(l.max_atoms, l.max_pairs, l.max_ell, true);
+    const int lds_g = lds_bytes(l.max_atoms, l.max_pairs, l.max_ell, false);
+    const int occ_s = kind_occupancy<1, true>(kind, lds_s);
+    const int occ_g = kind_occupancy<1, false>(kind, lds_g);
+    const int64_t need = std::min<int64_t>(items > 0 ? items : 1, (int64_t)occ_g * cus);
+    if (occ_s > 0 && (int64_t)occ_s * cus >= need)
+        *out = {0, lds_s, occ_s};
+    else
+        *out = {1, lds_g, occ_g};
+    return out->per_cu > 0 ? hipSuccess : hipErrorInvalidConfiguration;
+}
+
+hipError_t launch_score(const ScoreArgs& a, int n_cu, hipStream_t s)
 {
     hipError_t e = ensure_tables();
     if (e != hipSuccess) return e;
     if (a.n_poses <= 0) return hipSuccess;
-    const int lds = lds_bytes(a.l.max_atoms, a.l.max_pairs, a.l.max_ell);
-    const int grid = a.n_poses < 65536 ? a.n_poses : 65536;
-    if (a.l.max_atoms <= 64)
-        hipLaunchKernelGGL(score_kernel<1>, dim3(grid), dim3(64), lds, s, a);
+    LaunchShape sh;
+    if ((e = launch_shape(kKindScore, a.l, a.n_poses, n_cu, &sh)) != hipSuccess) return e;
+    // one resident wave per slot the CUs can hold; each takes a contiguous run
+    const int64_t cap = (int64_t)sh.per_cu * (n_cu > 0 ? n_cu : 1);
+    const int grid = (int)(a.n_poses < cap ? a.n_poses : cap);
+    if (sh.variant == 0)
+        hipLaunchKernelGGL((score_kernel<1, true>), dim3(grid), dim3(64), sh.lds, s, a);
+    else if (sh.variant == 1)
+        hipLaunchKernelGGL((score_kernel<1, false>), dim3(grid), dim3(64), sh.lds, s, a);
     else
-        hipLaunchKernelGGL(score_kernel<2>, dim3(grid), dim3(64), lds, s, a);
+        hipLaunchKernelGGL((score_kernel<2, false>), dim3(grid), dim3(64), sh.lds, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_dock(const DockArgs& a, int32_t workgroups, hipStream_t s)
+hipError_t launch_dock(const DockArgs& a, const LaunchShape& sh, int32_t workgroups, hipStream_t s)
 {
     hipError_t e = ensure_tables();
     if (e != hipSuccess) return e;
     if (a.n_items <= 0) return hipSuccess;
-    const int lds = lds_bytes(a.l.max_atoms, a.l.max_pairs, a.l.max_ell);
     const unsigned grid = a.persistent ? (unsigned)workgroups : (unsigned)a.n_items;
-    if (a.l.max_atoms <= 64)
-        hipLaunchKernelGGL(dock_kernel<1>, dim3(grid), dim3(64), lds, s, a);
+    if (sh.variant == 0)
+        hipLaunchKernelGGL((dock_kernel<1, true>), dim3(grid), dim3(64), sh.lds, s, a);
+    else if (sh.variant == 1)
+        hipLaunchKernelGGL((dock_kernel<1, false>), dim3(grid), dim3(64), sh.lds, s, a);
     else
-        hipLaunchKernelGGL(dock_kernel<2>, dim3(grid), dim3(64), lds, s, a);
+        hipLaunchKernelGGL((dock_kernel<2, false>), dim3(grid), dim3(64), sh.lds, s, a);
     return hipGetLastError();
 }
 
@@ -1348,26 +1396,21 @@ hipError_t launch_job_reduce(const float* cbe, const int64_t* cev, int32_t n_job
     return hipGetLastError();
 }
 
-hipError_t launch_local_opt(const OptArgs& a, hipStream_t s)
+hipError_t launch_local_opt(const OptArgs& a, int n_cu, hipStream_t s)
 {
     hipError_t e = ensure_tables();
     if (e != hipSuccess) return e;
     if (a.n_poses <= 0) return hipSuccess;
-    const int lds = lds_bytes(a.l.max_atoms, a.l.max_pairs, a.l.max_ell);
+    LaunchShape sh;
+    if ((e = launch_shape(kKindOpt, a.l, a.n_poses, n_cu, &sh)) != hipSuccess) return e;
     const int grid = a.n_poses < 65536 ? a.n_poses : 65536;
-    if (a.l.max_atoms <= 64)
-        hipLaunchKernelGGL(local_opt_kernel<1>, dim3(grid), dim3(64), lds, s, a);
+    if (sh.variant == 0)
+        hipLaunchKernelGGL((local_opt_kernel<1, true>), dim3(grid), dim3(64), sh.lds, s, a);
+    else if (sh.variant == 1)
+        hipLaunchKernelGGL((local_opt_kernel<1, false>), dim3(grid), dim3(64), sh.lds, s, a);
     else
-        hipLaunchKernelGGL(local_opt_kernel<2>, dim3(grid), dim3(64), lds, s, a);
+        hipLaunchKernelGGL((local_opt_kernel<2, false>), dim3(grid), dim3(64), sh.lds, s, a);
     return hipGetLastError();
-}
-
-hipError_t dock_occupancy(int max_atoms, int max_pairs, int max_ell, int* blocks_per_cu)
-{
-    const int lds = lds_bytes(max_atoms, max_pairs, max_ell);
-    if (max_atoms <= 64)
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, dock_kernel<1>, 64, lds);
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, dock_kernel<2>, 64, lds);
 }
 
 }  // namespace pv
