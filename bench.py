@@ -57,6 +57,12 @@ def main():
     ap.add_argument("--no-score", action="store_true")
     ap.add_argument("--cpu-chains", type=int, default=128)
     ap.add_argument("--workgroups", type=int, default=0)
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the uneven-batch (batched vs plain) and screening-stream legs")
+    ap.add_argument("--batch-ligands", type=int, default=256,
+                    help="ligands of the uneven batch (x 5 pockets = jobs)")
+    ap.add_argument("--plain-jobs", type=int, default=20, help="jobs of the uneven batch run one launch each")
+    ap.add_argument("--stream-jobs", type=int, default=2048, help="jobs taken from the screening stream")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device (calibrates the HBM byte counters) and exit")
     args = ap.parse_args()
@@ -178,6 +184,9 @@ def main():
     }
     if not args.no_score:
         result["score_grad"] = bench_score(pv, S, ctx, stream)
+    if not args.no_extra:
+        result["batching"] = bench_batching(pv, S, ctx, stream, args)
+        result["screening"] = bench_screening(pv, S, ctx, stream, args)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(S, cfg, rx, rt, bxs, mols, seed, args)
     print(json.dumps(result), flush=True)
@@ -234,6 +243,100 @@ def bench_score(pv, S, ctx, stream):
     ms = a.elapsed_time(b) / reps
     return {"workload": "16,384 poses, 64 ligands of 40 atoms / 10 torsions, one 24 A pocket",
             "ms_per_call": ms, "evals_per_s": cfg.n_poses / (ms * 1e-3)}
+
+
+def _timed(stream, fn):
+    import torch
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b)
+
+
+def bench_batching(pv, S, ctx, stream, args):
+    """Batched vs plain on the uneven batch: ligands of 10..60 atoms and
+    0..15 torsions, each docked into the 5 pockets of the multi-pocket
+    receptor, 32 chains x 500 MC steps per job.  The batched form runs the
+    first --batch-ligands x 5 jobs as one persistent hipGraph launch; the
+    plain form runs the first --plain-jobs jobs one launch each, and the same
+    jobs are also run batched."""
+    import torch
+    cfg = S.CONFIGS["c3"]
+    rx, rt, bxs = S.make_receptor(cfg)
+    mols = S.make_ligands(cfg, args.batch_ligands)
+    grids = pv.build_grids(ctx, rx, rt, bxs, penalty_slope=10.0)
+    ligs = pv.Ligands(ctx, mols)
+    jobs = S.make_jobs(cfg)[:args.batch_ligands * len(bxs)]
+    params = pv.dock_params(chains=cfg.chains, steps=cfg.steps, seed=S.philox_seed(cfg), flags=pv.PV_DOCK_GRAPH)
+    plan = pv.Plan(ctx, grids, ligs, jobs, params)
+    plan.run()
+    torch.cuda.synchronize()
+    ms = _timed(stream, plan.run)
+    ev = int(plan.outputs()["job_evals"].sum().item())
+    variant = pv.launch_info(ctx, ligs, pv.KIND_DOCK, len(jobs) * cfg.chains)[0]
+    plan.close()
+    few = jobs[:args.plain_jobs]
+    pplan = pv.Plan(ctx, grids, ligs, few, params)
+    pplan.run()
+    torch.cuda.synchronize()
+    ms_same = _timed(stream, pplan.run)
+    ms_plain = _timed(stream, lambda: pplan.run(plain=True))
+    ev_plain = int(pplan.outputs()["job_evals"].sum().item())
+    pplan.close()
+    names = ["slots", "gather", "gather2"]
+    return {
+        "workload": "uneven batch: ligands of 10..60 atoms / 0..15 torsions x 5 pockets of 24 A, "
+                    "32 chains x 500 MC steps per job",
+        "batched": {"jobs": len(jobs), "docks_per_s": len(jobs) / (ms * 1e-3), "evals_per_s": ev / (ms * 1e-3),
+                    "ms": ms, "variant": names[variant]},
+        "plain": {"jobs": len(few), "docks_per_s": len(few) / (ms_plain * 1e-3),
+                  "evals_per_s": ev_plain / (ms_plain * 1e-3), "ms": ms_plain},
+        "batched_same_jobs": {"jobs": len(few), "docks_per_s": len(few) / (ms_same * 1e-3), "ms": ms_same},
+        "batched_over_plain": (len(jobs) / ms) / (len(few) / ms_plain),
+    }
+
+
+def bench_screening(pv, S, ctx, stream, args):
+    """The screening stream: an 8,000-atom receptor with 16 pockets of
+    20..30 A (all maps resident), ligands of 8..80 atoms / 0..20 torsions,
+    16 chains x 300 MC steps per job, jobs in the stream's seeded order.  The
+    first --stream-jobs jobs run as one persistent launch with per-job device
+    timestamps: service time = last chain done - first chain dequeued."""
+    import torch
+    cfg = S.CONFIGS["c5"]
+    rx, rt, bxs = S.make_receptor(cfg)
+    jobs = S.make_jobs(cfg)[:args.stream_jobs]
+    uniq, local = np.unique(jobs[:, 0], return_inverse=True)
+    mols = [S.make_ligands(cfg, 1, int(i))[0] for i in uniq]
+    grids = pv.build_grids(ctx, rx, rt, bxs, penalty_slope=10.0)
+    torch.cuda.synchronize()
+    grid_ms = _timed(stream, grids.rebuild)
+    ligs = pv.Ligands(ctx, mols)
+    jl = np.stack([local.astype(np.int32), jobs[:, 1]], axis=1)
+    params = pv.dock_params(chains=cfg.chains, steps=cfg.steps, seed=S.philox_seed(cfg),
+                            flags=pv.PV_DOCK_GRAPH | pv.PV_DOCK_TIMESTAMPS)
+    plan = pv.Plan(ctx, grids, ligs, jl, params)
+    plan.run()
+    torch.cuda.synchronize()
+    ms = _timed(stream, plan.run)
+    out = plan.outputs()
+    t0 = out["job_t_start"].cpu().numpy().astype(np.int64)
+    t1 = out["job_t_end"].cpu().numpy().astype(np.int64)
+    ev = int(out["job_evals"].sum().item())
+    plan.close()
+    svc = (t1 - t0) / 100.0          # device clock ticks at 100 MHz -> us
+    span = (t1.max() - t0.min()) / 100.0
+    map_mb = sum(8 * int(np.prod(grids.info(b)[0])) * 4 for b in range(len(bxs))) / 1e6
+    return {
+        "workload": "screening stream: 8,000-atom receptor, 16 pockets of 20..30 A (%.0f MB of maps), "
+                    "ligands of 8..80 atoms / 0..20 torsions, 16 chains x 300 MC steps, first %d jobs "
+                    "of the seeded order" % (map_mb, len(jobs)),
+        "jobs": len(jobs), "ms": ms, "docks_per_s": len(jobs) / (ms * 1e-3), "evals_per_s": ev / (ms * 1e-3),
+        "service_us_p50": float(np.percentile(svc, 50)), "service_us_p99": float(np.percentile(svc, 99)),
+        "service_us_max": float(svc.max()), "makespan_us": float(span), "grid_build_ms_16_pockets": grid_ms,
+    }
 
 
 def cpu_baseline(S, cfg, rx, rt, bxs, mols, seed, args):
