@@ -55,6 +55,19 @@ __device__ __forceinline__ float wsum(float v)
     return (lane_f(v, 0) + lane_f(v, 16)) + (lane_f(v, 32) + lane_f(v, 48));
 }
 
+// sum over lanes 0..n-1 of v, where every lane from n up holds zero (n is
+// wave-uniform): rows past the last non-zero one are not read
+__device__ __forceinline__ float wsum_n(float v, int n)
+{
+    v += dpp0<0xB1>(v);
+    v += dpp0<0x4E>(v);
+    v += dpp0<0x141>(v);
+    v += dpp0<0x140>(v);
+    if (n <= 16) return lane_f(v, 0);
+    if (n <= 32) return lane_f(v, 0) + lane_f(v, 16);
+    return (lane_f(v, 0) + lane_f(v, 16)) + (lane_f(v, 32) + lane_f(v, 48));
+}
+
 // inclusive prefix sum over the 64 lanes in lane order
 __device__ __forceinline__ float wscan(float v)
 {
@@ -117,17 +130,20 @@ __device__ __forceinline__ void quat_mul(const float a[4], const float b[4], flo
 
 __device__ __forceinline__ void rotvec_quat(float tx, float ty, float tz, float q[4])
 {
-    // (cos(a/2), sin(a/2)/a * theta); sin(a/2)/a -> 1/2 as a -> 0
-    const float a = sqrtf(tx * tx + ty * ty + tz * tz);
+    // (cos(a/2), sin(a/2)/a * theta); sin(a/2)/a -> 1/2 as a -> 0.  One
+    // v_rsq gives both a = a^2 / a and 1 / a (hardware, ~1 ulp).
+    const float a2 = tx * tx + ty * ty + tz * tz;
+    const float inv = __builtin_amdgcn_rsqf(fmaxf(a2, 1e-30f));
+    const float a = a2 * inv;
     float s, c;
     __sincosf(0.5f * a, &s, &c);
-    const float k = a > 0.f ? __fdividef(s, a) : 0.5f;
+    const float k = a2 > 1e-30f ? s * inv : 0.5f;
     q[0] = c; q[1] = k * tx; q[2] = k * ty; q[3] = k * tz;
 }
 
 __device__ __forceinline__ void quat_normalize(float q[4])
 {
-    float n = rsqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    const float n = __builtin_amdgcn_rsqf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
     q[0] *= n; q[1] *= n; q[2] *= n; q[3] *= n;
 }
 
@@ -231,13 +247,13 @@ constexpr int kSlot = 40;
 enum { SLOT_X = 0, SLOT_XT = 1, SLOT_XA = 2, SLOT_CUR = 3, SLOT_BEST = 4, kNSlots = 5 };
 
 struct Lds {
-    float2* tp;        // [64] (Rsum, flags-as-bits)
+    float4* tp;        // [64] (Rsum, hydrophobic weight or 0, hydrogen-bond weight or 0, 0)
     float* pose;       // [kNSlots][kSlot]
     float* frame;      // [kMaxFrag][12] frames, then [kMaxFrag] ancestor links
     float4* pos;       // [max_atoms]
     float4* frc;       // [max_atoms]
     float* pre;        // [6][max_atoms]
-    uint32_t* pairs;   // [max_pairs]
+    uint2* pairs;      // [max_pairs] (i | j << 6 | type pair << 12, slot index of i | slot index of j << 16)
     float* cp;         // [max_pairs + 1] per-pair force coefficient (last = 0), global-table path
     uint32_t* ell;     // unused in LDS (the global-table path reads the table from memory)
     float4* fs;        // [max_ell] pair forces in atom-row slots (row stride n | 1), LDS-table path
@@ -256,8 +272,8 @@ __host__ __device__ inline int round_up(int v, int m) { return (v + m - 1) / m *
 __host__ __device__ inline int lds_bytes(int max_atoms, int max_pairs, int max_ell, bool slots)
 {
     int ma = round_up(max_atoms < 1 ? 1 : max_atoms, 64);
-    int b = 64 * 8 + kNSlots * kSlot * 4 + kMaxFrag * 13 * 4 + 12 + ma * 16 * 2 + 6 * ma * 4;
-    if (slots) b += round_up(max_pairs, 4) * 4 + max_ell * 16;
+    int b = 64 * 16 + kNSlots * kSlot * 4 + kMaxFrag * 13 * 4 + 12 + ma * 16 * 2 + 6 * ma * 4;
+    if (slots) b += round_up(max_pairs, 2) * 8 + max_ell * 16;
     else b += round_up(max_pairs + 1, 4) * 4;
     return b;
 }
@@ -267,7 +283,7 @@ __device__ __forceinline__ Lds carve(char* base, int max_atoms, int max_pairs, i
     Lds s;
     int ma = round_up(max_atoms < 1 ? 1 : max_atoms, 64);
     char* p = base;
-    s.tp = (float2*)p; p += 64 * 8;
+    s.tp = (float4*)p; p += 64 * 16;
     s.pos = (float4*)p; p += ma * 16;
     s.frc = (float4*)p; p += ma * 16;
     s.pose = (float*)p; p += kNSlots * kSlot * 4;
@@ -275,7 +291,7 @@ __device__ __forceinline__ Lds carve(char* base, int max_atoms, int max_pairs, i
     s.pre = (float*)p; p += 6 * ma * 4;
     s.ell = nullptr;
     if (slots) {
-        s.pairs = (uint32_t*)p; p += round_up(max_pairs, 4) * 4;
+        s.pairs = (uint2*)p; p += round_up(max_pairs, 2) * 8;
         s.fs = (float4*)p;
         s.cp = nullptr;
     } else {
@@ -290,7 +306,8 @@ __device__ __forceinline__ Lds carve(char* base, int max_atoms, int max_pairs, i
 __device__ __forceinline__ void stage_tp(const Lds& S, const float* rsum, const uint32_t* flags)
 {
     int l = lane_id();
-    S.tp[l] = make_float2(rsum[l], __uint_as_float(flags[l]));
+    const uint32_t f = flags[l];
+    S.tp[l] = make_float4(rsum[l], (f & 1u) ? kW4 : 0.f, (f & 2u) ? kW5 : 0.f, 0.f);
 }
 
 // ---------------------------------------------------------------- staged ligand
@@ -338,12 +355,15 @@ __device__ void stage_ligand(Topo<A, SL>& T, const LigDev& L, int lig, const Lds
     T.gpairs = L.pairs + d.pair_base;
     T.gell = L.ell + d.ell_base;
     if (SL) {
-        // pair word: i | j << 6 | type pair << 12 | slot in row i << 18 | slot in row j << 24
+        // pair record: i | j << 6 | type pair << 12, and the slot indices
+        // (slot * row stride + atom) the pair's forces go to in the two rows
         const uint32_t* ps = L.pslot + d.pair_base;
+        const uint32_t ns = (uint32_t)T.fs_stride;
         for (int p = l; p < T.np; p += kWave) {
             const uint32_t pk = T.gpairs[p], sl = ps[p];
-            S.pairs[p] = (pk & 0x3f) | (((pk >> 8) & 0x3f) << 6) | ((pk >> 16) << 12) | ((sl & 0x3f) << 18) |
-                         (((sl >> 16) & 0x3f) << 24);
+            const uint32_t i = pk & 0xff, j = (pk >> 8) & 0xff;
+            S.pairs[p] = make_uint2(i | (j << 6) | ((pk >> 16) << 12),
+                                    ((sl & 0xffff) * ns + i) | (((sl >> 16) * ns + j) << 16));
         }
         const int nfs = T.ell_w * T.fs_stride;
         for (int k = l; k < nfs; k += kWave) S.fs[k] = make_float4(0.f, 0.f, 0.f, 0.f);   // padding stays zero
@@ -432,13 +452,12 @@ __device__ __forceinline__ void frames(const Topo<A, SL>& T, const Lds& S, const
 
 // One intra pair: the Vina-form energy inside 8 A and the force
 // coefficient c = (dphi/dr) / r (0 outside the cutoff).
-__device__ __forceinline__ void pair_term(float4 xi, float4 xj, float2 tpe, float& en_out, float& c_out, bool& inside,
+__device__ __forceinline__ void pair_term(float4 xi, float4 xj, float4 tpe, float& en_out, float& c_out, bool& inside,
                                           float& dx, float& dy, float& dz)
 {
     dx = xi.x - xj.x; dy = xi.y - xj.y; dz = xi.z - xj.z;
     const float r2 = dx * dx + dy * dy + dz * dz;
     inside = r2 < kCut2;
-    const uint32_t fl = __float_as_uint(tpe.y);
     // one v_rsq_f32: r = r2 / sqrt(r2) and c = de / r = de * rsq; a zero
     // distance gets a tiny finite r and its zero direction zeroes the force
     const float r2c = fmaxf(r2, 1e-12f);
@@ -449,13 +468,14 @@ __device__ __forceinline__ void pair_term(float4 xi, float4 xj, float2 tpe, floa
     const float dm3 = d - 3.f;
     const float g2 = __expf(-0.25f * dm3 * dm3);
     const float dn = fminf(d, 0.f);                                  // repulsion d^2 for d < 0
-    const float hyf = (fl & 1u) ? 1.f : 0.f, hbf = (fl & 2u) ? 1.f : 0.f;
+    // tpe.y, tpe.z: the hydrophobic and hydrogen-bond weights of this type
+    // pair, 0 where the term does not apply
     const float hv = fminf(fmaxf(1.5f - d, 0.f), 1.f);              // 1 below 0.5, 0 above 1.5
-    const float hs = (d >= 0.5f && d < 1.5f) ? -1.f : 0.f;
+    const float hs = (d >= 0.5f && d < 1.5f) ? -tpe.y : 0.f;
     const float bv = fminf(fmaxf(-d * (1.f / 0.7f), 0.f), 1.f);     // 1 below -0.7, 0 above 0
-    const float bs = (d >= -0.7f && d < 0.f) ? -(1.f / 0.7f) : 0.f;
-    const float en = kW1 * g1 + kW2 * g2 + kW3 * dn * dn + hyf * kW4 * hv + hbf * kW5 * bv;
-    const float de = kW1 * g1 * (-8.f * d) + kW2 * g2 * (-0.5f * dm3) + kW3 * 2.f * dn + hyf * kW4 * hs + hbf * kW5 * bs;
+    const float bs = (d >= -0.7f && d < 0.f) ? tpe.z * -(1.f / 0.7f) : 0.f;
+    const float en = kW1 * g1 + kW2 * g2 + kW3 * dn * dn + tpe.y * hv + tpe.z * bv;
+    const float de = kW1 * g1 * (-8.f * d) + kW2 * g2 * (-0.5f * dm3) + kW3 * 2.f * dn + hs + bs;
     en_out = inside ? en : 0.f;
     c_out = inside ? de * rinv : 0.f;
 }
@@ -474,31 +494,36 @@ __device__ __forceinline__ float pair_loop(const Topo<A, SL>& T, const Lds& S, i
 {
     constexpr int U = kPairUnroll;
     const int l = lane_id();
-    const int np = T.np, ns = T.fs_stride;
+    const int np = T.np;
     float e = 0.f;
     for (int p0 = l; p0 - l < np; p0 += U * kWave) {
-        uint32_t pk[U];
+        uint32_t pk[U], sl[U];
         bool v[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int p = p0 + u * kWave;
             v[u] = p < np;
             // a lane past the end reads pair 0 (np >= 1 here) and discards it
-            pk[u] = SL ? S.pairs[v[u] ? p : 0] : T.gpairs[v[u] ? p : 0];
+            if (SL) {
+                const uint2 w = S.pairs[v[u] ? p : 0];
+                pk[u] = w.x;
+                sl[u] = w.y;
+            } else {
+                pk[u] = T.gpairs[v[u] ? p : 0];
+                sl[u] = 0u;
+            }
         }
-        int ii[U], jj[U];
-        float4 xi[U], xj[U];
-        float2 tpe[U];
+        float4 xi[U], xj[U], tpe[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            int t;
+            int i, j, t;
             if (SL) {
-                ii[u] = pk[u] & 0x3f; jj[u] = (pk[u] >> 6) & 0x3f; t = (pk[u] >> 12) & 0x3f;
+                i = pk[u] & 0x3f; j = (pk[u] >> 6) & 0x3f; t = pk[u] >> 12;
             } else {
-                ii[u] = pk[u] & 0xff; jj[u] = (pk[u] >> 8) & 0xff; t = pk[u] >> 16;
+                i = pk[u] & 0xff; j = (pk[u] >> 8) & 0xff; t = pk[u] >> 16;
             }
-            xi[u] = S.pos[ii[u]];
-            xj[u] = S.pos[jj[u]];
+            xi[u] = S.pos[i];
+            xj[u] = S.pos[j];
             tpe[u] = S.tp[t];
         }
 #pragma unroll
@@ -511,8 +536,8 @@ __device__ __forceinline__ float pair_loop(const Topo<A, SL>& T, const Lds& S, i
             if (v[u]) {
                 if (SL) {
                     const float fx = c * dx, fy = c * dy, fz = c * dz;
-                    S.fs[((pk[u] >> 18) & 0x3f) * ns + ii[u]] = make_float4(fx, fy, fz, 0.f);
-                    S.fs[((pk[u] >> 24) & 0x3f) * ns + jj[u]] = make_float4(-fx, -fy, -fz, 0.f);
+                    S.fs[sl[u] & 0xffff] = make_float4(fx, fy, fz, 0.f);
+                    S.fs[sl[u] >> 16] = make_float4(-fx, -fy, -fz, 0.f);
                 } else {
                     S.cp[p0 + u * kWave] = c;
                 }
@@ -531,12 +556,24 @@ __device__ __forceinline__ void gather_pair_forces(const Topo<A, SL>& T, const L
 {
     const int n = T.n;
     if (SL) {
-        for (int k = 0; k < T.ell_w; k += 4) {
+        // eight independent reads in flight per group (rows are padded to a
+        // multiple of four, so at most one group of four is left)
+        const float4* row = S.fs + i;
+        const int ns = T.fs_stride;
+        int k = 0;
+        for (; k + 8 <= T.ell_w; k += 8) {
+            float4 f[8];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const float4 f = S.fs[(k + u) * T.fs_stride + i];
-                gx += f.x; gy += f.y; gz += f.z;
-            }
+            for (int u = 0; u < 8; ++u) f[u] = row[(k + u) * ns];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) { gx += f[u].x; gy += f[u].y; gz += f[u].z; }
+        }
+        if (k < T.ell_w) {
+            float4 f[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) f[u] = row[(k + u) * ns];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) { gx += f[u].x; gy += f[u].y; gz += f[u].z; }
         }
         return;
     }
@@ -720,17 +757,14 @@ __device__ __forceinline__ void retract(const Lds& S, int dst, int src, float d,
     rotvec_quat(th0, th1, th2, dq);
     quat_mul(dq, q, nq);
     quat_normalize(nq);
-    float vt = 0.f, vpsi = 0.f;
-    if (l < 3) vt = x[l] + lam * d;
-    if (l >= 6 && l < 6 + nt) vpsi = x[l + 1] + lam * d;
-    wave_sync();
-    if (l < 3) o[l] = vt;
-    // one fixed-address store per quaternion component (no per-lane select)
-    if (l == 3) o[3] = nq[0];
-    if (l == 4) o[4] = nq[1];
-    if (l == 5) o[5] = nq[2];
-    if (l == 6) o[6] = nq[3];
-    if (l >= 6 && l < 6 + nt) o[l + 1] = vpsi;
+    // lanes 0..2 write t, 3..6 the quaternion, 6..5+nt the torsion of
+    // tangent lane l at pose entry l + 1 (dst and src are distinct slots)
+    float qv = nq[3];
+    qv = l == 5 ? nq[2] : qv;
+    qv = l == 4 ? nq[1] : qv;
+    qv = l == 3 ? nq[0] : qv;
+    if (l < 7) o[l] = l < 3 ? x[l] + lam * d : qv;
+    if (l >= 6 && l < 6 + nt) o[l + 1] = x[l + 1] + lam * d;
     wave_sync();
 }
 
@@ -776,7 +810,7 @@ __device__ BfgsOut bfgs(const Topo<A, SL>& T, const BoxView& B, const Lds& S, co
             bool accepted = false;
             if (ft > f + P.rho * lam * gd) {
                 beta = lam; beta_inf = false;
-            } else if (wsum(gt * d) < P.sigma * gd) {
+            } else if (wsum_n(gt * d, nd) < P.sigma * gd) {
                 lo = lam;
                 slot_copy(S, SLOT_XA, SLOT_XT, 7 + T.nt);
                 fa = ft; ga = gt;
@@ -798,8 +832,8 @@ __device__ BfgsOut bfgs(const Topo<A, SL>& T, const BoxView& B, const Lds& S, co
             }
             // s = lam d, y = g+ - g; cautious update (Eqs. qvina_eq_10, qvina_eq_11)
             const float sv = lam_ok * d, yv = gnw - g;
-            const float ys = wsum(yv * sv), ss = wsum(sv * sv);
-            if (ys / ss > P.eps_c * gn) {
+            const float ys = wsum_n(yv * sv, nd), ss = wsum_n(sv * sv, nd);
+            if (ys * __builtin_amdgcn_rcpf(ss) > P.eps_c * gn) {
                 if (hn == m) {
 #pragma unroll
                     for (int h = 0; h < kMaxM - 1; ++h) { Sh[h] = Sh[h + 1]; Yh[h] = Yh[h + 1]; rh[h] = rh[h + 1]; }
@@ -807,7 +841,7 @@ __device__ BfgsOut bfgs(const Topo<A, SL>& T, const BoxView& B, const Lds& S, co
                 }
 #pragma unroll
                 for (int h = 0; h < kMaxM; ++h)
-                    if (h == hn) { Sh[h] = sv; Yh[h] = yv; rh[h] = 1.f / ys; }
+                    if (h == hn) { Sh[h] = sv; Yh[h] = yv; rh[h] = __builtin_amdgcn_rcpf(ys); }
                 ++hn;
             }
             slot_copy(S, SLOT_X, SLOT_XT, 7 + T.nt);   // Eq. qvina_eq_9
@@ -818,7 +852,7 @@ __device__ BfgsOut bfgs(const Topo<A, SL>& T, const BoxView& B, const Lds& S, co
         }
         if (begin) {
             if (it >= max_iter) break;
-            gn = sqrtf(wsum(g * g));
+            gn = __builtin_amdgcn_sqrtf(wsum_n(g * g, nd));
             if (gn <= P.eps_g) break;                 // Eq. qvina_eq_12
             // two-loop recursion: d = -H g (d = -g with no pairs, Eq. qvina_eq_6)
             float q = g, al[kMaxM];
@@ -826,7 +860,7 @@ __device__ BfgsOut bfgs(const Topo<A, SL>& T, const BoxView& B, const Lds& S, co
             for (int h = kMaxM - 1; h >= 0; --h) {
                 al[h] = 0.f;
                 if (h < hn) {
-                    al[h] = rh[h] * wsum(Sh[h] * q);
+                    al[h] = rh[h] * wsum_n(Sh[h] * q, nd);
                     q -= al[h] * Yh[h];
                 }
             }
@@ -835,17 +869,17 @@ __device__ BfgsOut bfgs(const Topo<A, SL>& T, const BoxView& B, const Lds& S, co
 #pragma unroll
                 for (int h = 0; h < kMaxM; ++h)
                     if (h == hn - 1) { sy = Sh[h] * Yh[h]; yy = Yh[h] * Yh[h]; }
-                q *= wsum(sy) / wsum(yy);
+                q *= wsum_n(sy, nd) * __builtin_amdgcn_rcpf(wsum_n(yy, nd));
             }
 #pragma unroll
             for (int h = 0; h < kMaxM; ++h) {
                 if (h < hn) {
-                    const float bb = rh[h] * wsum(Yh[h] * q);
+                    const float bb = rh[h] * wsum_n(Yh[h] * q, nd);
                     q += Sh[h] * (al[h] - bb);
                 }
             }
             d = -q;
-            gd = wsum(g * d);
+            gd = wsum_n(g * d, nd);
             if (!(gd < 0.f)) break;                   // not a descent direction
             lo = 0.f; lam = 1.f; beta = 0.f; beta_inf = true; tr = 0;
             retract(S, SLOT_XT, SLOT_X, d, lam, T.nt);
@@ -1227,7 +1261,7 @@ __global__ __launch_bounds__(256) void gridmap_kernel(GridBuildArgs a)
             const float dz2 = dz * dz;
             const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz2));
             if (!(r2 < kCut2)) continue;
-            const float r = sqrtf(r2);
+            const float r = __builtin_amdgcn_sqrtf(r2);
             const int rt = __float_as_uint(at.w) & 0xff;
             const float Rr = rt <= 1 ? 1.9f : rt <= 4 ? 1.8f : rt <= 6 ? 1.7f : 2.0f;
             const bool r_hyd = rt == 0, r_don = rt == 3 || rt == 6, r_acc = rt == 4 || rt == 5 || rt == 6;
