@@ -178,7 +178,6 @@ pv_status pv_create(int32_t device, pv_ctx** out)
     HIP_TRY(hipSetDevice(device), "hipSetDevice");
     hipDeviceProp_t prop;
     HIP_TRY(hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties");
-    HIP_TRY(init_device_tables(device), "constant tables");
     pv_ctx* c = new (std::nothrow) pv_ctx;
     if (!c) return fail(PV_E_NOMEM, "host allocation");
     c->device = device;

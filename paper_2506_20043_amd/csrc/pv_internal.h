@@ -58,7 +58,8 @@ struct LigModel {
     std::vector<float> ref;         // [n][4] new order: x, y, z, w-bits
     std::vector<DevFrag> frags;     // preorder
     std::vector<int> tors_frag;     // torsion k -> fragment
-    std::vector<uint32_t> pairs;    // packed, grouped by interaction class
+    std::vector<uint32_t> pairs;    // i | j << 8 | rk << 16 | class << 19 (radius sum 3.4 + 0.1 rk;
+                                    // class 0 plain, 1 hydrophobic, 2 hydrogen bond), grouped by class
     std::vector<uint32_t> ell;      // [ell_w][n]
     std::vector<uint32_t> pslot;    // per pair: slot in row i | slot in row j << 16
     int ell_w = 0;
@@ -71,7 +72,6 @@ int build_ligand_model(int n, const float* xyz, const uint8_t* type, int nb, con
                        const uint8_t* rot, LigModel& out, std::string& err);
 
 // Type-pair table: Rsum = R_a + R_b, flags bit0 hydrophobic pair, bit1 hbond pair.
-void type_pair_table(float rsum[64], uint32_t flags[64]);
 
 // ------------------------------------------------------------ launchers
 struct GridDev {
@@ -188,7 +188,6 @@ hipError_t launch_job_reduce(const float* chain_best_e, const int64_t* chain_eva
                              int32_t* job_status, hipStream_t s);
 hipError_t launch_local_opt(const OptArgs& a, int n_cu, hipStream_t s);
 hipError_t launch_reset_times(uint64_t* t0, uint64_t* t1, int n, hipStream_t s);
-hipError_t init_device_tables(int device);
 
 // Tiles of the grid-map kernel.
 constexpr int kTileX = 16, kTileY = 4, kTileZ = 4;

@@ -247,13 +247,12 @@ constexpr int kSlot = 40;
 enum { SLOT_X = 0, SLOT_XT = 1, SLOT_XA = 2, SLOT_CUR = 3, SLOT_BEST = 4, kNSlots = 5 };
 
 struct Lds {
-    float4* tp;        // [64] (Rsum, hydrophobic weight or 0, hydrogen-bond weight or 0, 0)
     float* pose;       // [kNSlots][kSlot]
     float* frame;      // [kMaxFrag][12] frames, then [kMaxFrag] ancestor links
     float4* pos;       // [max_atoms]
     float4* frc;       // [max_atoms]
     float* pre;        // [6][max_atoms]
-    uint2* pairs;      // [max_pairs] (i | j << 6 | type pair << 12, slot index of i | slot index of j << 16)
+    uint2* pairs;      // [max_pairs] (i | j << 6 | rk << 12 | class << 15, slot index of i | of j << 16)
     float* cp;         // [max_pairs + 1] per-pair force coefficient (last = 0), global-table path
     uint32_t* ell;     // unused in LDS (the global-table path reads the table from memory)
     float4* fs;        // [max_ell] pair forces in atom-row slots (row stride n | 1), LDS-table path
@@ -272,7 +271,7 @@ __host__ __device__ inline int round_up(int v, int m) { return (v + m - 1) / m *
 __host__ __device__ inline int lds_bytes(int max_atoms, int max_pairs, int max_ell, bool slots)
 {
     int ma = round_up(max_atoms < 1 ? 1 : max_atoms, 64);
-    int b = 64 * 16 + kNSlots * kSlot * 4 + kMaxFrag * 13 * 4 + 12 + ma * 16 * 2 + 6 * ma * 4;
+    int b = kNSlots * kSlot * 4 + kMaxFrag * 13 * 4 + 12 + ma * 16 * 2 + 6 * ma * 4;
     if (slots) b += round_up(max_pairs, 2) * 8 + max_ell * 16;
     else b += round_up(max_pairs + 1, 4) * 4;
     return b;
@@ -283,7 +282,6 @@ __device__ __forceinline__ Lds carve(char* base, int max_atoms, int max_pairs, i
     Lds s;
     int ma = round_up(max_atoms < 1 ? 1 : max_atoms, 64);
     char* p = base;
-    s.tp = (float4*)p; p += 64 * 16;
     s.pos = (float4*)p; p += ma * 16;
     s.frc = (float4*)p; p += ma * 16;
     s.pose = (float*)p; p += kNSlots * kSlot * 4;
@@ -301,13 +299,6 @@ __device__ __forceinline__ Lds carve(char* base, int max_atoms, int max_pairs, i
     }
     s.ma = ma;
     return s;
-}
-
-__device__ __forceinline__ void stage_tp(const Lds& S, const float* rsum, const uint32_t* flags)
-{
-    int l = lane_id();
-    const uint32_t f = flags[l];
-    S.tp[l] = make_float4(rsum[l], (f & 1u) ? kW4 : 0.f, (f & 2u) ? kW5 : 0.f, 0.f);
 }
 
 // ---------------------------------------------------------------- staged ligand
@@ -355,14 +346,14 @@ __device__ void stage_ligand(Topo<A, SL>& T, const LigDev& L, int lig, const Lds
     T.gpairs = L.pairs + d.pair_base;
     T.gell = L.ell + d.ell_base;
     if (SL) {
-        // pair record: i | j << 6 | type pair << 12, and the slot indices
-        // (slot * row stride + atom) the pair's forces go to in the two rows
+        // pair record: i | j << 6 | radius-sum code << 12 | class << 15, and
+        // the slot indices (slot * row stride + atom) of the pair's forces
         const uint32_t* ps = L.pslot + d.pair_base;
         const uint32_t ns = (uint32_t)T.fs_stride;
         for (int p = l; p < T.np; p += kWave) {
             const uint32_t pk = T.gpairs[p], sl = ps[p];
             const uint32_t i = pk & 0xff, j = (pk >> 8) & 0xff;
-            S.pairs[p] = make_uint2(i | (j << 6) | ((pk >> 16) << 12),
+            S.pairs[p] = make_uint2(i | (j << 6) | (((pk >> 16) & 0x1f) << 12),
                                     ((sl & 0xffff) * ns + i) | (((sl >> 16) * ns + j) << 16));
         }
         const int nfs = T.ell_w * T.fs_stride;
@@ -450,44 +441,19 @@ __device__ __forceinline__ void frames(const Topo<A, SL>& T, const Lds& S, const
     }
 }
 
-// One intra pair: the Vina-form energy inside 8 A and the force
-// coefficient c = (dphi/dr) / r (0 outside the cutoff).
-__device__ __forceinline__ void pair_term(float4 xi, float4 xj, float4 tpe, float& en_out, float& c_out, bool& inside,
-                                          float& dx, float& dy, float& dz)
-{
-    dx = xi.x - xj.x; dy = xi.y - xj.y; dz = xi.z - xj.z;
-    const float r2 = dx * dx + dy * dy + dz * dz;
-    inside = r2 < kCut2;
-    // one v_rsq_f32: r = r2 / sqrt(r2) and c = de / r = de * rsq; a zero
-    // distance gets a tiny finite r and its zero direction zeroes the force
-    const float r2c = fmaxf(r2, 1e-12f);
-    const float rinv = __builtin_amdgcn_rsqf(r2c);
-    const float r = r2c * rinv;
-    const float d = r - tpe.x;
-    const float g1 = __expf(-4.f * d * d);
-    const float dm3 = d - 3.f;
-    const float g2 = __expf(-0.25f * dm3 * dm3);
-    const float dn = fminf(d, 0.f);                                  // repulsion d^2 for d < 0
-    // tpe.y, tpe.z: the hydrophobic and hydrogen-bond weights of this type
-    // pair, 0 where the term does not apply
-    const float hv = fminf(fmaxf(1.5f - d, 0.f), 1.f);              // 1 below 0.5, 0 above 1.5
-    const float hs = (d >= 0.5f && d < 1.5f) ? -tpe.y : 0.f;
-    const float bv = fminf(fmaxf(-d * (1.f / 0.7f), 0.f), 1.f);     // 1 below -0.7, 0 above 0
-    const float bs = (d >= -0.7f && d < 0.f) ? tpe.z * -(1.f / 0.7f) : 0.f;
-    const float en = kW1 * g1 + kW2 * g2 + kW3 * dn * dn + tpe.y * hv + tpe.z * bv;
-    const float de = kW1 * g1 * (-8.f * d) + kW2 * g2 * (-0.5f * dm3) + kW3 * 2.f * dn + hs + bs;
-    en_out = inside ? en : 0.f;
-    c_out = inside ? de * rinv : 0.f;
-}
-
 // Intra pairs, lanes over pairs, kPairUnroll pairs per lane and pass: every
-// load of a pass (pair words, then both positions and the type-pair entry)
+// load of a pass (pair records, then both positions and the type-pair entry)
 // is issued before any of its arithmetic, so the LDS latency is paid once
-// per pass.  With the tables in LDS each pair writes its force +f / -f into
-// its slots of the two atoms' rows; otherwise it stores its coefficient c
-// for the table gather.  No atomics either way.  Returns this lane's energy;
-// counts pairs inside the cutoff.
+// per pass.  Per pair, with d the surface distance and inside 8 A: the
+// gauss, repulsion, hydrophobic and hydrogen-bond terms of the Vina form and
+// the force coefficient c = (dphi/dr) / r.  Pairs are grouped by interaction
+// class, so a whole 64-pair chunk usually has no hydrophobic or hydrogen-bond
+// weight and skips those terms on a wave-uniform branch.  With the tables in
+// LDS each pair writes +f / -f into its slots of the two atoms' rows;
+// otherwise it stores c for the table gather.  No atomics either way.
+// Returns this lane's energy; counts pairs inside the cutoff.
 constexpr int kPairUnroll = 4;
+constexpr float kLog2e = 1.4426950408889634f;
 
 template <int A, bool SL>
 __device__ __forceinline__ float pair_loop(const Topo<A, SL>& T, const Lds& S, int& cnt)
@@ -513,29 +479,65 @@ __device__ __forceinline__ float pair_loop(const Topo<A, SL>& T, const Lds& S, i
                 sl[u] = 0u;
             }
         }
-        float4 xi[U], xj[U], tpe[U];
+        float4 xi[U], xj[U];
+        uint32_t code[U];   // radius-sum code | class << 3
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            int i, j, t;
+            int i, j;
             if (SL) {
-                i = pk[u] & 0x3f; j = (pk[u] >> 6) & 0x3f; t = pk[u] >> 12;
+                i = pk[u] & 0x3f; j = (pk[u] >> 6) & 0x3f; code[u] = pk[u] >> 12;
             } else {
-                i = pk[u] & 0xff; j = (pk[u] >> 8) & 0xff; t = pk[u] >> 16;
+                i = pk[u] & 0xff; j = (pk[u] >> 8) & 0xff; code[u] = pk[u] >> 16;
             }
             xi[u] = S.pos[i];
             xj[u] = S.pos[j];
-            tpe[u] = S.tp[t];
+        }
+        float dx[U], dy[U], dz[U], d[U], en[U], de[U], rinv[U];
+        bool in[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            dx[u] = xi[u].x - xj[u].x; dy[u] = xi[u].y - xj[u].y; dz[u] = xi[u].z - xj[u].z;
+            const float r2 = dx[u] * dx[u] + dy[u] * dy[u] + dz[u] * dz[u];
+            in[u] = v[u] && r2 < kCut2;
+            // one v_rsq_f32: r = r2 / sqrt(r2) and c = de / r = de * rsq; a
+            // zero distance gets a tiny finite r and its zero direction
+            // zeroes the force
+            const float r2c = fmaxf(r2, 1e-12f);
+            rinv[u] = __builtin_amdgcn_rsqf(r2c);
+            const float rsum = fmaf((float)(code[u] & 7u), 0.1f, 3.4f);
+            const float dd = r2c * rinv[u] - rsum;
+            d[u] = dd;
+            const float g1 = __builtin_amdgcn_exp2f(dd * dd * (-4.f * kLog2e));          // exp(-(d/0.5)^2)
+            const float dm3 = dd - 3.f;
+            const float g2 = __builtin_amdgcn_exp2f(dm3 * dm3 * (-0.25f * kLog2e));      // exp(-((d-3)/2)^2)
+            const float dn = fminf(dd, 0.f);                                             // repulsion d^2, d < 0
+            en[u] = fmaf(kW1, g1, fmaf(kW2, g2, kW3 * (dn * dn)));
+            de[u] = fmaf(g1, dd * (-8.f * kW1), fmaf(g2, dm3 * (-0.5f * kW2), dn * (2.f * kW3)));
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            float eu, c, dx, dy, dz;
-            bool in;
-            pair_term(xi[u], xj[u], tpe[u], eu, c, in, dx, dy, dz);
-            e += v[u] ? eu : 0.f;
-            cnt += __popcll(__ballot(in && v[u]));
+            // class 1 (both hydrophobic) adds the hydrophobic term, class 2
+            // (donor with acceptor) the hydrogen-bond term
+            const uint32_t cls = code[u] >> 3;
+            if (__ballot(cls != 0u)) {
+                const float wy = cls == 1u ? kW4 : 0.f, wz = cls == 2u ? kW5 : 0.f;
+                const float dd = d[u];
+                const float hv = fminf(fmaxf(1.5f - dd, 0.f), 1.f);            // 1 below 0.5, 0 above 1.5
+                const float bv = fminf(fmaxf(dd * -(1.f / 0.7f), 0.f), 1.f);   // 1 below -0.7, 0 above 0
+                en[u] = fmaf(wy, hv, fmaf(wz, bv, en[u]));
+                const float hs = (dd >= 0.5f && dd < 1.5f) ? -wy : 0.f;
+                const float bs = (dd >= -0.7f && dd < 0.f) ? wz * -(1.f / 0.7f) : 0.f;
+                de[u] += hs + bs;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            e += in[u] ? en[u] : 0.f;
+            cnt += __popcll(__ballot(in[u]));
+            const float c = in[u] ? de[u] * rinv[u] : 0.f;
             if (v[u]) {
                 if (SL) {
-                    const float fx = c * dx, fy = c * dy, fz = c * dz;
+                    const float fx = c * dx[u], fy = c * dy[u], fz = c * dz[u];
                     S.fs[sl[u] & 0xffff] = make_float4(fx, fy, fz, 0.f);
                     S.fs[sl[u] >> 16] = make_float4(-fx, -fy, -fz, 0.f);
                 } else {
@@ -1017,8 +1019,6 @@ __device__ ChainOut mc_chain(const Topo<A, SL>& T, const BoxView& B, const Lds& 
 }
 
 // ---------------------------------------------------------------- kernels
-__constant__ float c_rsum[64];
-__constant__ uint32_t c_tpflags[64];
 
 template <int A, bool SL>
 __global__ __launch_bounds__(64) void dock_kernel(DockArgs a)
@@ -1026,7 +1026,6 @@ __global__ __launch_bounds__(64) void dock_kernel(DockArgs a)
     extern __shared__ __align__(16) char smem[];
     const Lds S = carve(smem, a.l.max_atoms, a.l.max_pairs, a.l.max_ell, SL);
     const int l = lane_id();
-    stage_tp(S, c_rsum, c_tpflags);
     Topo<A, SL> T;
     T.lig = -1;
     const int chains = a.sp.chains;
@@ -1097,7 +1096,6 @@ __global__ __launch_bounds__(64) void score_kernel(ScoreArgs a)
     extern __shared__ __align__(16) char smem[];
     const Lds S = carve(smem, a.l.max_atoms, a.l.max_pairs, a.l.max_ell, SL);
     const int l = lane_id();
-    stage_tp(S, c_rsum, c_tpflags);
     Topo<A, SL> T;
     T.lig = -1;
     const float nanv = __int_as_float(0x7fc00000);
@@ -1174,7 +1172,6 @@ __global__ __launch_bounds__(64) void local_opt_kernel(OptArgs a)
     extern __shared__ __align__(16) char smem[];
     const Lds S = carve(smem, a.l.max_atoms, a.l.max_pairs, a.l.max_ell, SL);
     const int l = lane_id();
-    stage_tp(S, c_rsum, c_tpflags);
     Topo<A, SL> T;
     T.lig = -1;
     for (int pose = blockIdx.x; pose < a.n_poses; pose += gridDim.x) {
@@ -1300,33 +1297,6 @@ __global__ __launch_bounds__(256) void gridmap_kernel(GridBuildArgs a)
 }
 
 // ---------------------------------------------------------------- launchers
-// The type-pair table lives in __constant__ memory of every device; it is
-// written once per device when a context is created on it (never during a
-// stream capture).
-static bool tables_ready[64] = {};
-
-hipError_t init_device_tables(int device)
-{
-    if (device < 0 || device >= 64) return hipErrorInvalidDevice;
-    if (tables_ready[device]) return hipSuccess;
-    float rsum[64];
-    uint32_t fl[64];
-    type_pair_table(rsum, fl);
-    hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_rsum), rsum, sizeof(rsum));
-    if (e != hipSuccess) return e;
-    e = hipMemcpyToSymbol(HIP_SYMBOL(c_tpflags), fl, sizeof(fl));
-    if (e == hipSuccess) tables_ready[device] = true;
-    return e;
-}
-
-static hipError_t ensure_tables()
-{
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return e;
-    return tables_ready[dev] ? hipSuccess : hipErrorNotInitialized;
-}
-
 hipError_t launch_build_grids(const GridBuildArgs& a, int64_t n_tiles, hipStream_t s)
 {
     if (n_tiles <= 0) return hipSuccess;
@@ -1376,10 +1346,9 @@ hipError_t launch_shape(int kind, const LigDev& l, int64_t items, int n_cu, Laun
 
 hipError_t launch_score(const ScoreArgs& a, int n_cu, hipStream_t s)
 {
-    hipError_t e = ensure_tables();
-    if (e != hipSuccess) return e;
     if (a.n_poses <= 0) return hipSuccess;
     LaunchShape sh;
+    hipError_t e;
     if ((e = launch_shape(kKindScore, a.l, a.n_poses, n_cu, &sh)) != hipSuccess) return e;
     // one resident wave per slot the CUs can hold; each takes a contiguous run
     const int64_t cap = (int64_t)sh.per_cu * (n_cu > 0 ? n_cu : 1);
@@ -1395,8 +1364,6 @@ hipError_t launch_score(const ScoreArgs& a, int n_cu, hipStream_t s)
 
 hipError_t launch_dock(const DockArgs& a, const LaunchShape& sh, int32_t workgroups, hipStream_t s)
 {
-    hipError_t e = ensure_tables();
-    if (e != hipSuccess) return e;
     if (a.n_items <= 0) return hipSuccess;
     const unsigned grid = a.persistent ? (unsigned)workgroups : (unsigned)a.n_items;
     if (sh.variant == 0)
@@ -1432,10 +1399,9 @@ hipError_t launch_job_reduce(const float* cbe, const int64_t* cev, int32_t n_job
 
 hipError_t launch_local_opt(const OptArgs& a, int n_cu, hipStream_t s)
 {
-    hipError_t e = ensure_tables();
-    if (e != hipSuccess) return e;
     if (a.n_poses <= 0) return hipSuccess;
     LaunchShape sh;
+    hipError_t e;
     if ((e = launch_shape(kKindOpt, a.l, a.n_poses, n_cu, &sh)) != hipSuccess) return e;
     const int grid = a.n_poses < 65536 ? a.n_poses : 65536;
     if (sh.variant == 0)

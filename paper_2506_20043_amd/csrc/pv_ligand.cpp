@@ -29,18 +29,6 @@ int find_root(std::vector<int>& up, int a)
 }
 }  // namespace
 
-void type_pair_table(float rsum[64], uint32_t flags[64])
-{
-    for (int a = 0; a < kNTypes; ++a)
-        for (int b = 0; b < kNTypes; ++b) {
-            rsum[a * 8 + b] = (float)(kRadius[a] + kRadius[b]);
-            uint32_t f = 0;
-            if (kHyd[a] && kHyd[b]) f |= 1u;
-            if ((kDon[a] && kAcc[b]) || (kAcc[a] && kDon[b])) f |= 2u;
-            flags[a * 8 + b] = f;
-        }
-}
-
 int build_ligand_model(int n, const float* xyz, const uint8_t* type, int nb, const int32_t* bonds,
                        const uint8_t* rot, LigModel& M, std::string& err)
 {
@@ -241,8 +229,11 @@ int build_ligand_model(int n, const float* xyz, const uint8_t* type, int nb, con
     M.pairs.reserve(P);
     for (int idx = 0; idx < P; ++idx) {
         int i = pl[idx].first, j = pl[idx].second;
-        int tp = type[perm[i]] * 8 + type[perm[j]];
-        M.pairs.push_back((uint32_t)i | ((uint32_t)j << 8) | ((uint32_t)tp << 16));
+        // radius sum 3.4 + 0.1 rk A (every radius is 1.7 + 0.1 k A)
+        const int ta = type[perm[i]], tb = type[perm[j]];
+        const int rk = (int)std::lround((kRadius[ta] + kRadius[tb] - 3.4) * 10.0);
+        M.pairs.push_back((uint32_t)i | ((uint32_t)j << 8) | ((uint32_t)rk << 16) |
+                          ((uint32_t)cls(pl[idx]) << 19));
     }
     // atom -> pair rows (partners in ascending pair order), padded to the longest
     std::vector<std::vector<uint32_t>> rows(n);
