@@ -63,6 +63,7 @@ def main():
                     help="ligands of the uneven batch (x 5 pockets = jobs)")
     ap.add_argument("--plain-jobs", type=int, default=20, help="jobs of the uneven batch run one launch each")
     ap.add_argument("--stream-jobs", type=int, default=2048, help="jobs taken from the screening stream")
+    ap.add_argument("--sweep-steps", type=int, default=1000, help="MC steps per chain in the box-size sweep")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device (calibrates the HBM byte counters) and exit")
     args = ap.parse_args()
@@ -187,6 +188,7 @@ def main():
     if not args.no_extra:
         result["batching"] = bench_batching(pv, S, ctx, stream, args)
         result["screening"] = bench_screening(pv, S, ctx, stream, args)
+        result["box_sweep"] = bench_box_sweep(pv, S, ctx, stream, args)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(S, cfg, rx, rt, bxs, mols, seed, args)
     print(json.dumps(result), flush=True)
@@ -336,6 +338,41 @@ def bench_screening(pv, S, ctx, stream, args):
         "jobs": len(jobs), "ms": ms, "docks_per_s": len(jobs) / (ms * 1e-3), "evals_per_s": ev / (ms * 1e-3),
         "service_us_p50": float(np.percentile(svc, 50)), "service_us_p99": float(np.percentile(svc, 99)),
         "service_us_max": float(svc.max()), "makespan_us": float(span), "grid_build_ms_16_pockets": grid_ms,
+    }
+
+
+def bench_box_sweep(pv, S, ctx, stream, args):
+    """The box-size sweep: the 5 pockets of the multi-pocket receptor with
+    cubic boxes of 15..30 A in 1 A steps (80 boxes) built in one grid-map
+    launch, then the 35-atom ligand docked into every box (64 chains x
+    --sweep-steps MC steps) as one persistent launch.  Reports the grid build
+    rate and the mean best energy per box edge."""
+    import torch
+    cfg = S.CONFIGS["c2"]
+    rx, rt, bxs = S.make_receptor(cfg)
+    edges = list(range(15, 31))
+    sweep = S.box_sweep(bxs, edges)
+    grids = pv.build_grids(ctx, rx, rt, sweep, penalty_slope=10.0)
+    torch.cuda.synchronize()
+    grid_ms = min(_timed(stream, grids.rebuild) for _ in range(3))
+    points = sum(int(np.prod(grids.info(b)[0])) for b in range(len(sweep)))
+    ligs = pv.Ligands(ctx, S.make_ligands(cfg))
+    jobs = [(0, b) for b in range(len(sweep))]
+    params = pv.dock_params(chains=64, steps=args.sweep_steps, seed=S.philox_seed(cfg), flags=pv.PV_DOCK_GRAPH)
+    plan = pv.Plan(ctx, grids, ligs, jobs, params)
+    plan.run()
+    torch.cuda.synchronize()
+    ms = _timed(stream, plan.run)
+    out = plan.outputs()
+    best = out["job_best_e"].cpu().numpy().reshape(len(bxs), len(edges))
+    ev = int(out["job_evals"].sum().item())
+    plan.close()
+    return {
+        "workload": "box-size sweep: 5 pockets x edges 15..30 A (80 boxes, %.0f MB of maps); 35-atom ligand, "
+                    "64 chains x %d MC steps per box" % (points * 32 / 1e6, args.sweep_steps),
+        "grid_ms": grid_ms, "grid_points_per_s": points / (grid_ms * 1e-3),
+        "dock_ms": ms, "docks_per_s": len(jobs) / (ms * 1e-3), "evals_per_s": ev / (ms * 1e-3),
+        "edges_A": edges, "mean_best_e_by_edge": [float(v) for v in best.mean(axis=0)],
     }
 
 

@@ -67,6 +67,13 @@ def boxes(g: np.random.Generator, n: int, edge_lo: float, edge_hi: float, cube: 
     return out
 
 
+def box_sweep(pockets, edges=tuple(range(15, 31))):
+    """The box-size sweep: every pocket centre with cubic boxes of each edge
+    (15..30 A in 1 A steps by default), pocket-major."""
+    return [Box(np.asarray(b.center, np.float32).copy(), np.full(3, float(e), np.float32), b.spacing)
+            for b in pockets for e in edges]
+
+
 @dataclass
 class Molecule:
     xyz: np.ndarray        # (N, 3) float64 holding binary32 values

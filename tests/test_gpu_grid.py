@@ -94,3 +94,27 @@ def test_build_grids_rejects(pv_ctx):
     bad = S.Box(np.zeros(3, np.float32), np.array([5.0, 0.0, 5.0], np.float32), 0.375)
     with pytest.raises(pv.PvError, match="size"):
         pv.build_grids(pv_ctx, rx, np.array([0], np.uint8), [bad])
+
+
+def test_box_size_sweep_sampled(oracle, pv_ctx):
+    """The box-size sweep (edges 15..30 A in 1 A steps around two pockets of
+    the multi-pocket receptor) in one build: each box has n = ceil(s/h) + 1
+    points per axis and matches the oracle at its corners and at sampled
+    points."""
+    cfg = S.CONFIGS["c2"]
+    rx, rt, bxs = S.make_receptor(cfg)
+    sweep = S.box_sweep(bxs[:2])
+    assert len(sweep) == 32
+    grids, maps = _gpu_maps(pv_ctx, rx, rt, sweep)
+    g = np.random.default_rng(8)
+    for b, box in enumerate(sweep):
+        dims, org = grids.info(b)
+        n = int(np.ceil(float(box.size[0]) / box.spacing)) + 1
+        assert list(dims) == [n, n, n], (b, dims)
+        ldims, lorg = oracle.lattice(box.center.astype(np.float64), box.size.astype(np.float64), box.spacing)
+        assert list(ldims) == list(dims) and np.array_equal(np.float32(lorg), org)
+        m = n - 1
+        pts = [(0, 0, 0), (m, m, m), (m, 0, m // 2)] + [tuple(int(v) for v in g.integers(0, n, 3)) for _ in range(40)]
+        for i, j, k in pts:
+            ref = oracle.map_point(rx, rt, dims, org, box.spacing, i, j, k)
+            _assert_maps_close(maps[b][:, k, j, i], ref, "box %d point %s" % (b, (i, j, k)))
