@@ -183,6 +183,7 @@ def main():
         "flops_per_launch": flops,
         "launch_ms": dock_ms,
     }
+    result["output_stage"] = bench_output(pv, plan, stream)
     if not args.no_score:
         result["score_grad"] = bench_score(pv, S, ctx, stream)
     if not args.no_extra:
@@ -247,6 +248,20 @@ def bench_score(pv, S, ctx, stream):
             "ms_per_call": ms, "evals_per_s": cfg.n_poses / (ms * 1e-3)}
 
 
+def bench_output(pv, plan, stream):
+    """The output stage over a dock plan's last chain bests: clustering at
+    1 A, up to 20 modes per job, 30 BFGS iterations of refinement each,
+    rescoring, r.m.s.d. filter and sort."""
+    import torch
+    out = plan.outputs()
+    res = pv.output_stage(plan, out["chain_best_e"], out["chain_best_dof"])
+    torch.cuda.synchronize()
+    ms = _timed(stream, lambda: pv.output_stage(plan, out["chain_best_e"], out["chain_best_dof"]))
+    n = res["n_modes"].cpu().numpy()
+    return {"ms": ms, "jobs": int(plan.n_jobs), "jobs_per_s": plan.n_jobs / (ms * 1e-3),
+            "modes_per_job_mean": float(n.mean()), "best_affinity": float(res["mode_affinity"][:, 0].min().item())}
+
+
 def _timed(stream, fn):
     import torch
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -278,6 +293,7 @@ def bench_batching(pv, S, ctx, stream, args):
     ms = _timed(stream, plan.run)
     ev = int(plan.outputs()["job_evals"].sum().item())
     variant = pv.launch_info(ctx, ligs, pv.KIND_DOCK, len(jobs) * cfg.chains)[0]
+    output = bench_output(pv, plan, stream)
     plan.close()
     few = jobs[:args.plain_jobs]
     pplan = pv.Plan(ctx, grids, ligs, few, params)
@@ -297,6 +313,7 @@ def bench_batching(pv, S, ctx, stream, args):
                   "evals_per_s": ev_plain / (ms_plain * 1e-3), "ms": ms_plain},
         "batched_same_jobs": {"jobs": len(few), "docks_per_s": len(few) / (ms_same * 1e-3), "ms": ms_same},
         "batched_over_plain": (len(jobs) / ms) / (len(few) / ms_plain),
+        "output_stage": output,
     }
 
 

@@ -255,6 +255,48 @@ pv_status pv_local_opt(pv_ctx* ctx, const pv_grids* grids, const pv_ligands* lig
                        int32_t dof_stride, const pv_dock_params* params, float* dof_out, float* energy,
                        int64_t* n_evals, void* stream);
 
+/* Output stage (Methods, end of "Accelerated Docking with QuickVina 2-GPU
+ * 2.1"; the last steps of Supplementary Algorithm 2): per job, the chains'
+ * best poses are taken in ascending energy (ties to the lower chain, NaN
+ * last) and clustered greedily: a pose is kept unless its heavy-atom
+ * r.m.s.d. (same atom order) to a kept pose is below rmsd_cut, up to
+ * `modes` poses.  Each kept pose is refined by BFGS (refine_max_iter
+ * iterations with the plan's BFGS settings; the receptor is rigid) and
+ * rescored: its energy E = e_inter + e_intra and the reported affinity
+ * e_inter / (1 + affinity_w T).  The refined poses are sorted by E (ties to
+ * the earlier kept pose), filtered by r.m.s.d. the same way, and written in
+ * that order.  One wave per job.
+ *
+ * plan: the jobs, grids, ligands, chains and BFGS settings of a dock plan.
+ * chain_best_e [n_jobs][chains], chain_best_dof [n_jobs][chains][in_stride]:
+ * device, typically a pv_dock_out of that plan after pv_dock_run.
+ * Outputs (device, caller-owned): n_modes [n_jobs]; per job `modes`
+ * entries of mode_chain (source chain, -1 past n_modes), mode_e,
+ * mode_affinity (may be NULL) (NaN past n_modes) and mode_dof (may be NULL;
+ * [n_jobs][modes][dof_stride], unit quaternion, zero past n_modes and past
+ * 7 + T).  Limits: modes 1..PV_MAX_MODES, chains <= PV_MAX_OUTPUT_CHAINS,
+ * and the LDS of one workgroup (PV_E_RANGE). */
+#define PV_MAX_MODES 32
+#define PV_MAX_OUTPUT_CHAINS 4096
+typedef struct {
+    int32_t modes;           /* poses returned per job at most (the paper samples 20) */
+    int32_t refine_max_iter; /* BFGS iterations refining each kept pose; 0 = none */
+    float rmsd_cut;          /* A; returned poses are at least this far apart */
+    float affinity_w;        /* affinity = e_inter / (1 + affinity_w * torsions) */
+} pv_output_params;
+void pv_output_params_default(pv_output_params* p);   /* 20, 30, 1.0, 0.0585 */
+typedef struct {
+    int32_t* n_modes;
+    int32_t* mode_chain;
+    float* mode_e;
+    float* mode_affinity;
+    float* mode_dof;
+    int32_t dof_stride;
+} pv_modes_out;
+pv_status pv_output_stage(pv_plan* plan, const float* chain_best_e, const float* chain_best_dof,
+                          int32_t in_stride, const pv_output_params* params, const pv_modes_out* out,
+                          void* stream);
+
 /* Launch shape diagnostics (host only, no device work): the kernel variant
  * that a launch of `kind` over `items` waves (dock: jobs x chains; score and
  * local-opt: poses) on these ligands uses, its dynamic LDS bytes per

@@ -63,6 +63,11 @@ class McParams(C.Structure):
                 ("mut_rot_amp", C.c_double), ("seed", C.c_uint64)]
 
 
+class OutputParams(C.Structure):
+    _fields_ = [("modes", C.c_int32), ("refine_max_iter", C.c_int32), ("rmsd_cut", C.c_double),
+                ("affinity_w", C.c_double), ("bfgs", BfgsParams)]
+
+
 EVAL_FN = C.CFUNCTYPE(None, C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
                       C.POINTER(C.c_double))
 
@@ -104,6 +109,8 @@ def _declare(L):
                               C.c_int, _dp, _dp, _i64p]
     L.or_dock.argtypes = [C.c_int, C.POINTER(C.c_void_p), C.c_int, C.POINTER(_Grid), C.c_int,
                           _ip, C.POINTER(McParams), C.c_int, C.c_int, _dp, _dp, _i64p, _dp, _ip]
+    L.or_output_stage.argtypes = [C.c_void_p, C.POINTER(_Grid), C.c_int, _dp, _dp, C.POINTER(OutputParams),
+                                  _ip, _ip, _dp, _dp, _dp, _dp]
 
 
 def _p(a, t):
@@ -410,3 +417,29 @@ def dock(ligands, grids, jobs, params: McParams, dof_stride=None, n_threads=0):
         raise ValueError("invalid dock input (code %d)" % rc)
     return dict(chain_best_e=cbe.reshape(nj, ch), chain_best_dof=cbd.reshape(nj, ch, stride),
                 chain_evals=cev.reshape(nj, ch), job_best_e=jbe, job_best_chain=jbc)
+
+
+def output_stage(lig: Ligand, grid: Grid, dof, e, modes=20, refine_max_iter=0, rmsd_cut=1.0,
+                 affinity_w=0.0585, bfgs=None):
+    """The output stage of one job: cluster and sort the chains' best poses
+    dof [n][7+T] with energies e [n], refine and rescore the kept ones, then
+    r.m.s.d.-filter and sort (see or_output_stage)."""
+    d = _f64(np.asarray(dof, dtype=np.float64).reshape(-1, lig.ndof))
+    ee = _f64(e).reshape(-1)
+    n = len(ee)
+    assert d.shape[0] == n
+    P = OutputParams(int(modes), int(refine_max_iter), float(rmsd_cut), float(affinity_w),
+                     bfgs if bfgs is not None else bfgs_params())
+    no = C.c_int32()
+    ch = np.zeros(modes, np.int32)
+    oe = np.zeros(modes)
+    oa = np.zeros(modes)
+    od = np.zeros((modes, lig.ndof))
+    mg = np.zeros(2)
+    rc = lib().or_output_stage(lig.h, C.byref(grid.struct), n, _p(d, _dp), _p(ee, _dp), C.byref(P), C.byref(no),
+                               _p(ch, _ip), _p(oe, _dp), _p(oa, _dp), _p(od, _dp), _p(mg, _dp))
+    if rc != 0:
+        raise ValueError("invalid output-stage input (code %d)" % rc)
+    k = no.value
+    return {"chain": ch[:k], "e": oe[:k], "affinity": oa[:k], "dof": od[:k], "rmsd_margin": mg[0],
+            "energy_gap": mg[1]}

@@ -1103,3 +1103,134 @@ int or_dock(int n_lig, or_ligand* const* ligs, int n_grids, const or_grid* grids
     }
     return 0;
 }
+
+/* ---- output stage ------------------------------------------------------
+ * Methods (end of "Accelerated Docking with QuickVina 2-GPU 2.1") and the
+ * last steps of Supplementary Algorithm 2: every chain reports its best
+ * pose; the collected poses are clustered and sorted; the selected ones are
+ * refined and rescored; then an r.m.s.d. filter and a final sort give the
+ * top k.  Readings of what the paper leaves open:
+ *  - order: ascending energy, ties to the lower chain index (NaN last);
+ *  - clustering: walking that order, a pose is kept unless its heavy-atom
+ *    r.m.s.d. (same atom order, no symmetry) to an already kept pose is
+ *    below rmsd_cut; at most `modes` are kept;
+ *  - refinement: BFGS from each kept pose with refine_max_iter iterations
+ *    (the receptor is rigid, so there is no pocket refinement);
+ *  - rescoring: the refined pose's E = e_inter + e_intra is the sort key,
+ *    and the reported affinity is e_inter / (1 + affinity_w T);
+ *  - filter and final sort: ascending rescored energy, ties to the earlier
+ *    kept pose; a pose within rmsd_cut of a better one is dropped. */
+static int precedes(double ea, int ia, double eb, int ib)
+{
+    /* a before b: smaller energy, NaN after every number, then lower index */
+    const int na = ea != ea, nb = eb != eb;
+    if (na != nb) return nb;
+    if (!na && ea != eb) return ea < eb;
+    return ia < ib;
+}
+
+static double rmsd(int n, const double* a, const double* b)
+{
+    double s = 0.0;
+    for (int i = 0; i < 3 * n; ++i) s += (a[i] - b[i]) * (a[i] - b[i]);
+    return sqrt(s / n);
+}
+
+int or_output_stage(const or_ligand* L, const or_grid* G, int n_chains, const double* dof,
+                    const double* e, const or_output_params* P, int32_t* n_out,
+                    int32_t* out_chain, double* out_e, double* out_aff, double* out_dof,
+                    double margins[2])
+{
+    if (n_chains < 0 || P->modes < 1 || !(P->rmsd_cut >= 0.0)) return -1;
+    const int n = L->n, nd = 7 + L->nt, k = P->modes;
+    double m_rmsd = INFINITY, m_gap = INFINITY;
+    /* 1. sort the chains (insertion sort on (energy, index)) */
+    int* order = malloc(sizeof(int) * (n_chains > 0 ? n_chains : 1));
+    for (int c = 0; c < n_chains; ++c) {
+        int p = c;
+        while (p > 0 && precedes(e[c], c, e[order[p - 1]], order[p - 1])) {
+            order[p] = order[p - 1];
+            --p;
+        }
+        order[p] = c;
+    }
+    /* 2. greedy r.m.s.d. clustering over that order */
+    double* kx = malloc(sizeof(double) * 3 * n * k);
+    int* kc = malloc(sizeof(int) * k);
+    double* x = malloc(sizeof(double) * 3 * n);
+    int nk = 0;
+    for (int r = 0; r < n_chains && nk < k; ++r) {
+        const int c = order[r];
+        or_fk(L, dof + (size_t)c * nd, x);
+        int keep = 1;
+        for (int q = 0; q < nk; ++q) {
+            const double d = rmsd(n, x, kx + (size_t)3 * n * q);
+            if (fabs(d - P->rmsd_cut) < m_rmsd) m_rmsd = fabs(d - P->rmsd_cut);
+            if (d < P->rmsd_cut) { keep = 0; break; }
+        }
+        if (!keep) continue;
+        memcpy(kx + (size_t)3 * n * nk, x, sizeof(double) * 3 * n);
+        kc[nk++] = c;
+    }
+    /* 3. refine and rescore each kept pose */
+    double* rx = malloc(sizeof(double) * (size_t)nd * (nk > 0 ? nk : 1));
+    double* re = malloc(sizeof(double) * (nk > 0 ? nk : 1));
+    double* ra = malloc(sizeof(double) * (nk > 0 ? nk : 1));
+    for (int q = 0; q < nk; ++q) {
+        double* xo = rx + (size_t)nd * q;
+        const double* x0 = dof + (size_t)kc[q] * nd;
+        if (P->refine_max_iter > 0) {
+            or_bfgs_params bp = P->bfgs;
+            bp.max_iter = P->refine_max_iter;
+            double f;
+            int64_t ne;
+            int32_t ni;
+            or_bfgs(L, G, &bp, x0, xo, &f, &ne, &ni);
+        } else {
+            memcpy(xo, x0, sizeof(double) * nd);
+        }
+        const double qn = sqrt(xo[3] * xo[3] + xo[4] * xo[4] + xo[5] * xo[5] + xo[6] * xo[6]);
+        for (int a = 3; a < 7; ++a) xo[a] /= qn;
+        double e3[3];
+        or_score_grad(L, G, xo, e3, NULL, NULL, kx + (size_t)3 * n * q, NULL, NULL);
+        re[q] = e3[0];
+        ra[q] = e3[1] / (1.0 + P->affinity_w * L->nt);
+    }
+    /* 4. final sort of the refined poses and r.m.s.d. filter */
+    int* fo = malloc(sizeof(int) * (nk > 0 ? nk : 1));
+    for (int q = 0; q < nk; ++q) {
+        int p = q;
+        while (p > 0 && precedes(re[q], q, re[fo[p - 1]], fo[p - 1])) {
+            fo[p] = fo[p - 1];
+            --p;
+        }
+        fo[p] = q;
+    }
+    for (int q = 1; q < nk; ++q) {
+        const double g = fabs(re[fo[q]] - re[fo[q - 1]]);
+        if (g < m_gap) m_gap = g;
+    }
+    int no = 0;
+    for (int r = 0; r < nk; ++r) {
+        const int q = fo[r];
+        int keep = 1;
+        for (int s = 0; s < no; ++s) {
+            int qs = -1;
+            for (int t = 0; t < nk; ++t)
+                if (kc[t] == out_chain[s]) qs = t;
+            const double d = rmsd(n, kx + (size_t)3 * n * q, kx + (size_t)3 * n * qs);
+            if (fabs(d - P->rmsd_cut) < m_rmsd) m_rmsd = fabs(d - P->rmsd_cut);
+            if (d < P->rmsd_cut) { keep = 0; break; }
+        }
+        if (!keep) continue;
+        out_chain[no] = kc[q];
+        out_e[no] = re[q];
+        out_aff[no] = ra[q];
+        memcpy(out_dof + (size_t)nd * no, rx + (size_t)nd * q, sizeof(double) * nd);
+        ++no;
+    }
+    *n_out = no;
+    if (margins) { margins[0] = m_rmsd; margins[1] = m_gap; }
+    free(order); free(kx); free(kc); free(x); free(rx); free(re); free(ra); free(fo);
+    return 0;
+}

@@ -128,6 +128,26 @@ int or_dock(int n_lig, or_ligand* const* ligs, int n_grids, const or_grid* grids
             int n_threads, double* chain_best_e, double* chain_best_dof,
             int64_t* chain_evals, double* job_best_e, int32_t* job_best_chain);
 
+/* ---- output stage (Methods, end of "Accelerated Docking with QuickVina
+ * 2-GPU 2.1"; last steps of Supplementary Algorithm 2): the chains' best
+ * poses are clustered and sorted, the selected ones refined and rescored,
+ * then r.m.s.d.-filtered and sorted again, and at most `modes` returned.
+ * dof [n_chains][7+T], e [n_chains]; outputs [modes] in final order:
+ * chain index, energy (e_inter + e_intra of the refined pose), affinity
+ * e_inter / (1 + affinity_w T), pose [7+T] with a unit quaternion.
+ * margins (may be NULL): [0] smallest |rmsd - rmsd_cut| over the cluster
+ * and filter decisions taken, [1] smallest energy gap between neighbours of
+ * the final sort. */
+typedef struct {
+    int32_t modes, refine_max_iter;
+    double rmsd_cut, affinity_w;
+    or_bfgs_params bfgs;
+} or_output_params;
+int or_output_stage(const or_ligand* L, const or_grid* G, int n_chains, const double* dof,
+                    const double* e, const or_output_params* P, int32_t* n_out,
+                    int32_t* out_chain, double* out_e, double* out_aff, double* out_dof,
+                    double margins[2]);
+
 #ifdef __cplusplus
 }
 #endif

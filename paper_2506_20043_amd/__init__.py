@@ -58,6 +58,16 @@ class DockOut(C.Structure):
                 ("job_t_start", C.c_void_p), ("job_t_end", C.c_void_p), ("dof_stride", C.c_int32)]
 
 
+class OutputParams(C.Structure):
+    _fields_ = [("modes", C.c_int32), ("refine_max_iter", C.c_int32), ("rmsd_cut", C.c_float),
+                ("affinity_w", C.c_float)]
+
+
+class ModesOut(C.Structure):
+    _fields_ = [("n_modes", C.c_void_p), ("mode_chain", C.c_void_p), ("mode_e", C.c_void_p),
+                ("mode_affinity", C.c_void_p), ("mode_dof", C.c_void_p), ("dof_stride", C.c_int32)]
+
+
 _vp = C.c_void_p
 _ip = C.POINTER(C.c_int32)
 _i32 = C.c_int32
@@ -88,6 +98,8 @@ SIGNATURES = {
     "pv_dock": (C.c_int, [_vp, _vp, _vp, C.POINTER(Job), _i32, C.POINTER(DockParams), C.POINTER(DockOut), _vp]),
     "pv_local_opt": (C.c_int, [_vp, _vp, _vp, _i32, _vp, _vp, _vp, _i32, C.POINTER(DockParams), _vp, _vp, _vp, _vp]),
     "pv_launch_info": (C.c_int, [_vp, _vp, _i32, C.c_int64, _ip, _ip, _ip]),
+    "pv_output_params_default": (None, [C.POINTER(OutputParams)]),
+    "pv_output_stage": (C.c_int, [_vp, _vp, _vp, _i32, C.POINTER(OutputParams), C.POINTER(ModesOut), _vp]),
 }
 
 
@@ -508,3 +520,37 @@ def launch_info(ctx: Context, ligs: Ligands, kind: int, items: int):
     _check(lib().pv_launch_info(ctx.h, ligs.h, int(kind), int(items), C.byref(v), C.byref(lds), C.byref(occ)),
            "pv_launch_info")
     return v.value, lds.value, occ.value
+
+
+def output_params(**kw) -> OutputParams:
+    p = OutputParams()
+    lib().pv_output_params_default(C.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def output_stage(plan: Plan, chain_best_e, chain_best_dof, params: OutputParams | None = None, stream=None):
+    """Cluster, refine, rescore, filter and sort every job's chain bests
+    (device tensors [n_jobs*chains] and [n_jobs*chains, stride]); returns
+    device tensors n_modes [n_jobs], mode_chain / mode_e / mode_affinity
+    [n_jobs, modes] and mode_dof [n_jobs, modes, stride]."""
+    torch = _torch()
+    dev = plan.ctx.torch_device
+    p = params if params is not None else output_params()
+    e = _dev_tensor(chain_best_e, torch.float32, dev)
+    d = _dev_tensor(chain_best_dof, torch.float32, dev)
+    stride = int(d.shape[-1])
+    nj, m = plan.n_jobs, int(p.modes)
+    out = {"n_modes": torch.empty(nj, dtype=torch.int32, device=dev),
+           "mode_chain": torch.empty((nj, m), dtype=torch.int32, device=dev),
+           "mode_e": torch.empty((nj, m), dtype=torch.float32, device=dev),
+           "mode_affinity": torch.empty((nj, m), dtype=torch.float32, device=dev),
+           "mode_dof": torch.empty((nj, m, stride), dtype=torch.float32, device=dev)}
+    o = ModesOut(out["n_modes"].data_ptr(), out["mode_chain"].data_ptr(), out["mode_e"].data_ptr(),
+                 out["mode_affinity"].data_ptr(), out["mode_dof"].data_ptr(), stride)
+    _check(lib().pv_output_stage(plan.h, _ptr(e), _ptr(d), stride, C.byref(p), C.byref(o), _stream(stream)),
+           "pv_output_stage")
+    return out

@@ -61,6 +61,7 @@ void dfree(void* p)
 struct pv_ctx {
     int device;
     int n_cu;
+    int lds_per_block;   // dynamic LDS bytes one workgroup may use
     uint32_t magic;
 };
 
@@ -182,6 +183,7 @@ pv_status pv_create(int32_t device, pv_ctx** out)
     if (!c) return fail(PV_E_NOMEM, "host allocation");
     c->device = device;
     c->n_cu = prop.multiProcessorCount;
+    c->lds_per_block = (int)prop.sharedMemPerBlock;
     c->magic = 0x70766378u;
     *out = c;
     return PV_OK;
@@ -857,6 +859,61 @@ pv_status pv_local_opt(pv_ctx* ctx, const pv_grids* grids, const pv_ligands* lig
     a.n_evals = n_evals;
     hipError_t e = launch_local_opt(a, ctx->n_cu, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "local-opt launch");
+    return PV_OK;
+}
+
+void pv_output_params_default(pv_output_params* p)
+{
+    if (!p) return;
+    p->modes = 20;
+    p->refine_max_iter = 30;
+    p->rmsd_cut = 1.0f;
+    p->affinity_w = 0.0585f;
+}
+
+pv_status pv_output_stage(pv_plan* P, const float* chain_best_e, const float* chain_best_dof, int32_t in_stride,
+                          const pv_output_params* params, const pv_modes_out* out, void* stream)
+{
+    if (!P) return fail(PV_E_INVALID, "plan is NULL");
+    if (!params || !out) return fail(PV_E_INVALID, "params or out is NULL");
+    if (!chain_best_e || !chain_best_dof) return fail(PV_E_INVALID, "chain bests are NULL");
+    if (!out->n_modes || !out->mode_chain || !out->mode_e) return fail(PV_E_INVALID, "n_modes, mode_chain, mode_e are required");
+    if (params->modes < 1 || params->modes > PV_MAX_MODES) return fail(PV_E_RANGE, "modes must be 1..32");
+    if (params->refine_max_iter < 0) return fail(PV_E_INVALID, "refine_max_iter < 0");
+    if (!(params->rmsd_cut >= 0.f) || !std::isfinite(params->rmsd_cut)) return fail(PV_E_INVALID, "rmsd_cut must be finite and >= 0");
+    if (!std::isfinite(params->affinity_w) || !(params->affinity_w >= 0.f)) return fail(PV_E_INVALID, "affinity_w must be finite and >= 0");
+    const int need = 7 + P->ligs->max_tors;
+    if (in_stride < need || in_stride > 64) return fail(PV_E_INVALID, "in_stride must be 7 + max torsions .. 64");
+    if (out->mode_dof && (out->dof_stride < need || out->dof_stride > 64))
+        return fail(PV_E_INVALID, "dof_stride must be 7 + max torsions .. 64");
+    if (P->sp.chains > PV_MAX_OUTPUT_CHAINS) return fail(PV_E_RANGE, "the output stage takes at most 4096 chains per job");
+    pv_status st = set_device(P->ctx);
+    if (st != PV_OK) return st;
+    OutputArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.g = grid_view(P->grids);
+    a.l = lig_view(P->ligs);
+    a.sp = P->sp;
+    a.jobs = P->jobs;
+    a.n_jobs = P->n_jobs;
+    a.chains = P->sp.chains;
+    a.chain_e = chain_best_e;
+    a.chain_dof = chain_best_dof;
+    a.in_stride = in_stride;
+    a.modes = params->modes;
+    a.refine_max_iter = params->refine_max_iter;
+    a.rmsd_cut = params->rmsd_cut;
+    a.affinity_w = params->affinity_w;
+    a.n_modes = out->n_modes;
+    a.mode_chain = out->mode_chain;
+    a.mode_e = out->mode_e;
+    a.mode_affinity = out->mode_affinity;
+    a.mode_dof = out->mode_dof;
+    a.out_stride = out->dof_stride;
+    if (output_lds_bytes(a.l, a.chains, a.modes) > P->ctx->lds_per_block)
+        return fail(PV_E_RANGE, "chains, modes and ligand size need more LDS than one workgroup has");
+    hipError_t e = launch_output(a, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "output-stage launch");
     return PV_OK;
 }
 

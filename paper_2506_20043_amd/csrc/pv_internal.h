@@ -156,6 +156,25 @@ struct OptArgs {
     int64_t* n_evals;
 };
 
+struct OutputArgs {
+    GridDev g;
+    LigDev l;
+    SearchParams sp;          // BFGS settings of the refinement
+    const int2* jobs;         // (ligand, box)
+    int32_t n_jobs, chains;
+    const float* chain_e;     // [n_jobs][chains]
+    const float* chain_dof;   // [n_jobs][chains][in_stride]
+    int32_t in_stride;
+    int32_t modes, refine_max_iter;
+    float rmsd_cut, affinity_w;
+    int32_t* n_modes;         // [n_jobs]
+    int32_t* mode_chain;      // [n_jobs][modes]
+    float* mode_e;
+    float* mode_affinity;
+    float* mode_dof;          // [n_jobs][modes][out_stride]
+    int32_t out_stride;
+};
+
 struct GridBuildArgs {
     const float4* atoms;      // per box: receptor atoms near the box (x, y, z, w = type bits)
     const int32_t* atom_off;  // [box+1]
@@ -187,6 +206,8 @@ hipError_t launch_job_reduce(const float* chain_best_e, const int64_t* chain_eva
                              int32_t chains, float* job_best_e, int32_t* job_best_chain, int64_t* job_evals,
                              int32_t* job_status, hipStream_t s);
 hipError_t launch_local_opt(const OptArgs& a, int n_cu, hipStream_t s);
+hipError_t launch_output(const OutputArgs& a, hipStream_t s);
+int output_lds_bytes(const LigDev& l, int chains, int modes);
 hipError_t launch_reset_times(uint64_t* t0, uint64_t* t1, int n, hipStream_t s);
 
 // Tiles of the grid-map kernel.

@@ -596,6 +596,19 @@ __device__ __forceinline__ void gather_pair_forces(const Topo<A, SL>& T, const L
     }
 }
 
+// World position of one atom from its reference record (x, y, z, type |
+// fragment << 8) and its fragment's frame in LDS.
+__device__ __forceinline__ float4 atom_position(float4 ref, const Lds& S)
+{
+    const int f = __float_as_uint(ref.w) >> 8;
+    const float4* fr = (const float4*)(S.frame + 12 * f);
+    const float4 r0 = fr[0], r1 = fr[1], r2 = fr[2];
+    const float x = r0.x * ref.x + r0.y * ref.y + r0.z * ref.z + r2.y;
+    const float y = r0.w * ref.x + r1.x * ref.y + r1.y * ref.z + r2.z;
+    const float z = r1.z * ref.x + r1.w * ref.y + r2.x * ref.z + r2.w;
+    return make_float4(x, y, z, 0.f);
+}
+
 // Score and tangent gradient of the pose in `pose` (an LDS slot).  Leaves
 // atom positions in S.pos and dE/dx in S.frc.
 template <int A, bool SL>
@@ -622,17 +635,10 @@ __device__ Eval evaluate(const Topo<A, SL>& T, const BoxView& B, const Lds& S, c
         X4[a] = make_float4(0.f, 0.f, 0.f, 0.f);
         G[a][0] = G[a][1] = G[a][2] = 0.f;
         if (i < T.n) {
-            const uint32_t w = __float_as_uint(T.ref[a].w);
-            const int ty = w & 0xff, f = w >> 8;
-            const float4* fr = (const float4*)(S.frame + 12 * f);
-            const float4 r0 = fr[0], r1 = fr[1], r2 = fr[2];
-            const float X = T.ref[a].x, Y = T.ref[a].y, Z = T.ref[a].z;
-            const float x = r0.x * X + r0.y * Y + r0.z * Z + r2.y;
-            const float y = r0.w * X + r1.x * Y + r1.y * Z + r2.z;
-            const float z = r1.z * X + r1.w * Y + r2.x * Z + r2.w;
-            X4[a] = make_float4(x, y, z, 0.f);
+            const int ty = __float_as_uint(T.ref[a].w) & 0xff;
+            X4[a] = atom_position(T.ref[a], S);
             S.pos[i] = X4[a];
-            tri_issue(B, ty, x, y, z, TL[a]);
+            tri_issue(B, ty, X4[a].x, X4[a].y, X4[a].z, TL[a]);
         }
     }
     wave_sync();
@@ -1199,6 +1205,190 @@ __global__ __launch_bounds__(64) void local_opt_kernel(OptArgs a)
     }
 }
 
+// ---------------------------------------------------------------- output stage
+// Atom positions of the pose in `pose` (an LDS slot) into S.pos.
+template <int A, bool SL>
+__device__ void pose_positions(const Topo<A, SL>& T, const Lds& S, const float* pose)
+{
+    const int l = lane_id();
+    float R[9], b[3];
+    frames(T, S, pose, R, b);
+    if (l < T.nf) {
+        float* fr = S.frame + 12 * l;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) fr[k] = R[k];
+        fr[9] = b[0]; fr[10] = b[1]; fr[11] = b[2];
+    }
+    wave_sync();
+#pragma unroll
+    for (int a = 0; a < A; ++a) {
+        const int i = l * A + a;
+        if (i < T.n) S.pos[i] = atom_position(T.ref[a], S);
+    }
+    wave_sync();
+}
+
+// Order of the output stage: a before b for a smaller energy, any number
+// before NaN, then the lower index.
+__device__ __forceinline__ bool precedes(float ea, int ia, float eb, int ib)
+{
+    const bool na = ea != ea, nb = eb != eb;
+    if (na != nb) return nb;
+    if (!na && ea != eb) return ea < eb;
+    return ia < ib;
+}
+
+// Sum over atoms of |S.pos - other|^2 (identical in every lane).
+template <int A, bool SL>
+__device__ __forceinline__ float sq_dev(const Topo<A, SL>& T, const Lds& S, const float4* other)
+{
+    const int l = lane_id();
+    float s = 0.f;
+#pragma unroll
+    for (int a = 0; a < A; ++a) {
+        const int i = l * A + a;
+        if (i < T.n) {
+            const float4 p = S.pos[i], q = other[i];
+            const float dx = p.x - q.x, dy = p.y - q.y, dz = p.z - q.z;
+            s += dx * dx + dy * dy + dz * dz;
+        }
+    }
+    return wsum(s);
+}
+
+// One wave per job (Methods, end of "Accelerated Docking with QuickVina
+// 2-GPU 2.1"; last steps of Supplementary Algorithm 2): the chains' best
+// poses in ascending energy; greedy r.m.s.d. clustering keeps a pose unless
+// it lies within rmsd_cut of a kept one, up to `modes`; each kept pose is
+// refined by BFGS and rescored (E, and the affinity e_inter / (1 + w T));
+// the refined poses are sorted again, filtered by r.m.s.d. the same way and
+// written out.  r.m.s.d. < cut is tested as sum |dx|^2 < cut^2 N.
+template <int A>
+__global__ __launch_bounds__(64) void output_kernel(OutputArgs a)
+{
+    extern __shared__ __align__(16) char smem[];
+    const Lds S = carve(smem, a.l.max_atoms, a.l.max_pairs, a.l.max_ell, false);
+    char* ext = smem + lds_bytes(a.l.max_atoms, a.l.max_pairs, a.l.max_ell, false);
+    const int ma = S.ma, M = a.modes, C = a.chains;
+    int* order = (int*)ext;     ext += round_up(C, 4) * 4;
+    float4* rep = (float4*)ext; ext += M * ma * 16;
+    float* rdof = (float*)ext;  ext += M * kSlot * 4;
+    float* re = (float*)ext;    ext += round_up(M, 4) * 4;
+    float* ra = (float*)ext;    ext += round_up(M, 4) * 4;
+    int* kc = (int*)ext;        ext += round_up(M, 4) * 4;
+    int* fo = (int*)ext;        ext += round_up(M, 4) * 4;
+    int* so = (int*)ext;
+    const int l = lane_id();
+    const int job = blockIdx.x;
+    Topo<A, false> T;
+    T.lig = -1;
+    const int2 jb = a.jobs[job];
+    stage_ligand(T, a.l, jb.x, S);
+    const BoxView B = box_view(a.g, jb.y);
+    const float* ce = a.chain_e + (int64_t)job * C;
+    const float cut2n = a.rmsd_cut * a.rmsd_cut * (float)T.n;
+    float* x = S.pose + SLOT_X * kSlot;
+    // 1. chains in ascending energy (rank of each chain by counting)
+    for (int c = l; c < C; c += kWave) {
+        const float ec = ce[c];
+        int rank = 0;
+        for (int c2 = 0; c2 < C; ++c2) rank += precedes(ce[c2], c2, ec, c) ? 1 : 0;
+        order[rank] = c;
+    }
+    wave_sync();
+    // 2. greedy clustering in that order
+    int nk = 0;
+    for (int r = 0; r < C && nk < M; ++r) {
+        const int c = order[r];
+        const float* src = a.chain_dof + ((int64_t)job * C + c) * a.in_stride;
+        if (l < 7 + T.nt) x[l] = src[l];
+        wave_sync();
+        pose_positions(T, S, x);
+        bool keep = true;
+        for (int q = 0; q < nk && keep; ++q) keep = !(sq_dev(T, S, rep + q * ma) < cut2n);
+        if (keep) {
+#pragma unroll
+            for (int aa = 0; aa < A; ++aa) {
+                const int i = l * A + aa;
+                if (i < T.n) rep[nk * ma + i] = S.pos[i];
+            }
+            if (l == 0) kc[nk] = c;
+            ++nk;
+        }
+        wave_sync();
+    }
+    // 3. refine and rescore every kept pose
+    for (int q = 0; q < nk; ++q) {
+        const float* src = a.chain_dof + ((int64_t)job * C + kc[q]) * a.in_stride;
+        if (l < 7 + T.nt) x[l] = src[l];
+        wave_sync();
+        if (a.refine_max_iter > 0) bfgs(T, B, S, a.sp, a.refine_max_iter);
+        // a unit quaternion, then the rescoring evaluation
+        float v = l < 7 + T.nt ? x[l] : 0.f;
+        const float q0 = lane_f(v, 3), q1 = lane_f(v, 4), q2 = lane_f(v, 5), q3 = lane_f(v, 6);
+        const float qn = 1.f / sqrtf(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+        if (l >= 3 && l < 7) v *= qn;
+        wave_sync();
+        if (l < 7 + T.nt) x[l] = v;
+        wave_sync();
+        const Eval ev = evaluate(T, B, S, x);
+#pragma unroll
+        for (int aa = 0; aa < A; ++aa) {
+            const int i = l * A + aa;
+            if (i < T.n) rep[q * ma + i] = S.pos[i];
+        }
+        if (l < kSlot) rdof[q * kSlot + l] = v;
+        if (l == 0) {
+            re[q] = ev.e;
+            ra[q] = ev.e_inter / (1.f + a.affinity_w * (float)T.nt);
+        }
+        wave_sync();
+    }
+    // 4. final sort of the refined poses, r.m.s.d. filter, output
+    if (l < nk) {
+        int rank = 0;
+        for (int q2 = 0; q2 < nk; ++q2) rank += precedes(re[q2], q2, re[l], l) ? 1 : 0;
+        fo[rank] = l;
+    }
+    wave_sync();
+    const int64_t o0 = (int64_t)job * M;
+    int no = 0;
+    for (int r = 0; r < nk; ++r) {
+        const int q = fo[r];
+        // S.pos <- refined pose q, compared with the poses already written
+#pragma unroll
+        for (int aa = 0; aa < A; ++aa) {
+            const int i = l * A + aa;
+            if (i < T.n) S.pos[i] = rep[q * ma + i];
+        }
+        wave_sync();
+        bool keep = true;
+        for (int s2 = 0; s2 < no && keep; ++s2) keep = !(sq_dev(T, S, rep + so[s2] * ma) < cut2n);
+        if (keep) {
+            if (l == 0) {
+                so[no] = q;
+                a.mode_chain[o0 + no] = kc[q];
+                a.mode_e[o0 + no] = re[q];
+                if (a.mode_affinity) a.mode_affinity[o0 + no] = ra[q];
+            }
+            if (a.mode_dof && l < a.out_stride)
+                a.mode_dof[(o0 + no) * a.out_stride + l] = l < 7 + T.nt ? rdof[q * kSlot + l] : 0.f;
+            ++no;
+        }
+        wave_sync();
+    }
+    const float nanv = __int_as_float(0x7fc00000);
+    for (int o = no + l; o < M; o += kWave) {
+        a.mode_chain[o0 + o] = -1;
+        a.mode_e[o0 + o] = nanv;
+        if (a.mode_affinity) a.mode_affinity[o0 + o] = nanv;
+    }
+    if (a.mode_dof)
+        for (int o = no; o < M; ++o)
+            if (l < a.out_stride) a.mode_dof[(o0 + o) * a.out_stride + l] = 0.f;
+    if (l == 0) a.n_modes[job] = no;
+}
+
 // ---------------------------------------------------------------- grid maps
 // One workgroup per 16x4x4 tile of one box (a wave writes 16-float = 64 B
 // rows).  Receptor atoms near the box are
@@ -1411,6 +1601,24 @@ hipError_t launch_local_opt(const OptArgs& a, int n_cu, hipStream_t s)
     else
         hipLaunchKernelGGL((local_opt_kernel<2, false>), dim3(grid), dim3(64), sh.lds, s, a);
     return hipGetLastError();
+}
+
+hipError_t launch_output(const OutputArgs& a, hipStream_t s)
+{
+    if (a.n_jobs <= 0) return hipSuccess;
+    const int lds = output_lds_bytes(a.l, a.chains, a.modes);
+    if (a.l.max_atoms <= 64)
+        hipLaunchKernelGGL((output_kernel<1>), dim3(a.n_jobs), dim3(64), lds, s, a);
+    else
+        hipLaunchKernelGGL((output_kernel<2>), dim3(a.n_jobs), dim3(64), lds, s, a);
+    return hipGetLastError();
+}
+
+int output_lds_bytes(const LigDev& l, int chains, int modes)
+{
+    const int ma = round_up(l.max_atoms < 1 ? 1 : l.max_atoms, 64);
+    return lds_bytes(l.max_atoms, l.max_pairs, l.max_ell, false) + round_up(chains, 4) * 4 + modes * ma * 16 +
+           modes * kSlot * 4 + 5 * round_up(modes, 4) * 4;
 }
 
 }  // namespace pv

@@ -1,0 +1,178 @@
+"""Pins of the oracle's output stage (Methods, end of "Accelerated Docking
+with QuickVina 2-GPU 2.1"; last steps of Supplementary Algorithm 2).
+
+The chain sets are built with a known answer: tight copies of far-apart
+centres, so the clusters, the best member of each and the separation of the
+kept poses follow from the construction, not from re-running the greedy
+walk.  Further pins: a zero cut reduces the first stage to a plain sort,
+refinement never raises an energy, a rigid ligand's affinity is its
+e_inter, and degenerate inputs."""
+import numpy as np
+import pytest
+
+from paper_2506_20043_amd import synth as S
+
+KAPPA = 10.0
+
+
+@pytest.fixture(scope="module")
+def c1(oracle):
+    cfg = S.CONFIGS["c1"]
+    rx, rt, bxs = S.make_receptor(cfg)
+    m = S.make_ligands(cfg)[0]
+    b = bxs[0]
+    G = oracle.Grid.build(rx, rt, b.center.astype(np.float64), b.size.astype(np.float64), b.spacing, kappa=KAPPA)
+    L = oracle.Ligand(m.xyz, m.types, m.bonds, m.rotatable)
+    return L, G
+
+
+def _rmsd(a, b):
+    return float(np.sqrt(np.mean(np.sum((a - b) ** 2, axis=1))))
+
+
+def _small_rotation(g, angle):
+    axis = g.normal(size=3)
+    axis /= np.linalg.norm(axis)
+    return np.concatenate([[np.cos(angle / 2)], np.sin(angle / 2) * axis])
+
+
+def _qmul(a, b):
+    w1, x1, y1, z1 = a
+    w2, x2, y2, z2 = b
+    return np.array([w1 * w2 - x1 * x2 - y1 * y2 - z1 * z2, w1 * x2 + x1 * w2 + y1 * z2 - z1 * y2,
+                     w1 * y2 - x1 * z2 + y1 * w2 + z1 * x2, w1 * z2 + x1 * y2 - y1 * x2 + z1 * w2])
+
+
+def cluster_set(L, G, g, n_centres, sizes, sep=2.5, spread=0.03, margin=2.0):
+    """Chain bests made of `n_centres` centres (pairwise r.m.s.d. > sep) and
+    copies perturbed by ~spread (A, rad).  Returns dof [n][7+T] (binary32
+    values), cluster label per chain, and binary32 energies, all distinct.
+    Centres keep `margin` A from the box faces."""
+    lo, hi = G.origin.astype(np.float64) + margin, G.origin + G.h * (G.dims - 1) - margin
+    while True:
+        cen = S.poses(g, n_centres, lo, hi, L.n_tors)
+        xs = [L.fk(c) for c in cen]
+        if all(_rmsd(xs[a], xs[b]) > sep for a in range(n_centres) for b in range(a)):
+            break
+    dof, lab = [], []
+    for k in range(n_centres):
+        for _ in range(sizes[k]):
+            d = cen[k].copy()
+            d[:3] += g.normal(scale=spread, size=3)
+            d[3:7] = _qmul(_small_rotation(g, spread), d[3:7])
+            d[7:] += g.normal(scale=spread, size=L.n_tors)
+            dof.append(d)
+            lab.append(k)
+    perm = g.permutation(len(dof))
+    dof = np.float32(np.array(dof)[perm]).astype(np.float64)
+    lab = np.array(lab)[perm]
+    e = np.float32(g.permutation(len(dof)) * 0.25 - 7.0).astype(np.float64)
+    return dof, lab, e
+
+
+def test_clusters_by_construction(oracle, c1):
+    L, G = c1
+    g = np.random.default_rng(31)
+    sizes = [1, 3, 5, 2, 4, 1, 6, 2, 3, 2]
+    dof, lab, e = cluster_set(L, G, g, 10, sizes)
+    xs = [L.fk(d) for d in dof]
+    for a in range(len(dof)):
+        for b in range(a):
+            if lab[a] == lab[b]:
+                assert _rmsd(xs[a], xs[b]) < 0.5
+    # expected: the best member of each cluster, the `modes` best clusters,
+    # then sorted by the rescored energy
+    best = {}
+    for c in range(len(dof)):
+        k = lab[c]
+        if k not in best or (e[c], c) < (e[best[k]], best[k]):
+            best[k] = c
+    modes = 7
+    picked = sorted(best.values(), key=lambda c: (e[c], c))[:modes]
+    rescored = {c: L.score_grad(G, dof[c]) for c in picked}
+    expect = sorted(picked, key=lambda c: (rescored[c]["e"], picked.index(c)))
+    r = oracle.output_stage(L, G, dof, e, modes=modes, refine_max_iter=0, rmsd_cut=1.0)
+    assert list(r["chain"]) == expect
+    for o, c in enumerate(expect):
+        assert r["e"][o] == pytest.approx(rescored[c]["e"], rel=1e-12, abs=1e-12)
+        assert r["affinity"][o] == pytest.approx(rescored[c]["e_inter"] / (1 + 0.0585 * L.n_tors), rel=1e-12)
+        q = r["dof"][o][3:7]
+        assert np.linalg.norm(q) == pytest.approx(1.0, abs=1e-12)
+        np.testing.assert_allclose(r["dof"][o][3:7], dof[c][3:7] / np.linalg.norm(dof[c][3:7]), atol=1e-12)
+        np.testing.assert_array_equal(r["dof"][o][[0, 1, 2]], dof[c][[0, 1, 2]])
+    assert r["rmsd_margin"] > 0.4
+    # all clusters fit: one pose per cluster
+    r = oracle.output_stage(L, G, dof, e, modes=20, refine_max_iter=0, rmsd_cut=1.0)
+    assert sorted(r["chain"]) == sorted(best.values())
+
+
+def test_zero_cut_is_a_plain_sort(oracle, c1):
+    L, G = c1
+    g = np.random.default_rng(5)
+    lo, hi = G.origin.astype(np.float64), G.origin + G.h * (G.dims - 1)
+    dof = S.poses(g, 40, lo, hi, L.n_tors)
+    e = np.float32(g.integers(-5, 5, 40)).astype(np.float64)   # many ties: broken by index
+    r = oracle.output_stage(L, G, dof, e, modes=12, refine_max_iter=0, rmsd_cut=0.0)
+    first = list(np.lexsort((np.arange(40), e))[:12])
+    re = {c: L.score_grad(G, dof[c])["e"] for c in first}
+    expect = sorted(first, key=lambda c: (re[c], first.index(c)))
+    assert list(r["chain"]) == expect
+
+
+def test_nan_energies_sort_last(oracle, c1):
+    L, G = c1
+    g = np.random.default_rng(6)
+    lo, hi = G.origin.astype(np.float64), G.origin + G.h * (G.dims - 1)
+    dof = S.poses(g, 6, lo, hi, L.n_tors)
+    e = np.array([np.nan, 3.0, np.nan, -1.0, 2.0, -1.0])
+    r = oracle.output_stage(L, G, dof, e, modes=4, refine_max_iter=0, rmsd_cut=0.0)
+    assert sorted(r["chain"]) == [1, 3, 4, 5]
+
+
+def test_refinement_descends_and_separates(oracle, c1):
+    L, G = c1
+    g = np.random.default_rng(9)
+    lo, hi = G.origin.astype(np.float64), G.origin + G.h * (G.dims - 1)
+    dof = S.poses(g, 24, lo, hi, L.n_tors)
+    e = np.array([L.score_grad(G, d)["e"] for d in dof])
+    r = oracle.output_stage(L, G, dof, e, modes=10, refine_max_iter=30, rmsd_cut=1.0)
+    n = len(r["chain"])
+    assert 1 <= n <= 10
+    assert np.all(np.diff(r["e"]) >= 0)
+    xs = [L.fk(d) for d in r["dof"]]
+    for o in range(n):
+        assert r["e"][o] <= e[r["chain"][o]] + 1e-9
+        assert r["e"][o] == pytest.approx(L.score_grad(G, r["dof"][o])["e"], abs=1e-9)
+        for p in range(o):
+            assert _rmsd(xs[o], xs[p]) >= 1.0
+    assert len(set(r["chain"])) == n
+
+
+def test_rigid_ligand_affinity_is_inter_energy(oracle, c1):
+    _, G = c1
+    g = np.random.default_rng(4)
+    m = S.tree_ligand(g, 10, 0)
+    L = oracle.Ligand(m.xyz, m.types, m.bonds, m.rotatable)
+    lo, hi = G.origin.astype(np.float64), G.origin + G.h * (G.dims - 1)
+    dof = S.poses(g, 8, lo, hi, 0)
+    e = np.arange(8.0)
+    r = oracle.output_stage(L, G, dof, e, modes=3, refine_max_iter=0, rmsd_cut=1.0)
+    for o in range(len(r["chain"])):
+        assert r["affinity"][o] == L.score_grad(G, r["dof"][o])["e_inter"]
+
+
+def test_degenerate_inputs(oracle, c1):
+    L, G = c1
+    r = oracle.output_stage(L, G, np.zeros((0, L.ndof)), np.zeros(0), modes=5)
+    assert len(r["chain"]) == 0
+    g = np.random.default_rng(2)
+    lo, hi = G.origin.astype(np.float64), G.origin + G.h * (G.dims - 1)
+    one = S.poses(g, 1, lo, hi, L.n_tors)
+    dof = np.repeat(one, 9, axis=0)
+    e = np.array([3.0, 1.0, 2.0, 1.0, 5.0, 4.0, 1.0, 9.0, 0.5])
+    r = oracle.output_stage(L, G, dof, e, modes=5, refine_max_iter=0, rmsd_cut=0.1)
+    assert list(r["chain"]) == [8]
+    r = oracle.output_stage(L, G, dof, e, modes=1, refine_max_iter=0, rmsd_cut=0.0)
+    assert list(r["chain"]) == [8]
+    with pytest.raises(ValueError):
+        oracle.output_stage(L, G, dof, e, modes=0)
