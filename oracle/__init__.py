@@ -58,7 +58,7 @@ class BfgsParams(C.Structure):
 
 class McParams(C.Structure):
     _fields_ = [("chains", C.c_int32), ("steps", C.c_int32), ("bfgs", BfgsParams),
-                ("refine_max_iter", C.c_int32), ("pad", C.c_int32),
+                ("refine_max_iter", C.c_int32), ("consistency", C.c_int32),
                 ("temperature", C.c_double), ("mut_pos_amp", C.c_double),
                 ("mut_rot_amp", C.c_double), ("seed", C.c_uint64)]
 
@@ -109,6 +109,7 @@ def _declare(L):
                               C.c_int, _dp, _dp, _i64p]
     L.or_dock.argtypes = [C.c_int, C.POINTER(C.c_void_p), C.c_int, C.POINTER(_Grid), C.c_int,
                           _ip, C.POINTER(McParams), C.c_int, C.c_int, _dp, _dp, _i64p, _dp, _ip]
+    L.or_consistency_passes.argtypes = [C.c_int, _dp, C.c_double, _dp, _dp, C.c_double, _dp, C.c_int, C.c_int]
     L.or_output_stage.argtypes = [C.c_void_p, C.POINTER(_Grid), C.c_int, _dp, _dp, C.POINTER(OutputParams),
                                   _ip, _ip, _dp, _dp, _dp, _dp]
 
@@ -338,10 +339,10 @@ def bfgs_params(max_iter=30, m=5, ls_max=10, rho=1e-4, sigma=0.1, eps_g=1e-3, ep
 
 
 def mc_params(chains, steps, seed, bfgs=None, refine_max_iter=None, temperature=1.2,
-              mut_pos_amp=2.0, mut_rot_amp=2.0):
+              mut_pos_amp=2.0, mut_rot_amp=2.0, consistency=False):
     b = bfgs if bfgs is not None else bfgs_params()
     return McParams(int(chains), int(steps), b,
-                    int(b.max_iter if refine_max_iter is None else refine_max_iter), 0,
+                    int(b.max_iter if refine_max_iter is None else refine_max_iter), int(bool(consistency)),
                     float(temperature), float(mut_pos_amp), float(mut_rot_amp),
                     int(seed) & 0xFFFFFFFFFFFFFFFF)
 
@@ -443,3 +444,12 @@ def output_stage(lig: Ligand, grid: Grid, dof, e, modes=20, refine_max_iter=0, r
     k = no.value
     return {"chain": ch[:k], "e": oe[:k], "affinity": oa[:k], "dof": od[:k], "rmsd_margin": mg[0],
             "energy_gap": mg[1]}
+
+
+def consistency_passes(nt, x, fx, gx, y, fy, gy, p_lo=0, p_hi=None):
+    """The first-order consistency check of a mutated pose x against its
+    neighbour y over tangent coordinates [p_lo, p_hi) (or_consistency_passes)."""
+    xa, ya, gxa, gya = _f64(x), _f64(y), _f64(gx), _f64(gy)
+    hi = 6 + int(nt) if p_hi is None else int(p_hi)
+    return bool(lib().or_consistency_passes(int(nt), _p(xa, _dp), float(fx), _p(gxa, _dp), _p(ya, _dp), float(fy),
+                                            _p(gya, _dp), int(p_lo), hi))

@@ -1029,6 +1029,51 @@ static void mutate(const or_ligand* L, const or_mc_params* P, const uint64_t w[8
     }
 }
 
+/* ---- first-order consistency check ------------------------------------
+ * Eqs. qvina_eq_4 and qvina_eq_5 and the check of Supplementary Algorithm
+ * 2.  Readings: the neighbouring conformation of the mutated pose is the
+ * chain's current pose, the one it was mutated from, with the gradient of
+ * its last evaluation; the coordinates p tested are those the mutation
+ * moved (the translation, the rotation vector, or the one torsion).  The
+ * check passes, and BFGS runs, when in some moved coordinate the derivative
+ * changes sign between the two poses (Eq. qvina_eq_4) or disagrees with the
+ * secant slope from the current pose (Eq. qvina_eq_5).  Otherwise the
+ * mutated pose lies on the slope it came up from in every moved direction,
+ * a descent from it would return towards the current basin, and the step
+ * ends without optimisation or Metropolis move. */
+static int sgn(double v) { return (v > 0.0) - (v < 0.0); }
+
+int or_consistency_passes(int nt, const double* x, double fx, const double* gx,
+                          const double* y, double fy, const double* gy, int p_lo, int p_hi)
+{
+    double dlt[6 + 32];
+    for (int a = 0; a < 3; ++a) dlt[a] = x[a] - y[a];
+    /* rotation vector of q_x conj(q_y), w >= 0 */
+    double qx[4], qy[4];
+    const double nx = sqrt(x[3] * x[3] + x[4] * x[4] + x[5] * x[5] + x[6] * x[6]);
+    const double ny = sqrt(y[3] * y[3] + y[4] * y[4] + y[5] * y[5] + y[6] * y[6]);
+    for (int a = 0; a < 4; ++a) { qx[a] = x[3 + a] / nx; qy[a] = y[3 + a] / ny; }
+    const double cy[4] = {qy[0], -qy[1], -qy[2], -qy[3]};
+    double qd[4];
+    quat_mul(qx, cy, qd);
+    if (qd[0] < 0.0) for (int a = 0; a < 4; ++a) qd[a] = -qd[a];
+    const double vn = sqrt(qd[1] * qd[1] + qd[2] * qd[2] + qd[3] * qd[3]);
+    const double ang = 2.0 * atan2(vn, qd[0]);
+    for (int a = 0; a < 3; ++a) dlt[3 + a] = vn > 0.0 ? ang * qd[1 + a] / vn : 0.0;
+    for (int k = 0; k < nt; ++k) {
+        double d = x[7 + k] - y[7 + k];
+        d -= 2.0 * PI * floor((d + PI) / (2.0 * PI));   /* into [-pi, pi) */
+        if (d == -PI) d = PI;                          /* (-pi, pi] */
+        dlt[6 + k] = d;
+    }
+    for (int p = p_lo; p < p_hi; ++p) {
+        const int sx = sgn(gx[p]);
+        if (sx * sgn(gy[p]) <= 0) return 1;                    /* Eq. qvina_eq_4 */
+        if (sx * sgn(fx - fy) * sgn(dlt[p]) <= 0) return 1;    /* Eq. qvina_eq_5 */
+    }
+    return 0;
+}
+
 int or_mc_chain(const or_ligand* L, const or_grid* G, const or_mc_params* P,
                 int job, int chain, double* best_dof, double* best_e, int64_t* n_evals)
 {
@@ -1046,28 +1091,51 @@ int or_mc_chain(const or_ligand* L, const or_grid* G, const or_mc_params* P,
     memcpy(best_dof, cur, sizeof(double) * nx);
     or_bfgs_params rp = P->bfgs;
     rp.max_iter = P->refine_max_iter;
+    const int nd = 6 + L->nt;
+    double* gm = malloc(sizeof(double) * nd);
+    /* gt holds the gradient at the current pose (the check's neighbour) */
     for (int s = 0; s < P->steps; ++s) {
         uint64_t w[8];
         draw_block(P->seed, job, chain, (uint64_t)s + 1, 0, w);
         draw_block(P->seed, job, chain, (uint64_t)s + 1, 1, w + 4);
         memcpy(mut, cur, sizeof(double) * nx);
         mutate(L, P, w, mut);
+        if (P->consistency) {
+            /* the check evaluates the mutated pose; when BFGS follows, this is
+             * its first evaluation (counted there) */
+            const int ent = (int)(((w[0] >> 32) * (uint64_t)(2 + L->nt)) >> 32);
+            const int p_lo = ent == 0 ? 0 : (ent == 1 ? 3 : 4 + ent);
+            const int p_hi = ent <= 1 ? p_lo + 3 : p_lo + 1;
+            double fm;
+            pose_eval(&pc, mut, &fm, gm);
+            if (!or_consistency_passes(L->nt, mut, fm, gm, cur, e_cur, gt, p_lo, p_hi)) { ++ne; continue; }
+        }
         double e_o;
         or_bfgs(L, G, &P->bfgs, mut, opt, &e_o, &e1, &it); ne += e1;
         double um = u01(w[7]);
+        int moved = 0;
         if (e_o < e_cur || um < exp((e_cur - e_o) / P->temperature)) {
             memcpy(cur, opt, sizeof(double) * nx); e_cur = e_o;
+            moved = 1;
         }
         if (e_o < e_best) {
             double e_r;
             or_bfgs(L, G, &rp, opt, ref, &e_r, &e1, &it); ne += e1;
             memcpy(best_dof, ref, sizeof(double) * nx); e_best = e_r;
             memcpy(cur, ref, sizeof(double) * nx); e_cur = e_r;
+            moved = 1;
+        }
+        if (moved && P->consistency) {
+            /* the neighbour's gradient (an oracle-side re-evaluation; the
+             * kernel keeps the one its BFGS ended with, so it is not counted) */
+            double f;
+            pose_eval(&pc, cur, &f, gt);
         }
     }
     *best_e = e_best;
     if (n_evals) *n_evals = ne;
     free(cur); free(mut); free(opt); free(ref); free(gt);
+    free(gm);
     return 0;
 }
 

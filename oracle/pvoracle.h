@@ -109,11 +109,24 @@ int or_bfgs_generic(int n, or_eval_fn fn, void* user, const or_bfgs_params* P,
                     const double* x0, double* xout, double* fout, int64_t* n_evals,
                     int32_t* n_iters);
 
+/* ---- first-order consistency check (Eqs. qvina_eq_4 and qvina_eq_5):
+ * 1 (local optimisation warranted) when, for some tangent coordinate p in
+ * [p_lo, p_hi), with x the mutated pose (energy fx, tangent gradient gx
+ * [6+T]) and y its neighbour (fy, gy),
+ *   sign(gx_p) sign(gy_p) <= 0                          (Eq. qvina_eq_4)
+ * or, failing that,
+ *   sign(gx_p) sign((fx - fy) (x - y)_p) <= 0          (Eq. qvina_eq_5)
+ * with (x - y) the tangent difference: translation, the rotation vector of
+ * q_x conj(q_y), torsions wrapped to (-pi, pi]. */
+int or_consistency_passes(int nt, const double* x, double fx, const double* gx,
+                          const double* y, double fy, const double* gy, int p_lo, int p_hi);
+
 /* ---- Monte Carlo chains (Supplementary Algorithm 2) */
 typedef struct {
     int32_t chains, steps;
     or_bfgs_params bfgs;
-    int32_t refine_max_iter, pad;
+    int32_t refine_max_iter;
+    int32_t consistency;   /* 1: the first-order consistency check gates BFGS; 0: every step runs BFGS */
     double temperature, mut_pos_amp, mut_rot_amp;
     uint64_t seed;
 } or_mc_params;
