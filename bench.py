@@ -184,6 +184,9 @@ def main():
         "launch_ms": dock_ms,
     }
     result["output_stage"] = bench_output(pv, plan, stream)
+    if not args.no_extra:
+        result["consistency_check"] = bench_consistency(pv, ctx, grids, ligs, jobs, args, seed, stream,
+                                                        n_evals, dock_ms, plan.outputs())
     if not args.no_score:
         result["score_grad"] = bench_score(pv, S, ctx, stream)
     if not args.no_extra:
@@ -246,6 +249,31 @@ def bench_score(pv, S, ctx, stream):
     ms = a.elapsed_time(b) / reps
     return {"workload": "16,384 poses, 64 ligands of 40 atoms / 10 torsions, one 24 A pocket",
             "ms_per_call": ms, "evals_per_s": cfg.n_poses / (ms * 1e-3)}
+
+
+def bench_consistency(pv, ctx, grids, ligs, jobs, args, seed, stream, evals_off, ms_off, out_off):
+    """The same multi-pocket dock with the first-order consistency check
+    gating every step's BFGS: evaluations saved and the change of the chain
+    bests against the run without it."""
+    import torch
+    params = pv.dock_params(chains=args.chains, steps=args.mc_steps, seed=seed, flags=pv.PV_DOCK_GRAPH,
+                            consistency=1)
+    plan = pv.Plan(ctx, grids, ligs, jobs, params)
+    plan.run()
+    torch.cuda.synchronize()
+    ms = _timed(stream, plan.run)
+    out = plan.outputs()
+    ev = int(out["job_evals"].sum().item())
+    on_best = out["chain_best_e"].cpu().numpy()
+    off_best = out_off["chain_best_e"].cpu().numpy()
+    res = {"dock_ms": ms, "docks_per_s": len(jobs) / (ms * 1e-3), "evals_per_s": ev / (ms * 1e-3),
+           "evals_per_dock": ev / len(jobs), "evals_per_dock_without": evals_off / len(jobs),
+           "evals_saved_frac": 1.0 - ev / evals_off, "speedup_over_without": ms_off / ms,
+           "mean_chain_best": float(on_best.mean()), "mean_chain_best_without": float(off_best.mean()),
+           "job_best": [float(v) for v in out["job_best_e"].cpu().numpy()],
+           "job_best_without": [float(v) for v in out_off["job_best_e"].cpu().numpy()]}
+    plan.close()
+    return res
 
 
 def bench_output(pv, plan, stream):

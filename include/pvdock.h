@@ -179,6 +179,13 @@ pv_status pv_score_grad_xyz(pv_ctx* ctx, const pv_grids* grids, const pv_ligands
  * radius mut_rot_amp / R_g; or one torsion redrawn), BFGS, Metropolis
  * acceptance exp((e_cur - e_new) / temperature), and a new best refined by a
  * second BFGS of at most refine_max_iter iterations.
+ * consistency = 1 gates the step's BFGS with the first-order consistency
+ * check (Eqs. qvina_eq_4 and qvina_eq_5): the mutated pose is compared with
+ * the current pose, its neighbour, in the tangent coordinates the mutation
+ * moved (translation, rotation vector, or the one torsion).  BFGS runs when
+ * in one of them the derivative changes sign between the two poses or
+ * disagrees with the secant slope; otherwise the step ends after that one
+ * evaluation, with no optimisation and no Metropolis move.
  * Random numbers: Philox4x64-10 keyed (seed, 0) with counter (block, step,
  * chain, job). */
 typedef struct {
@@ -193,7 +200,7 @@ typedef struct {
     uint32_t flags;          /* PV_DOCK_* */
     uint64_t seed;
     int32_t workgroups;      /* persistent launch width; 0 = chosen by the library */
-    int32_t reserved;
+    int32_t consistency;     /* 0: every step runs BFGS (default); 1: the consistency check gates it */
 } pv_dock_params;
 
 #define PV_DOCK_TIMESTAMPS 1u /* write per-job device timestamps */

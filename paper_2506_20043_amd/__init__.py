@@ -43,7 +43,7 @@ class DockParams(C.Structure):
                 ("ls_rho", C.c_float), ("ls_sigma", C.c_float), ("eps_grad", C.c_float),
                 ("eps_curv", C.c_float), ("temperature", C.c_float), ("mut_pos_amp", C.c_float),
                 ("mut_rot_amp", C.c_float), ("flags", C.c_uint32), ("seed", C.c_uint64),
-                ("workgroups", C.c_int32), ("reserved", C.c_int32)]
+                ("workgroups", C.c_int32), ("consistency", C.c_int32)]
 
 
 class Job(C.Structure):

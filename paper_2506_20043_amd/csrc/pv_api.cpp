@@ -621,6 +621,7 @@ static pv_status check_search(const pv_dock_params* p, bool mc)
     if (!(p->eps_grad >= 0.f) || !(p->eps_curv >= 0.f)) return fail(PV_E_INVALID, "epsilons must be >= 0");
     if (mc && !(p->temperature > 0.f)) return fail(PV_E_INVALID, "temperature must be > 0");
     if (mc && (!(p->mut_pos_amp >= 0.f) || !(p->mut_rot_amp >= 0.f))) return fail(PV_E_INVALID, "amplitudes must be >= 0");
+    if (p->consistency != 0 && p->consistency != 1) return fail(PV_E_INVALID, "consistency must be 0 or 1");
     return PV_OK;
 }
 
@@ -641,6 +642,7 @@ static SearchParams to_sp(const pv_dock_params* p)
     s.pos_amp = p->mut_pos_amp;
     s.rot_amp = p->mut_rot_amp;
     s.flags = p->flags;
+    s.consistency = p->consistency;
     s.seed = p->seed;
     return s;
 }

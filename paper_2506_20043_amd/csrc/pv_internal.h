@@ -119,6 +119,7 @@ struct SearchParams {
     int32_t chains, steps, max_iter, m, ls_max, refine_max_iter;
     float rho, sigma, eps_g, eps_c, temperature, pos_amp, rot_amp;
     uint32_t flags;
+    int32_t consistency;   // 1: the first-order consistency check gates the step's BFGS
     uint64_t seed;
 };
 

@@ -781,15 +781,61 @@ constexpr int kMaxM = 8;
 
 struct BfgsOut {
     float f;
+    float g;          // this lane's tangent gradient component at the result
     int evals;
     int64_t pairs;
+    bool skipped;     // the consistency check ended the run after its first evaluation
 };
+
+// The neighbour of a mutated pose for the first-order consistency check:
+// the current pose (LDS slot SLOT_CUR), its energy and this lane's tangent
+// gradient component, and the tangent coordinates [p_lo, p_hi) the
+// mutation moved.
+struct CheckIn {
+    float f, g;
+    int p_lo, p_hi;
+};
+
+__device__ __forceinline__ float fsgn(float v) { return (float)((v > 0.f) - (v < 0.f)); }
+
+// Eqs. qvina_eq_4 and qvina_eq_5 for the pose in `x` (energy fx, this
+// lane's gradient gx) against its neighbour: true (optimise) when in some
+// tested coordinate the derivative changes sign between the two poses or
+// disagrees with the secant slope.  Tangent differences: translation, the
+// rotation vector of q_x conj(q_cur) (only its sign is used), torsions
+// wrapped to (-pi, pi].
+__device__ __forceinline__ bool consistency_passes(const Lds& S, const float* x, float fx, float gx, const CheckIn& ck)
+{
+    const int l = lane_id();
+    const float* y = S.pose + SLOT_CUR * kSlot;
+    float dl = 0.f;
+    if (l < 3) {
+        dl = x[l] - y[l];
+    } else if (l < 6) {
+        const float qx[4] = {x[3], x[4], x[5], x[6]};
+        const float cy[4] = {y[3], -y[4], -y[5], -y[6]};
+        float qd[4];
+        quat_mul(qx, cy, qd);
+        const float v = l == 3 ? qd[1] : (l == 4 ? qd[2] : qd[3]);
+        dl = qd[0] < 0.f ? -v : v;
+    } else if (l + 1 < kSlot) {
+        const float kPi = 3.14159265358979f, k2Pi = 6.28318530717959f;
+        float d = x[l + 1] - y[l + 1];
+        d -= k2Pi * floorf((d + kPi) * (1.f / k2Pi));
+        dl = d == -kPi ? kPi : d;
+    }
+    const bool in = l >= ck.p_lo && l < ck.p_hi;
+    const float sx = fsgn(gx);
+    const bool hold = sx * fsgn(ck.g) <= 0.f || sx * fsgn(fx - ck.f) * fsgn(dl) <= 0.f;
+    return __ballot(in && hold) != 0;
+}
 
 // Minimises from the pose in SLOT_X; the result is left in SLOT_X.  Written
 // as one loop around a single evaluation (the first at x0, then one per
 // line-search trial) so the kernel carries one copy of the evaluation code.
 template <int A, bool SL>
-__device__ BfgsOut bfgs(const Topo<A, SL>& T, const BoxView& B, const Lds& S, const SearchParams& P, int max_iter)
+__device__ BfgsOut bfgs(const Topo<A, SL>& T, const BoxView& B, const Lds& S, const SearchParams& P, int max_iter,
+                        bool check = false, CheckIn ck = CheckIn{0.f, 0.f, 0, 0})
 {
     const int l = lane_id();
     const int nd = 6 + T.nt;
@@ -797,6 +843,7 @@ __device__ BfgsOut bfgs(const Topo<A, SL>& T, const BoxView& B, const Lds& S, co
     BfgsOut out;
     out.evals = 0;
     out.pairs = 0;
+    out.skipped = false;
     float Sh[kMaxM], Yh[kMaxM], rh[kMaxM];
 #pragma unroll
     for (int h = 0; h < kMaxM; ++h) { Sh[h] = 0.f; Yh[h] = 0.f; rh[h] = 0.f; }
@@ -813,6 +860,10 @@ __device__ BfgsOut bfgs(const Topo<A, SL>& T, const BoxView& B, const Lds& S, co
         bool begin = false;
         if (initial) {
             f = ft; g = gt; initial = false; begin = true;
+            if (check && !consistency_passes(S, S.pose + SLOT_X * kSlot, ft, gt, ck)) {
+                out.skipped = true;
+                break;
+            }
         } else {
             // Lewis-Overton trial at step lam (Eqs. qvina_eq_7 and qvina_eq_8)
             bool accepted = false;
@@ -894,6 +945,7 @@ __device__ BfgsOut bfgs(const Topo<A, SL>& T, const BoxView& B, const Lds& S, co
         }
     }
     out.f = f;
+    out.g = g;
     return out;
 }
 
@@ -979,29 +1031,38 @@ __device__ ChainOut mc_chain(const Topo<A, SL>& T, const BoxView& B, const Lds& 
     out.pairs = 0;
     init_pose(T, B, S, SLOT_X, P.seed, job, chain);
     float e_cur = 0.f, e_best = 0.f, um = 0.f;
+    CheckIn ck;            // the current pose as the consistency check's neighbour
+    ck.g = 0.f;
+    ck.p_lo = ck.p_hi = 0;
     int s = 0, mode = 0;   // 0 initial pose, 1 step optimisation, 2 refinement
     while (true) {
         const int iters = mode == 0 ? 0 : (mode == 1 ? P.max_iter : P.refine_max_iter);
-        const BfgsOut bo = bfgs(T, B, S, P, iters);
+        ck.f = e_cur;
+        const BfgsOut bo = bfgs(T, B, S, P, iters, mode == 1 && P.consistency, ck);
         out.evals += bo.evals;
         out.pairs += bo.pairs;
         bool next = true;
         if (mode == 0) {
             e_cur = e_best = bo.f;
+            ck.g = bo.g;
             slot_copy(S, SLOT_CUR, SLOT_X, 7 + T.nt);
             slot_copy(S, SLOT_BEST, SLOT_X, 7 + T.nt);
         } else if (mode == 1) {
-            const float e_o = bo.f;
-            if (e_o < e_cur || um < __expf((e_cur - e_o) / P.temperature)) {   // Eq. qvina_eq_13
-                slot_copy(S, SLOT_CUR, SLOT_X, 7 + T.nt);
-                e_cur = e_o;
+            if (!bo.skipped) {
+                const float e_o = bo.f;
+                if (e_o < e_cur || um < __expf((e_cur - e_o) / P.temperature)) {   // Eq. qvina_eq_13
+                    slot_copy(S, SLOT_CUR, SLOT_X, 7 + T.nt);
+                    e_cur = e_o;
+                    ck.g = bo.g;
+                }
+                if (e_o < e_best) { mode = 2; next = false; }
             }
-            if (e_o < e_best) { mode = 2; next = false; }
         } else {
             slot_copy(S, SLOT_BEST, SLOT_X, 7 + T.nt);
             slot_copy(S, SLOT_CUR, SLOT_X, 7 + T.nt);
             e_best = bo.f;
             e_cur = bo.f;
+            ck.g = bo.g;
         }
         if (!next) continue;
         if (s >= P.steps) break;
@@ -1015,6 +1076,10 @@ __device__ ChainOut mc_chain(const Topo<A, SL>& T, const BoxView& B, const Lds& 
             w[k] = ((uint64_t)hi << 32) | lo;
         }
         um = u01(w[7]);
+        // tangent coordinates the mutation moves (its entity draw, as in mutate)
+        const int ent = (int)(((w[0] >> 32) * (uint64_t)(2 + T.nt)) >> 32);
+        ck.p_lo = ent == 0 ? 0 : (ent == 1 ? 3 : 4 + ent);
+        ck.p_hi = ent <= 1 ? ck.p_lo + 3 : ck.p_lo + 1;
         slot_copy(S, SLOT_X, SLOT_CUR, 7 + T.nt);
         mutate(T, S, SLOT_X, P, w);
         ++s;

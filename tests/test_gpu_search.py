@@ -44,7 +44,8 @@ def _oparams(oracle, p):
                             sigma=p.ls_sigma, eps_g=p.eps_grad, eps_c=p.eps_curv)
     return oracle.mc_params(chains=p.chains, steps=p.steps, seed=p.seed, bfgs=bp,
                             refine_max_iter=p.refine_max_iter, temperature=p.temperature,
-                            mut_pos_amp=p.mut_pos_amp, mut_rot_amp=p.mut_rot_amp)
+                            mut_pos_amp=p.mut_pos_amp, mut_rot_amp=p.mut_rot_amp,
+                            consistency=bool(p.consistency))
 
 
 def test_initial_poses_match_oracle_draws(oracle, pv_ctx, c1):
