@@ -110,6 +110,8 @@ def _declare(L):
     L.or_dock.argtypes = [C.c_int, C.POINTER(C.c_void_p), C.c_int, C.POINTER(_Grid), C.c_int,
                           _ip, C.POINTER(McParams), C.c_int, C.c_int, _dp, _dp, _i64p, _dp, _ip]
     L.or_consistency_passes.argtypes = [C.c_int, _dp, C.c_double, _dp, _dp, C.c_double, _dp, C.c_int, C.c_int]
+    L.or_sas_points.argtypes = [C.c_int, _fp, _ip, C.c_int, _fp, C.c_float, C.c_int, _fp, _ip]
+    L.or_point_features.argtypes = [C.c_int, _fp, _ip, C.c_int, _fp, _dp]
     L.or_output_stage.argtypes = [C.c_void_p, C.POINTER(_Grid), C.c_int, _dp, _dp, C.POINTER(OutputParams),
                                   _ip, _ip, _dp, _dp, _dp, _dp]
 
@@ -453,3 +455,28 @@ def consistency_passes(nt, x, fx, gx, y, fy, gy, p_lo=0, p_hi=None):
     hi = 6 + int(nt) if p_hi is None else int(p_hi)
     return bool(lib().or_consistency_passes(int(nt), _p(xa, _dp), float(fx), _p(gxa, _dp), _p(ya, _dp), float(fy),
                                             _p(gya, _dp), int(p_lo), hi))
+
+
+def sas_points(rec_xyz, rec_type, dirs, probe=1.6):
+    """Surface points (binary32 [n][3]) and their atom, see or_sas_points."""
+    x = _f32(rec_xyz)
+    t = _i32(rec_type)
+    d = _f32(dirs)
+    cap = max(len(t) * (d.size // 3), 1)
+    pts = np.zeros((cap, 3), np.float32)
+    atom = np.zeros(cap, np.int32)
+    n = lib().or_sas_points(len(t), _p(x, _fp), _p(t, _ip), d.size // 3, _p(d, _fp), float(np.float32(probe)), cap,
+                            _p(pts, _fp), _p(atom, _ip))
+    if n < 0:
+        raise ValueError("invalid surface input")
+    return pts[:n].copy(), atom[:n].copy()
+
+
+def point_features(rec_xyz, rec_type, pts):
+    """Eq. prank_eq_1 features and protrusion per point [n][12]."""
+    x = _f32(rec_xyz)
+    t = _i32(rec_type)
+    p = _f32(pts)
+    out = np.zeros((p.size // 3, 12))
+    lib().or_point_features(len(t), _p(x, _fp), _p(t, _ip), p.size // 3, _p(p, _fp), _p(out, _dp))
+    return out

@@ -1302,3 +1302,65 @@ int or_output_stage(const or_ligand* L, const or_grid* G, int n_chains, const do
     free(order); free(kx); free(kc); free(x); free(rx); free(re); free(ra); free(fo);
     return 0;
 }
+
+/* ---- receptor surface points and point features --------------------------
+ * Methods, "Pocket prediction with P2Rank": points on the solvent-accessible
+ * surface, and per point a distance-weighted sum of atomic properties over
+ * the atoms within 6 A (Eq. prank_eq_1) plus the protrusion count of atoms
+ * within 10 A.  Readings: the atom radius is the X-Score radius of its XS
+ * type plus the probe; the surface is sampled along given unit directions;
+ * the properties are the one-hot XS type and its hydrophobic, donor and
+ * acceptor flags.  Every in/out decision is taken on binary32 values with
+ * explicit fused multiply-adds, as stated in the header; sums are binary64. */
+static float sas_radius(int t, float probe) { return (float)T_RADIUS[t] + probe; }
+
+int or_sas_points(int n_rec, const float* x, const int32_t* type, int n_dirs, const float* dirs, float probe,
+                  int cap, float* pts, int32_t* atom)
+{
+    if (n_rec < 0 || n_dirs < 0 || !(probe >= 0.0f)) return -1;
+    for (int a = 0; a < n_rec; ++a)
+        if (type[a] < 0 || type[a] >= OR_NTYPES) return -1;
+    int n = 0;
+    for (int a = 0; a < n_rec; ++a) {
+        const float ra = sas_radius(type[a], probe);
+        for (int k = 0; k < n_dirs; ++k) {
+            float c[3];
+            for (int d = 0; d < 3; ++d) c[d] = fmaf(ra, dirs[3 * k + d], x[3 * a + d]);
+            int buried = 0;
+            for (int b = 0; b < n_rec && !buried; ++b) {
+                if (b == a) continue;
+                const float rb = sas_radius(type[b], probe);
+                const float dx = c[0] - x[3 * b], dy = c[1] - x[3 * b + 1], dz = c[2] - x[3 * b + 2];
+                const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                if (d2 < rb * rb) buried = 1;
+            }
+            if (buried) continue;
+            if (n < cap) {
+                for (int d = 0; d < 3; ++d) pts[3 * n + d] = c[d];
+                atom[n] = a;
+            }
+            ++n;
+        }
+    }
+    return n;
+}
+
+void or_point_features(int n_rec, const float* x, const int32_t* type, int n_pts, const float* pts, double* feat)
+{
+    for (int p = 0; p < n_pts; ++p) {
+        double* f = feat + (size_t)12 * p;
+        for (int c = 0; c < 12; ++c) f[c] = 0.0;
+        for (int b = 0; b < n_rec; ++b) {
+            const float dx = pts[3 * p] - x[3 * b], dy = pts[3 * p + 1] - x[3 * b + 1], dz = pts[3 * p + 2] - x[3 * b + 2];
+            const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+            if (d2 < 100.0f) f[11] += 1.0;
+            if (!(d2 < 36.0f)) continue;
+            const double w = 1.0 - sqrt((double)d2) / 6.0;     /* Eq. prank_eq_1 weight */
+            const int t = type[b];
+            f[t] += w;
+            if (T_HYD[t]) f[8] += w;
+            if (T_DON[t]) f[9] += w;
+            if (T_ACC[t]) f[10] += w;
+        }
+    }
+}

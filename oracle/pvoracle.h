@@ -161,6 +161,23 @@ int or_output_stage(const or_ligand* L, const or_grid* G, int n_chains, const do
                     int32_t* out_chain, double* out_e, double* out_aff, double* out_dof,
                     double margins[2]);
 
+/* ---- receptor surface points and point features (the step before the
+ * path: Methods, "Pocket prediction with P2Rank", Eq. prank_eq_1).
+ * Candidates: for every atom a and direction u_k, c = x_a + r_a u_k with
+ * r_a = radius(a) + probe, each coordinate fmaf(r_a, u_k, x_a) in binary32.
+ * A candidate is kept unless, for some other atom b,
+ * fmaf(dx,dx,fmaf(dy,dy,dz*dz)) < r_b*r_b in binary32 (strictly inside b's
+ * expanded sphere).  Kept points in (atom, direction) order.  Returns the
+ * number kept (<= cap; -1 on invalid input). */
+int or_sas_points(int n_rec, const float* rec_xyz, const int32_t* rec_type, int n_dirs,
+                  const float* dirs, float probe, int cap, float* pts, int32_t* atom);
+/* Eq. prank_eq_1 per point: channel c of 11 (one-hot XS type 0..7, then
+ * hydrophobic, donor, acceptor) sums max(0, 1 - d/6) over atoms with
+ * d^2 < 36 (binary32 decision as above); channel 11 (protrusion) counts the
+ * atoms with d^2 < 100.  feat [n_pts][12]. */
+void or_point_features(int n_rec, const float* rec_xyz, const int32_t* rec_type, int n_pts,
+                       const float* pts, double* feat);
+
 #ifdef __cplusplus
 }
 #endif

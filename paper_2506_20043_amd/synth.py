@@ -74,6 +74,17 @@ def box_sweep(pockets, edges=tuple(range(15, 31))):
             for b in pockets for e in edges]
 
 
+def sphere_directions(n: int) -> np.ndarray:
+    """n unit vectors spread over the sphere (golden-angle spiral), binary32."""
+    k = np.arange(n, dtype=np.float64) + 0.5
+    z = 1.0 - 2.0 * k / n
+    r = np.sqrt(np.maximum(0.0, 1.0 - z * z))
+    phi = np.pi * (3.0 - np.sqrt(5.0)) * k
+    d = np.stack([r * np.cos(phi), r * np.sin(phi), z], axis=1)
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    return d.astype(np.float32)
+
+
 @dataclass
 class Molecule:
     xyz: np.ndarray        # (N, 3) float64 holding binary32 values
