@@ -193,6 +193,7 @@ def main():
         result["batching"] = bench_batching(pv, S, ctx, stream, args)
         result["screening"] = bench_screening(pv, S, ctx, stream, args)
         result["box_sweep"] = bench_box_sweep(pv, S, ctx, stream, args)
+        result["surface"] = bench_surface(pv, S, ctx, stream)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(S, cfg, rx, rt, bxs, mols, seed, args)
     print(json.dumps(result), flush=True)
@@ -419,6 +420,27 @@ def bench_box_sweep(pv, S, ctx, stream, args):
         "dock_ms": ms, "docks_per_s": len(jobs) / (ms * 1e-3), "evals_per_s": ev / (ms * 1e-3),
         "edges_A": edges, "mean_best_e_by_edge": [float(v) for v in best.mean(axis=0)],
     }
+
+
+def bench_surface(pv, S, ctx, stream):
+    """The step before the path: solvent-accessible surface points of the
+    screening receptor (8,000 atoms, 30 directions per atom, 1.6 A probe)
+    and their Eq. prank_eq_1 features."""
+    import torch
+    rx, rt, _ = S.make_receptor(S.CONFIGS["c5"])
+    dirs = S.sphere_directions(30)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sas = pv.SurfacePoints(ctx, rx, rt, dirs, 1.6)
+    build_ms = (time.perf_counter() - t0) * 1e3
+    feat = sas.features()
+    torch.cuda.synchronize()
+    feat_ms = min(_timed(stream, lambda: sas.features(out=feat)) for _ in range(3))
+    n = sas.n_points
+    sas.close()
+    return {"workload": "8,000-atom receptor, 30 directions per atom, probe 1.6 A",
+            "candidates": len(rt) * len(dirs), "points": n, "build_ms_host_wall": build_ms,
+            "features_ms": feat_ms, "point_atom_pairs_per_s": n * len(rt) / (feat_ms * 1e-3)}
 
 
 def cpu_baseline(S, cfg, rx, rt, bxs, mols, seed, args):

@@ -304,6 +304,33 @@ pv_status pv_output_stage(pv_plan* plan, const float* chain_best_e, const float*
                           int32_t in_stride, const pv_output_params* params, const pv_modes_out* out,
                           void* stream);
 
+/* ------------------------------------------------------- receptor surface
+ * The step before the path (Methods, "Pocket prediction with P2Rank"):
+ * points on the receptor's solvent-accessible surface and the per-point
+ * features of Eq. prank_eq_1.
+ *
+ * pv_sas_build: for every atom a and unit direction u_k (host dirs
+ * [n_dirs][3]) the candidate c = x_a + r_a u_k, r_a = X-Score radius of a's
+ * XS type + probe, each coordinate one binary32 fused multiply-add; a
+ * candidate is dropped when it lies strictly inside another atom's
+ * expanded sphere (binary32 fma(dx,dx,fma(dy,dy,dz*dz)) < r_b*r_b).  The
+ * kept points are numbered in (atom, direction) order.  Host inputs; the
+ * call synchronises `stream` once (it reads the point count back).
+ * pv_sas_copy: device xyz [n][3] and atom [n] (either may be NULL); with
+ * no points, pv_sas_copy and pv_sas_features write nothing and accept NULL.
+ * pv_sas_features: device features [n][12]: channels 0..7 the one-hot XS
+ * type, 8..10 the hydrophobic, donor and acceptor flags, each summing
+ * max(0, 1 - d/6) over atoms with d^2 < 36; channel 11 the protrusion, the
+ * number of atoms with d^2 < 100 (binary32 decisions as above). */
+#define PV_MAX_SAS_DIRS 4096
+typedef struct pv_sas pv_sas;
+pv_status pv_sas_build(pv_ctx* ctx, int32_t n_rec, const float* rec_xyz, const uint8_t* rec_type, int32_t n_dirs,
+                       const float* dirs, float probe, void* stream, pv_sas** out);
+pv_status pv_sas_info(const pv_sas* sas, int32_t* n_points);
+pv_status pv_sas_copy(const pv_sas* sas, float* xyz, int32_t* atom, void* stream);
+pv_status pv_sas_features(const pv_sas* sas, float* features, void* stream);
+void pv_sas_free(pv_sas* sas);
+
 /* Launch shape diagnostics (host only, no device work): the kernel variant
  * that a launch of `kind` over `items` waves (dock: jobs x chains; score and
  * local-opt: poses) on these ligands uses, its dynamic LDS bytes per

@@ -98,6 +98,11 @@ SIGNATURES = {
     "pv_dock": (C.c_int, [_vp, _vp, _vp, C.POINTER(Job), _i32, C.POINTER(DockParams), C.POINTER(DockOut), _vp]),
     "pv_local_opt": (C.c_int, [_vp, _vp, _vp, _i32, _vp, _vp, _vp, _i32, C.POINTER(DockParams), _vp, _vp, _vp, _vp]),
     "pv_launch_info": (C.c_int, [_vp, _vp, _i32, C.c_int64, _ip, _ip, _ip]),
+    "pv_sas_build": (C.c_int, [_vp, _i32, _vp, _vp, _i32, _vp, C.c_float, _vp, C.POINTER(C.c_void_p)]),
+    "pv_sas_info": (C.c_int, [_vp, _ip]),
+    "pv_sas_copy": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "pv_sas_features": (C.c_int, [_vp, _vp, _vp]),
+    "pv_sas_free": (None, [_vp]),
     "pv_output_params_default": (None, [C.POINTER(OutputParams)]),
     "pv_output_stage": (C.c_int, [_vp, _vp, _vp, _i32, C.POINTER(OutputParams), C.POINTER(ModesOut), _vp]),
 }
@@ -554,3 +559,46 @@ def output_stage(plan: Plan, chain_best_e, chain_best_dof, params: OutputParams 
     _check(lib().pv_output_stage(plan.h, _ptr(e), _ptr(d), stride, C.byref(p), C.byref(o), _stream(stream)),
            "pv_output_stage")
     return out
+
+
+class SurfacePoints:
+    """Solvent-accessible surface points of a receptor and their Eq.
+    prank_eq_1 features (pv_sas_build / pv_sas_features)."""
+
+    def __init__(self, ctx: Context, rec_xyz, rec_type, dirs, probe: float = 1.6, stream=None):
+        x = np.ascontiguousarray(rec_xyz, np.float32).reshape(-1, 3)
+        t = np.ascontiguousarray(rec_type, np.uint8).reshape(-1)
+        d = np.ascontiguousarray(dirs, np.float32).reshape(-1, 3)
+        h = C.c_void_p()
+        _check(lib().pv_sas_build(ctx.h, len(t), x.ctypes.data_as(_vp), t.ctypes.data_as(_vp), len(d),
+                                  d.ctypes.data_as(_vp), float(probe), _stream(stream), C.byref(h)), "pv_sas_build")
+        self.ctx, self.h = ctx, h
+        n = C.c_int32()
+        _check(lib().pv_sas_info(h, C.byref(n)), "pv_sas_info")
+        self.n_points = n.value
+
+    def points(self, stream=None):
+        torch = _torch()
+        dev = self.ctx.torch_device
+        xyz = torch.empty((self.n_points, 3), dtype=torch.float32, device=dev)
+        atom = torch.empty(self.n_points, dtype=torch.int32, device=dev)
+        _check(lib().pv_sas_copy(self.h, _ptr(xyz), _ptr(atom), _stream(stream)), "pv_sas_copy")
+        return xyz, atom
+
+    def features(self, out=None, stream=None):
+        torch = _torch()
+        f = out if out is not None else torch.empty((self.n_points, 12), dtype=torch.float32,
+                                                    device=self.ctx.torch_device)
+        _check(lib().pv_sas_features(self.h, _ptr(f), _stream(stream)), "pv_sas_features")
+        return f
+
+    def close(self):
+        if self.h:
+            lib().pv_sas_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -694,6 +694,14 @@ pv_status pv_dock_plan(pv_ctx* ctx, const pv_grids* grids, const pv_ligands* lig
     return PV_OK;
 }
 
+struct pv_sas {
+    pv_ctx* ctx;
+    int32_t n_rec;
+    int32_t n_points;
+    float4* atoms;   // (x, y, z, type bits)
+    float4* pts;     // (x, y, z, atom index bits)
+};
+
 static DockArgs dock_args(pv_plan* P, const pv_dock_out* o, float* cbe, int64_t* cev)
 {
     DockArgs a;
@@ -917,6 +925,125 @@ pv_status pv_output_stage(pv_plan* P, const float* chain_best_e, const float* ch
     hipError_t e = launch_output(a, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "output-stage launch");
     return PV_OK;
+}
+
+pv_status pv_sas_build(pv_ctx* ctx, int32_t n_rec, const float* rec_xyz, const uint8_t* rec_type, int32_t n_dirs,
+                       const float* dirs, float probe, void* stream, pv_sas** out)
+{
+    if (!out) return fail(PV_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!ctx_ok(ctx)) return fail(PV_E_INVALID, "bad context");
+    if (n_rec < 0) return fail(PV_E_INVALID, "n_rec < 0");
+    if (n_rec > 0 && (!rec_xyz || !rec_type)) return fail(PV_E_INVALID, "receptor arrays are NULL");
+    if (n_dirs < 1 || n_dirs > PV_MAX_SAS_DIRS) return fail(PV_E_RANGE, "n_dirs must be 1..4096");
+    if (!dirs) return fail(PV_E_INVALID, "dirs is NULL");
+    if (!(probe >= 0.f) || !std::isfinite(probe)) return fail(PV_E_INVALID, "probe must be finite and >= 0");
+    const int64_t n_cand = (int64_t)n_rec * n_dirs;
+    if (n_cand > (int64_t)INT32_MAX) return fail(PV_E_RANGE, "atoms x directions too large");
+    std::vector<float4> ha((size_t)std::max(n_rec, 1));
+    for (int32_t a = 0; a < n_rec; ++a) {
+        if (rec_type[a] >= kNTypes) return fail(PV_E_INVALID, "receptor type out of range");
+        const float x = rec_xyz[3 * a], y = rec_xyz[3 * a + 1], z = rec_xyz[3 * a + 2];
+        if (!std::isfinite(x) || !std::isfinite(y) || !std::isfinite(z)) return fail(PV_E_INVALID, "non-finite coordinate");
+        uint32_t tb = rec_type[a];
+        float w;
+        std::memcpy(&w, &tb, 4);
+        ha[a] = make_float4(x, y, z, w);
+    }
+    for (int32_t k = 0; k < 3 * n_dirs; ++k)
+        if (!std::isfinite(dirs[k])) return fail(PV_E_INVALID, "non-finite direction");
+    pv_status st = set_device(ctx);
+    if (st != PV_OK) return st;
+    pv_sas* h = new (std::nothrow) pv_sas();
+    if (!h) return fail(PV_E_NOMEM, "host allocation");
+    h->ctx = ctx;
+    h->n_rec = n_rec;
+    hipStream_t s = (hipStream_t)stream;
+    const int bs = sas_block_size();
+    const int64_t n_blocks = (n_cand + bs - 1) / bs;
+    float* ddirs = nullptr;
+    float4* cand = nullptr;
+    uint8_t* keep = nullptr;
+    int32_t* bcount = nullptr;
+    int32_t* boff = nullptr;
+    auto cleanup = [&]() { dfree(ddirs); dfree(cand); dfree(keep); dfree(bcount); dfree(boff); };
+    if ((st = upload(&h->atoms, ha.data(), ha.size(), "receptor")) != PV_OK ||
+        (st = upload(&ddirs, dirs, (size_t)3 * n_dirs, "directions")) != PV_OK ||
+        (st = upload(&cand, (const float4*)nullptr, (size_t)std::max<int64_t>(n_cand, 1), "candidates")) != PV_OK ||
+        (st = upload(&keep, (const uint8_t*)nullptr, (size_t)std::max<int64_t>(n_cand, 1), "candidates")) != PV_OK ||
+        (st = upload(&bcount, (const int32_t*)nullptr, (size_t)std::max<int64_t>(n_blocks, 1), "counts")) != PV_OK) {
+        cleanup();
+        pv_sas_free(h);
+        return st;
+    }
+    hipError_t e = launch_sas_candidates(h->atoms, n_rec, ddirs, n_dirs, probe, n_cand, cand, keep, bcount, s);
+    std::vector<int32_t> hc((size_t)std::max<int64_t>(n_blocks, 1), 0);
+    if (e == hipSuccess && n_blocks > 0)
+        e = hipMemcpyAsync(hc.data(), bcount, sizeof(int32_t) * n_blocks, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { cleanup(); pv_sas_free(h); return hip_fail(e, "surface candidates"); }
+    int64_t total = 0;
+    for (int64_t b = 0; b < n_blocks; ++b) {
+        const int32_t c = hc[b];
+        hc[b] = (int32_t)total;
+        total += c;
+    }
+    h->n_points = (int32_t)total;
+    if ((st = upload(&boff, hc.data(), hc.size(), "offsets")) != PV_OK ||
+        (st = upload(&h->pts, (const float4*)nullptr, (size_t)std::max<int64_t>(total, 1), "points")) != PV_OK) {
+        cleanup();
+        pv_sas_free(h);
+        return st;
+    }
+    e = launch_sas_scatter(cand, keep, boff, n_cand, h->pts, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    cleanup();
+    if (e != hipSuccess) { pv_sas_free(h); return hip_fail(e, "surface points"); }
+    *out = h;
+    return PV_OK;
+}
+
+pv_status pv_sas_info(const pv_sas* h, int32_t* n_points)
+{
+    if (!h || !n_points) return fail(PV_E_INVALID, "handle or output is NULL");
+    *n_points = h->n_points;
+    return PV_OK;
+}
+
+pv_status pv_sas_copy(const pv_sas* h, float* xyz, int32_t* atom, void* stream)
+{
+    if (!h) return fail(PV_E_INVALID, "handle is NULL");
+    if (h->n_points == 0) return PV_OK;
+    pv_status st = set_device(h->ctx);
+    if (st != PV_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if (xyz)
+        HIP_TRY(hipMemcpy2DAsync(xyz, 12, h->pts, 16, 12, h->n_points, hipMemcpyDeviceToDevice, s), "copy points");
+    if (atom)
+        HIP_TRY(hipMemcpy2DAsync(atom, 4, (const char*)h->pts + 12, 16, 4, h->n_points, hipMemcpyDeviceToDevice, s),
+                "copy atoms");
+    return PV_OK;
+}
+
+pv_status pv_sas_features(const pv_sas* h, float* features, void* stream)
+{
+    if (!h) return fail(PV_E_INVALID, "handle is NULL");
+    if (h->n_points == 0) return PV_OK;
+    if (!features) return fail(PV_E_INVALID, "features is NULL");
+    pv_status st = set_device(h->ctx);
+    if (st != PV_OK) return st;
+    HIP_TRY(launch_sas_features(h->atoms, h->n_rec, h->pts, h->n_points, features, (hipStream_t)stream),
+            "surface features");
+    return PV_OK;
+}
+
+void pv_sas_free(pv_sas* h)
+{
+    if (!h) return;
+    if (h->ctx) (void)hipSetDevice(h->ctx->device);
+    dfree(h->atoms);
+    dfree(h->pts);
+    delete h;
 }
 
 pv_status pv_launch_info(pv_ctx* ctx, const pv_ligands* ligs, int32_t kind, int64_t items, int32_t* variant,

@@ -208,6 +208,13 @@ hipError_t launch_job_reduce(const float* chain_best_e, const int64_t* chain_eva
                              int32_t* job_status, hipStream_t s);
 hipError_t launch_local_opt(const OptArgs& a, int n_cu, hipStream_t s);
 hipError_t launch_output(const OutputArgs& a, hipStream_t s);
+hipError_t launch_sas_candidates(const float4* atoms, int n_rec, const float* dirs, int n_dirs, float probe,
+                                 int64_t n_cand, float4* cand, uint8_t* keep, int32_t* block_count, hipStream_t s);
+hipError_t launch_sas_scatter(const float4* cand, const uint8_t* keep, const int32_t* block_offset, int64_t n_cand,
+                              float4* pts, hipStream_t s);
+hipError_t launch_sas_features(const float4* atoms, int n_rec, const float4* pts, int n_pts, float* feat,
+                               hipStream_t s);
+int sas_block_size();
 int output_lds_bytes(const LigDev& l, int chains, int modes);
 hipError_t launch_reset_times(uint64_t* t0, uint64_t* t1, int n, hipStream_t s);
 

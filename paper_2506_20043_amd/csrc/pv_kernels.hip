@@ -1551,6 +1551,132 @@ __global__ __launch_bounds__(256) void gridmap_kernel(GridBuildArgs a)
     }
 }
 
+// ---------------------------------------------------------------- surface points
+// The step before the path (Methods, "Pocket prediction with P2Rank"):
+// solvent-accessible surface points of the receptor and their Eq.
+// prank_eq_1 features.  Atom records are float4 (x, y, z, type bits) with
+// the expanded radius r = X-Score radius + probe computed in binary32.
+constexpr int kSasThreads = 256;
+
+__device__ __forceinline__ float sas_radius(int t, float probe)
+{
+    const float R = t <= 1 ? 1.9f : (t <= 4 ? 1.8f : (t <= 6 ? 1.7f : 2.0f));
+    return R + probe;
+}
+
+// One thread per candidate c = x_a + r_a u_k (atom-major); the receptor is
+// streamed through LDS.  A candidate strictly inside another atom's
+// expanded sphere is dropped.  Writes the candidate, its keep flag and the
+// block's kept count.
+__global__ __launch_bounds__(kSasThreads) void sas_candidates_kernel(const float4* atoms, int n_rec, const float* dirs,
+                                                                     int n_dirs, float probe, int64_t n_cand,
+                                                                     float4* cand, uint8_t* keep, int32_t* block_count)
+{
+    __shared__ float4 tile[kSasThreads];
+    __shared__ int count;
+    const int64_t idx = (int64_t)blockIdx.x * kSasThreads + threadIdx.x;
+    const bool valid = idx < n_cand;
+    int a = 0;
+    float cx = 0.f, cy = 0.f, cz = 0.f;
+    if (valid) {
+        a = (int)(idx / n_dirs);
+        const int k = (int)(idx % n_dirs);
+        const float4 xa = atoms[a];
+        const float ra = sas_radius(__float_as_uint(xa.w) & 0xff, probe);
+        cx = __builtin_fmaf(ra, dirs[3 * k], xa.x);
+        cy = __builtin_fmaf(ra, dirs[3 * k + 1], xa.y);
+        cz = __builtin_fmaf(ra, dirs[3 * k + 2], xa.z);
+    }
+    if (threadIdx.x == 0) count = 0;
+    __syncthreads();
+    bool buried = false;
+    for (int base = 0; base < n_rec; base += kSasThreads) {
+        __syncthreads();
+        const int b = base + threadIdx.x;
+        if (b < n_rec) {
+            const float4 xb = atoms[b];
+            const float rb = sas_radius(__float_as_uint(xb.w) & 0xff, probe);
+            tile[threadIdx.x] = make_float4(xb.x, xb.y, xb.z, rb * rb);
+        }
+        __syncthreads();
+        const int nb = min(kSasThreads, n_rec - base);
+        if (valid && !buried)
+            for (int j = 0; j < nb; ++j) {
+                const float4 t = tile[j];
+                const float dx = cx - t.x, dy = cy - t.y, dz = cz - t.z;
+                const float d2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+                if (d2 < t.w && base + j != a) { buried = true; break; }
+            }
+    }
+    if (valid) {
+        cand[idx] = make_float4(cx, cy, cz, __int_as_float(a));
+        keep[idx] = buried ? 0 : 1;
+        if (!buried) atomicAdd(&count, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) block_count[blockIdx.x] = count;
+}
+
+// Kept candidates to their place: the block's offset plus the number of
+// kept candidates before this one in the block (in candidate order).
+__global__ __launch_bounds__(kSasThreads) void sas_scatter_kernel(const float4* cand, const uint8_t* keep,
+                                                                  const int32_t* block_offset, int64_t n_cand,
+                                                                  float4* pts)
+{
+    __shared__ int pre[kSasThreads];
+    const int64_t idx = (int64_t)blockIdx.x * kSasThreads + threadIdx.x;
+    const int k = idx < n_cand ? keep[idx] : 0;
+    pre[threadIdx.x] = k;
+    __syncthreads();
+    for (int off = 1; off < kSasThreads; off <<= 1) {   // inclusive scan in the block
+        const int v = threadIdx.x >= off ? pre[threadIdx.x - off] : 0;
+        __syncthreads();
+        pre[threadIdx.x] += v;
+        __syncthreads();
+    }
+    if (k) pts[block_offset[blockIdx.x] + pre[threadIdx.x] - 1] = cand[idx];
+}
+
+// Eq. prank_eq_1 per point: channels 0..7 the one-hot XS type, 8..10 the
+// hydrophobic, donor and acceptor flags, each summing max(0, 1 - d/6) over
+// atoms with d^2 < 36; channel 11 counts the atoms with d^2 < 100 (the
+// protrusion).  One thread per point, receptor streamed through LDS.
+__global__ __launch_bounds__(kSasThreads) void sas_features_kernel(const float4* atoms, int n_rec, const float4* pts,
+                                                                   int n_pts, float* feat)
+{
+    __shared__ float4 tile[kSasThreads];
+    const int p = blockIdx.x * kSasThreads + threadIdx.x;
+    const bool valid = p < n_pts;
+    const float4 c = valid ? pts[p] : make_float4(0.f, 0.f, 0.f, 0.f);
+    float f[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) f[k] = 0.f;
+    for (int base = 0; base < n_rec; base += kSasThreads) {
+        __syncthreads();
+        if (base + threadIdx.x < n_rec) tile[threadIdx.x] = atoms[base + threadIdx.x];
+        __syncthreads();
+        const int nb = min(kSasThreads, n_rec - base);
+        for (int j = 0; j < nb; ++j) {
+            const float4 t = tile[j];
+            const float dx = c.x - t.x, dy = c.y - t.y, dz = c.z - t.z;
+            const float d2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+            f[11] += d2 < 100.f ? 1.f : 0.f;
+            if (d2 < 36.f) {
+                const float w = 1.f - __builtin_amdgcn_sqrtf(d2) * (1.f / 6.f);
+                const int ty = __float_as_uint(t.w) & 0xff;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) f[k] += ty == k ? w : 0.f;
+                f[8] += ty == 0 ? w : 0.f;
+                f[9] += (ty == 3 || ty == 6) ? w : 0.f;
+                f[10] += (ty == 4 || ty == 5 || ty == 6) ? w : 0.f;
+            }
+        }
+    }
+    if (valid)
+#pragma unroll
+        for (int k = 0; k < 12; ++k) feat[(int64_t)p * 12 + k] = f[k];
+}
+
 // ---------------------------------------------------------------- launchers
 hipError_t launch_build_grids(const GridBuildArgs& a, int64_t n_tiles, hipStream_t s)
 {
@@ -1685,5 +1811,36 @@ int output_lds_bytes(const LigDev& l, int chains, int modes)
     return lds_bytes(l.max_atoms, l.max_pairs, l.max_ell, false) + round_up(chains, 4) * 4 + modes * ma * 16 +
            modes * kSlot * 4 + 5 * round_up(modes, 4) * 4;
 }
+
+hipError_t launch_sas_candidates(const float4* atoms, int n_rec, const float* dirs, int n_dirs, float probe,
+                                 int64_t n_cand, float4* cand, uint8_t* keep, int32_t* block_count, hipStream_t s)
+{
+    if (n_cand <= 0) return hipSuccess;
+    const int64_t blocks = (n_cand + kSasThreads - 1) / kSasThreads;
+    hipLaunchKernelGGL(sas_candidates_kernel, dim3((unsigned)blocks), dim3(kSasThreads), 0, s, atoms, n_rec, dirs,
+                       n_dirs, probe, n_cand, cand, keep, block_count);
+    return hipGetLastError();
+}
+
+hipError_t launch_sas_scatter(const float4* cand, const uint8_t* keep, const int32_t* block_offset, int64_t n_cand,
+                              float4* pts, hipStream_t s)
+{
+    if (n_cand <= 0) return hipSuccess;
+    const int64_t blocks = (n_cand + kSasThreads - 1) / kSasThreads;
+    hipLaunchKernelGGL(sas_scatter_kernel, dim3((unsigned)blocks), dim3(kSasThreads), 0, s, cand, keep, block_offset,
+                       n_cand, pts);
+    return hipGetLastError();
+}
+
+hipError_t launch_sas_features(const float4* atoms, int n_rec, const float4* pts, int n_pts, float* feat,
+                               hipStream_t s)
+{
+    if (n_pts <= 0) return hipSuccess;
+    const int blocks = (n_pts + kSasThreads - 1) / kSasThreads;
+    hipLaunchKernelGGL(sas_features_kernel, dim3(blocks), dim3(kSasThreads), 0, s, atoms, n_rec, pts, n_pts, feat);
+    return hipGetLastError();
+}
+
+int sas_block_size() { return kSasThreads; }
 
 }  // namespace pv
