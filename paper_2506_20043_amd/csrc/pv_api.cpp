@@ -95,7 +95,16 @@ struct pv_ligands {
     uint32_t* ell;
     uint32_t* pslot;
     int32_t max_ell;
-    std::vector<std::array<int32_t, 8>>* info;
+    std::vector<std::array<int32_t, 9>>* info;   // pv_ligands_info's 8 values, then the slot-table size
+};
+
+struct DockGroup {
+    LigDev lv;               // the ligand view with this group's maxima
+    LaunchShape shape;       // batched launch over the group's (job, chain) items
+    LaunchShape plain_shape; // one launch per job of the group
+    int32_t workgroups;
+    int32_t n_jobs;
+    int32_t* job_map;        // device [n_jobs]: group job -> plan job
 };
 
 struct pv_plan {
@@ -109,9 +118,11 @@ struct pv_plan {
     uint32_t* queue;
     float* scratch_best;      // chain_best_e when the caller does not want it
     int64_t* scratch_evals;   // chain_evals when only job_evals is wanted
-    int32_t workgroups;
-    LaunchShape shape;        // batched launch
-    LaunchShape plain_shape;  // one launch per job
+    // Jobs in size classes (ligands of at most 64 atoms, larger ones), each
+    // with its own LDS limits, kernel variant and persistent launch; jobs
+    // keep their indices through a per-group job map.
+    std::vector<DockGroup> groups;
+    std::vector<int32_t> job_group;   // per job
     hipStream_t cap_stream;
     hipGraph_t graph;
     hipGraphExec_t exec;
@@ -395,7 +406,7 @@ pv_status pv_ligands_create(pv_ctx* ctx, int32_t n_lig, const int32_t* atom_off,
     std::vector<uint32_t> pairs;
     std::vector<uint32_t> ell;
     std::vector<uint32_t> pslot;
-    auto* info = new (std::nothrow) std::vector<std::array<int32_t, 8>>(n_lig);
+    auto* info = new (std::nothrow) std::vector<std::array<int32_t, 9>>(n_lig);
     if (!info) return fail(PV_E_NOMEM, "host allocation");
     int max_atoms = 0, max_pairs = 0, max_tors = 0, max_ell = 0;
     for (int32_t i = 0; i < n_lig; ++i) {
@@ -430,7 +441,7 @@ pv_status pv_ligands_create(pv_ctx* ctx, int32_t n_lig, const int32_t* atom_off,
         ell.insert(ell.end(), M.ell.begin(), M.ell.end());
         pslot.insert(pslot.end(), M.pslot.begin(), M.pslot.end());
         max_ell = std::max(max_ell, M.ell_w * (M.n | 1));   // slot rows have an odd stride
-        (*info)[i] = {M.n, M.nf, M.nt, M.np, M.root_size, M.depth, 7 + M.nt, 0};
+        (*info)[i] = {M.n, M.nf, M.nt, M.np, M.root_size, M.depth, 7 + M.nt, 0, M.ell_w * (M.n | 1)};
         max_atoms = std::max(max_atoms, M.n);
         max_pairs = std::max(max_pairs, M.np);
         max_tors = std::max(max_tors, M.nt);
@@ -675,19 +686,48 @@ pv_status pv_dock_plan(pv_ctx* ctx, const pv_grids* grids, const pv_ligands* lig
     P->h_jobs = hj;
     const size_t nchain = (size_t)n_jobs * params->chains;
     if ((st = upload(&P->jobs, hj.data(), hj.size(), "job table")) != PV_OK ||
-        (st = upload(&P->queue, (const uint32_t*)nullptr, 1, "queue")) != PV_OK ||
+        (st = upload(&P->queue, (const uint32_t*)nullptr, 2, "queue")) != PV_OK ||
         (st = upload(&P->scratch_best, (const float*)nullptr, nchain, "scratch")) != PV_OK ||
         (st = upload(&P->scratch_evals, (const int64_t*)nullptr, nchain, "scratch")) != PV_OK) {
         pv_plan_free(P);
         return st;
     }
-    const LigDev lv = lig_view(ligs);
-    hipError_t e = launch_shape(kKindDock, lv, (int64_t)nchain, ctx->n_cu, &P->shape);
-    if (e == hipSuccess) e = launch_shape(kKindDock, lv, params->chains, ctx->n_cu, &P->plain_shape);
+    // size classes: one atom per lane (at most 64 atoms) and two
+    std::vector<int32_t> members[2];
+    P->job_group.assign(n_jobs, 0);
+    for (int32_t j = 0; j < n_jobs; ++j) {
+        const int g = (*ligs->info)[hj[j].x][0] > 64 ? 1 : 0;
+        P->job_group[j] = g;
+        members[g].push_back(j);
+    }
+    hipError_t e = hipSuccess;
+    for (int g = 0; g < 2 && e == hipSuccess; ++g) {
+        if (members[g].empty()) continue;
+        DockGroup G;
+        std::memset(&G, 0, sizeof(G));
+        G.lv = lig_view(ligs);
+        G.lv.max_atoms = G.lv.max_pairs = G.lv.max_tors = G.lv.max_ell = 0;
+        for (int32_t j : members[g]) {
+            const auto& in = (*ligs->info)[hj[j].x];
+            G.lv.max_atoms = std::max(G.lv.max_atoms, in[0]);
+            G.lv.max_tors = std::max(G.lv.max_tors, in[2]);
+            G.lv.max_pairs = std::max(G.lv.max_pairs, in[3]);
+            G.lv.max_ell = std::max(G.lv.max_ell, in[8]);
+        }
+        G.n_jobs = (int32_t)members[g].size();
+        const int64_t items = (int64_t)G.n_jobs * params->chains;
+        e = launch_shape(kKindDock, G.lv, items, ctx->n_cu, &G.shape);
+        if (e == hipSuccess) e = launch_shape(kKindDock, G.lv, params->chains, ctx->n_cu, &G.plain_shape);
+        if (e != hipSuccess) break;
+        int64_t wg = params->workgroups > 0 ? params->workgroups : (int64_t)G.shape.per_cu * ctx->n_cu;
+        G.workgroups = (int32_t)std::min<int64_t>(wg, std::max<int64_t>(items, 1));
+        if ((st = upload(&G.job_map, members[g].data(), members[g].size(), "job map")) != PV_OK) {
+            pv_plan_free(P);
+            return st;
+        }
+        P->groups.push_back(G);
+    }
     if (e != hipSuccess) { pv_plan_free(P); return hip_fail(e, "dock launch shape"); }
-    int64_t wg = params->workgroups > 0 ? params->workgroups : (int64_t)P->shape.per_cu * ctx->n_cu;
-    wg = std::min<int64_t>(wg, std::max<int64_t>((int64_t)nchain, 1));
-    P->workgroups = (int32_t)wg;
     e = hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) { pv_plan_free(P); return hip_fail(e, "hipStreamCreate"); }
     *out = P;
@@ -736,18 +776,24 @@ static hipError_t enqueue_batched(pv_plan* P, const pv_dock_out* o, hipStream_t 
 {
     float* cbe = o->chain_best_e ? o->chain_best_e : P->scratch_best;
     int64_t* cev = o->chain_evals ? o->chain_evals : P->scratch_evals;
-    DockArgs a = dock_args(P, o, cbe, cev);
-    a.job_begin = 0;
-    a.n_items = (int64_t)P->n_jobs * P->sp.chains;
-    a.persistent = 1;
-    hipError_t e = launch_reset_queue(P->queue, s);
-    if (e != hipSuccess) return e;
+    hipError_t e = hipSuccess;
     if (P->sp.flags & PV_DOCK_TIMESTAMPS) {
         e = launch_reset_times(o->job_t_start, o->job_t_end, P->n_jobs, s);
         if (e != hipSuccess) return e;
     }
-    e = launch_dock(a, P->shape, P->workgroups, s);
-    if (e != hipSuccess) return e;
+    for (size_t g = 0; g < P->groups.size(); ++g) {
+        const DockGroup& G = P->groups[g];
+        DockArgs a = dock_args(P, o, cbe, cev);
+        a.l = G.lv;
+        a.job_map = G.job_map;
+        a.queue = P->queue + g;
+        a.job_begin = 0;
+        a.n_items = (int64_t)G.n_jobs * P->sp.chains;
+        a.persistent = 1;
+        e = launch_reset_queue(a.queue, s);
+        if (e == hipSuccess) e = launch_dock(a, G.shape, G.workgroups, s);
+        if (e != hipSuccess) return e;
+    }
     if (o->job_best_e || o->job_best_chain || o->job_evals || o->job_status)
         e = launch_job_reduce(cbe, cev, P->n_jobs, P->sp.chains, o->job_best_e, o->job_best_chain, o->job_evals,
                               o->job_status, s);
@@ -801,11 +847,13 @@ pv_status pv_dock_run_plain(pv_plan* P, const pv_dock_out* o, void* stream)
     int64_t* cev = o->chain_evals ? o->chain_evals : P->scratch_evals;
     if (P->sp.flags & PV_DOCK_TIMESTAMPS) HIP_TRY(launch_reset_times(o->job_t_start, o->job_t_end, P->n_jobs, s), "reset");
     for (int32_t j = 0; j < P->n_jobs; ++j) {
+        const DockGroup& G = P->groups[P->groups.size() == 1 ? 0 : P->job_group[j]];
         DockArgs a = dock_args(P, o, cbe, cev);
+        a.l = G.lv;
         a.job_begin = j;
         a.n_items = P->sp.chains;
         a.persistent = 0;
-        HIP_TRY(launch_dock(a, P->plain_shape, 0, s), "dock launch");
+        HIP_TRY(launch_dock(a, G.plain_shape, 0, s), "dock launch");
     }
     if (o->job_best_e || o->job_best_chain || o->job_evals || o->job_status)
         HIP_TRY(launch_job_reduce(cbe, cev, P->n_jobs, P->sp.chains, o->job_best_e, o->job_best_chain, o->job_evals,
@@ -824,6 +872,7 @@ void pv_plan_free(pv_plan* P)
     }
     if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
     dfree(P->jobs); dfree(P->queue); dfree(P->scratch_best); dfree(P->scratch_evals);
+    for (DockGroup& G : P->groups) dfree(G.job_map);
     delete P;
 }
 

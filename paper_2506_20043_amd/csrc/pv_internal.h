@@ -132,6 +132,7 @@ struct DockArgs {
     int32_t job_begin;        // first job of this launch
     int64_t n_items;          // (job, chain) items of this launch
     uint32_t* queue;          // work counter (persistent launch)
+    const int32_t* job_map;   // persistent launch: item / chains -> job (NULL: job_begin + item / chains)
     int32_t persistent;
     // outputs
     float* chain_best_e;

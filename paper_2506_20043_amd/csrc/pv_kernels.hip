@@ -1108,7 +1108,8 @@ __global__ __launch_bounds__(64) void dock_kernel(DockArgs a)
             item = (int64_t)(uint32_t)lane_i((int)v, 0);
         }
         if (item >= a.n_items) break;
-        const int job = a.job_begin + (int)(item / chains);
+        const int gj = (int)(item / chains);
+        const int job = a.job_map ? a.job_map[gj] : a.job_begin + gj;
         const int chain = (int)(item % chains);
         const int2 jb = a.jobs[job];
         if (jb.x != T.lig) stage_ligand(T, a.l, jb.x, S);

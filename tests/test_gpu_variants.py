@@ -125,3 +125,39 @@ def test_gather_local_opt_is_valid(oracle, pv_ctx, big):
         L = big.ol[lig[b]]
         r = L.score_grad(big.og[0], cpu_dof(out[b, :L.ndof]))
         assert abs(r["e"] - e[b]) <= e_tol(r["e"]) + (0.01 if r["min_cut"] < 1e-4 else 0.0), (b, r["e"], e[b])
+
+
+def test_mixed_size_jobs(oracle, pv_ctx, big):
+    """Jobs of a 30-atom and an 80-atom ligand in one plan run as two size
+    classes (one and two atoms per lane): the batched launch matches the
+    plain one exactly, every job's outputs land at its own index, and
+    without BFGS both ligands' chains replay the oracle."""
+    import paper_2506_20043_amd as pv
+    from test_gpu_search import _oparams
+    g = np.random.default_rng(13)
+    small, large = S.tree_ligand(g, 30, 6), S.tree_ligand(g, 80, 10)
+    ligs = pv.Ligands(pv_ctx, [small, large])
+    jobs = [(0, 0), (1, 0), (1, 0), (0, 0), (1, 0)]
+    p = pv.dock_params(chains=32, steps=25, seed=777, flags=pv.PV_DOCK_GRAPH | pv.PV_DOCK_TIMESTAMPS)
+    plan = pv.Plan(pv_ctx, big.grids, ligs, jobs, p)
+    bat = {k: v.cpu().numpy().copy() for k, v in plan.run().items()}
+    pla = {k: v.cpu().numpy().copy() for k, v in plan.run(plain=True).items()}
+    plan.close()
+    for k in ("chain_best_e", "chain_evals", "chain_best_dof", "job_best_e", "job_best_chain"):
+        assert np.array_equal(bat[k], pla[k]), k
+    assert np.all(bat["job_t_end"] >= bat["job_t_start"]) and np.all(bat["job_t_start"] > 0)
+    # different ligands' jobs differ, same ligand's jobs draw their own streams
+    e = bat["chain_best_e"].reshape(5, 32)
+    assert not np.array_equal(e[0], e[3]) and not np.array_equal(e[1], e[2])
+    p0 = pv.dock_params(chains=32, steps=20, seed=778, bfgs_max_iter=0, refine_max_iter=0)
+    res = pv.dock(pv_ctx, big.grids, ligs, jobs, p0)
+    cbe = res["chain_best_e"].cpu().numpy().reshape(5, 32)
+    ev = res["chain_evals"].cpu().numpy().reshape(5, 32)
+    ol = [oracle.Ligand(m.xyz, m.types, m.bonds, m.rotatable) for m in (small, large)]
+    same = total = 0
+    for j, (lig, _) in enumerate(jobs):
+        for c in range(0, 32, 4):
+            d, e_ref, ne = oracle.mc_chain(ol[lig], big.og[0], _oparams(oracle, p0), j, c)
+            same += int(ne == ev[j, c] and abs(cbe[j, c] - e_ref) <= e_tol(e_ref))
+            total += 1
+    assert same >= total - 3, (same, total)
