@@ -379,32 +379,31 @@ template <int A, bool SL>
 __device__ __forceinline__ void frames(const Topo<A, SL>& T, const Lds& S, const float* pose, float R[9], float b[3])
 {
     const int l = lane_id();
-    const float tx = pose[0], ty = pose[1], tz = pose[2];
-    int anc = -1;
-    if (l == 0) {
-        float q[4] = {pose[3], pose[4], pose[5], pose[6]};
-        quat_normalize(q);
-        float w = q[0], x = q[1], y = q[2], z = q[3];
-        R[0] = 1.f - 2.f * (y * y + z * z); R[1] = 2.f * (x * y - w * z); R[2] = 2.f * (x * z + w * y);
-        R[3] = 2.f * (x * y + w * z); R[4] = 1.f - 2.f * (x * x + z * z); R[5] = 2.f * (y * z - w * x);
-        R[6] = 2.f * (x * z - w * y); R[7] = 2.f * (y * z + w * x); R[8] = 1.f - 2.f * (x * x + y * y);
-        b[0] = tx - (R[0] * T.anc_x + R[1] * T.anc_y + R[2] * T.anc_z);
-        b[1] = ty - (R[3] * T.anc_x + R[4] * T.anc_y + R[5] * T.anc_z);
-        b[2] = tz - (R[6] * T.anc_x + R[7] * T.anc_y + R[8] * T.anc_z);
-    } else if (l < T.nf) {
-        float s, c;
-        __sincosf(pose[7 + T.f_tors], &s, &c);
-        float t = 1.f - c, ux = T.ax, uy = T.ay, uz = T.az;
-        R[0] = c + t * ux * ux;      R[1] = t * ux * uy - s * uz; R[2] = t * ux * uz + s * uy;
-        R[3] = t * uy * ux + s * uz; R[4] = c + t * uy * uy;      R[5] = t * uy * uz - s * ux;
-        R[6] = t * uz * ux - s * uy; R[7] = t * uz * uy + s * ux; R[8] = c + t * uz * uz;
-        b[0] = T.cx - (R[0] * T.cx + R[1] * T.cy + R[2] * T.cz);
-        b[1] = T.cy - (R[3] * T.cx + R[4] * T.cy + R[5] * T.cz);
-        b[2] = T.cz - (R[6] * T.cx + R[7] * T.cy + R[8] * T.cz);
-        anc = T.f_parent;
-    } else {
-        R[0] = R[4] = R[8] = 1.f; R[1] = R[2] = R[3] = R[5] = R[6] = R[7] = 0.f; b[0] = b[1] = b[2] = 0.f;
-    }
+    // Local map of every fragment lane, one formula for the root and the
+    // torsions: R = I + [s]x + w w^T - |w|^2 I, b = p - R a.
+    //   root:     unit q = (qw, v): s = 2 qw v, w = sqrt(2) v; p = t, a = anchor
+    //   torsion:  angle psi about unit axis u through c: with h = psi / 2,
+    //             s = 2 sin h cos h u, w = sqrt(2) sin h u; p = a = c
+    const float qw = pose[3], qx = pose[4], qy = pose[5], qz = pose[6];
+    const float qi = __builtin_amdgcn_rsqf(qw * qw + qx * qx + qy * qy + qz * qz);
+    const bool root = l == 0;
+    float sh, ch;
+    __sincosf(0.5f * pose[7 + (root ? 0 : T.f_tors)], &sh, &ch);
+    const float ux = root ? qx * qi : T.ax, uy = root ? qy * qi : T.ay, uz = root ? qz * qi : T.az;
+    const float k1 = root ? 2.f * qw * qi : 2.f * sh * ch;
+    const float k2 = root ? 1.41421356f : 1.41421356f * sh;
+    const float sx = k1 * ux, sy = k1 * uy, sz = k1 * uz;
+    const float wx = k2 * ux, wy = k2 * uy, wz = k2 * uz;
+    const float c0 = 1.f - (wx * wx + wy * wy + wz * wz);
+    R[0] = c0 + wx * wx; R[1] = wx * wy - sz;  R[2] = wx * wz + sy;
+    R[3] = wy * wx + sz; R[4] = c0 + wy * wy;  R[5] = wy * wz - sx;
+    R[6] = wz * wx - sy; R[7] = wz * wy + sx;  R[8] = c0 + wz * wz;
+    const float px = root ? pose[0] : T.cx, py = root ? pose[1] : T.cy, pz = root ? pose[2] : T.cz;
+    const float ax = root ? T.anc_x : T.cx, ay = root ? T.anc_y : T.cy, az = root ? T.anc_z : T.cz;
+    b[0] = px - (R[0] * ax + R[1] * ay + R[2] * az);
+    b[1] = py - (R[3] * ax + R[4] * ay + R[5] * az);
+    b[2] = pz - (R[6] * ax + R[7] * ay + R[8] * az);
+    int anc = (!root && l < T.nf) ? T.f_parent : -1;
     // pointer doubling through LDS: every round each fragment reads the
     // partial frame and ancestor link of its current ancestor
     float* fr = S.frame + 12 * l;
