@@ -440,7 +440,7 @@ pv_status pv_ligands_create(pv_ctx* ctx, int32_t n_lig, const int32_t* atom_off,
         pairs.insert(pairs.end(), M.pairs.begin(), M.pairs.end());
         ell.insert(ell.end(), M.ell.begin(), M.ell.end());
         pslot.insert(pslot.end(), M.pslot.begin(), M.pslot.end());
-        max_ell = std::max(max_ell, M.ell_w * (M.n | 1));   // slot rows have an odd stride
+        max_ell = std::max(max_ell, M.ell_w * (M.n | 1));   // slot rows of an odd number of atoms
         (*info)[i] = {M.n, M.nf, M.nt, M.np, M.root_size, M.depth, 7 + M.nt, 0, M.ell_w * (M.n | 1)};
         max_atoms = std::max(max_atoms, M.n);
         max_pairs = std::max(max_pairs, M.np);

@@ -42,10 +42,11 @@ struct alignas(16) DevFrag {
     float xc[4];         // reference position of the child-side atom
 };
 
-// Intra pair packed as i | j << 8 | type_pair << 16 (new atom order).
+// Intra pair packed as i | j << 8 | rk << 16 | class << 19 (new atom order).
 // Atom record: x, y, z and w = bits(type | fragment << 8).
 // pslot (same index as the pair list): the slot the pair occupies in the
-// row of its first atom | in the row of its second atom << 16.
+// row of its first atom | in the row of its second atom << 16 (force-slot
+// layout: slot s of atom a at s * (n | 1) + a, slots below ell_w).
 // Atom -> pair table (ELL, [ell_w][n] words): entry k of atom i is
 // p | j << 16, the k-th pair p (index into the pair list) that holds atom i
 // and its partner j; rows shorter than ell_w are padded with p = n_pairs
@@ -71,7 +72,6 @@ struct LigModel {
 int build_ligand_model(int n, const float* xyz, const uint8_t* type, int nb, const int32_t* bonds,
                        const uint8_t* rot, LigModel& out, std::string& err);
 
-// Type-pair table: Rsum = R_a + R_b, flags bit0 hydrophobic pair, bit1 hbond pair.
 
 // ------------------------------------------------------------ launchers
 struct GridDev {

@@ -255,7 +255,7 @@ struct Lds {
     uint2* pairs;      // [max_pairs] (i | j << 6 | rk << 12 | class << 15, slot index of i | of j << 16)
     float* cp;         // [max_pairs + 1] per-pair force coefficient (last = 0), global-table path
     uint32_t* ell;     // unused in LDS (the global-table path reads the table from memory)
-    float4* fs;        // [max_ell] pair forces in atom-row slots (row stride n | 1), LDS-table path
+    float4* fs;        // [max_ell] pair forces in slot rows of n | 1 atoms (slot-major), LDS-table path
     int ma;
 };
 
@@ -324,8 +324,9 @@ __device__ void stage_ligand(Topo<A, SL>& T, const LigDev& L, int lig, const Lds
     T.lig = lig;
     T.n = d.n_atoms; T.nf = d.n_frag; T.nt = d.n_tors; T.np = d.n_pairs; T.rounds = d.rounds;
     T.ell_w = d.ell_w;
-    // slot rows of an odd number of float4: lanes writing slots of one atom
-    // then fall in different LDS banks
+    // slot rows of an odd number of float4 (one per atom): the row reads of
+    // the gather are contiguous, and the slots of one atom fall in different
+    // LDS banks
     T.fs_stride = T.n | 1;
     T.anc_x = d.anchor[0]; T.anc_y = d.anchor[1]; T.anc_z = d.anchor[2]; T.rot_scale = d.rot_amp_scale;
 #pragma unroll
@@ -452,6 +453,7 @@ __device__ __forceinline__ void frames(const Topo<A, SL>& T, const Lds& S, const
 // otherwise it stores c for the table gather.  No atomics either way.
 // Returns this lane's energy; counts pairs inside the cutoff.
 constexpr int kPairUnroll = 4;
+typedef float f3v __attribute__((ext_vector_type(3)));
 constexpr float kLog2e = 1.4426950408889634f;
 
 template <int A, bool SL>
@@ -536,9 +538,11 @@ __device__ __forceinline__ float pair_loop(const Topo<A, SL>& T, const Lds& S, i
             const float c = in[u] ? de[u] * rinv[u] : 0.f;
             if (v[u]) {
                 if (SL) {
+                    // 12-byte writes (ds_write_b96) into the 16-byte slots; the
+                    // gather reads x, y, z
                     const float fx = c * dx[u], fy = c * dy[u], fz = c * dz[u];
-                    S.fs[sl[u] & 0xffff] = make_float4(fx, fy, fz, 0.f);
-                    S.fs[sl[u] >> 16] = make_float4(-fx, -fy, -fz, 0.f);
+                    *(f3v*)(S.fs + (sl[u] & 0xffff)) = f3v{fx, fy, fz};
+                    *(f3v*)(S.fs + (sl[u] >> 16)) = f3v{-fx, -fy, -fz};
                 } else {
                     S.cp[p0 + u * kWave] = c;
                 }

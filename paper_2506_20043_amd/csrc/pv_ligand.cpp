@@ -237,10 +237,8 @@ int build_ligand_model(int n, const float* xyz, const uint8_t* type, int nb, con
     }
     // atom -> pair rows (partners in ascending pair order), padded to the longest
     std::vector<std::vector<uint32_t>> rows(n);
-    M.pslot.assign(P, 0u);
     for (int q = 0; q < P; ++q) {
         const uint32_t i = M.pairs[q] & 0xff, j = (M.pairs[q] >> 8) & 0xff;
-        M.pslot[q] = (uint32_t)rows[i].size() | ((uint32_t)rows[j].size() << 16);
         rows[i].push_back((uint32_t)q | (j << 16));
         rows[j].push_back((uint32_t)q | (i << 16));
     }
@@ -248,6 +246,36 @@ int build_ligand_model(int n, const float* xyz, const uint8_t* type, int nb, con
     for (int i = 0; i < n; ++i) w = std::max(w, (int)rows[i].size());
     w = (w + 3) / 4 * 4;   // the kernels read rows four entries at a time
     M.ell_w = w;
+    // Slots of the force-slot layout: each pair takes one free slot below w
+    // for each of its atoms (any one: an atom sums all its slots).  In LDS
+    // slot s of atom a sits at s * (n | 1) + a (float4), and the forces of 16
+    // consecutive pairs (an aligned group) are written in one LDS pass per
+    // side, so the slots are picked to give each side of a group distinct
+    // (s * (n | 1) + a) mod 16: distinct bank groups.
+    M.pslot.assign(P, 0u);
+    {
+        const int stride = n | 1;
+        std::vector<uint8_t> used((size_t)n * (w > 0 ? w : 1), 0);
+        for (int g0 = 0; g0 < P; g0 += 16) {
+            const int g1 = std::min(P, g0 + 16);
+            for (int side = 0; side < 2; ++side) {
+                uint32_t taken = 0;   // bank groups used by this side of the group
+                for (int q = g0; q < g1; ++q) {
+                    const int a = side == 0 ? (int)(M.pairs[q] & 0xff) : (int)((M.pairs[q] >> 8) & 0xff);
+                    int pick = -1, any = -1;
+                    for (int sl = 0; sl < w; ++sl) {
+                        if (used[(size_t)a * w + sl]) continue;
+                        if (any < 0) any = sl;
+                        if (!((taken >> ((sl * stride + a) & 15)) & 1u)) { pick = sl; break; }
+                    }
+                    if (pick < 0) pick = any;   // a row always has a free slot: w >= its length
+                    used[(size_t)a * w + pick] = 1;
+                    taken |= 1u << ((pick * stride + a) & 15);
+                    M.pslot[q] |= (uint32_t)pick << (16 * side);
+                }
+            }
+        }
+    }
     M.ell.assign((size_t)w * n, 0u);
     for (int i = 0; i < n; ++i)
         for (int k = 0; k < w; ++k)
