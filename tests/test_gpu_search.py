@@ -209,3 +209,30 @@ def test_dock_rejects(pv_ctx, c1):
         pv.Plan(pv_ctx, c1["grids"], c1["ligs"], [(0, 0)], _params(pv, chains=0))
     with pytest.raises(pv.PvError, match="ls_rho"):
         pv.Plan(pv_ctx, c1["grids"], c1["ligs"], [(0, 0)], _params(pv, ls_rho=0.5, ls_sigma=0.1))
+
+
+def test_dock_edge_cases(oracle, pv_ctx, c1):
+    """No jobs; one chain of zero steps (the initial pose); a persistent
+    launch of only 3 workgroups pulling 96 items reproduces the default
+    launch chain by chain; the output stage refuses more than 4,096 chains."""
+    import paper_2506_20043_amd as pv
+    empty = pv.Plan(pv_ctx, c1["grids"], c1["ligs"], [], _params(pv, flags=pv.PV_DOCK_GRAPH))
+    empty.run()
+    empty.run(plain=True)
+    empty.close()
+    one = pv.dock(pv_ctx, c1["grids"], c1["ligs"], [(0, 0)], _params(pv, chains=1, steps=0, seed=5))
+    L, G = c1["ol"], c1["og"]
+    ref = L.score_grad(G, oracle.init_pose(L, G, 5, 0, 0))["e"]
+    assert abs(one["chain_best_e"].item() - ref) <= e_tol(ref) + 0.01
+    assert one["chain_evals"].item() == 1
+    jobs = [(0, 0)] * 6
+    base = pv.dock(pv_ctx, c1["grids"], c1["ligs"], jobs, _params(pv, chains=16, steps=15, seed=9))
+    few = pv.dock(pv_ctx, c1["grids"], c1["ligs"], jobs, _params(pv, chains=16, steps=15, seed=9, workgroups=3))
+    for k in ("chain_best_e", "chain_evals", "chain_best_dof"):
+        assert np.array_equal(base[k].cpu().numpy(), few[k].cpu().numpy()), k
+    big = pv.Plan(pv_ctx, c1["grids"], c1["ligs"], [(0, 0)], _params(pv, chains=4097, steps=0))
+    e = np.zeros(4097, np.float32)
+    d = np.zeros((4097, c1["ligs"].dof_stride), np.float32)
+    with pytest.raises(pv.PvError, match="4096"):
+        pv.output_stage(big, e, d)
+    big.close()
