@@ -68,6 +68,14 @@ __device__ __forceinline__ float wsum_n(float v, int n)
     return (lane_f(v, 0) + lane_f(v, 16)) + (lane_f(v, 32) + lane_f(v, 48));
 }
 
+// integer sum over the 64 lanes, identical in every lane
+__device__ __forceinline__ int64_t wsum_i64(int64_t v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
 // inclusive prefix sum over the 64 lanes in lane order
 __device__ __forceinline__ float wscan(float v)
 {
@@ -247,19 +255,42 @@ constexpr int kSlot = 40;
 enum { SLOT_X = 0, SLOT_XT = 1, SLOT_XA = 2, SLOT_CUR = 3, SLOT_BEST = 4, kNSlots = 5 };
 
 struct Lds {
+    char* base;        // start of the workgroup's dynamic LDS
     float* pose;       // [kNSlots][kSlot]
     float* frame;      // [kMaxFrag][12] frames, then [kMaxFrag] ancestor links
-    float4* pos;       // [max_atoms]
+    float4* pos;       // [ma + 1]; entry ma is a point far outside every box
     float4* frc;       // [max_atoms]
     float* pre;        // [6][max_atoms]
-    uint2* pairs;      // [max_pairs] (i | j << 6 | rk << 12 | class << 15, slot index of i | of j << 16)
+    uint4* pairs;      // [max_pairs rounded up to kPairPass] pair records, LDS-table path (see stage_ligand)
     float* cp;         // [max_pairs + 1] per-pair force coefficient (last = 0), global-table path
     uint32_t* ell;     // unused in LDS (the global-table path reads the table from memory)
-    float4* fs;        // [max_ell] pair forces in slot rows of n | 1 atoms (slot-major), LDS-table path
+    float4* fs;        // [max_ell + 1] pair forces in slot rows of n | 1 atoms (slot-major), then one
+                       // write-only slot for the padding records, LDS-table path
     int ma;
 };
 
+// LDS byte address of a pointer into LDS, and back.
+typedef __attribute__((address_space(3))) char lds_char;
+__device__ __forceinline__ uint32_t lds_addr(const void* p)
+{
+    return (uint32_t)(uintptr_t)(const lds_char*)p;
+}
+template <typename V>
+__device__ __forceinline__ __attribute__((address_space(3))) V* lds_ptr(uint32_t a)
+{
+    return (__attribute__((address_space(3))) V*)(uintptr_t)a;
+}
+
+// Pairs per pass of the pair loop (lanes x pairs per lane); the LDS pair
+// records are padded to a multiple of it.
+constexpr int kPairUnroll = 4;
+constexpr int kPairPass = kPairUnroll * kWave;
+
 __host__ __device__ inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+// Atom entries of the per-wave atom arrays (a multiple of 4 keeps every
+// region 16-byte aligned).
+__host__ __device__ inline int lds_atoms(int max_atoms) { return round_up(max_atoms < 1 ? 1 : max_atoms, 4); }
 
 // Two layouts of the intra-force tables.  Slots (ligands of at most 64
 // atoms, one atom per lane): the pair list sits in LDS, packed with the slots
@@ -270,9 +301,9 @@ __host__ __device__ inline int round_up(int v, int m) { return (v + m - 1) / m *
 // ligands or launches that need many resident waves).
 __host__ __device__ inline int lds_bytes(int max_atoms, int max_pairs, int max_ell, bool slots)
 {
-    int ma = round_up(max_atoms < 1 ? 1 : max_atoms, 64);
-    int b = kNSlots * kSlot * 4 + kMaxFrag * 13 * 4 + 12 + ma * 16 * 2 + 6 * ma * 4;
-    if (slots) b += round_up(max_pairs, 2) * 8 + max_ell * 16;
+    int ma = lds_atoms(max_atoms);
+    int b = kNSlots * kSlot * 4 + kMaxFrag * 13 * 4 + 12 + (ma + 1) * 16 + ma * 16 + 6 * ma * 4;
+    if (slots) b += round_up(max_pairs < 1 ? 1 : max_pairs, kPairPass) * 16 + (max_ell + 1) * 16;
     else b += round_up(max_pairs + 1, 4) * 4;
     return b;
 }
@@ -280,16 +311,17 @@ __host__ __device__ inline int lds_bytes(int max_atoms, int max_pairs, int max_e
 __device__ __forceinline__ Lds carve(char* base, int max_atoms, int max_pairs, int max_ell, bool slots)
 {
     Lds s;
-    int ma = round_up(max_atoms < 1 ? 1 : max_atoms, 64);
+    int ma = lds_atoms(max_atoms);
     char* p = base;
-    s.pos = (float4*)p; p += ma * 16;
+    s.base = base;
+    s.pos = (float4*)p; p += (ma + 1) * 16;
     s.frc = (float4*)p; p += ma * 16;
     s.pose = (float*)p; p += kNSlots * kSlot * 4;
     s.frame = (float*)p; p += kMaxFrag * 13 * 4 + 12;
     s.pre = (float*)p; p += 6 * ma * 4;
     s.ell = nullptr;
     if (slots) {
-        s.pairs = (uint2*)p; p += round_up(max_pairs, 2) * 8;
+        s.pairs = (uint4*)p; p += round_up(max_pairs < 1 ? 1 : max_pairs, kPairPass) * 16;
         s.fs = (float4*)p;
         s.cp = nullptr;
     } else {
@@ -346,18 +378,38 @@ __device__ void stage_ligand(Topo<A, SL>& T, const LigDev& L, int lig, const Lds
     T.dof_frag = (l >= 6 && l < 6 + T.nt) ? (int)L.tors_frag[d.tors_base + l - 6] : 0;
     T.gpairs = L.pairs + d.pair_base;
     T.gell = L.ell + d.ell_base;
+    if (l == 0) S.pos[S.ma] = make_float4(1e18f, 1e18f, 1e18f, 0.f);
     if (SL) {
-        // pair record: i | j << 6 | radius-sum code << 12 | class << 15, and
-        // the slot indices (slot * row stride + atom) of the pair's forces
+        // Pair record, everything the pair loop needs without decoding:
+        //   x: LDS byte addresses of both positions (i | j << 16; S.pos opens
+        //      the LDS, so both fit) | class << 30
+        //   y, z: LDS byte addresses of the pair's force slots in the rows of
+        //         i and of j (slot * row stride + atom)
+        //   w: the radius sum 3.4 + 0.1 rk (bits)
+        // Records past the last pair fill the final pass: their first atom is
+        // the far point, so they fall outside the cutoff, and both their
+        // slots are the write-only one past the rows.
         const uint32_t* ps = L.pslot + d.pair_base;
         const uint32_t ns = (uint32_t)T.fs_stride;
-        for (int p = l; p < T.np; p += kWave) {
-            const uint32_t pk = T.gpairs[p], sl = ps[p];
-            const uint32_t i = pk & 0xff, j = (pk >> 8) & 0xff;
-            S.pairs[p] = make_uint2(i | (j << 6) | (((pk >> 16) & 0x1f) << 12),
-                                    ((sl & 0xffff) * ns + i) | (((sl >> 16) * ns + j) << 16));
-        }
         const int nfs = T.ell_w * T.fs_stride;
+        const uint32_t fs0 = lds_addr(S.fs), pos0 = lds_addr(S.pos);
+        const int npad = round_up(T.np < 1 ? 1 : T.np, kPairPass);
+        for (int p = l; p < npad; p += kWave) {
+            uint4 r;
+            if (p < T.np) {
+                const uint32_t pk = T.gpairs[p], sl = ps[p];
+                const uint32_t i = pk & 0xff, j = (pk >> 8) & 0xff;
+                r.x = (pos0 + (i << 4)) | (pos0 + (j << 4)) << 16 | ((pk >> 19) << 30);
+                r.y = fs0 + (((sl & 0xffff) * ns + i) << 4);
+                r.z = fs0 + (((sl >> 16) * ns + j) << 4);
+                r.w = __float_as_uint(fmaf((float)((pk >> 16) & 7u), 0.1f, 3.4f));
+            } else {
+                r.x = pos0 + ((uint32_t)S.ma << 4);
+                r.y = r.z = fs0 + ((uint32_t)nfs << 4);
+                r.w = __float_as_uint(3.4f);
+            }
+            S.pairs[p] = r;
+        }
         for (int k = l; k < nfs; k += kWave) S.fs[k] = make_float4(0.f, 0.f, 0.f, 0.f);   // padding stays zero
     } else {
         if (l == 0) S.cp[T.np] = 0.f;
@@ -369,7 +421,7 @@ __device__ void stage_ligand(Topo<A, SL>& T, const LigDev& L, int lig, const Lds
 struct Eval {
     float e, e_inter, e_intra;
     float g;          // this lane's tangent component (lane < 6 + T)
-    int pairs_in;
+    int pairs_in;     // this lane's intra pairs inside the cutoff
 };
 
 // Frame of every fragment: x = R X + b on reference coordinates.  Lane f
@@ -442,17 +494,17 @@ __device__ __forceinline__ void frames(const Topo<A, SL>& T, const Lds& S, const
 }
 
 // Intra pairs, lanes over pairs, kPairUnroll pairs per lane and pass: every
-// load of a pass (pair records, then both positions and the type-pair entry)
-// is issued before any of its arithmetic, so the LDS latency is paid once
-// per pass.  Per pair, with d the surface distance and inside 8 A: the
-// gauss, repulsion, hydrophobic and hydrogen-bond terms of the Vina form and
-// the force coefficient c = (dphi/dr) / r.  Pairs are grouped by interaction
-// class, so a whole 64-pair chunk usually has no hydrophobic or hydrogen-bond
-// weight and skips those terms on a wave-uniform branch.  With the tables in
-// LDS each pair writes +f / -f into its slots of the two atoms' rows;
-// otherwise it stores c for the table gather.  No atomics either way.
-// Returns this lane's energy; counts pairs inside the cutoff.
-constexpr int kPairUnroll = 4;
+// load of a pass (pair records, then both positions) is issued before any of
+// its arithmetic, so the LDS latency is paid once per pass.  Per pair, with d
+// the surface distance and inside 8 A: the gauss, repulsion, hydrophobic and
+// hydrogen-bond terms of the Vina form and the force coefficient
+// c = (dphi/dr) / r.  Pairs are grouped by interaction class, so a whole
+// 64-pair chunk usually has no hydrophobic or hydrogen-bond weight and skips
+// those terms on a wave-uniform branch.  With the tables in LDS each pair
+// writes +f / -f into its slots of the two atoms' rows (the padded records
+// make every pass full, with no per-lane guard); otherwise it stores c for
+// the table gather.  No atomics either way.  Returns this lane's energy; adds
+// this lane's pairs inside the cutoff to cnt.
 typedef float f3v __attribute__((ext_vector_type(3)));
 constexpr float kLog2e = 1.4426950408889634f;
 
@@ -462,36 +514,33 @@ __device__ __forceinline__ float pair_loop(const Topo<A, SL>& T, const Lds& S, i
     constexpr int U = kPairUnroll;
     const int l = lane_id();
     const int np = T.np;
+    const uint32_t pos0 = lds_addr(S.pos);
     float e = 0.f;
-    for (int p0 = l; p0 - l < np; p0 += U * kWave) {
-        uint32_t pk[U], sl[U];
+    for (int p0 = l; p0 - l < np; p0 += kPairPass) {
+        uint32_t pk[U], ya[U], za[U];
+        float rs[U];
         bool v[U];
+        float4 xi[U], xj[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int p = p0 + u * kWave;
-            v[u] = p < np;
-            // a lane past the end reads pair 0 (np >= 1 here) and discards it
             if (SL) {
-                const uint2 w = S.pairs[v[u] ? p : 0];
-                pk[u] = w.x;
-                sl[u] = w.y;
+                const uint4 w = S.pairs[p];
+                pk[u] = w.x; ya[u] = w.y; za[u] = w.z; rs[u] = __uint_as_float(w.w);
+                v[u] = true;
             } else {
-                pk[u] = T.gpairs[v[u] ? p : 0];
-                sl[u] = 0u;
+                // a lane past the end reads pair 0 (np >= 1 here) and discards it
+                v[u] = p < np;
+                const uint32_t g = T.gpairs[v[u] ? p : 0];
+                pk[u] = (pos0 + ((g & 0xffu) << 4)) | (pos0 + (((g >> 8) & 0xffu) << 4)) << 16 | (g >> 19) << 30;
+                rs[u] = fmaf((float)((g >> 16) & 7u), 0.1f, 3.4f);
+                ya[u] = za[u] = 0u;
             }
         }
-        float4 xi[U], xj[U];
-        uint32_t code[U];   // radius-sum code | class << 3
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            int i, j;
-            if (SL) {
-                i = pk[u] & 0x3f; j = (pk[u] >> 6) & 0x3f; code[u] = pk[u] >> 12;
-            } else {
-                i = pk[u] & 0xff; j = (pk[u] >> 8) & 0xff; code[u] = pk[u] >> 16;
-            }
-            xi[u] = S.pos[i];
-            xj[u] = S.pos[j];
+            xi[u] = *(const float4*)lds_ptr<const float4>(pk[u] & 0xffffu);
+            xj[u] = *(const float4*)lds_ptr<const float4>((pk[u] >> 16) & 0x3fffu);
         }
         float dx[U], dy[U], dz[U], d[U], en[U], de[U], rinv[U];
         bool in[U];
@@ -505,8 +554,7 @@ __device__ __forceinline__ float pair_loop(const Topo<A, SL>& T, const Lds& S, i
             // zeroes the force
             const float r2c = fmaxf(r2, 1e-12f);
             rinv[u] = __builtin_amdgcn_rsqf(r2c);
-            const float rsum = fmaf((float)(code[u] & 7u), 0.1f, 3.4f);
-            const float dd = r2c * rinv[u] - rsum;
+            const float dd = r2c * rinv[u] - rs[u];
             d[u] = dd;
             const float g1 = __builtin_amdgcn_exp2f(dd * dd * (-4.f * kLog2e));          // exp(-(d/0.5)^2)
             const float dm3 = dd - 3.f;
@@ -519,8 +567,8 @@ __device__ __forceinline__ float pair_loop(const Topo<A, SL>& T, const Lds& S, i
         for (int u = 0; u < U; ++u) {
             // class 1 (both hydrophobic) adds the hydrophobic term, class 2
             // (donor with acceptor) the hydrogen-bond term
-            const uint32_t cls = code[u] >> 3;
-            if (__ballot(cls != 0u)) {
+            if (__ballot(pk[u] >= (1u << 30))) {
+                const uint32_t cls = pk[u] >> 30;
                 const float wy = cls == 1u ? kW4 : 0.f, wz = cls == 2u ? kW5 : 0.f;
                 const float dd = d[u];
                 const float hv = fminf(fmaxf(1.5f - dd, 0.f), 1.f);            // 1 below 0.5, 0 above 1.5
@@ -534,18 +582,16 @@ __device__ __forceinline__ float pair_loop(const Topo<A, SL>& T, const Lds& S, i
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             e += in[u] ? en[u] : 0.f;
-            cnt += __popcll(__ballot(in[u]));
+            cnt += in[u] ? 1 : 0;
             const float c = in[u] ? de[u] * rinv[u] : 0.f;
-            if (v[u]) {
-                if (SL) {
-                    // 12-byte writes (ds_write_b96) into the 16-byte slots; the
-                    // gather reads x, y, z
-                    const float fx = c * dx[u], fy = c * dy[u], fz = c * dz[u];
-                    *(f3v*)(S.fs + (sl[u] & 0xffff)) = f3v{fx, fy, fz};
-                    *(f3v*)(S.fs + (sl[u] >> 16)) = f3v{-fx, -fy, -fz};
-                } else {
-                    S.cp[p0 + u * kWave] = c;
-                }
+            if (SL) {
+                // 12-byte writes (ds_write_b96) into the 16-byte slots; the
+                // gather reads x, y, z
+                const float fx = c * dx[u], fy = c * dy[u], fz = c * dz[u];
+                *(f3v*)lds_ptr<f3v>(ya[u]) = f3v{fx, fy, fz};
+                *(f3v*)lds_ptr<f3v>(za[u]) = f3v{-fx, -fy, -fz};
+            } else if (v[u]) {
+                S.cp[p0 + u * kWave] = c;
             }
         }
     }
@@ -786,7 +832,7 @@ struct BfgsOut {
     float f;
     float g;          // this lane's tangent gradient component at the result
     int evals;
-    int64_t pairs;
+    int64_t pairs;    // this lane's share of the intra pairs inside the cutoff
     bool skipped;     // the consistency check ended the run after its first evaluation
 };
 
@@ -955,7 +1001,7 @@ __device__ BfgsOut bfgs(const Topo<A, SL>& T, const BoxView& B, const Lds& S, co
 // ---------------------------------------------------------------- Monte Carlo
 struct ChainOut {
     float best_e;
-    int64_t evals, pairs;
+    int64_t evals, pairs;   // pairs: this lane's share
 };
 
 template <int A, bool SL>
@@ -1120,13 +1166,14 @@ __global__ __launch_bounds__(64) void dock_kernel(DockArgs a)
         uint64_t t0 = 0;
         if (a.sp.flags & 1u) t0 = wall_clock64();
         ChainOut co = mc_chain(T, B, S, a.sp, job, chain);
+        const int64_t pairs = wsum_i64(co.pairs);
         const int64_t ci = (int64_t)job * chains + chain;
         if (a.chain_best_dof && l < a.dof_stride)
             a.chain_best_dof[ci * a.dof_stride + l] = l < 7 + T.nt ? S.pose[SLOT_BEST * kSlot + l] : 0.f;
         if (l == 0) {
             if (a.chain_best_e) a.chain_best_e[ci] = co.best_e;
             if (a.chain_evals) a.chain_evals[ci] = co.evals;
-            if (a.chain_pairs) a.chain_pairs[ci] = co.pairs;
+            if (a.chain_pairs) a.chain_pairs[ci] = pairs;
             if (a.sp.flags & 1u) {
                 const uint64_t t1 = wall_clock64();
                 atomicMin((unsigned long long*)&a.job_t_start[job], (unsigned long long)t0);
@@ -1811,7 +1858,7 @@ hipError_t launch_output(const OutputArgs& a, hipStream_t s)
 
 int output_lds_bytes(const LigDev& l, int chains, int modes)
 {
-    const int ma = round_up(l.max_atoms < 1 ? 1 : l.max_atoms, 64);
+    const int ma = lds_atoms(l.max_atoms);
     return lds_bytes(l.max_atoms, l.max_pairs, l.max_ell, false) + round_up(chains, 4) * 4 + modes * ma * 16 +
            modes * kSlot * 4 + 5 * round_up(modes, 4) * 4;
 }
