@@ -258,7 +258,7 @@ struct Lds {
     char* base;        // start of the workgroup's dynamic LDS
     float* pose;       // [kNSlots][kSlot]
     float* frame;      // [kMaxFrag][12] frames, then [kMaxFrag] ancestor links
-    float4* pos;       // [ma + 1]; entry ma is a point far outside every box
+    float4* pos;       // [ma + 1]; entry ma: a point far outside every box (LDS-table path)
     float4* frc;       // [max_atoms]
     float* pre;        // [6][max_atoms]
     uint4* pairs;      // [max_pairs rounded up to kPairPass] pair records, LDS-table path (see stage_ligand)
@@ -378,8 +378,8 @@ __device__ void stage_ligand(Topo<A, SL>& T, const LigDev& L, int lig, const Lds
     T.dof_frag = (l >= 6 && l < 6 + T.nt) ? (int)L.tors_frag[d.tors_base + l - 6] : 0;
     T.gpairs = L.pairs + d.pair_base;
     T.gell = L.ell + d.ell_base;
-    if (l == 0) S.pos[S.ma] = make_float4(1e18f, 1e18f, 1e18f, 0.f);
     if (SL) {
+        if (l == 0) S.pos[S.ma] = make_float4(1e18f, 1e18f, 1e18f, 0.f);
         // Pair record, everything the pair loop needs without decoding:
         //   x: LDS byte addresses of both positions (i | j << 16; S.pos opens
         //      the LDS, so both fit) | class << 30
@@ -517,8 +517,9 @@ __device__ __forceinline__ float pair_loop(const Topo<A, SL>& T, const Lds& S, i
     const uint32_t pos0 = lds_addr(S.pos);
     float e = 0.f;
     for (int p0 = l; p0 - l < np; p0 += kPairPass) {
-        uint32_t pk[U], ya[U], za[U];
-        float rs[U];
+        // position addresses; slot addresses; radius sum bits (slots) or
+        // radius-sum code | class << 3 (gather)
+        uint32_t ai[U], aj[U], ya[U], za[U], rc[U];
         bool v[U];
         float4 xi[U], xj[U];
 #pragma unroll
@@ -526,21 +527,22 @@ __device__ __forceinline__ float pair_loop(const Topo<A, SL>& T, const Lds& S, i
             const int p = p0 + u * kWave;
             if (SL) {
                 const uint4 w = S.pairs[p];
-                pk[u] = w.x; ya[u] = w.y; za[u] = w.z; rs[u] = __uint_as_float(w.w);
+                ai[u] = w.x & 0xffffu; aj[u] = w.x >> 16;   // the class sits above bit 29: kept for the test
+                ya[u] = w.y; za[u] = w.z; rc[u] = w.w;
                 v[u] = true;
             } else {
                 // a lane past the end reads pair 0 (np >= 1 here) and discards it
                 v[u] = p < np;
                 const uint32_t g = T.gpairs[v[u] ? p : 0];
-                pk[u] = (pos0 + ((g & 0xffu) << 4)) | (pos0 + (((g >> 8) & 0xffu) << 4)) << 16 | (g >> 19) << 30;
-                rs[u] = fmaf((float)((g >> 16) & 7u), 0.1f, 3.4f);
+                ai[u] = pos0 + ((g & 0xffu) << 4); aj[u] = pos0 + (((g >> 8) & 0xffu) << 4);
+                rc[u] = g >> 16;
                 ya[u] = za[u] = 0u;
             }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            xi[u] = *(const float4*)lds_ptr<const float4>(pk[u] & 0xffffu);
-            xj[u] = *(const float4*)lds_ptr<const float4>((pk[u] >> 16) & 0x3fffu);
+            xi[u] = *(const float4*)lds_ptr<const float4>(ai[u]);
+            xj[u] = *(const float4*)lds_ptr<const float4>(aj[u] & 0x3fffu);
         }
         float dx[U], dy[U], dz[U], d[U], en[U], de[U], rinv[U];
         bool in[U];
@@ -554,7 +556,8 @@ __device__ __forceinline__ float pair_loop(const Topo<A, SL>& T, const Lds& S, i
             // zeroes the force
             const float r2c = fmaxf(r2, 1e-12f);
             rinv[u] = __builtin_amdgcn_rsqf(r2c);
-            const float dd = r2c * rinv[u] - rs[u];
+            const float rs = SL ? __uint_as_float(rc[u]) : fmaf((float)(rc[u] & 7u), 0.1f, 3.4f);
+            const float dd = r2c * rinv[u] - rs;
             d[u] = dd;
             const float g1 = __builtin_amdgcn_exp2f(dd * dd * (-4.f * kLog2e));          // exp(-(d/0.5)^2)
             const float dm3 = dd - 3.f;
@@ -567,8 +570,8 @@ __device__ __forceinline__ float pair_loop(const Topo<A, SL>& T, const Lds& S, i
         for (int u = 0; u < U; ++u) {
             // class 1 (both hydrophobic) adds the hydrophobic term, class 2
             // (donor with acceptor) the hydrogen-bond term
-            if (__ballot(pk[u] >= (1u << 30))) {
-                const uint32_t cls = pk[u] >> 30;
+            const uint32_t cls = SL ? aj[u] >> 14 : rc[u] >> 3;
+            if (__ballot(cls != 0u)) {
                 const float wy = cls == 1u ? kW4 : 0.f, wz = cls == 2u ? kW5 : 0.f;
                 const float dd = d[u];
                 const float hv = fminf(fmaxf(1.5f - dd, 0.f), 1.f);            // 1 below 0.5, 0 above 1.5
