@@ -161,3 +161,43 @@ def test_mixed_size_jobs(oracle, pv_ctx, big):
             same += int(ne == ev[j, c] and abs(cbe[j, c] - e_ref) <= e_tol(e_ref))
             total += 1
     assert same >= total - 3, (same, total)
+
+
+def _seeded_ligand(seed):
+    """A tree ligand drawn the way the boundary search drew it: with seeds
+    37, 241, 705 and 452 it has 256, 255, 257 and 512 intra pairs."""
+    g = np.random.default_rng(seed)
+    n = int(g.integers(24, 46))
+    nt = int(g.integers(3, 12))
+    return S.tree_ligand(g, n, nt)
+
+
+def test_slot_records_at_pass_boundaries(oracle, pv_ctx):
+    """The slot layout pads its pair records to whole passes of 256: ligands
+    with 0, 255, 256, 257 and 512 intra pairs and one of 64 atoms (the far
+    point right after the last atom) score like the oracle in the slot
+    variant, and like the gather variant of a large launch."""
+    import paper_2506_20043_amd as pv
+    cfg = S.CONFIGS["c2"]
+    rx, rt, bxs = S.make_receptor(cfg)
+    g = np.random.default_rng(31)
+    mols = [S.tree_ligand(g, 12, 0)] + [_seeded_ligand(s) for s in (241, 37, 705, 452)]
+    mols.append(S.tree_ligand(np.random.default_rng(1000), 64, 10))
+    st = Setup(oracle, pv_ctx, rx, rt, bxs[:1], mols)
+    counts = [st.ol[k].n_pairs for k in range(len(mols))]
+    assert counts[:5] == [0, 255, 256, 257, 512] and st.ol[5].n_atoms == 64, counts
+    per = 24
+    lig = np.repeat(np.arange(len(mols), dtype=np.int32), per)
+    B = len(lig)
+    box = np.zeros(B, np.int32)
+    dof = _poses(st, g, lig, B)
+    assert pv.launch_info(pv_ctx, st.ligs, pv.KIND_SCORE, B)[0] == pv.VARIANT_SLOTS
+    out = pv.score_grad(pv_ctx, st.grids, st.ligs, lig, box, dof, parts=True)
+    compare(st, lig, box, dof, out, range(B))
+    # the same poses at the head of a launch large enough for the gather
+    reps = 8192 // B + 1
+    big_lig, big_box, big_dof = np.tile(lig, reps), np.tile(box, reps), np.tile(dof, (reps, 1))
+    assert pv.launch_info(pv_ctx, st.ligs, pv.KIND_SCORE, len(big_lig))[0] != pv.VARIANT_SLOTS
+    big = pv.score_grad(pv_ctx, st.grids, st.ligs, big_lig, big_box, big_dof)
+    es, eb = out["energy"].cpu().numpy(), big["energy"].cpu().numpy()[:B]
+    assert np.all(np.abs(es - eb) <= e_tol(es))
