@@ -457,24 +457,20 @@ __device__ __forceinline__ void frames(const Topo<A, SL>& T, const Lds& S, const
     b[1] = py - (R[3] * ax + R[4] * ay + R[5] * az);
     b[2] = pz - (R[6] * ax + R[7] * ay + R[8] * az);
     int anc = (!root && l < T.nf) ? T.f_parent : -1;
-    // pointer doubling through LDS: every round each fragment reads the
-    // partial frame and ancestor link of its current ancestor
-    float* fr = S.frame + 12 * l;
-    int* lk = (int*)(S.frame + 12 * kMaxFrag);
+    // pointer doubling across lanes: every round each fragment fetches the
+    // partial frame and ancestor link of its current ancestor straight from
+    // that lane's registers (ds_bpermute, all lanes taking part), then
+    // composes; a lane without an ancestor fetches its own values and keeps
+    // its frame
     for (int r = 0; r < T.rounds; ++r) {
-        if (l < T.nf) {
+        const int src = (anc >= 0 ? anc : l) << 2;
+        float P[9], pb[3];
 #pragma unroll
-            for (int k = 0; k < 9; ++k) fr[k] = R[k];
-            fr[9] = b[0]; fr[10] = b[1]; fr[11] = b[2];
-            lk[l] = anc;
-        }
-        wave_sync();
+        for (int k = 0; k < 9; ++k) P[k] = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(R[k])));
+#pragma unroll
+        for (int k = 0; k < 3; ++k) pb[k] = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(b[k])));
+        const int panc = __builtin_amdgcn_ds_bpermute(src, anc);
         if (anc >= 0) {
-            const float4* pf = (const float4*)(S.frame + 12 * anc);
-            const float4 q0 = pf[0], q1 = pf[1], q2 = pf[2];
-            const float P[9] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, q2.x};
-            const float pb[3] = {q2.y, q2.z, q2.w};
-            const int panc = lk[anc];
             float N[9], nb[3];
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
@@ -489,7 +485,6 @@ __device__ __forceinline__ void frames(const Topo<A, SL>& T, const Lds& S, const
             for (int k = 0; k < 3; ++k) b[k] = nb[k];
             anc = panc;
         }
-        wave_sync();
     }
 }
 
