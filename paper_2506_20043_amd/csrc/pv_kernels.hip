@@ -665,27 +665,50 @@ __device__ Eval evaluate(const Topo<A, SL>& T, const BoxView& B, const Lds& S, c
     Eval out;
     float R[9], b[3];
     frames(T, S, pose, R, b);
-    if (l < T.nf) {
-        float* fr = S.frame + 12 * l;
+    if (A > 1) {
+        if (l < T.nf) {
+            float* fr = S.frame + 12 * l;
 #pragma unroll
-        for (int k = 0; k < 9; ++k) fr[k] = R[k];
-        fr[9] = b[0]; fr[10] = b[1]; fr[11] = b[2];
+            for (int k = 0; k < 9; ++k) fr[k] = R[k];
+            fr[9] = b[0]; fr[10] = b[1]; fr[11] = b[2];
+        }
+        wave_sync();
     }
-    wave_sync();
     float e_in = 0.f;
     float4 X4[A];
     float G[A][3];
     TriLoad TL[A];
+    if (A == 1) {
+        // one atom per lane: its fragment's frame straight from that lane
+        const int src = (int)(__float_as_uint(T.ref[0].w) >> 8) << 2;
+        float P[9], pb[3];
 #pragma unroll
-    for (int a = 0; a < A; ++a) {
-        const int i = l * A + a;
-        X4[a] = make_float4(0.f, 0.f, 0.f, 0.f);
-        G[a][0] = G[a][1] = G[a][2] = 0.f;
-        if (i < T.n) {
-            const int ty = __float_as_uint(T.ref[a].w) & 0xff;
-            X4[a] = atom_position(T.ref[a], S);
-            S.pos[i] = X4[a];
-            tri_issue(B, ty, X4[a].x, X4[a].y, X4[a].z, TL[a]);
+        for (int k = 0; k < 9; ++k) P[k] = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(R[k])));
+#pragma unroll
+        for (int k = 0; k < 3; ++k) pb[k] = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(b[k])));
+        const float4 rf = T.ref[0];
+        X4[0] = make_float4(P[0] * rf.x + P[1] * rf.y + P[2] * rf.z + pb[0],
+                            P[3] * rf.x + P[4] * rf.y + P[5] * rf.z + pb[1],
+                            P[6] * rf.x + P[7] * rf.y + P[8] * rf.z + pb[2], 0.f);
+        G[0][0] = G[0][1] = G[0][2] = 0.f;
+        if (l < T.n) {
+            S.pos[l] = X4[0];
+            tri_issue(B, __float_as_uint(rf.w) & 0xff, X4[0].x, X4[0].y, X4[0].z, TL[0]);
+        } else {
+            X4[0] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    } else {
+#pragma unroll
+        for (int a = 0; a < A; ++a) {
+            const int i = l * A + a;
+            X4[a] = make_float4(0.f, 0.f, 0.f, 0.f);
+            G[a][0] = G[a][1] = G[a][2] = 0.f;
+            if (i < T.n) {
+                const int ty = __float_as_uint(T.ref[a].w) & 0xff;
+                X4[a] = atom_position(T.ref[a], S);
+                S.pos[i] = X4[a];
+                tri_issue(B, ty, X4[a].x, X4[a].y, X4[a].z, TL[a]);
+            }
         }
     }
     wave_sync();
