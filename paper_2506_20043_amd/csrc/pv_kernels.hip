@@ -741,13 +741,19 @@ __device__ Eval evaluate(const Topo<A, SL>& T, const BoxView& B, const Lds& S, c
     float incl[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) incl[c] = wscan(run[c]);
+    // atom i's prefix: lane i's inclusive scan (one atom per lane), else the
+    // lane's exclusive scan plus its running sum up to the atom
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
-        const float excl = incl[c] - run[c];
+        if (A == 1) {
+            if (l < T.n) S.pre[c * S.ma + l] = incl[c];
+        } else {
+            const float excl = incl[c] - run[c];
 #pragma unroll
-        for (int a = 0; a < A; ++a) {
-            const int i = l * A + a;
-            if (i < T.n) S.pre[c * S.ma + i] = excl + v[a][c];
+            for (int a = 0; a < A; ++a) {
+                const int i = l * A + a;
+                if (i < T.n) S.pre[c * S.ma + i] = excl + v[a][c];
+            }
         }
     }
     wave_sync();
