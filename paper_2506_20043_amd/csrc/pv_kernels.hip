@@ -714,10 +714,14 @@ __device__ Eval evaluate(const Topo<A, SL>& T, const BoxView& B, const Lds& S, c
     wave_sync();
     int cnt = 0;
     const float e_ia = pair_loop(T, S, cnt);   // hides the map loads
+    // the energy sums start here, so their cross-lane steps overlap the
+    // force gather and the scans below
+    out.e_intra = wsum(e_ia);
     wave_sync();
 #pragma unroll
     for (int a = 0; a < A; ++a)
         if (l * A + a < T.n) e_in += tri_finish(B, TL[a], G[a][0], G[a][1], G[a][2]);
+    out.e_inter = wsum(e_in);
     // per-atom force (inter + intra) and torque about t, blocked scan over atoms
     const float tx = pose[0], ty = pose[1], tz = pose[2];
     float v[A][6];
@@ -782,8 +786,6 @@ __device__ Eval evaluate(const Topo<A, SL>& T, const BoxView& B, const Lds& S, c
     if (l < 6) g = S.pre[l * S.ma + last];
     else if (l < 6 + T.nt) g = dps[T.dof_frag];
     out.g = g;
-    out.e_inter = wsum(e_in);
-    out.e_intra = wsum(e_ia);
     out.e = out.e_inter + out.e_intra;
     out.pairs_in = cnt;
     wave_sync();
