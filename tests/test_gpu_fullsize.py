@@ -1,10 +1,13 @@
-"""The multi-pocket dock at full size, in the launch the benchmark times (5
-pockets of 24 A, one 35-atom ligand, 256 chains x 1,000 Monte Carlo steps
-with RILC-BFGS, one persistent launch replayed as a graph; Supplementary
-Algorithm 2).  Chains with BFGS are chaotic, so the oracle checks what it can
-compute one chain at a time: the per-job reductions exactly, every sampled
-chain's best pose re-scored to its energy and no worse than the chain's
-initial pose, and the distribution of chain bests of one pocket against the
+"""The docking launches the benchmark times, at full size (Supplementary
+Algorithm 2): the multi-pocket dock (5 pockets of 24 A, one 35-atom ligand,
+256 chains x 1,000 Monte Carlo steps with RILC-BFGS, one persistent launch
+replayed as a graph), the uneven batch (1,280 jobs of ligands of 10..60
+atoms, 32 chains x 500 steps) and the screening stream (2,048 jobs over 16
+pockets, ligands of 8..80 atoms, 16 chains x 300 steps).  Chains with BFGS are
+chaotic, so the oracle checks what it can compute one chain at a time: the
+per-job reductions exactly, sampled chains' best poses re-scored to their
+energies and no worse than the chains' initial poses, and for the
+multi-pocket dock the distribution of one pocket's chain bests against the
 oracle's own chains on the same Philox streams."""
 import numpy as np
 import pytest
@@ -15,6 +18,56 @@ from paper_2506_20043_amd import synth as S
 
 pytestmark = pytest.mark.gpu
 KAPPA = 10.0
+
+
+def _grid(oracle, rx, rt, b):
+    return oracle.Grid.build(rx, rt, b.center.astype(np.float64), b.size.astype(np.float64), b.spacing, kappa=KAPPA)
+
+
+def _check(oracle, out, jobs, chains, steps, seed, lig_of, grid_of, sample):
+    """Exact per-job reductions over all jobs; oracle checks of the sampled
+    (job, chain) pairs; lig_of(ligand) and grid_of(box) give oracle objects.
+    Returns the chain bests as [jobs][chains]."""
+    nj = len(jobs)
+    cbe = out["chain_best_e"].reshape(nj, chains)
+    cev = out["chain_evals"].reshape(nj, chains)
+    cbd = out["chain_best_dof"].reshape(nj, chains, -1)
+    assert np.array_equal(out["job_best_e"], cbe.min(axis=1))
+    assert np.array_equal(out["job_best_chain"], np.argmin(cbe, axis=1))
+    assert np.array_equal(out["job_evals"], cev.sum(axis=1))
+    assert np.all(out["job_status"] == 0)
+    assert np.all(cev >= 1 + steps)          # one evaluation of the start, then one or more per step
+    assert np.all(np.isfinite(cbe))
+    for j, c in sample:
+        L, G = lig_of(int(jobs[j][0])), grid_of(int(jobs[j][1]))
+        d = cpu_dof(cbd[j, c, :L.ndof])
+        assert np.linalg.norm(d[3:7]) == pytest.approx(1.0, abs=1e-5)
+        assert np.all(cbd[j, c, L.ndof:] == 0.0)
+        r = L.score_grad(G, d)
+        slack = 0.01 if r["min_cut"] < 1e-4 else 0.0
+        assert abs(r["e"] - cbe[j, c]) <= e_tol(r["e"]) + slack, (j, c, cbe[j, c], r["e"])
+        e0 = L.score_grad(G, oracle.init_pose(L, G, seed, j, int(c)))["e"]
+        assert cbe[j, c] <= e0 + e_tol(e0), (j, c, cbe[j, c], e0)
+    return cbe
+
+
+class _Cache:
+    """Oracle ligands and grids built on first use."""
+
+    def __init__(self, oracle, mols, rx, rt, boxes):
+        self.oracle, self.mols, self.rx, self.rt, self.boxes = oracle, mols, rx, rt, boxes
+        self.ol, self.og = {}, {}
+
+    def lig(self, i):
+        if i not in self.ol:
+            m = self.mols[i]
+            self.ol[i] = self.oracle.Ligand(m.xyz, m.types, m.bonds, m.rotatable)
+        return self.ol[i]
+
+    def grid(self, b):
+        if b not in self.og:
+            self.og[b] = _grid(self.oracle, self.rx, self.rt, self.boxes[b])
+        return self.og[b]
 
 
 def test_multipocket_dock_full_size(oracle):
@@ -29,39 +82,78 @@ def test_multipocket_dock_full_size(oracle):
     ligs = pv.Ligands(ctx, mols)
     jobs = [(0, b) for b in range(len(bxs))]
     chains, steps = 256, 1000
-    p = pv.dock_params(chains=chains, steps=steps, seed=seed, flags=pv.PV_DOCK_GRAPH)
-    plan = pv.Plan(ctx, grids, ligs, jobs, p)
+    plan = pv.Plan(ctx, grids, ligs, jobs, pv.dock_params(chains=chains, steps=steps, seed=seed,
+                                                          flags=pv.PV_DOCK_GRAPH))
     out = {k: v.cpu().numpy().copy() for k, v in plan.run().items()}
     plan.close()
-    nj = len(jobs)
-    cbe = out["chain_best_e"].reshape(nj, chains)
-    cev = out["chain_evals"].reshape(nj, chains)
-    cbd = out["chain_best_dof"].reshape(nj, chains, -1)
-    # per-job reductions: the lowest chain best, ties to the lowest chain
-    assert np.array_equal(out["job_best_e"], cbe.min(axis=1))
-    assert np.array_equal(out["job_best_chain"], np.argmin(cbe, axis=1))
-    assert np.array_equal(out["job_evals"], cev.sum(axis=1))
-    assert np.all(out["job_status"] == 0)
-    # every step optimises at least once, after the one evaluation of the start
-    assert np.all(cev >= 1 + steps)
-    assert np.all(np.isfinite(cbe))
-    L = oracle.Ligand(mols[0].xyz, mols[0].types, mols[0].bonds, mols[0].rotatable)
-    G = [oracle.Grid.build(rx, rt, b.center.astype(np.float64), b.size.astype(np.float64), b.spacing, kappa=KAPPA)
-         for b in bxs]
+    cache = _Cache(oracle, mols, rx, rt, bxs)
     rng = np.random.default_rng(7)
-    for j in range(nj):
-        for c in rng.choice(chains, 8, replace=False):
-            d = cpu_dof(cbd[j, c, :L.ndof])
-            assert np.linalg.norm(d[3:7]) == pytest.approx(1.0, abs=1e-5)
-            r = L.score_grad(G[j], d)
-            slack = 0.01 if r["min_cut"] < 1e-4 else 0.0
-            assert abs(r["e"] - cbe[j, c]) <= e_tol(r["e"]) + slack, (j, c, cbe[j, c], r["e"])
-            e0 = L.score_grad(G[j], oracle.init_pose(L, G[j], seed, j, int(c)))["e"]
-            assert cbe[j, c] <= e0 + e_tol(e0), (j, c, cbe[j, c], e0)
+    sample = [(j, int(c)) for j in range(len(jobs)) for c in rng.choice(chains, 8, replace=False)]
+    cbe = _check(oracle, out, jobs, chains, steps, seed, cache.lig, cache.grid, sample)
     # the oracle's first 24 chains of pocket 0 (the same Philox streams)
     p24 = pv.dock_params(chains=24, steps=steps, seed=seed)
-    ref = oracle.dock([L], [G[0]], [(0, 0)], _oparams(oracle, p24))
+    ref = oracle.dock([cache.lig(0)], [cache.grid(0)], [(0, 0)], _oparams(oracle, p24))
     oe = ref["chain_best_e"][0]
     assert len(oe) == 24
     ks = stats.ks_2samp(cbe[0], oe)
     assert ks.pvalue > 0.01, (ks, np.median(cbe[0]), np.median(oe))
+
+
+def test_uneven_batch_full_size(oracle):
+    """The benchmark's uneven batch: the first 256 ligands x 5 pockets (1,280
+    jobs, 40,960 chains of 32 x 500 steps) in one persistent graph launch."""
+    import paper_2506_20043_amd as pv
+    cfg = S.CONFIGS["c3"]
+    rx, rt, bxs = S.make_receptor(cfg)
+    mols = S.make_ligands(cfg, 256)
+    seed = S.philox_seed(cfg)
+    ctx = pv.Context(0)
+    grids = pv.build_grids(ctx, rx, rt, bxs, penalty_slope=KAPPA)
+    ligs = pv.Ligands(ctx, mols)
+    jobs = S.make_jobs(cfg)[:256 * len(bxs)]
+    assert len(jobs) == 1280
+    plan = pv.Plan(ctx, grids, ligs, jobs, pv.dock_params(chains=cfg.chains, steps=cfg.steps, seed=seed,
+                                                          flags=pv.PV_DOCK_GRAPH))
+    out = {k: v.cpu().numpy().copy() for k, v in plan.run().items()}
+    plan.close()
+    rng = np.random.default_rng(11)
+    sample = [(int(j), int(c)) for j, c in zip(rng.choice(len(jobs), 32, replace=False),
+                                               rng.integers(0, cfg.chains, 32))]
+    cache = _Cache(oracle, mols, rx, rt, bxs)
+    _check(oracle, out, jobs, cfg.chains, cfg.steps, seed, cache.lig, cache.grid, sample)
+
+
+def test_screening_stream_full_size(oracle):
+    """The benchmark's screening stream: the first 2,048 jobs of the seeded
+    order over 16 pockets of 20..30 A, ligands of 8..80 atoms (both size
+    classes), one persistent graph launch per class with device timestamps."""
+    import paper_2506_20043_amd as pv
+    cfg = S.CONFIGS["c5"]
+    rx, rt, bxs = S.make_receptor(cfg)
+    jobs = S.make_jobs(cfg)[:2048]
+    uniq, local = np.unique(jobs[:, 0], return_inverse=True)
+    mols = [S.make_ligands(cfg, 1, int(i))[0] for i in uniq]
+    seed = S.philox_seed(cfg)
+    ctx = pv.Context(0)
+    grids = pv.build_grids(ctx, rx, rt, bxs, penalty_slope=KAPPA)
+    ligs = pv.Ligands(ctx, mols)
+    jl = np.stack([local.astype(np.int32), jobs[:, 1]], axis=1)
+    sizes = np.array([m.xyz.shape[0] for m in mols])
+    assert sizes.min() <= 64 < sizes.max()
+    plan = pv.Plan(ctx, grids, ligs, jl, pv.dock_params(chains=cfg.chains, steps=cfg.steps, seed=seed,
+                                                        flags=pv.PV_DOCK_GRAPH | pv.PV_DOCK_TIMESTAMPS))
+    out = {k: v.cpu().numpy().copy() for k, v in plan.run().items()}
+    plan.close()
+    t0, t1 = out["job_t_start"].astype(np.int64), out["job_t_end"].astype(np.int64)
+    assert np.all(t0 > 0) and np.all(t1 >= t0)
+    # sample jobs in 5 of the 16 pockets (an oracle grid each), from both size classes
+    rng = np.random.default_rng(13)
+    pockets = rng.choice(len(bxs), 5, replace=False)
+    cand = np.flatnonzero(np.isin(jl[:, 1], pockets))
+    small = cand[sizes[jl[cand, 0]] <= 64]
+    big = cand[sizes[jl[cand, 0]] > 64]
+    assert len(small) >= 16 and len(big) >= 1
+    picked = list(rng.choice(small, 16, replace=False)) + list(rng.choice(big, min(8, len(big)), replace=False))
+    sample = [(int(j), int(rng.integers(0, cfg.chains))) for j in picked]
+    cache = _Cache(oracle, mols, rx, rt, bxs)
+    _check(oracle, out, jl, cfg.chains, cfg.steps, seed, cache.lig, cache.grid, sample)
