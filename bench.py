@@ -64,6 +64,8 @@ def main():
     ap.add_argument("--plain-jobs", type=int, default=20, help="jobs of the uneven batch run one launch each")
     ap.add_argument("--stream-jobs", type=int, default=2048, help="jobs taken from the screening stream")
     ap.add_argument("--sweep-steps", type=int, default=1000, help="MC steps per chain in the box-size sweep")
+    ap.add_argument("--leg", choices=["score", "batching", "screening", "box_sweep", "surface"], default=None,
+                    help="run only this secondary leg and print its JSON (for profiling it alone)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device (calibrates the HBM byte counters) and exit")
     args = ap.parse_args()
@@ -86,6 +88,17 @@ def main():
 
     import paper_2506_20043_amd as pv
     from paper_2506_20043_amd import synth as S
+
+    if args.leg:
+        ctx = pv.Context(0)
+        stream = torch.cuda.current_stream()
+        legs = {"score": lambda: bench_score(pv, S, ctx, stream),
+                "batching": lambda: bench_batching(pv, S, ctx, stream, args),
+                "screening": lambda: bench_screening(pv, S, ctx, stream, args),
+                "box_sweep": lambda: bench_box_sweep(pv, S, ctx, stream, args),
+                "surface": lambda: bench_surface(pv, S, ctx, stream)}
+        print(json.dumps({"leg": args.leg, "result": legs[args.leg]()}), flush=True)
+        return
 
     cfg = S.CONFIGS["c2"]
     rx, rt, bxs = S.make_receptor(cfg)
