@@ -113,6 +113,7 @@ def main():
     params = pv.dock_params(chains=args.chains, steps=args.mc_steps, seed=seed,
                             flags=pv.PV_DOCK_GRAPH, workgroups=args.workgroups)
     plan = pv.Plan(ctx, grids, ligs, jobs, params)
+    tuning = tune(plan, stream)
     torch.cuda.synchronize()
 
     def step():
@@ -171,6 +172,7 @@ def main():
         "grid_ms": grid_ms,
         "dock_ms": dock_ms,
         "workgroups": plan_workgroups(plan),
+        "autotune": tuning,
     }
     # plain path: one launch per job, same kernel and draws
     if not args.no_plain:
@@ -273,6 +275,7 @@ def bench_consistency(pv, ctx, grids, ligs, jobs, args, seed, stream, evals_off,
     params = pv.dock_params(chains=args.chains, steps=args.mc_steps, seed=seed, flags=pv.PV_DOCK_GRAPH,
                             consistency=1)
     plan = pv.Plan(ctx, grids, ligs, jobs, params)
+    tune(plan, stream)
     plan.run()
     torch.cuda.synchronize()
     ms = _timed(stream, plan.run)
@@ -304,6 +307,24 @@ def bench_output(pv, plan, stream):
             "modes_per_job_mean": float(n.mean()), "best_affinity": float(res["mode_affinity"][:, 0].min().item())}
 
 
+VARIANTS = ["slots", "gather", "gather2"]
+
+
+def tune(plan, stream, steps=20):
+    """Runs the library's autotuner on the plan (outside every timed region)
+    and reports the schedules it set."""
+    t = time.perf_counter()
+    res = plan.autotune(steps=steps, repeats=2, stream=stream)
+    dt = time.perf_counter() - t
+    sched = []
+    for g in range(plan.groups()):
+        sc = plan.schedule(g)
+        sched.append({"variant": VARIANTS[sc["variant"]], "workgroups": sc["workgroups"],
+                      "lds_bytes": sc["lds_bytes"], "per_cu": sc["per_cu"], "jobs": sc["n_jobs"]})
+    return {"schedules": sched, "candidates_timed": sum(1 for r in res if not r["cached"]),
+            "tune_steps": steps, "tune_s": dt}
+
+
 def _timed(stream, fn):
     import torch
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -330,11 +351,12 @@ def bench_batching(pv, S, ctx, stream, args):
     jobs = S.make_jobs(cfg)[:args.batch_ligands * len(bxs)]
     params = pv.dock_params(chains=cfg.chains, steps=cfg.steps, seed=S.philox_seed(cfg), flags=pv.PV_DOCK_GRAPH)
     plan = pv.Plan(ctx, grids, ligs, jobs, params)
+    tuning = tune(plan, stream, steps=10)
     plan.run()
     torch.cuda.synchronize()
     ms = _timed(stream, plan.run)
     ev = int(plan.outputs()["job_evals"].sum().item())
-    variant = pv.launch_info(ctx, ligs, pv.KIND_DOCK, len(jobs) * cfg.chains)[0]
+    variant = plan.schedule(0)["variant"]
     output = bench_output(pv, plan, stream)
     plan.close()
     few = jobs[:args.plain_jobs]
@@ -350,7 +372,7 @@ def bench_batching(pv, S, ctx, stream, args):
         "workload": "uneven batch: ligands of 10..60 atoms / 0..15 torsions x 5 pockets of 24 A, "
                     "32 chains x 500 MC steps per job",
         "batched": {"jobs": len(jobs), "docks_per_s": len(jobs) / (ms * 1e-3), "evals_per_s": ev / (ms * 1e-3),
-                    "ms": ms, "variant": names[variant]},
+                    "ms": ms, "variant": names[variant], "autotune": tuning},
         "plain": {"jobs": len(few), "docks_per_s": len(few) / (ms_plain * 1e-3),
                   "evals_per_s": ev_plain / (ms_plain * 1e-3), "ms": ms_plain},
         "batched_same_jobs": {"jobs": len(few), "docks_per_s": len(few) / (ms_same * 1e-3), "ms": ms_same},
@@ -379,6 +401,7 @@ def bench_screening(pv, S, ctx, stream, args):
     params = pv.dock_params(chains=cfg.chains, steps=cfg.steps, seed=S.philox_seed(cfg),
                             flags=pv.PV_DOCK_GRAPH | pv.PV_DOCK_TIMESTAMPS)
     plan = pv.Plan(ctx, grids, ligs, jl, params)
+    tuning = tune(plan, stream, steps=10)
     plan.run()
     torch.cuda.synchronize()
     ms = _timed(stream, plan.run)
@@ -397,6 +420,7 @@ def bench_screening(pv, S, ctx, stream, args):
         "jobs": len(jobs), "ms": ms, "docks_per_s": len(jobs) / (ms * 1e-3), "evals_per_s": ev / (ms * 1e-3),
         "service_us_p50": float(np.percentile(svc, 50)), "service_us_p99": float(np.percentile(svc, 99)),
         "service_us_max": float(svc.max()), "makespan_us": float(span), "grid_build_ms_16_pockets": grid_ms,
+        "autotune": tuning,
     }
 
 
@@ -419,6 +443,7 @@ def bench_box_sweep(pv, S, ctx, stream, args):
     jobs = [(0, b) for b in range(len(sweep))]
     params = pv.dock_params(chains=64, steps=args.sweep_steps, seed=S.philox_seed(cfg), flags=pv.PV_DOCK_GRAPH)
     plan = pv.Plan(ctx, grids, ligs, jobs, params)
+    tune(plan, stream)
     plan.run()
     torch.cuda.synchronize()
     ms = _timed(stream, plan.run)

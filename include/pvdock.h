@@ -249,6 +249,54 @@ pv_status pv_dock_run(pv_plan* plan, const pv_dock_out* out, void* stream);
 pv_status pv_dock_run_plain(pv_plan* plan, const pv_dock_out* out, void* stream);
 void pv_plan_free(pv_plan* plan);
 
+/* Schedules.  A plan splits its jobs into size classes (ligands of at most
+ * 64 atoms first, larger ones second; classes without jobs are left out),
+ * and each class runs one persistent launch of pv_dock_run.  Its schedule:
+ * the kernel variant (PV_VARIANT_*, below), the launch width in one-wave
+ * workgroups and, reported only, the dynamic LDS bytes per workgroup, the
+ * workgroups one CU holds and the class's job count.  The plan starts from
+ * the occupancy model of pv_launch_info; pv_dock_run_plain always uses that
+ * model for its per-job launches. */
+typedef struct {
+    int32_t variant;
+    int32_t workgroups;
+    int32_t lds_bytes;
+    int32_t per_cu;
+    int32_t n_jobs;
+} pv_schedule;
+pv_status pv_plan_groups(const pv_plan* plan, int32_t* n_groups);
+pv_status pv_plan_schedule(const pv_plan* plan, int32_t group, pv_schedule* out);
+/* Sets a class's variant and width.  PV_VARIANT_SLOTS and PV_VARIANT_GATHER
+ * need ligands of at most 64 atoms; PV_VARIANT_GATHER2 takes any.  A
+ * workgroup of the variant must fit a CU (PV_E_RANGE otherwise); workgroups
+ * 0 = all the CUs hold at once, else 1 .. jobs x chains of the class.  Drops
+ * a captured graph (the next pv_dock_run captures again). */
+pv_status pv_plan_set_schedule(pv_plan* plan, int32_t group, int32_t variant, int32_t workgroups);
+
+/* Autotuner of the batched launch.  For every size class it times each
+ * candidate schedule -- every variant legal for the class, at widths of 1,
+ * 3/4 and 1/2 of the workgroups the CUs hold (capped by the class's work) --
+ * on a short run of the class's launch (tune_steps >= 1 Monte Carlo steps per
+ * chain, outputs to the plan's own scratch, no timestamps), keeps the best of
+ * `repeats` >= 1 timings (HIP events on `stream`) and sets the candidate
+ * with the most evaluations per second; on a tie the earlier candidate (the
+ * model's schedule comes first) wins.  The choice is remembered by the
+ * context, keyed by the class's ligand limits, work items, tune_steps and
+ * search settings, and a later call on a plan of the same key takes it
+ * without timing (reported with cached = 1).  results: host, up to
+ * max_results entries (may be NULL); n_results: how many were written (may
+ * be NULL).  Synchronises `stream`; drops a captured graph.  Calls that
+ * overlap on one plan race; the context's memory of choices is locked. */
+typedef struct {
+    int32_t group, variant, workgroups;
+    int32_t chosen;    /* 1 for the candidate the class now runs */
+    int32_t cached;    /* 1 when taken from the context without timing */
+    float ms;          /* best timing of the short run (0 when cached) */
+    double evals_per_s;
+} pv_tune_result;
+pv_status pv_dock_autotune(pv_plan* plan, int32_t tune_steps, int32_t repeats, void* stream,
+                           pv_tune_result* results, int32_t max_results, int32_t* n_results);
+
 /* plan + batched run + free in one call; it synchronises `stream` before
  * it releases the plan, so it returns after the dock has completed */
 pv_status pv_dock(pv_ctx* ctx, const pv_grids* grids, const pv_ligands* ligs, const pv_job* jobs,

@@ -63,6 +63,16 @@ class OutputParams(C.Structure):
                 ("affinity_w", C.c_float)]
 
 
+class Schedule(C.Structure):
+    _fields_ = [("variant", C.c_int32), ("workgroups", C.c_int32), ("lds_bytes", C.c_int32),
+                ("per_cu", C.c_int32), ("n_jobs", C.c_int32)]
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("group", C.c_int32), ("variant", C.c_int32), ("workgroups", C.c_int32), ("chosen", C.c_int32),
+                ("cached", C.c_int32), ("ms", C.c_float), ("evals_per_s", C.c_double)]
+
+
 class ModesOut(C.Structure):
     _fields_ = [("n_modes", C.c_void_p), ("mode_chain", C.c_void_p), ("mode_e", C.c_void_p),
                 ("mode_affinity", C.c_void_p), ("mode_dof", C.c_void_p), ("dof_stride", C.c_int32)]
@@ -95,6 +105,10 @@ SIGNATURES = {
     "pv_dock_run": (C.c_int, [_vp, C.POINTER(DockOut), _vp]),
     "pv_dock_run_plain": (C.c_int, [_vp, C.POINTER(DockOut), _vp]),
     "pv_plan_free": (None, [_vp]),
+    "pv_plan_groups": (C.c_int, [_vp, _ip]),
+    "pv_plan_schedule": (C.c_int, [_vp, _i32, C.POINTER(Schedule)]),
+    "pv_plan_set_schedule": (C.c_int, [_vp, _i32, _i32, _i32]),
+    "pv_dock_autotune": (C.c_int, [_vp, _i32, _i32, _vp, C.POINTER(TuneResult), _i32, _ip]),
     "pv_dock": (C.c_int, [_vp, _vp, _vp, C.POINTER(Job), _i32, C.POINTER(DockParams), C.POINTER(DockOut), _vp]),
     "pv_local_opt": (C.c_int, [_vp, _vp, _vp, _i32, _vp, _vp, _vp, _i32, C.POINTER(DockParams), _vp, _vp, _vp, _vp]),
     "pv_launch_info": (C.c_int, [_vp, _vp, _i32, C.c_int64, _ip, _ip, _ip]),
@@ -473,6 +487,31 @@ class Plan:
         fn = lib().pv_dock_run_plain if plain else lib().pv_dock_run
         _check(fn(self.h, C.byref(self._c_out), _stream(stream)), "pv_dock_run")
         return self._out
+
+    def groups(self) -> int:
+        """Size classes of the plan's jobs (each runs one persistent launch)."""
+        n = C.c_int32()
+        _check(lib().pv_plan_groups(self.h, C.byref(n)), "pv_plan_groups")
+        return n.value
+
+    def schedule(self, group: int = 0) -> dict:
+        """Variant, width, LDS bytes, workgroups per CU and jobs of a size class."""
+        sc = Schedule()
+        _check(lib().pv_plan_schedule(self.h, group, C.byref(sc)), "pv_plan_schedule")
+        return {k: getattr(sc, k) for k, _ in Schedule._fields_}
+
+    def set_schedule(self, group: int, variant: int, workgroups: int = 0):
+        _check(lib().pv_plan_set_schedule(self.h, group, variant, workgroups), "pv_plan_set_schedule")
+
+    def autotune(self, steps: int = 20, repeats: int = 2, stream=None) -> list:
+        """Times the candidate schedules of every size class on a short run
+        and keeps the fastest; returns one dict per candidate."""
+        cap = 16 * max(self.groups(), 1)
+        res = (TuneResult * cap)()
+        n = C.c_int32()
+        _check(lib().pv_dock_autotune(self.h, steps, repeats, _stream(stream), res, cap, C.byref(n)),
+               "pv_dock_autotune")
+        return [{k: getattr(res[i], k) for k, _ in TuneResult._fields_} for i in range(n.value)]
 
     def close(self):
         if self.h:

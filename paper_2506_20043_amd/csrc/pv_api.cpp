@@ -6,6 +6,7 @@
 #include <array>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -58,11 +59,21 @@ void dfree(void* p)
 
 }  // namespace
 
+// One autotuner choice: the key of a size class's launch, and its schedule.
+struct TuneEntry {
+    int32_t max_atoms, max_pairs, max_ell, max_tors;
+    int64_t items;
+    int32_t steps, max_iter, refine_max_iter, m, ls_max, consistency;
+    int32_t variant, workgroups;
+};
+
 struct pv_ctx {
     int device;
     int n_cu;
     int lds_per_block;   // dynamic LDS bytes one workgroup may use
     uint32_t magic;
+    std::mutex tune_mu;
+    std::vector<TuneEntry> tune;
 };
 
 struct pv_grids {
@@ -122,7 +133,7 @@ struct pv_plan {
     // with its own LDS limits, kernel variant and persistent launch; jobs
     // keep their indices through a per-group job map.
     std::vector<DockGroup> groups;
-    std::vector<int32_t> job_group;   // per job
+    std::vector<int32_t> job_group;   // per job: index into groups
     hipStream_t cap_stream;
     hipGraph_t graph;
     hipGraphExec_t exec;
@@ -695,11 +706,7 @@ pv_status pv_dock_plan(pv_ctx* ctx, const pv_grids* grids, const pv_ligands* lig
     // size classes: one atom per lane (at most 64 atoms) and two
     std::vector<int32_t> members[2];
     P->job_group.assign(n_jobs, 0);
-    for (int32_t j = 0; j < n_jobs; ++j) {
-        const int g = (*ligs->info)[hj[j].x][0] > 64 ? 1 : 0;
-        P->job_group[j] = g;
-        members[g].push_back(j);
-    }
+    for (int32_t j = 0; j < n_jobs; ++j) members[(*ligs->info)[hj[j].x][0] > 64 ? 1 : 0].push_back(j);
     hipError_t e = hipSuccess;
     for (int g = 0; g < 2 && e == hipSuccess; ++g) {
         if (members[g].empty()) continue;
@@ -725,6 +732,7 @@ pv_status pv_dock_plan(pv_ctx* ctx, const pv_grids* grids, const pv_ligands* lig
             pv_plan_free(P);
             return st;
         }
+        for (int32_t j : members[g]) P->job_group[j] = (int32_t)P->groups.size();
         P->groups.push_back(G);
     }
     if (e != hipSuccess) { pv_plan_free(P); return hip_fail(e, "dock launch shape"); }
@@ -847,7 +855,7 @@ pv_status pv_dock_run_plain(pv_plan* P, const pv_dock_out* o, void* stream)
     int64_t* cev = o->chain_evals ? o->chain_evals : P->scratch_evals;
     if (P->sp.flags & PV_DOCK_TIMESTAMPS) HIP_TRY(launch_reset_times(o->job_t_start, o->job_t_end, P->n_jobs, s), "reset");
     for (int32_t j = 0; j < P->n_jobs; ++j) {
-        const DockGroup& G = P->groups[P->groups.size() == 1 ? 0 : P->job_group[j]];
+        const DockGroup& G = P->groups[P->job_group[j]];
         DockArgs a = dock_args(P, o, cbe, cev);
         a.l = G.lv;
         a.job_begin = j;
@@ -874,6 +882,189 @@ void pv_plan_free(pv_plan* P)
     dfree(P->jobs); dfree(P->queue); dfree(P->scratch_best); dfree(P->scratch_evals);
     for (DockGroup& G : P->groups) dfree(G.job_map);
     delete P;
+}
+
+// ------------------------------------------------------------------ schedules
+static void drop_graph(pv_plan* P)
+{
+    if (P->have_graph) {
+        (void)hipGraphExecDestroy(P->exec);
+        (void)hipGraphDestroy(P->graph);
+        P->have_graph = false;
+    }
+}
+
+pv_status pv_plan_groups(const pv_plan* P, int32_t* n_groups)
+{
+    if (!P || !n_groups) return fail(PV_E_INVALID, "plan or output is NULL");
+    *n_groups = (int32_t)P->groups.size();
+    return PV_OK;
+}
+
+pv_status pv_plan_schedule(const pv_plan* P, int32_t group, pv_schedule* out)
+{
+    if (!P || !out) return fail(PV_E_INVALID, "plan or output is NULL");
+    if (group < 0 || group >= (int32_t)P->groups.size()) return fail(PV_E_RANGE, "no such size class");
+    const DockGroup& G = P->groups[group];
+    out->variant = G.shape.variant;
+    out->workgroups = G.workgroups;
+    out->lds_bytes = G.shape.lds;
+    out->per_cu = G.shape.per_cu;
+    out->n_jobs = G.n_jobs;
+    return PV_OK;
+}
+
+// Shape and width of `variant` for a size class; workgroups 0 = all the CUs
+// hold, capped by the class's work.  The device must be current.
+static pv_status group_shape(const pv_plan* P, int32_t group, int32_t variant, int32_t workgroups, LaunchShape* sh,
+                             int32_t* wg)
+{
+    const DockGroup& G = P->groups[group];
+    const hipError_t e = launch_shape_variant(kKindDock, G.lv, variant, sh);
+    if (e == hipErrorInvalidValue) return fail(PV_E_INVALID, "variant not available for this size class");
+    if (e != hipSuccess || sh->lds > P->ctx->lds_per_block)
+        return fail(PV_E_RANGE, "a workgroup of this variant does not fit a CU");
+    const int64_t items = (int64_t)G.n_jobs * P->sp.chains;
+    if (workgroups < 0 || workgroups > items) return fail(PV_E_RANGE, "workgroups must be 0 .. jobs x chains of the class");
+    *wg = workgroups > 0 ? workgroups
+                         : (int32_t)std::min<int64_t>((int64_t)sh->per_cu * P->ctx->n_cu, std::max<int64_t>(items, 1));
+    return PV_OK;
+}
+
+pv_status pv_plan_set_schedule(pv_plan* P, int32_t group, int32_t variant, int32_t workgroups)
+{
+    if (!P) return fail(PV_E_INVALID, "plan is NULL");
+    if (group < 0 || group >= (int32_t)P->groups.size()) return fail(PV_E_RANGE, "no such size class");
+    pv_status st = set_device(P->ctx);
+    if (st != PV_OK) return st;
+    LaunchShape sh;
+    int32_t wg = 0;
+    if ((st = group_shape(P, group, variant, workgroups, &sh, &wg)) != PV_OK) return st;
+    P->groups[group].shape = sh;
+    P->groups[group].workgroups = wg;
+    drop_graph(P);
+    return PV_OK;
+}
+
+static bool same_key(const TuneEntry& a, const TuneEntry& b)
+{
+    return a.max_atoms == b.max_atoms && a.max_pairs == b.max_pairs && a.max_ell == b.max_ell &&
+           a.max_tors == b.max_tors && a.items == b.items && a.steps == b.steps && a.max_iter == b.max_iter &&
+           a.refine_max_iter == b.refine_max_iter && a.m == b.m && a.ls_max == b.ls_max &&
+           a.consistency == b.consistency;
+}
+
+pv_status pv_dock_autotune(pv_plan* P, int32_t tune_steps, int32_t repeats, void* stream, pv_tune_result* results,
+                           int32_t max_results, int32_t* n_results)
+{
+    if (n_results) *n_results = 0;
+    if (!P) return fail(PV_E_INVALID, "plan is NULL");
+    if (tune_steps < 1) return fail(PV_E_INVALID, "tune_steps < 1");
+    if (repeats < 1 || repeats > 100) return fail(PV_E_RANGE, "repeats must be 1 .. 100");
+    if (max_results < 0 || (max_results > 0 && !results)) return fail(PV_E_INVALID, "results is NULL");
+    pv_status st = set_device(P->ctx);
+    if (st != PV_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    int32_t written = 0;
+    auto put = [&](const pv_tune_result& r) -> int32_t {
+        if (written >= max_results) return -1;
+        results[written] = r;
+        return written++;
+    };
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    hipError_t e = hipEventCreate(&t0);
+    if (e == hipSuccess) e = hipEventCreate(&t1);
+    auto done = [&](pv_status r) {
+        if (t0) (void)hipEventDestroy(t0);
+        if (t1) (void)hipEventDestroy(t1);
+        drop_graph(P);
+        if (n_results) *n_results = written;
+        return r;
+    };
+    if (e != hipSuccess) return done(hip_fail(e, "hipEventCreate"));
+    const int32_t chains = P->sp.chains;
+    std::vector<int64_t> hev((size_t)P->n_jobs * chains);
+    pv_dock_out none;
+    std::memset(&none, 0, sizeof(none));
+    for (size_t g = 0; g < P->groups.size(); ++g) {
+        DockGroup& G = P->groups[g];
+        const int64_t items = (int64_t)G.n_jobs * chains;
+        TuneEntry key = {G.lv.max_atoms, G.lv.max_pairs, G.lv.max_ell, G.lv.max_tors, items, tune_steps,
+                         P->sp.max_iter, P->sp.refine_max_iter, P->sp.m, P->sp.ls_max, P->sp.consistency, 0, 0};
+        bool cached = false;
+        {
+            std::lock_guard<std::mutex> lock(P->ctx->tune_mu);
+            for (const TuneEntry& t : P->ctx->tune)
+                if (same_key(t, key)) { key.variant = t.variant; key.workgroups = t.workgroups; cached = true; break; }
+        }
+        if (cached) {
+            LaunchShape sh;
+            int32_t wg = 0;
+            if ((st = group_shape(P, (int32_t)g, key.variant, key.workgroups, &sh, &wg)) != PV_OK) return done(st);
+            G.shape = sh;
+            G.workgroups = wg;
+            put(pv_tune_result{(int32_t)g, sh.variant, wg, 1, 1, 0.f, 0.0});
+            continue;
+        }
+        // candidates: the current schedule first, then every legal variant
+        // at 1, 3/4 and 1/2 of the width the CUs hold
+        std::vector<std::pair<LaunchShape, int32_t>> cand;
+        cand.push_back({G.shape, G.workgroups});
+        for (int v = G.lv.max_atoms <= 64 ? 0 : 2; v <= 2; ++v) {
+            LaunchShape sh;
+            if (launch_shape_variant(kKindDock, G.lv, v, &sh) != hipSuccess || sh.lds > P->ctx->lds_per_block) continue;
+            const int64_t full = std::min<int64_t>((int64_t)sh.per_cu * P->ctx->n_cu, std::max<int64_t>(items, 1));
+            for (int q = 4; q >= 2; --q) {
+                const int32_t wg = (int32_t)std::max<int64_t>(1, (full * q + 3) / 4);
+                bool seen = false;
+                for (const auto& c : cand) seen = seen || (c.first.variant == v && c.second == wg);
+                if (!seen) cand.push_back({sh, wg});
+            }
+        }
+        size_t best = 0;
+        double best_rate = -1.0;
+        std::vector<int32_t> slot(cand.size(), -1);
+        for (size_t k = 0; k < cand.size(); ++k) {
+            DockArgs a = dock_args(P, &none, P->scratch_best, P->scratch_evals);
+            a.sp.steps = tune_steps;
+            a.sp.flags &= ~PV_DOCK_TIMESTAMPS;
+            a.l = G.lv;
+            a.job_map = G.job_map;
+            a.queue = P->queue + g;
+            a.job_begin = 0;
+            a.n_items = items;
+            a.persistent = 1;
+            float best_ms = 0.f;
+            for (int r = 0; r < repeats; ++r) {
+                e = launch_reset_queue(a.queue, s);
+                if (e == hipSuccess) e = hipEventRecord(t0, s);
+                if (e == hipSuccess) e = launch_dock(a, cand[k].first, cand[k].second, s);
+                if (e == hipSuccess) e = hipEventRecord(t1, s);
+                if (e == hipSuccess) e = hipEventSynchronize(t1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+                if (e != hipSuccess) return done(hip_fail(e, "autotune launch"));
+                best_ms = r == 0 ? ms : std::min(best_ms, ms);
+            }
+            e = hipMemcpy(hev.data(), P->scratch_evals, hev.size() * sizeof(int64_t), hipMemcpyDeviceToHost);
+            if (e != hipSuccess) return done(hip_fail(e, "autotune evaluation counts"));
+            int64_t ev = 0;
+            for (int32_t j = 0; j < P->n_jobs; ++j)
+                if (P->job_group[j] == (int32_t)g)
+                    for (int32_t c = 0; c < chains; ++c) ev += hev[(size_t)j * chains + c];
+            const double rate = best_ms > 0.f ? (double)ev / (best_ms * 1e-3) : 0.0;
+            slot[k] = put(pv_tune_result{(int32_t)g, cand[k].first.variant, cand[k].second, 0, 0, best_ms, rate});
+            if (rate > best_rate) { best_rate = rate; best = k; }
+        }
+        G.shape = cand[best].first;
+        G.workgroups = cand[best].second;
+        if (slot[best] >= 0) results[slot[best]].chosen = 1;
+        key.variant = G.shape.variant;
+        key.workgroups = G.workgroups;
+        std::lock_guard<std::mutex> lock(P->ctx->tune_mu);
+        P->ctx->tune.push_back(key);
+    }
+    return done(PV_OK);
 }
 
 pv_status pv_dock(pv_ctx* ctx, const pv_grids* grids, const pv_ligands* ligs, const pv_job* jobs, int32_t n_jobs,

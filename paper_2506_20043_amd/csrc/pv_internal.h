@@ -200,6 +200,9 @@ struct LaunchShape {
 };
 enum KernelKind { kKindDock = 0, kKindScore = 1, kKindOpt = 2 };
 hipError_t launch_shape(int kind, const LigDev& l, int64_t items, int n_cu, LaunchShape* out);
+// The shape of one given variant (0 and 1 need ligands of at most 64 atoms);
+// hipErrorInvalidConfiguration when no workgroup of it fits a CU.
+hipError_t launch_shape_variant(int kind, const LigDev& l, int variant, LaunchShape* out);
 
 hipError_t launch_score(const ScoreArgs& a, int n_cu, hipStream_t s);
 hipError_t launch_dock(const DockArgs& a, const LaunchShape& sh, int32_t workgroups, hipStream_t s);

@@ -1805,6 +1805,19 @@ hipError_t launch_shape(int kind, const LigDev& l, int64_t items, int n_cu, Laun
     return out->per_cu > 0 ? hipSuccess : hipErrorInvalidConfiguration;
 }
 
+hipError_t launch_shape_variant(int kind, const LigDev& l, int variant, LaunchShape* out)
+{
+    *out = {variant, 0, 0};
+    if (variant < 0 || variant > 2 || (variant < 2 && l.max_atoms > 64)) return hipErrorInvalidValue;
+    const int lds = lds_bytes(l.max_atoms, l.max_pairs, l.max_ell, variant == 0);
+    int occ;
+    if (variant == 0) occ = kind_occupancy<1, true>(kind, lds);
+    else if (variant == 1) occ = kind_occupancy<1, false>(kind, lds);
+    else occ = kind_occupancy<2, false>(kind, lds);
+    *out = {variant, lds, occ};
+    return occ > 0 ? hipSuccess : hipErrorInvalidConfiguration;
+}
+
 hipError_t launch_score(const ScoreArgs& a, int n_cu, hipStream_t s)
 {
     if (a.n_poses <= 0) return hipSuccess;

@@ -1,0 +1,135 @@
+"""Schedules of the batched dock and the autotuner: every kernel variant a
+size class can run, forced at full and narrow persistent widths, replays the
+oracle's Monte Carlo chains (without BFGS, decision by decision); the
+autotuner times the candidates of every class, applies one, remembers it in
+the context, and the tuned run stays valid against the oracle."""
+import numpy as np
+import pytest
+
+from gpu_util import cpu_dof, e_tol
+from paper_2506_20043_amd import synth as S
+
+pytestmark = pytest.mark.gpu
+KAPPA = 10.0
+
+
+@pytest.fixture(scope="module")
+def pv_ctx():
+    import paper_2506_20043_amd as pv
+    return pv.Context(0)
+
+
+@pytest.fixture(scope="module")
+def setup(oracle, pv_ctx):
+    """The multi-pocket receptor's first pocket with a 30-atom and an
+    80-atom ligand (two size classes)."""
+    import paper_2506_20043_amd as pv
+    cfg = S.CONFIGS["c2"]
+    rx, rt, bxs = S.make_receptor(cfg)
+    g = np.random.default_rng(41)
+    mols = [S.tree_ligand(g, 30, 6), S.tree_ligand(g, 80, 10)]
+    b = bxs[0]
+    return dict(grids=pv.build_grids(pv_ctx, rx, rt, bxs[:1], penalty_slope=KAPPA),
+                ligs=pv.Ligands(pv_ctx, mols),
+                og=oracle.Grid.build(rx, rt, b.center.astype(np.float64), b.size.astype(np.float64), b.spacing,
+                                     kappa=KAPPA),
+                ol=[oracle.Ligand(m.xyz, m.types, m.bonds, m.rotatable) for m in mols])
+
+
+def _replays(oracle, setup, out, jobs, p, chains, step=4):
+    from test_gpu_search import _oparams
+    cbe = out["chain_best_e"].cpu().numpy().reshape(len(jobs), chains)
+    ev = out["chain_evals"].cpu().numpy().reshape(len(jobs), chains)
+    same = total = 0
+    for j, (lig, _) in enumerate(jobs):
+        for c in range(0, chains, step):
+            d, e_ref, ne = oracle.mc_chain(setup["ol"][lig], setup["og"], _oparams(oracle, p), j, c)
+            same += int(ne == ev[j, c] and abs(cbe[j, c] - e_ref) <= e_tol(e_ref))
+            total += 1
+    return same, total
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_forced_variants_replay_oracle(oracle, pv_ctx, setup, variant):
+    import paper_2506_20043_amd as pv
+    jobs = [(0, 0), (0, 0), (1, 0)]
+    chains = 24
+    p = pv.dock_params(chains=chains, steps=25, seed=91, bfgs_max_iter=0, refine_max_iter=0,
+                       flags=pv.PV_DOCK_GRAPH)
+    import torch
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    plan = pv.Plan(pv_ctx, setup["grids"], setup["ligs"], jobs, p)
+    assert plan.groups() == 2
+    assert plan.schedule(0)["n_jobs"] == 2 and plan.schedule(1)["n_jobs"] == 1
+    for width in (0, 5):
+        plan.set_schedule(0, variant, width)
+        sc = plan.schedule(0)
+        assert sc["variant"] == variant and sc["per_cu"] >= 1
+        assert sc["workgroups"] == (width if width else min(sc["per_cu"] * n_cu, 2 * chains))
+        out = {k: v.clone() for k, v in plan.run().items()}
+        same, total = _replays(oracle, setup, out, jobs, p, chains)
+        assert same >= total - 2, (variant, width, same, total)
+    plan.close()
+
+
+def test_autotune_chooses_remembers_and_stays_valid(oracle, pv_ctx, setup):
+    import paper_2506_20043_amd as pv
+    jobs = [(0, 0), (1, 0), (0, 0)]
+    chains = 32
+    p = pv.dock_params(chains=chains, steps=40, seed=92, flags=pv.PV_DOCK_GRAPH)
+    plan = pv.Plan(pv_ctx, setup["grids"], setup["ligs"], jobs, p)
+    before = [plan.schedule(g) for g in range(plan.groups())]
+    res = plan.autotune(steps=3, repeats=1)
+    for g in range(plan.groups()):
+        mine = [r for r in res if r["group"] == g]
+        assert len(mine) >= 2 and all(r["cached"] == 0 and r["ms"] > 0 for r in mine)
+        # the model's schedule is the first candidate of its class
+        assert (mine[0]["variant"], mine[0]["workgroups"]) == (before[g]["variant"], before[g]["workgroups"])
+        chosen = [r for r in mine if r["chosen"]]
+        assert len(chosen) == 1
+        assert chosen[0]["evals_per_s"] == max(r["evals_per_s"] for r in mine)
+        sc = plan.schedule(g)
+        assert (sc["variant"], sc["workgroups"]) == (chosen[0]["variant"], chosen[0]["workgroups"])
+    # the small class may run any of the three variants, the large one only two atoms per lane
+    assert {r["variant"] for r in res if r["group"] == 0} == {0, 1, 2}
+    assert {r["variant"] for r in res if r["group"] == 1} == {2}
+    out = {k: v.cpu().numpy() for k, v in plan.run().items()}
+    cbe = out["chain_best_e"].reshape(len(jobs), chains)
+    cbd = out["chain_best_dof"].reshape(len(jobs), chains, -1)
+    assert np.array_equal(out["job_best_e"], cbe.min(axis=1))
+    assert np.all(out["chain_evals"] >= 1 + p.steps)
+    for j, (lig, _) in enumerate(jobs):
+        L = setup["ol"][lig]
+        for c in range(0, chains, 8):
+            r = L.score_grad(setup["og"], cpu_dof(cbd[j, c, :L.ndof]))
+            slack = 0.01 if r["min_cut"] < 1e-4 else 0.0
+            assert abs(r["e"] - cbe[j, c]) <= e_tol(r["e"]) + slack, (j, c, cbe[j, c], r["e"])
+    # a second plan of the same shape takes the remembered choice without timing
+    plan2 = pv.Plan(pv_ctx, setup["grids"], setup["ligs"], jobs, p)
+    res2 = plan2.autotune(steps=3, repeats=1)
+    assert len(res2) == plan.groups() and all(r["cached"] == 1 and r["chosen"] == 1 for r in res2)
+    for g in range(plan.groups()):
+        a, b = plan.schedule(g), plan2.schedule(g)
+        assert (a["variant"], a["workgroups"]) == (b["variant"], b["workgroups"])
+    o2 = {k: v.cpu().numpy() for k, v in plan2.run().items()}
+    assert np.array_equal(o2["chain_best_e"], out["chain_best_e"])
+    plan.close()
+    plan2.close()
+
+
+def test_schedule_rejects(pv_ctx, setup):
+    import paper_2506_20043_amd as pv
+    p = pv.dock_params(chains=8, steps=5, seed=93)
+    plan = pv.Plan(pv_ctx, setup["grids"], setup["ligs"], [(0, 0), (1, 0)], p)
+    for args in ((-1, 0, 0), (2, 0, 0), (1, 0, 0), (1, 1, 0), (0, 3, 0), (0, -1, 0), (0, 1, 9), (0, 1, -1)):
+        with pytest.raises(pv.PvError):
+            plan.set_schedule(*args)
+    for kw in ({"steps": 0}, {"repeats": 0}, {"repeats": 101}):
+        with pytest.raises(pv.PvError):
+            plan.autotune(**kw)
+    empty = pv.Plan(pv_ctx, setup["grids"], setup["ligs"], [], p)
+    assert empty.groups() == 0 and empty.autotune() == []
+    with pytest.raises(pv.PvError):
+        empty.schedule(0)
+    empty.close()
+    plan.close()
