@@ -718,9 +718,20 @@ __device__ Eval evaluate(const Topo<A, SL>& T, const BoxView& B, const Lds& S, c
     // force gather and the scans below
     out.e_intra = wsum(e_ia);
     wave_sync();
+    // intra forces first (LDS only), so the map loads get the gather's time
+    // too before their values are needed
+    float F[A][3];
+#pragma unroll
+    for (int a = 0; a < A; ++a) {
+        F[a][0] = F[a][1] = F[a][2] = 0.f;
+        if (l * A + a < T.n) gather_pair_forces(T, S, l * A + a, X4[a], F[a][0], F[a][1], F[a][2]);
+    }
 #pragma unroll
     for (int a = 0; a < A; ++a)
-        if (l * A + a < T.n) e_in += tri_finish(B, TL[a], G[a][0], G[a][1], G[a][2]);
+        if (l * A + a < T.n) {
+            e_in += tri_finish(B, TL[a], G[a][0], G[a][1], G[a][2]);
+            G[a][0] += F[a][0]; G[a][1] += F[a][1]; G[a][2] += F[a][2];
+        }
     out.e_inter = wsum(e_in);
     // per-atom force (inter + intra) and torque about t, blocked scan over atoms
     const float tx = pose[0], ty = pose[1], tz = pose[2];
@@ -731,7 +742,6 @@ __device__ Eval evaluate(const Topo<A, SL>& T, const BoxView& B, const Lds& S, c
         const int i = l * A + a;
         float rx = 0, ry = 0, rz = 0;
         if (i < T.n) {
-            gather_pair_forces(T, S, i, X4[a], G[a][0], G[a][1], G[a][2]);
             S.frc[i] = make_float4(G[a][0], G[a][1], G[a][2], 0.f);
             rx = X4[a].x - tx; ry = X4[a].y - ty; rz = X4[a].z - tz;
         }
