@@ -657,9 +657,13 @@ __device__ __forceinline__ float4 atom_position(float4 ref, const Lds& S)
 }
 
 // Score and tangent gradient of the pose in `pose` (an LDS slot).  Leaves
-// atom positions in S.pos and dE/dx in S.frc.
+// atom positions in S.pos and dE/dx in S.frc.  When the energy exceeds
+// e_limit (a line-search trial that fails the sufficient-decrease test,
+// whose gradient nobody reads) it returns after the energy, with g = 0 and
+// S.frc not written.
 template <int A, bool SL>
-__device__ Eval evaluate(const Topo<A, SL>& T, const BoxView& B, const Lds& S, const float* pose)
+__device__ Eval evaluate(const Topo<A, SL>& T, const BoxView& B, const Lds& S, const float* pose,
+                         float e_limit = __builtin_inff())
 {
     const int l = lane_id();
     Eval out;
@@ -718,21 +722,20 @@ __device__ Eval evaluate(const Topo<A, SL>& T, const BoxView& B, const Lds& S, c
     // force gather and the scans below
     out.e_intra = wsum(e_ia);
     wave_sync();
-    // intra forces first (LDS only), so the map loads get the gather's time
-    // too before their values are needed
-    float F[A][3];
 #pragma unroll
-    for (int a = 0; a < A; ++a) {
-        F[a][0] = F[a][1] = F[a][2] = 0.f;
-        if (l * A + a < T.n) gather_pair_forces(T, S, l * A + a, X4[a], F[a][0], F[a][1], F[a][2]);
+    for (int a = 0; a < A; ++a)
+        if (l * A + a < T.n) e_in += tri_finish(B, TL[a], G[a][0], G[a][1], G[a][2]);
+    out.e_inter = wsum(e_in);
+    out.e = out.e_inter + out.e_intra;
+    out.pairs_in = cnt;
+    if (out.e > e_limit) {    // wave-uniform
+        out.g = 0.f;
+        wave_sync();
+        return out;
     }
 #pragma unroll
     for (int a = 0; a < A; ++a)
-        if (l * A + a < T.n) {
-            e_in += tri_finish(B, TL[a], G[a][0], G[a][1], G[a][2]);
-            G[a][0] += F[a][0]; G[a][1] += F[a][1]; G[a][2] += F[a][2];
-        }
-    out.e_inter = wsum(e_in);
+        if (l * A + a < T.n) gather_pair_forces(T, S, l * A + a, X4[a], G[a][0], G[a][1], G[a][2]);
     // per-atom force (inter + intra) and torque about t, blocked scan over atoms
     const float tx = pose[0], ty = pose[1], tz = pose[2];
     float v[A][6];
@@ -796,8 +799,6 @@ __device__ Eval evaluate(const Topo<A, SL>& T, const BoxView& B, const Lds& S, c
     if (l < 6) g = S.pre[l * S.ma + last];
     else if (l < 6 + T.nt) g = dps[T.dof_frag];
     out.g = g;
-    out.e = out.e_inter + out.e_intra;
-    out.pairs_in = cnt;
     wave_sync();
     return out;
 }
@@ -941,7 +942,9 @@ __device__ BfgsOut bfgs(const Topo<A, SL>& T, const BoxView& B, const Lds& S, co
     float lo = 0.f, lam = 1.f, beta = 0.f, fa = 0.f, ga = 0.f;
     bool beta_inf = true, initial = true;
     while (true) {
-        const Eval ev = evaluate(T, B, S, S.pose + (initial ? SLOT_X : SLOT_XT) * kSlot);
+        // a trial above the sufficient-decrease bound needs no gradient
+        const float armijo = initial ? __builtin_inff() : f + P.rho * lam * gd;
+        const Eval ev = evaluate(T, B, S, S.pose + (initial ? SLOT_X : SLOT_XT) * kSlot, armijo);
         ++out.evals;
         out.pairs += ev.pairs_in;
         const float ft = ev.e, gt = act ? ev.g : 0.f;
@@ -955,7 +958,7 @@ __device__ BfgsOut bfgs(const Topo<A, SL>& T, const BoxView& B, const Lds& S, co
         } else {
             // Lewis-Overton trial at step lam (Eqs. qvina_eq_7 and qvina_eq_8)
             bool accepted = false;
-            if (ft > f + P.rho * lam * gd) {
+            if (ft > armijo) {
                 beta = lam; beta_inf = false;
             } else if (wsum_n(gt * d, nd) < P.sigma * gd) {
                 lo = lam;
