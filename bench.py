@@ -25,24 +25,33 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_VECTOR = 157.3e12   # MI355X vector FP32, FLOP/s
 PEAK_HBM = 8.0e12             # MI355X HBM3E, B/s
 
-# Algorithmic work of one score + gradient evaluation, counted from the
-# operations the method needs ("Roofline"): per intra pair
-# tested (difference, squared distance), per pair inside the cutoff (terms,
-# derivative, force on both atoms), per atom (frame transform, trilinear
-# value and gradient, force/torque accumulation), per torsion (local
-# rotation, frame composition, torsion derivative), per evaluation (root
-# frame) and BFGS vector work per evaluation.
+# Algorithmic work of one evaluation, counted from the operations the method
+# needs, energy part and gradient part: per intra pair tested (difference,
+# squared distance); per pair inside the cutoff, the terms (20) and with the
+# gradient the derivative and the force on both atoms (16); per atom, the
+# frame transform and the trilinear value (48) and with the gradient the
+# trilinear gradient and the force/torque accumulation (43); per torsion, the
+# local rotation and the frame composition (109) and with the gradient the
+# torsion derivative (32); per evaluation the root frame and the BFGS vector
+# work.  A line-search trial above the sufficient-decrease bound needs only
+# the energy (the kernel stops there), so the gradient part counts once per
+# evaluation that computed it.
 FLOP_PAIR_TEST = 8
-FLOP_PAIR_IN = 36
-FLOP_ATOM = 91
-FLOP_TORS = 141
+FLOP_PAIR_IN, FLOP_PAIR_IN_GRAD = 20, 16
+FLOP_ATOM, FLOP_ATOM_GRAD = 48, 43
+FLOP_TORS, FLOP_TORS_GRAD = 109, 32
 FLOP_EVAL = 50
 
 
-def flops_per_launch(n_evals, pairs_in, n_atoms, n_tors, n_pairs, m=5):
-    per_eval = FLOP_PAIR_TEST * n_pairs + FLOP_ATOM * n_atoms + FLOP_TORS * n_tors + FLOP_EVAL
-    per_eval += (4 * m + 10) * (6 + n_tors)
-    return float(n_evals) * per_eval + float(pairs_in) * FLOP_PAIR_IN
+def flops_per_launch(n_evals, n_grads, pairs_in, n_atoms, n_tors, n_pairs, m=5):
+    energy = FLOP_PAIR_TEST * n_pairs + FLOP_ATOM * n_atoms + FLOP_TORS * n_tors + FLOP_EVAL
+    energy += (4 * m + 10) * (6 + n_tors)
+    grad = FLOP_ATOM_GRAD * n_atoms + FLOP_TORS_GRAD * n_tors
+    # pairs inside the cutoff are counted over all evaluations; their gradient
+    # share follows the share of evaluations with a gradient
+    share = n_grads / n_evals if n_evals else 0.0
+    return (float(n_evals) * energy + float(n_grads) * grad +
+            float(pairs_in) * (FLOP_PAIR_IN + share * FLOP_PAIR_IN_GRAD))
 
 
 def main():
@@ -137,13 +146,14 @@ def main():
     out = plan.outputs()
     n_evals = int(out["job_evals"].sum().item())
     pairs_in = int(out["chain_pairs"].sum().item())
+    n_grads = int(out["chain_grads"].sum().item())
     grid_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
     dock_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
     ms_per_step = wall * 1e3 / args.steps
     docks = len(jobs) * args.steps
     docks_per_s = docks / wall
     evals_per_s = n_evals * args.steps / wall
-    flops = flops_per_launch(n_evals, pairs_in, n_atoms, n_tors, n_pairs)
+    flops = flops_per_launch(n_evals, n_grads, pairs_in, n_atoms, n_tors, n_pairs)
     achieved = flops / (dock_ms * 1e-3)
     result = {
         "metric": "ligand-pocket docks/s and score+grad evals/s, batched vs plain on 1 MI355X",
@@ -169,6 +179,7 @@ def main():
         },
         "evals_per_s": evals_per_s,
         "evals_per_step": n_evals,
+        "gradient_evals_per_step": n_grads,
         "grid_ms": grid_ms,
         "dock_ms": dock_ms,
         "workgroups": plan_workgroups(plan),

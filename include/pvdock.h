@@ -220,7 +220,9 @@ typedef struct { int32_t ligand, box; } pv_job;
  *   job_best_e [jobs], job_best_chain [jobs] (ties: lowest chain),
  *   job_evals [jobs], job_status [jobs] (0 ok, 1 non-finite best energy),
  *   job_t_start, job_t_end [jobs] (device clock, 100 MHz; with
- *   PV_DOCK_TIMESTAMPS). */
+ *   PV_DOCK_TIMESTAMPS), chain_grads [jobs*chains] (the evaluations that
+ *   computed the gradient: a line-search trial above the sufficient-decrease
+ *   bound stops after its energy, since no step reads its gradient). */
 typedef struct {
     float* chain_best_e;
     float* chain_best_dof;
@@ -233,6 +235,7 @@ typedef struct {
     uint64_t* job_t_start;
     uint64_t* job_t_end;
     int32_t dof_stride;
+    int64_t* chain_grads;
 } pv_dock_out;
 
 /* A dock plan: the job table uploaded once and the parameters checked.

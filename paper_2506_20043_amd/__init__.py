@@ -55,7 +55,8 @@ class DockOut(C.Structure):
                 ("chain_evals", C.c_void_p), ("chain_pairs", C.c_void_p),
                 ("job_best_e", C.c_void_p), ("job_best_chain", C.c_void_p),
                 ("job_evals", C.c_void_p), ("job_status", C.c_void_p),
-                ("job_t_start", C.c_void_p), ("job_t_end", C.c_void_p), ("dof_stride", C.c_int32)]
+                ("job_t_start", C.c_void_p), ("job_t_end", C.c_void_p), ("dof_stride", C.c_int32),
+                ("chain_grads", C.c_void_p)]
 
 
 class OutputParams(C.Structure):
@@ -468,6 +469,7 @@ class Plan:
                 chain_best_dof=torch.zeros((nj * ch, stride), dtype=torch.float32, device=dev),
                 chain_evals=torch.empty(nj * ch, dtype=torch.int64, device=dev),
                 chain_pairs=torch.empty(nj * ch, dtype=torch.int64, device=dev),
+                chain_grads=torch.empty(nj * ch, dtype=torch.int64, device=dev),
                 job_best_e=torch.empty(nj, dtype=torch.float32, device=dev),
                 job_best_chain=torch.empty(nj, dtype=torch.int32, device=dev),
                 job_evals=torch.empty(nj, dtype=torch.int64, device=dev),

@@ -764,6 +764,7 @@ static DockArgs dock_args(pv_plan* P, const pv_dock_out* o, float* cbe, int64_t*
     a.chain_best_dof = o->chain_best_dof;
     a.chain_evals = cev;
     a.chain_pairs = o->chain_pairs;
+    a.chain_grads = o->chain_grads;
     a.job_t_start = o->job_t_start;
     a.job_t_end = o->job_t_end;
     a.dof_stride = o->dof_stride;

@@ -139,6 +139,7 @@ struct DockArgs {
     float* chain_best_dof;
     int64_t* chain_evals;
     int64_t* chain_pairs;
+    int64_t* chain_grads;     // evaluations that computed the gradient
     uint64_t* job_t_start;
     uint64_t* job_t_end;
     int32_t dof_stride;

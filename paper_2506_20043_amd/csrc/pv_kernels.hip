@@ -872,6 +872,7 @@ struct BfgsOut {
     float f;
     float g;          // this lane's tangent gradient component at the result
     int evals;
+    int grads;        // evaluations that computed the gradient
     int64_t pairs;    // this lane's share of the intra pairs inside the cutoff
     bool skipped;     // the consistency check ended the run after its first evaluation
 };
@@ -931,6 +932,7 @@ __device__ BfgsOut bfgs(const Topo<A, SL>& T, const BoxView& B, const Lds& S, co
     const bool act = l < nd;
     BfgsOut out;
     out.evals = 0;
+    out.grads = 0;
     out.pairs = 0;
     out.skipped = false;
     float Sh[kMaxM], Yh[kMaxM], rh[kMaxM];
@@ -946,6 +948,7 @@ __device__ BfgsOut bfgs(const Topo<A, SL>& T, const BoxView& B, const Lds& S, co
         const float armijo = initial ? __builtin_inff() : f + P.rho * lam * gd;
         const Eval ev = evaluate(T, B, S, S.pose + (initial ? SLOT_X : SLOT_XT) * kSlot, armijo);
         ++out.evals;
+        out.grads += ev.e > armijo ? 0 : 1;
         out.pairs += ev.pairs_in;
         const float ft = ev.e, gt = act ? ev.g : 0.f;
         bool begin = false;
@@ -1043,7 +1046,7 @@ __device__ BfgsOut bfgs(const Topo<A, SL>& T, const BoxView& B, const Lds& S, co
 // ---------------------------------------------------------------- Monte Carlo
 struct ChainOut {
     float best_e;
-    int64_t evals, pairs;   // pairs: this lane's share
+    int64_t evals, grads, pairs;   // pairs: this lane's share
 };
 
 template <int A, bool SL>
@@ -1119,6 +1122,7 @@ __device__ ChainOut mc_chain(const Topo<A, SL>& T, const BoxView& B, const Lds& 
     const int l = lane_id();
     ChainOut out;
     out.evals = 0;
+    out.grads = 0;
     out.pairs = 0;
     init_pose(T, B, S, SLOT_X, P.seed, job, chain);
     float e_cur = 0.f, e_best = 0.f, um = 0.f;
@@ -1131,6 +1135,7 @@ __device__ ChainOut mc_chain(const Topo<A, SL>& T, const BoxView& B, const Lds& 
         ck.f = e_cur;
         const BfgsOut bo = bfgs(T, B, S, P, iters, mode == 1 && P.consistency, ck);
         out.evals += bo.evals;
+        out.grads += bo.grads;
         out.pairs += bo.pairs;
         bool next = true;
         if (mode == 0) {
@@ -1216,6 +1221,7 @@ __global__ __launch_bounds__(64) void dock_kernel(DockArgs a)
             if (a.chain_best_e) a.chain_best_e[ci] = co.best_e;
             if (a.chain_evals) a.chain_evals[ci] = co.evals;
             if (a.chain_pairs) a.chain_pairs[ci] = pairs;
+            if (a.chain_grads) a.chain_grads[ci] = co.grads;
             if (a.sp.flags & 1u) {
                 const uint64_t t1 = wall_clock64();
                 atomicMin((unsigned long long*)&a.job_t_start[job], (unsigned long long)t0);

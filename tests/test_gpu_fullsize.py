@@ -37,6 +37,10 @@ def _check(oracle, out, jobs, chains, steps, seed, lig_of, grid_of, sample):
     assert np.array_equal(out["job_evals"], cev.sum(axis=1))
     assert np.all(out["job_status"] == 0)
     assert np.all(cev >= 1 + steps)          # one evaluation of the start, then one or more per step
+    # the start and every step's first evaluation compute the gradient; a
+    # line-search trial above the sufficient-decrease bound stops at its energy
+    cgr = out["chain_grads"].reshape(nj, chains)
+    assert np.all(cgr >= 1 + steps) and np.all(cgr <= cev)
     assert np.all(np.isfinite(cbe))
     for j, c in sample:
         L, G = lig_of(int(jobs[j][0])), grid_of(int(jobs[j][1]))

@@ -80,6 +80,7 @@ def test_mc_without_bfgs_replays_oracle(oracle, pv_ctx, c1):
     cbd = res["chain_best_dof"].cpu().numpy()
     cbe = res["chain_best_e"].cpu().numpy()
     ev = res["chain_evals"].cpu().numpy()
+    assert np.array_equal(res["chain_grads"].cpu().numpy(), ev)   # no line search: every evaluation has its gradient
     L, G = c1["ol"], c1["og"]
     same = 0
     for c in range(64):
