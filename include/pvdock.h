@@ -286,7 +286,8 @@ pv_status pv_plan_set_schedule(pv_plan* plan, int32_t group, int32_t variant, in
  * model's schedule comes first) wins.  The choice is remembered by the
  * context, keyed by the class's ligand limits, work items, tune_steps and
  * search settings, and a later call on a plan of the same key takes it
- * without timing (reported with cached = 1).  results: host, up to
+ * without timing (reported with cached = 1); it keeps the latest 256 such
+ * choices.  results: host, up to
  * max_results entries (may be NULL); n_results: how many were written (may
  * be NULL).  Synchronises `stream`; drops a captured graph.  Calls that
  * overlap on one plan race; the context's memory of choices is locked. */

@@ -67,6 +67,8 @@ struct TuneEntry {
     int32_t variant, workgroups;
 };
 
+constexpr size_t kTuneMemory = 256;   // autotuner choices a context remembers
+
 struct pv_ctx {
     int device;
     int n_cu;
@@ -1063,6 +1065,7 @@ pv_status pv_dock_autotune(pv_plan* P, int32_t tune_steps, int32_t repeats, void
         key.variant = G.shape.variant;
         key.workgroups = G.workgroups;
         std::lock_guard<std::mutex> lock(P->ctx->tune_mu);
+        if (P->ctx->tune.size() >= kTuneMemory) P->ctx->tune.erase(P->ctx->tune.begin());   // the oldest goes
         P->ctx->tune.push_back(key);
     }
     return done(PV_OK);
