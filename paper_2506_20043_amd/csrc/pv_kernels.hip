@@ -626,10 +626,13 @@ __device__ __forceinline__ void gather_pair_forces(const Topo<A, SL>& T, const L
         }
         return;
     }
+    // unsigned 32-bit offsets from the table's base let the loads use a
+    // scalar base plus one vector offset
     for (int k = 0; k < T.ell_w; k += 4) {
         uint32_t e[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) e[u] = T.gell[(k + u) * n + i];
+        for (int u = 0; u < 4; ++u)
+            e[u] = *(const uint32_t*)((const char*)T.gell + (uint32_t)(((k + u) * n + i) * 4));
         float c[4];
         float4 xj[4];
 #pragma unroll
