@@ -88,6 +88,8 @@ __device__ __forceinline__ float wscan(float v)
     return v;
 }
 
+// the lane within the wave for the one-wave workgroups of the docking kernels
+// (multi-wave kernels take threadIdx.x & (kWave - 1))
 __device__ __forceinline__ int lane_id() { return threadIdx.x; }
 
 // Synchronisation of a one-wave workgroup.  The LDS executes the requests of
@@ -1560,14 +1562,17 @@ __global__ __launch_bounds__(64) void output_kernel(OutputArgs a)
 // One workgroup per 16x4x4 tile of one box (a wave writes 16-float = 64 B
 // rows).  Receptor atoms near the box are
 // streamed in chunks of 256; those within reach of the tile's bounding box
-// are compacted into LDS and every lane adds their terms to its point's 8
-// accumulators (one per ligand type).
+// are compacted into LDS in the atoms' order (a ballot per wave, the waves'
+// counts in wave order), so every point sums its terms in the same order on
+// every build and the maps are reproducible bit for bit; every lane adds the
+// candidates' terms to its point's 8 accumulators (one per ligand type).
 constexpr int kGridThreads = kTileX * kTileY * kTileZ;  // 256
 
 __global__ __launch_bounds__(256) void gridmap_kernel(GridBuildArgs a)
 {
     __shared__ float4 cand[kGridThreads];
-    __shared__ int n_cand;
+    __shared__ int wave_n[kGridThreads / kWave];
+    const int wv = threadIdx.x / kWave;
     // which box and which tile of it
     const int tile = blockIdx.x;
     int box = 0;
@@ -1594,21 +1599,31 @@ __global__ __launch_bounds__(256) void gridmap_kernel(GridBuildArgs a)
     // element radii C N O S and the receptor-type table
     const float Rel[4] = {1.9f, 1.8f, 1.7f, 2.0f};
     for (int base = abeg; base < aend; base += kGridThreads) {
-        if (threadIdx.x == 0) n_cand = 0;
-        __syncthreads();
         const int ai = base + threadIdx.x;
+        bool keep = false;
+        float4 at = make_float4(0.f, 0.f, 0.f, 0.f);
         if (ai < aend) {
-            const float4 at = a.atoms[ai];
+            at = a.atoms[ai];
             const float ddx = fmaxf(fmaxf(lox - at.x, at.x - hix), 0.f);
             const float ddy = fmaxf(fmaxf(loy - at.y, at.y - hiy), 0.f);
             const float ddz = fmaxf(fmaxf(loz - at.z, at.z - hiz), 0.f);
-            if (ddx * ddx + ddy * ddy + ddz * ddz < reach2) {
-                const int slot = atomicAdd(&n_cand, 1);
-                cand[slot] = at;
-            }
+            keep = ddx * ddx + ddy * ddy + ddz * ddz < reach2;
         }
+        // the barrier that ends each chunk has let every reader of the last
+        // chunk's wave_n and cand pass, so both may be rewritten here
+        const uint64_t m = __ballot(keep);
+        if ((threadIdx.x & (kWave - 1)) == 0) wave_n[wv] = __popcll(m);
         __syncthreads();
-        const int nc = n_cand;
+        int off = 0, nc = 0;
+#pragma unroll
+        for (int q = 0; q < kGridThreads / kWave; ++q) {
+            const int c = wave_n[q];
+            off += q < wv ? c : 0;
+            nc += c;
+        }
+        if (keep)
+            cand[off + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] = at;
+        __syncthreads();
         for (int c = 0; c < nc; ++c) {
             const float4 at = cand[c];
             const float dx = gx - at.x, dy = gy - at.y, dz = gz - at.z;

@@ -56,6 +56,36 @@ def test_five_pockets_sampled(oracle, pv_ctx):
             _assert_maps_close(maps[b][:, k, j, i], ref, "box %d point %s" % (b, (i, j, k)))
 
 
+def test_maps_reproducible_and_docks_repeat(pv_ctx):
+    """Two builds and a rebuild of the five pockets give the same maps bit for
+    bit (the candidate atoms keep their order, so every point sums in the same
+    order), and a dock on either build repeats exactly: the chains are chaotic,
+    so an ulp of difference in a map would move them."""
+    import torch
+
+    import paper_2506_20043_amd as pv
+    cfg = S.CONFIGS["c2"]
+    rx, rt, bxs = S.make_receptor(cfg)
+    g1, m1 = _gpu_maps(pv_ctx, rx, rt, bxs)
+    g2, m2 = _gpu_maps(pv_ctx, rx, rt, bxs)
+    for b in range(len(bxs)):
+        assert np.array_equal(m1[b], m2[b]), b
+    g1.rebuild()
+    torch.cuda.synchronize()
+    for b in range(len(bxs)):
+        assert np.array_equal(g1.maps(b).cpu().numpy(), m1[b]), b
+    ligs = pv.Ligands(pv_ctx, S.make_ligands(cfg))
+    jobs = [(0, b) for b in range(len(bxs))]
+    p = pv.dock_params(chains=64, steps=60, seed=S.philox_seed(cfg), flags=pv.PV_DOCK_GRAPH)
+    outs = []
+    for grids in (g1, g2):
+        plan = pv.Plan(pv_ctx, grids, ligs, jobs, p)
+        outs.append({k: v.cpu().numpy().copy() for k, v in plan.run().items()})
+        plan.close()
+    for k in ("chain_best_e", "chain_evals", "chain_best_dof", "job_best_e"):
+        assert np.array_equal(outs[0][k], outs[1][k]), k
+
+
 def test_ragged_and_degenerate_boxes(oracle, pv_ctx):
     g = np.random.default_rng(1)
     rx, rt = S.receptor(g, 400, 20.0)
