@@ -1120,6 +1120,20 @@ __device__ void mutate(const Topo<A, SL>& T, const Lds& S, int slot, const Searc
     wave_sync();
 }
 
+// Wave priority from the chain's predicted remaining work: its evaluations
+// per step so far times the steps left, per step of the whole run.  Waves
+// that share a SIMD (or a CU's LDS and memory pipes) then serve the chain
+// with the most work left first, which shortens a launch that ends with its
+// longest chain.  Arbitration only: the results do not change.
+__device__ __forceinline__ void chain_priority(int64_t evals, int s, int steps)
+{
+    const float q = (float)evals * (float)(steps - s) / ((float)s * (float)steps);
+    if (q >= 24.f) __builtin_amdgcn_s_setprio(3);
+    else if (q >= 16.f) __builtin_amdgcn_s_setprio(2);
+    else if (q >= 8.f) __builtin_amdgcn_s_setprio(1);
+    else __builtin_amdgcn_s_setprio(0);
+}
+
 template <int A, bool SL>
 __device__ ChainOut mc_chain(const Topo<A, SL>& T, const BoxView& B, const Lds& S, const SearchParams& P, int job,
                              int chain)
@@ -1185,7 +1199,9 @@ __device__ ChainOut mc_chain(const Topo<A, SL>& T, const BoxView& B, const Lds& 
         mutate(T, S, SLOT_X, P, w);
         ++s;
         mode = 1;
+        chain_priority(out.evals, s, P.steps);
     }
+    __builtin_amdgcn_s_setprio(0);
     out.best_e = e_best;
     return out;
 }
