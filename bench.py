@@ -24,6 +24,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32_VECTOR = 157.3e12   # MI355X vector FP32, FLOP/s
 PEAK_HBM = 8.0e12             # MI355X HBM3E, B/s
+MAP_BYTES_PER_ATOM = 32       # 8 trilinear corners x 4 B, per atom and evaluation
 
 # Algorithmic work of one evaluation, counted from the operations the method
 # needs, energy part and gradient part: per intra pair tested (difference,
@@ -182,6 +183,7 @@ def main():
         "gradient_evals_per_step": n_grads,
         "grid_ms": grid_ms,
         "dock_ms": dock_ms,
+        "docks_per_s_without_grid_build": len(jobs) / (dock_ms * 1e-3),
         "workgroups": plan_workgroups(plan),
         "autotune": tuning,
     }
@@ -208,6 +210,12 @@ def main():
         "traffic": recorded_traffic(),
         "flops_per_launch": flops,
         "launch_ms": dock_ms,
+        # the second ceiling: every evaluation reads 8 corners x 4 B per atom
+        # from the maps (L2 / Infinity Cache hits mostly), priced at HBM's peak
+        "map_gather": {"bytes_per_launch": MAP_BYTES_PER_ATOM * n_atoms * n_evals,
+                       "achieved_GBps": MAP_BYTES_PER_ATOM * n_atoms * n_evals / (dock_ms * 1e-3) / 1e9,
+                       "peak_GBps": PEAK_HBM / 1e9,
+                       "frac": MAP_BYTES_PER_ATOM * n_atoms * n_evals / (dock_ms * 1e-3) / PEAK_HBM},
     }
     result["output_stage"] = bench_output(pv, plan, stream)
     if not args.no_extra:
@@ -251,7 +259,8 @@ def plan_workgroups(plan):
 
 def bench_score(pv, S, ctx, stream):
     """score+grad of the differentiation workload: 16,384 poses of 64
-    ligands (40 atoms, 10 torsions) in one 24 A pocket, timed over 20 calls."""
+    ligands (40 atoms, 10 torsions) in one 24 A pocket: 5 runs of 200 calls
+    (1,000 in all), the median run's time per call."""
     import torch
     cfg = S.CONFIGS["c4"]
     rx, rt, bxs = S.make_receptor(cfg)
@@ -266,16 +275,19 @@ def bench_score(pv, S, ctx, stream):
     for _ in range(3):
         pv.score_grad(ctx, grids, ligs, lig, box, dof)
     torch.cuda.synchronize()
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    reps = 20
-    a.record(stream)
-    for _ in range(reps):
-        pv.score_grad(ctx, grids, ligs, lig, box, dof)
-    b.record(stream)
-    torch.cuda.synchronize()
-    ms = a.elapsed_time(b) / reps
+    reps, runs = 200, []
+    for _ in range(5):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            pv.score_grad(ctx, grids, ligs, lig, box, dof)
+        b.record(stream)
+        torch.cuda.synchronize()
+        runs.append(a.elapsed_time(b) / reps)
+    ms = float(np.median(runs))
     return {"workload": "16,384 poses, 64 ligands of 40 atoms / 10 torsions, one 24 A pocket",
-            "ms_per_call": ms, "evals_per_s": cfg.n_poses / (ms * 1e-3)}
+            "ms_per_call": ms, "evals_per_s": cfg.n_poses / (ms * 1e-3), "calls": 5 * reps,
+            "ms_per_call_runs": runs}
 
 
 def bench_consistency(pv, ctx, grids, ligs, jobs, args, seed, stream, evals_off, ms_off, out_off):
@@ -507,10 +519,29 @@ def cpu_baseline(S, cfg, rx, rt, bxs, mols, seed, args):
     dt = time.perf_counter() - t0
     evals = int(res["chain_evals"].sum())
     frac = args.cpu_chains / args.chains
+    # one core: the first 4 chains of the same sample
+    P1 = O.mc_params(4, args.mc_steps, seed)
+    t1 = time.perf_counter()
+    r1 = O.dock([L], [G], [(0, 0)], P1, n_threads=1)
+    d1 = time.perf_counter() - t1
     return {"value": frac / dt, "unit": "docks/s", "cores": threads, "kind": "oracle",
             "sample": "pocket 0, %d of %d chains x %d MC steps (%.3f of one dock), %.1f s wall"
                       % (args.cpu_chains, args.chains, args.mc_steps, frac, dt),
-            "evals_per_s": evals / dt}
+            "evals_per_s": evals / dt, "cpu": cpu_model(),
+            "single_core": {"evals_per_s": int(r1["chain_evals"].sum()) / d1,
+                            "docks_per_s": (4 / args.chains) / d1,
+                            "sample": "pocket 0, 4 chains x %d MC steps, %.1f s" % (args.mc_steps, d1)}}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 if __name__ == "__main__":
