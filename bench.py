@@ -110,7 +110,7 @@ def main():
         print(json.dumps({"leg": args.leg, "result": legs[args.leg]()}), flush=True)
         return
 
-    cfg = S.CONFIGS["c2"]
+    cfg = S.CONFIGS["multi_pocket"]
     rx, rt, bxs = S.make_receptor(cfg)
     mols = S.make_ligands(cfg)
     seed = S.philox_seed(cfg)
@@ -262,7 +262,7 @@ def bench_score(pv, S, ctx, stream):
     ligands (40 atoms, 10 torsions) in one 24 A pocket: 5 runs of 200 calls
     (1,000 in all), the median run's time per call."""
     import torch
-    cfg = S.CONFIGS["c4"]
+    cfg = S.CONFIGS["differentiation"]
     rx, rt, bxs = S.make_receptor(cfg)
     mols = S.make_ligands(cfg)
     grids = pv.build_grids(ctx, rx, rt, bxs[:1], penalty_slope=10.0)
@@ -366,7 +366,7 @@ def bench_batching(pv, S, ctx, stream, args):
     plain form runs the first --plain-jobs jobs one launch each, and the same
     jobs are also run batched."""
     import torch
-    cfg = S.CONFIGS["c3"]
+    cfg = S.CONFIGS["uneven_batch"]
     rx, rt, bxs = S.make_receptor(cfg)
     mols = S.make_ligands(cfg, args.batch_ligands)
     grids = pv.build_grids(ctx, rx, rt, bxs, penalty_slope=10.0)
@@ -411,7 +411,7 @@ def bench_screening(pv, S, ctx, stream, args):
     first --stream-jobs jobs run as one persistent launch with per-job device
     timestamps: service time = last chain done - first chain dequeued."""
     import torch
-    cfg = S.CONFIGS["c5"]
+    cfg = S.CONFIGS["screening"]
     rx, rt, bxs = S.make_receptor(cfg)
     jobs = S.make_jobs(cfg)[:args.stream_jobs]
     uniq, local = np.unique(jobs[:, 0], return_inverse=True)
@@ -454,7 +454,7 @@ def bench_box_sweep(pv, S, ctx, stream, args):
     --sweep-steps MC steps) as one persistent launch.  Reports the grid build
     rate and the mean best energy per box edge."""
     import torch
-    cfg = S.CONFIGS["c2"]
+    cfg = S.CONFIGS["multi_pocket"]
     rx, rt, bxs = S.make_receptor(cfg)
     edges = list(range(15, 31))
     sweep = S.box_sweep(bxs, edges)
@@ -488,7 +488,7 @@ def bench_surface(pv, S, ctx, stream):
     screening receptor (8,000 atoms, 30 directions per atom, 1.6 A probe)
     and their Eq. prank_eq_1 features."""
     import torch
-    rx, rt, _ = S.make_receptor(S.CONFIGS["c5"])
+    rx, rt, _ = S.make_receptor(S.CONFIGS["screening"])
     dirs = S.sphere_directions(30)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -176,13 +176,13 @@ class Config:
 
 
 CONFIGS = {
-    "c1": Config("tiny", 0, 2000, 30.0, 1, (20, 20), True, 1, (20, 20), (4, 4), 8, 200),
-    "c2": Config("multi-pocket", 1, 5000, 50.0, 5, (24, 24), False, 1, (35, 35), (8, 8), 256, 1000),
-    "c3": Config("batched-uneven", 2, 5000, 50.0, 5, (24, 24), False, 4096, (10, 60), (0, 15), 32, 500,
+    "tiny": Config("tiny", 0, 2000, 30.0, 1, (20, 20), True, 1, (20, 20), (4, 4), 8, 200),
+    "multi_pocket": Config("multi-pocket", 1, 5000, 50.0, 5, (24, 24), False, 1, (35, 35), (8, 8), 256, 1000),
+    "uneven_batch": Config("batched-uneven", 2, 5000, 50.0, 5, (24, 24), False, 4096, (10, 60), (0, 15), 32, 500,
                  shared_from=1),
-    "c4": Config("differentiation", 3, 5000, 50.0, 1, (24, 24), False, 64, (40, 40), (10, 10), 0, 0,
+    "differentiation": Config("differentiation", 3, 5000, 50.0, 1, (24, 24), False, 64, (40, 40), (10, 10), 0, 0,
                  n_poses=16384, shared_from=1),
-    "c5": Config("screening", 4, 8000, 60.0, 16, (20, 30), False, 6250, (8, 80), (0, 20), 16, 300),
+    "screening": Config("screening", 4, 8000, 60.0, 16, (20, 30), False, 6250, (8, 80), (0, 20), 16, 300),
 }
 
 
@@ -212,7 +212,7 @@ def make_ligands(cfg: Config, count: int | None = None, first: int = 0):
 
 
 def make_jobs(cfg: Config):
-    """(ligand, box) pairs.  c5: every ligand in every box, seeded random order."""
+    """(ligand, box) pairs.  Screening: every ligand in every box, seeded random order."""
     pairs = np.array([(l, b) for l in range(cfg.n_ligands) for b in range(cfg.n_boxes)],
                      np.int32).reshape(-1, 2)
     if cfg.name == "screening":

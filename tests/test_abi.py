@@ -93,10 +93,10 @@ def _check_same_model(oracle, m):
     assert len(set(pairs_map.values())) == L.n_frag
 
 
-@pytest.mark.parametrize("cfg", ["c1", "c2", "c3", "c4", "c5"])
+@pytest.mark.parametrize("cfg", ["tiny", "multi_pocket", "uneven_batch", "differentiation", "screening"])
 def test_ligand_model_matches_oracle(oracle, cfg):
     c = S.CONFIGS[cfg]
-    n = {"c1": 1, "c2": 1, "c3": 40, "c4": 8, "c5": 40}[cfg]
+    n = {"tiny": 1, "multi_pocket": 1, "uneven_batch": 40, "differentiation": 8, "screening": 40}[cfg]
     for m in S.make_ligands(c, count=n):
         _check_same_model(oracle, m)
 

@@ -77,7 +77,7 @@ class _Cache:
 def test_multipocket_dock_full_size(oracle):
     import paper_2506_20043_amd as pv
     from test_gpu_search import _oparams
-    cfg = S.CONFIGS["c2"]
+    cfg = S.CONFIGS["multi_pocket"]
     rx, rt, bxs = S.make_receptor(cfg)
     mols = S.make_ligands(cfg)
     seed = S.philox_seed(cfg)
@@ -107,7 +107,7 @@ def test_uneven_batch_full_size(oracle):
     """The benchmark's uneven batch: the first 256 ligands x 5 pockets (1,280
     jobs, 40,960 chains of 32 x 500 steps) in one persistent graph launch."""
     import paper_2506_20043_amd as pv
-    cfg = S.CONFIGS["c3"]
+    cfg = S.CONFIGS["uneven_batch"]
     rx, rt, bxs = S.make_receptor(cfg)
     mols = S.make_ligands(cfg, 256)
     seed = S.philox_seed(cfg)
@@ -132,7 +132,7 @@ def test_screening_stream_full_size(oracle):
     order over 16 pockets of 20..30 A, ligands of 8..80 atoms (both size
     classes), one persistent graph launch per class with device timestamps."""
     import paper_2506_20043_amd as pv
-    cfg = S.CONFIGS["c5"]
+    cfg = S.CONFIGS["screening"]
     rx, rt, bxs = S.make_receptor(cfg)
     jobs = S.make_jobs(cfg)[:2048]
     uniq, local = np.unique(jobs[:, 0], return_inverse=True)

@@ -30,7 +30,7 @@ def _assert_maps_close(gpu, ref, what):
 
 
 def test_tiny_config_every_value(oracle, pv_ctx):
-    cfg = S.CONFIGS["c1"]
+    cfg = S.CONFIGS["tiny"]
     rx, rt, bxs = S.make_receptor(cfg)
     grids, maps = _gpu_maps(pv_ctx, rx, rt, bxs)
     dims, org = grids.info(0)
@@ -39,11 +39,11 @@ def test_tiny_config_every_value(oracle, pv_ctx):
     np.testing.assert_array_equal(org, oorg)
     ref = oracle.build_maps(rx, rt, dims, org, bxs[0].spacing)
     assert maps[0].shape == ref.shape == (8, 55, 55, 55)
-    _assert_maps_close(maps[0], ref, "c1")
+    _assert_maps_close(maps[0], ref, "tiny")
 
 
 def test_five_pockets_sampled(oracle, pv_ctx):
-    cfg = S.CONFIGS["c2"]
+    cfg = S.CONFIGS["multi_pocket"]
     rx, rt, bxs = S.make_receptor(cfg)
     grids, maps = _gpu_maps(pv_ctx, rx, rt, bxs)
     g = np.random.default_rng(0)
@@ -64,7 +64,7 @@ def test_maps_reproducible_and_docks_repeat(pv_ctx):
     import torch
 
     import paper_2506_20043_amd as pv
-    cfg = S.CONFIGS["c2"]
+    cfg = S.CONFIGS["multi_pocket"]
     rx, rt, bxs = S.make_receptor(cfg)
     g1, m1 = _gpu_maps(pv_ctx, rx, rt, bxs)
     g2, m2 = _gpu_maps(pv_ctx, rx, rt, bxs)
@@ -131,7 +131,7 @@ def test_box_size_sweep_sampled(oracle, pv_ctx):
     the multi-pocket receptor) in one build: each box has n = ceil(s/h) + 1
     points per axis and matches the oracle at its corners and at sampled
     points."""
-    cfg = S.CONFIGS["c2"]
+    cfg = S.CONFIGS["multi_pocket"]
     rx, rt, bxs = S.make_receptor(cfg)
     sweep = S.box_sweep(bxs[:2])
     assert len(sweep) == 32

@@ -57,7 +57,7 @@ def _compare(oracle, L, G, res, dof, e, j, chains, modes, refine, cut=1.0):
 
 def test_output_matches_oracle_without_refinement(oracle, pv_ctx):
     import paper_2506_20043_amd as pv
-    cfg = S.CONFIGS["c1"]
+    cfg = S.CONFIGS["tiny"]
     rx, rt, bxs = S.make_receptor(cfg)
     mols = S.make_ligands(cfg)
     grids, ligs, G = _setup(oracle, pv_ctx, rx, rt, bxs[0], mols)
@@ -128,7 +128,7 @@ def test_output_of_a_dock_is_valid(oracle, pv_ctx):
     cut, each re-scored by the oracle to its energy and affinity, never
     above its source chain's energy, unit quaternions."""
     import paper_2506_20043_amd as pv
-    cfg = S.CONFIGS["c1"]
+    cfg = S.CONFIGS["tiny"]
     rx, rt, bxs = S.make_receptor(cfg)
     mols = S.make_ligands(cfg)
     grids, ligs, G = _setup(oracle, pv_ctx, rx, rt, bxs[0], mols)
@@ -164,7 +164,7 @@ def test_output_of_a_dock_is_valid(oracle, pv_ctx):
 
 def test_output_rejects(pv_ctx):
     import paper_2506_20043_amd as pv
-    cfg = S.CONFIGS["c1"]
+    cfg = S.CONFIGS["tiny"]
     rx, rt, bxs = S.make_receptor(cfg)
     grids = pv.build_grids(pv_ctx, rx, rt, bxs, penalty_slope=KAPPA)
     ligs = pv.Ligands(pv_ctx, S.make_ligands(cfg))

@@ -46,7 +46,7 @@ def test_small_receptor_every_point(oracle, pv_ctx):
 def test_multi_pocket_receptor_full_size(oracle, pv_ctx):
     """The 5,000-atom receptor of the multi-pocket workload, 30 directions:
     every point, features at 3,000 sampled points."""
-    rx, rt, _ = S.make_receptor(S.CONFIGS["c2"])
+    rx, rt, _ = S.make_receptor(S.CONFIGS["multi_pocket"])
     _check(oracle, pv_ctx, rx, rt, S.sphere_directions(30), sample=3000)
 
 

@@ -24,7 +24,7 @@ def setup(oracle, pv_ctx):
     """The multi-pocket receptor's first pocket with a 30-atom and an
     80-atom ligand (two size classes)."""
     import paper_2506_20043_amd as pv
-    cfg = S.CONFIGS["c2"]
+    cfg = S.CONFIGS["multi_pocket"]
     rx, rt, bxs = S.make_receptor(cfg)
     g = np.random.default_rng(41)
     mols = [S.tree_ligand(g, 30, 6), S.tree_ligand(g, 80, 10)]

@@ -66,7 +66,7 @@ def compare(st, lig, box, dof, out, idx, max_excused=0.05):
 
 def test_tiny_config_poses(oracle, pv_ctx):
     import paper_2506_20043_amd as pv
-    cfg = S.CONFIGS["c1"]
+    cfg = S.CONFIGS["tiny"]
     rx, rt, bxs = S.make_receptor(cfg)
     mols = S.make_ligands(cfg)
     st = Setup(oracle, pv_ctx, rx, rt, bxs, mols)
@@ -83,7 +83,7 @@ def test_differentiation_workload_full_size(oracle, pv_ctx):
     """16,384 poses of 64 ligands (40 atoms, 10 torsions) in one 24 A pocket,
     the launch the benchmark times; the oracle checks a sample."""
     import paper_2506_20043_amd as pv
-    cfg = S.CONFIGS["c4"]
+    cfg = S.CONFIGS["differentiation"]
     rx, rt, bxs = S.make_receptor(cfg)
     mols = S.make_ligands(cfg)
     st = Setup(oracle, pv_ctx, rx, rt, bxs[:1], mols)
@@ -143,9 +143,9 @@ def test_invalid_rows_and_empty_batch(oracle, pv_ctx):
 
 def test_score_on_coordinates(oracle, pv_ctx):
     import paper_2506_20043_amd as pv
-    cfg = S.CONFIGS["c1"]
+    cfg = S.CONFIGS["tiny"]
     rx, rt, bxs = S.make_receptor(cfg)
-    mols = S.make_ligands(S.CONFIGS["c3"], count=6)
+    mols = S.make_ligands(S.CONFIGS["uneven_batch"], count=6)
     st = Setup(oracle, pv_ctx, rx, rt, bxs, mols)
     g = np.random.default_rng(4)
     lo, hi = st.lohi(0)
@@ -178,7 +178,7 @@ def test_autograd_backward(oracle, pv_ctx):
     import torch
 
     import paper_2506_20043_amd as pv
-    cfg = S.CONFIGS["c1"]
+    cfg = S.CONFIGS["tiny"]
     rx, rt, bxs = S.make_receptor(cfg)
     mols = S.make_ligands(cfg)
     st = Setup(oracle, pv_ctx, rx, rt, bxs, mols)

@@ -21,9 +21,9 @@ def pv_ctx():
 
 
 @pytest.fixture(scope="module")
-def c1(oracle, pv_ctx):
+def tiny(oracle, pv_ctx):
     import paper_2506_20043_amd as pv
-    cfg = S.CONFIGS["c1"]
+    cfg = S.CONFIGS["tiny"]
     rx, rt, bxs = S.make_receptor(cfg)
     mols = S.make_ligands(cfg)
     b = bxs[0]
@@ -48,16 +48,16 @@ def _oparams(oracle, p):
                             consistency=bool(p.consistency))
 
 
-def test_initial_poses_match_oracle_draws(oracle, pv_ctx, c1):
+def test_initial_poses_match_oracle_draws(oracle, pv_ctx, tiny):
     """steps = 0: each chain's best is its Philox-drawn initial pose."""
     import paper_2506_20043_amd as pv
-    p = _params(pv, chains=64, steps=0, seed=c1["seed"])
-    res = pv.dock(pv_ctx, c1["grids"], c1["ligs"], [(0, 0), (0, 0)], p)
+    p = _params(pv, chains=64, steps=0, seed=tiny["seed"])
+    res = pv.dock(pv_ctx, tiny["grids"], tiny["ligs"], [(0, 0), (0, 0)], p)
     cbd = res["chain_best_dof"].cpu().numpy().reshape(2, 64, -1)
     cbe = res["chain_best_e"].cpu().numpy().reshape(2, 64)
     ev = res["chain_evals"].cpu().numpy()
     assert np.all(ev == 1)
-    L, G = c1["ol"], c1["og"]
+    L, G = tiny["ol"], tiny["og"]
     for j in range(2):
         for c in range(64):
             ref = oracle.init_pose(L, G, p.seed, j, c)
@@ -69,19 +69,19 @@ def test_initial_poses_match_oracle_draws(oracle, pv_ctx, c1):
     assert not np.allclose(cbd[0], cbd[1])
 
 
-def test_mc_without_bfgs_replays_oracle(oracle, pv_ctx, c1):
+def test_mc_without_bfgs_replays_oracle(oracle, pv_ctx, tiny):
     """With no BFGS iterations the chain is mutate + Metropolis only: the same
     Philox draws give the same trajectory, so the best pose and energy match
     the oracle's unless a Metropolis test lands within rounding of its
     threshold (rare)."""
     import paper_2506_20043_amd as pv
-    p = _params(pv, chains=64, steps=40, seed=c1["seed"] + 1, bfgs_max_iter=0, refine_max_iter=0)
-    res = pv.dock(pv_ctx, c1["grids"], c1["ligs"], [(0, 0)], p)
+    p = _params(pv, chains=64, steps=40, seed=tiny["seed"] + 1, bfgs_max_iter=0, refine_max_iter=0)
+    res = pv.dock(pv_ctx, tiny["grids"], tiny["ligs"], [(0, 0)], p)
     cbd = res["chain_best_dof"].cpu().numpy()
     cbe = res["chain_best_e"].cpu().numpy()
     ev = res["chain_evals"].cpu().numpy()
     assert np.array_equal(res["chain_grads"].cpu().numpy(), ev)   # no line search: every evaluation has its gradient
-    L, G = c1["ol"], c1["og"]
+    L, G = tiny["ol"], tiny["og"]
     same = 0
     for c in range(64):
         d, e, ne = oracle.mc_chain(L, G, _oparams(oracle, p), 0, c)
@@ -127,14 +127,14 @@ def test_local_opt_matches_oracle_on_smooth_objective(oracle, pv_ctx):
     assert agree >= 20, agree
 
 
-def test_local_opt_decreases_and_is_valid(oracle, pv_ctx, c1):
+def test_local_opt_decreases_and_is_valid(oracle, pv_ctx, tiny):
     import paper_2506_20043_amd as pv
-    L, G = c1["ol"], c1["og"]
+    L, G = tiny["ol"], tiny["og"]
     g = np.random.default_rng(7)
     lo, hi = G.origin.astype(np.float64), G.origin + G.h * (G.dims - 1)
     B = 128
     dof = S.poses(g, B, lo + 2, hi - 2, L.n_tors)
-    out, e, ne = pv.local_opt(pv_ctx, c1["grids"], c1["ligs"], np.zeros(B), np.zeros(B), dof, _params(pv))
+    out, e, ne = pv.local_opt(pv_ctx, tiny["grids"], tiny["ligs"], np.zeros(B), np.zeros(B), dof, _params(pv))
     out, e, ne = out.cpu().numpy(), e.cpu().numpy(), ne.cpu().numpy()
     assert np.all(ne >= 1) and np.all(np.abs(np.linalg.norm(out[:, 3:7], axis=1) - 1) < 1e-5)
     fo = np.zeros(B)
@@ -151,17 +151,17 @@ def test_local_opt_decreases_and_is_valid(oracle, pv_ctx, c1):
     assert ks.pvalue > 0.01, (ks, np.median(e), np.median(fo))
 
 
-def test_dock_valid_and_statistically_like_oracle(oracle, pv_ctx, c1):
+def test_dock_valid_and_statistically_like_oracle(oracle, pv_ctx, tiny):
     """Full MC + BFGS on the tiny configuration with 64 chains: every GPU
     chain best re-scores to its reported energy under the oracle, never
     exceeds its initial energy, and the distribution of chain bests matches
     the oracle's run on the same Philox streams."""
     import paper_2506_20043_amd as pv
-    p = _params(pv, chains=64, steps=200, seed=c1["seed"])
-    res = pv.dock(pv_ctx, c1["grids"], c1["ligs"], [(0, 0)], p)
+    p = _params(pv, chains=64, steps=200, seed=tiny["seed"])
+    res = pv.dock(pv_ctx, tiny["grids"], tiny["ligs"], [(0, 0)], p)
     cbd = res["chain_best_dof"].cpu().numpy()
     cbe = res["chain_best_e"].cpu().numpy()
-    L, G = c1["ol"], c1["og"]
+    L, G = tiny["ol"], tiny["og"]
     for c in range(64):
         r = L.score_grad(G, cpu_dof(cbd[c, :L.ndof]))
         assert abs(r["e"] - cbe[c]) <= e_tol(r["e"]) + 0.01, (c, cbe[c], r["e"])
@@ -174,20 +174,20 @@ def test_dock_valid_and_statistically_like_oracle(oracle, pv_ctx, c1):
     assert res["job_best_chain"].cpu().numpy()[0] == int(np.argmin(cbe))
 
 
-def test_batched_plain_graph_agree(pv_ctx, c1):
+def test_batched_plain_graph_agree(pv_ctx, tiny):
     import torch
 
     import paper_2506_20043_amd as pv
     jobs = [(0, 0)] * 6
-    p = _params(pv, chains=16, steps=30, seed=c1["seed"] + 7)
-    plan = pv.Plan(pv_ctx, c1["grids"], c1["ligs"], jobs, p)
+    p = _params(pv, chains=16, steps=30, seed=tiny["seed"] + 7)
+    plan = pv.Plan(pv_ctx, tiny["grids"], tiny["ligs"], jobs, p)
     a = {k: v.clone() for k, v in plan.run().items()}
     b = {k: v.clone() for k, v in plan.run(plain=True).items()}
     torch.cuda.synchronize()
     for k in ("chain_best_e", "chain_best_dof", "chain_evals", "job_best_e"):
         assert torch.equal(a[k], b[k]), k
-    gp = _params(pv, chains=16, steps=30, seed=c1["seed"] + 7, flags=pv.PV_DOCK_GRAPH | pv.PV_DOCK_TIMESTAMPS)
-    gplan = pv.Plan(pv_ctx, c1["grids"], c1["ligs"], jobs, gp)
+    gp = _params(pv, chains=16, steps=30, seed=tiny["seed"] + 7, flags=pv.PV_DOCK_GRAPH | pv.PV_DOCK_TIMESTAMPS)
+    gplan = pv.Plan(pv_ctx, tiny["grids"], tiny["ligs"], jobs, gp)
     for rep in range(3):
         out = gplan.run()
         torch.cuda.synchronize()
@@ -200,40 +200,40 @@ def test_batched_plain_graph_agree(pv_ctx, c1):
     gplan.close()
 
 
-def test_dock_rejects(pv_ctx, c1):
+def test_dock_rejects(pv_ctx, tiny):
     import paper_2506_20043_amd as pv
     with pytest.raises(pv.PvError, match="ligand"):
-        pv.Plan(pv_ctx, c1["grids"], c1["ligs"], [(1, 0)], _params(pv))
+        pv.Plan(pv_ctx, tiny["grids"], tiny["ligs"], [(1, 0)], _params(pv))
     with pytest.raises(pv.PvError, match="box"):
-        pv.Plan(pv_ctx, c1["grids"], c1["ligs"], [(0, 3)], _params(pv))
+        pv.Plan(pv_ctx, tiny["grids"], tiny["ligs"], [(0, 3)], _params(pv))
     with pytest.raises(pv.PvError, match="chains"):
-        pv.Plan(pv_ctx, c1["grids"], c1["ligs"], [(0, 0)], _params(pv, chains=0))
+        pv.Plan(pv_ctx, tiny["grids"], tiny["ligs"], [(0, 0)], _params(pv, chains=0))
     with pytest.raises(pv.PvError, match="ls_rho"):
-        pv.Plan(pv_ctx, c1["grids"], c1["ligs"], [(0, 0)], _params(pv, ls_rho=0.5, ls_sigma=0.1))
+        pv.Plan(pv_ctx, tiny["grids"], tiny["ligs"], [(0, 0)], _params(pv, ls_rho=0.5, ls_sigma=0.1))
 
 
-def test_dock_edge_cases(oracle, pv_ctx, c1):
+def test_dock_edge_cases(oracle, pv_ctx, tiny):
     """No jobs; one chain of zero steps (the initial pose); a persistent
     launch of only 3 workgroups pulling 96 items reproduces the default
     launch chain by chain; the output stage refuses more than 4,096 chains."""
     import paper_2506_20043_amd as pv
-    empty = pv.Plan(pv_ctx, c1["grids"], c1["ligs"], [], _params(pv, flags=pv.PV_DOCK_GRAPH))
+    empty = pv.Plan(pv_ctx, tiny["grids"], tiny["ligs"], [], _params(pv, flags=pv.PV_DOCK_GRAPH))
     empty.run()
     empty.run(plain=True)
     empty.close()
-    one = pv.dock(pv_ctx, c1["grids"], c1["ligs"], [(0, 0)], _params(pv, chains=1, steps=0, seed=5))
-    L, G = c1["ol"], c1["og"]
+    one = pv.dock(pv_ctx, tiny["grids"], tiny["ligs"], [(0, 0)], _params(pv, chains=1, steps=0, seed=5))
+    L, G = tiny["ol"], tiny["og"]
     ref = L.score_grad(G, oracle.init_pose(L, G, 5, 0, 0))["e"]
     assert abs(one["chain_best_e"].item() - ref) <= e_tol(ref) + 0.01
     assert one["chain_evals"].item() == 1
     jobs = [(0, 0)] * 6
-    base = pv.dock(pv_ctx, c1["grids"], c1["ligs"], jobs, _params(pv, chains=16, steps=15, seed=9))
-    few = pv.dock(pv_ctx, c1["grids"], c1["ligs"], jobs, _params(pv, chains=16, steps=15, seed=9, workgroups=3))
+    base = pv.dock(pv_ctx, tiny["grids"], tiny["ligs"], jobs, _params(pv, chains=16, steps=15, seed=9))
+    few = pv.dock(pv_ctx, tiny["grids"], tiny["ligs"], jobs, _params(pv, chains=16, steps=15, seed=9, workgroups=3))
     for k in ("chain_best_e", "chain_evals", "chain_best_dof"):
         assert np.array_equal(base[k].cpu().numpy(), few[k].cpu().numpy()), k
-    big = pv.Plan(pv_ctx, c1["grids"], c1["ligs"], [(0, 0)], _params(pv, chains=4097, steps=0))
+    big = pv.Plan(pv_ctx, tiny["grids"], tiny["ligs"], [(0, 0)], _params(pv, chains=4097, steps=0))
     e = np.zeros(4097, np.float32)
-    d = np.zeros((4097, c1["ligs"].dof_stride), np.float32)
+    d = np.zeros((4097, tiny["ligs"].dof_stride), np.float32)
     with pytest.raises(pv.PvError, match="4096"):
         pv.output_stage(big, e, d)
     big.close()

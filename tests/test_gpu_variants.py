@@ -23,7 +23,7 @@ def pv_ctx():
 def big(oracle, pv_ctx):
     """Two ligands near the one-atom-per-lane limit in a 24 A pocket of the
     multi-pocket receptor: their force slots take ~60 KB of LDS."""
-    cfg = S.CONFIGS["c2"]
+    cfg = S.CONFIGS["multi_pocket"]
     rx, rt, bxs = S.make_receptor(cfg)
     g = np.random.default_rng(77)
     mols = [S.tree_ligand(g, 60, 12), S.tree_ligand(g, 58, 9)]
@@ -51,7 +51,7 @@ def test_variant_selection(pv_ctx, big):
     huge = pv.Ligands(pv_ctx, [S.tree_ligand(g, 100, 20)])
     assert pv.launch_info(pv_ctx, huge, pv.KIND_SCORE, 16)[0] == pv.VARIANT_GATHER2
     # the multi-pocket dock (5 pockets x 256 chains of a 35-atom ligand) keeps the slots
-    cfg = S.CONFIGS["c2"]
+    cfg = S.CONFIGS["multi_pocket"]
     lc2 = pv.Ligands(pv_ctx, S.make_ligands(cfg))
     assert pv.launch_info(pv_ctx, lc2, pv.KIND_DOCK, 5 * 256)[0] == pv.VARIANT_SLOTS
     with pytest.raises(pv.PvError):
@@ -178,7 +178,7 @@ def test_slot_records_at_pass_boundaries(oracle, pv_ctx):
     point right after the last atom) score like the oracle in the slot
     variant, and like the gather variant of a large launch."""
     import paper_2506_20043_amd as pv
-    cfg = S.CONFIGS["c2"]
+    cfg = S.CONFIGS["multi_pocket"]
     rx, rt, bxs = S.make_receptor(cfg)
     g = np.random.default_rng(31)
     mols = [S.tree_ligand(g, 12, 0)] + [_seeded_ligand(s) for s in (241, 37, 705, 452)]

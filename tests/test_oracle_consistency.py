@@ -96,7 +96,7 @@ def test_steepest_descent_neighbour_is_explained(oracle):
     """On the tiny configuration's landscape, a point a tiny step down (or
     up) the gradient of y stays on y's slope in every coordinate, so the
     check fails; moving one coordinate the other way makes it pass."""
-    cfg = S.CONFIGS["c1"]
+    cfg = S.CONFIGS["tiny"]
     rx, rt, bxs = S.make_receptor(cfg)
     m = S.make_ligands(cfg)[0]
     b = bxs[0]
@@ -133,7 +133,7 @@ def test_steepest_descent_neighbour_is_explained(oracle):
 def test_chain_with_the_check(oracle):
     """With the check the chain still returns a best that re-scores to its
     energy, and steps it skips cost one evaluation, so the count falls."""
-    cfg = S.CONFIGS["c1"]
+    cfg = S.CONFIGS["tiny"]
     rx, rt, bxs = S.make_receptor(cfg)
     m = S.make_ligands(cfg)[0]
     b = bxs[0]

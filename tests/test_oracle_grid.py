@@ -190,7 +190,7 @@ def test_grid_converges_to_pairwise_h2(oracle):
 
 def test_grid_score_translation_invariance(oracle):
     """Shifting receptor, ligand and box together leaves the grid score unchanged."""
-    cfg = S.CONFIGS["c1"]
+    cfg = S.CONFIGS["tiny"]
     rx, rt = _small_receptor(9, 600, 20.0)
     # coordinates on a 2^-10 grid, so the shifted receptor is exactly representable
     rx = (np.round(rx.astype(np.float64) * 1024) / 1024).astype(np.float32)

@@ -172,7 +172,7 @@ def test_intra_invariant_under_root_motion(oracle):
 
 
 def _c1_grid(oracle):
-    cfg = S.CONFIGS["c1"]
+    cfg = S.CONFIGS["tiny"]
     rx, rt, bxs = S.make_receptor(cfg)
     b = bxs[0]
     return oracle.Grid.build(rx, rt, b.center, b.size, b.spacing)

@@ -16,8 +16,8 @@ KAPPA = 10.0
 
 
 @pytest.fixture(scope="module")
-def c1(oracle):
-    cfg = S.CONFIGS["c1"]
+def tiny(oracle):
+    cfg = S.CONFIGS["tiny"]
     rx, rt, bxs = S.make_receptor(cfg)
     m = S.make_ligands(cfg)[0]
     b = bxs[0]
@@ -70,8 +70,8 @@ def cluster_set(L, G, g, n_centres, sizes, sep=2.5, spread=0.03, margin=2.0):
     return dof, lab, e
 
 
-def test_clusters_by_construction(oracle, c1):
-    L, G = c1
+def test_clusters_by_construction(oracle, tiny):
+    L, G = tiny
     g = np.random.default_rng(31)
     sizes = [1, 3, 5, 2, 4, 1, 6, 2, 3, 2]
     dof, lab, e = cluster_set(L, G, g, 10, sizes)
@@ -106,8 +106,8 @@ def test_clusters_by_construction(oracle, c1):
     assert sorted(r["chain"]) == sorted(best.values())
 
 
-def test_zero_cut_is_a_plain_sort(oracle, c1):
-    L, G = c1
+def test_zero_cut_is_a_plain_sort(oracle, tiny):
+    L, G = tiny
     g = np.random.default_rng(5)
     lo, hi = G.origin.astype(np.float64), G.origin + G.h * (G.dims - 1)
     dof = S.poses(g, 40, lo, hi, L.n_tors)
@@ -119,8 +119,8 @@ def test_zero_cut_is_a_plain_sort(oracle, c1):
     assert list(r["chain"]) == expect
 
 
-def test_nan_energies_sort_last(oracle, c1):
-    L, G = c1
+def test_nan_energies_sort_last(oracle, tiny):
+    L, G = tiny
     g = np.random.default_rng(6)
     lo, hi = G.origin.astype(np.float64), G.origin + G.h * (G.dims - 1)
     dof = S.poses(g, 6, lo, hi, L.n_tors)
@@ -129,8 +129,8 @@ def test_nan_energies_sort_last(oracle, c1):
     assert sorted(r["chain"]) == [1, 3, 4, 5]
 
 
-def test_refinement_descends_and_separates(oracle, c1):
-    L, G = c1
+def test_refinement_descends_and_separates(oracle, tiny):
+    L, G = tiny
     g = np.random.default_rng(9)
     lo, hi = G.origin.astype(np.float64), G.origin + G.h * (G.dims - 1)
     dof = S.poses(g, 24, lo, hi, L.n_tors)
@@ -148,8 +148,8 @@ def test_refinement_descends_and_separates(oracle, c1):
     assert len(set(r["chain"])) == n
 
 
-def test_rigid_ligand_affinity_is_inter_energy(oracle, c1):
-    _, G = c1
+def test_rigid_ligand_affinity_is_inter_energy(oracle, tiny):
+    _, G = tiny
     g = np.random.default_rng(4)
     m = S.tree_ligand(g, 10, 0)
     L = oracle.Ligand(m.xyz, m.types, m.bonds, m.rotatable)
@@ -161,8 +161,8 @@ def test_rigid_ligand_affinity_is_inter_energy(oracle, c1):
         assert r["affinity"][o] == L.score_grad(G, r["dof"][o])["e_inter"]
 
 
-def test_degenerate_inputs(oracle, c1):
-    L, G = c1
+def test_degenerate_inputs(oracle, tiny):
+    L, G = tiny
     r = oracle.output_stage(L, G, np.zeros((0, L.ndof)), np.zeros(0), modes=5)
     assert len(r["chain"]) == 0
     g = np.random.default_rng(2)
