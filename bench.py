@@ -362,7 +362,8 @@ def bench_batching(pv, S, ctx, stream, args):
     """Batched vs plain on the uneven batch: ligands of 10..60 atoms and
     0..15 torsions, each docked into the 5 pockets of the multi-pocket
     receptor, 32 chains x 500 MC steps per job.  The batched form runs the
-    first --batch-ligands x 5 jobs as one persistent hipGraph launch; the
+    first --batch-ligands x 5 jobs as one persistent hipGraph launch, handing
+    out the most costly ligands' chains first (PV_DOCK_LARGEST_FIRST); the
     plain form runs the first --plain-jobs jobs one launch each, and the same
     jobs are also run batched."""
     import torch
@@ -372,7 +373,8 @@ def bench_batching(pv, S, ctx, stream, args):
     grids = pv.build_grids(ctx, rx, rt, bxs, penalty_slope=10.0)
     ligs = pv.Ligands(ctx, mols)
     jobs = S.make_jobs(cfg)[:args.batch_ligands * len(bxs)]
-    params = pv.dock_params(chains=cfg.chains, steps=cfg.steps, seed=S.philox_seed(cfg), flags=pv.PV_DOCK_GRAPH)
+    params = pv.dock_params(chains=cfg.chains, steps=cfg.steps, seed=S.philox_seed(cfg),
+                            flags=pv.PV_DOCK_GRAPH | pv.PV_DOCK_LARGEST_FIRST)
     plan = pv.Plan(ctx, grids, ligs, jobs, params)
     tuning = tune(plan, stream, steps=10)
     plan.run()

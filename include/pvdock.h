@@ -205,6 +205,13 @@ typedef struct {
 
 #define PV_DOCK_TIMESTAMPS 1u /* write per-job device timestamps */
 #define PV_DOCK_GRAPH 2u      /* pv_dock_run captures its launches in a hipGraph once and replays it */
+/* hand out each size class's jobs most costly ligand first (an evaluation's
+ * energy work: 8 x pairs + 48 x atoms + 109 x torsions; ties keep the job
+ * order), so that short chains fill the end of the launch.  Only the order in
+ * which chains start changes: every chain's result depends on (seed, job,
+ * chain) alone, so the outputs are identical bit for bit.  Other flag bits are
+ * rejected (PV_E_INVALID). */
+#define PV_DOCK_LARGEST_FIRST 4u
 
 /* fills the defaults: 30 BFGS iterations, m = 5, 10 trials, rho 1e-4,
  * sigma 0.1, eps_grad 1e-3, eps_curv 1e-6, temperature 1.2, amplitudes 2 A */

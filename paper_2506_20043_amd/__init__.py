@@ -26,6 +26,7 @@ _lib = None
 
 PV_DOCK_TIMESTAMPS = 1
 PV_DOCK_GRAPH = 2
+PV_DOCK_LARGEST_FIRST = 4
 MAX_ATOMS, MAX_TORS = 128, 32
 
 

@@ -679,6 +679,8 @@ pv_status pv_dock_plan(pv_ctx* ctx, const pv_grids* grids, const pv_ligands* lig
     pv_status st = check_pair(ctx, grids, ligs);
     if (st != PV_OK) return st;
     if ((st = check_search(params, true)) != PV_OK) return st;
+    if (params->flags & ~(PV_DOCK_TIMESTAMPS | PV_DOCK_GRAPH | PV_DOCK_LARGEST_FIRST))
+        return fail(PV_E_INVALID, "unknown dock flag");
     if (n_jobs < 0) return fail(PV_E_INVALID, "n_jobs < 0");
     if (n_jobs > 0 && !jobs) return fail(PV_E_INVALID, "jobs is NULL");
     if ((int64_t)n_jobs * params->chains > (int64_t)INT32_MAX) return fail(PV_E_RANGE, "jobs * chains too large");
@@ -709,6 +711,17 @@ pv_status pv_dock_plan(pv_ctx* ctx, const pv_grids* grids, const pv_ligands* lig
     std::vector<int32_t> members[2];
     P->job_group.assign(n_jobs, 0);
     for (int32_t j = 0; j < n_jobs; ++j) members[(*ligs->info)[hj[j].x][0] > 64 ? 1 : 0].push_back(j);
+    if (params->flags & PV_DOCK_LARGEST_FIRST) {
+        // the queue hands out the jobs of a class in job-map order: the most
+        // costly first (an evaluation's energy work: pairs tested, atoms,
+        // torsions), so that the short ones fill the launch's tail
+        auto cost = [&](int32_t j) {
+            const auto& in = (*ligs->info)[hj[j].x];
+            return 8 * (int64_t)in[3] + 48 * (int64_t)in[0] + 109 * (int64_t)in[2];
+        };
+        for (auto& m : members)
+            std::stable_sort(m.begin(), m.end(), [&](int32_t a, int32_t b) { return cost(a) > cost(b); });
+    }
     hipError_t e = hipSuccess;
     for (int g = 0; g < 2 && e == hipSuccess; ++g) {
         if (members[g].empty()) continue;
