@@ -115,7 +115,9 @@ void pv_grids_free(pv_grids* g);
  * [atoms][3], type [atoms]; bond_off [n_lig+1], bonds [bonds][2] with
  * ligand-local atom indices, rotatable [bonds] (0/1).  Each ligand must be
  * connected, every rotatable bond must be a bridge, and n_atoms <= 128,
- * rotatable bonds <= 32.  Rings are allowed inside fragments. */
+ * rotatable bonds <= 32.  Rings are allowed inside fragments.  PV_E_RANGE if
+ * a concatenated device table (pairs, force-slot table) would pass 2^31
+ * entries. */
 typedef struct pv_ligands pv_ligands;
 pv_status pv_ligands_create(pv_ctx* ctx, int32_t n_lig, const int32_t* atom_off, const float* ref_xyz,
                             const uint8_t* type, const int32_t* bond_off, const int32_t* bonds,

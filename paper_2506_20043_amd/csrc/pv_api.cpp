@@ -459,6 +459,9 @@ pv_status pv_ligands_create(pv_ctx* ctx, int32_t n_lig, const int32_t* atom_off,
         max_pairs = std::max(max_pairs, M.np);
         max_tors = std::max(max_tors, M.nt);
     }
+    // the device tables are addressed with 32-bit offsets
+    for (size_t n : {perm.size(), frags.size(), tors_frag.size(), pairs.size(), ell.size(), pslot.size()})
+        if (n > (size_t)INT32_MAX) { delete info; return fail(PV_E_RANGE, "ligand tables exceed 2^31 entries"); }
     pv_status st = set_device(ctx);
     if (st != PV_OK) { delete info; return st; }
     pv_ligands* L = new (std::nothrow) pv_ligands();
