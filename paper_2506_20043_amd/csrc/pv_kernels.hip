@@ -1290,10 +1290,10 @@ __global__ __launch_bounds__(64) void score_kernel(ScoreArgs a)
     Topo<A, SL> T;
     T.lig = -1;
     const float nanv = __int_as_float(0x7fc00000);
-    // a contiguous run of poses per workgroup: runs of one ligand stage it once
-    const int chunk = (a.n_poses + (int)gridDim.x - 1) / (int)gridDim.x;
-    const int p_begin = (int)blockIdx.x * chunk;
-    const int p_end = min(a.n_poses, p_begin + chunk);
+    // a contiguous run of poses per workgroup (runs of one ligand stage it
+    // once), the runs' lengths differing by at most one so no wave idles
+    const int p_begin = (int)(((int64_t)blockIdx.x * a.n_poses) / (int64_t)gridDim.x);
+    const int p_end = (int)(((int64_t)(blockIdx.x + 1) * a.n_poses) / (int64_t)gridDim.x);
     for (int pose = p_begin; pose < p_end; ++pose) {
         const int lig = a.lig_of_pose[pose], box = a.box_of_pose[pose];
         if (lig < 0 || lig >= a.l.n_lig || box < 0 || box >= a.g.n_boxes) {
