@@ -80,8 +80,9 @@ def main():
                     help="only copy MIB MiB device-to-device (calibrates the HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
-              "(the work shards by pocket across GPUs, see DESIGN.md)" % args.gpus, file=sys.stderr)
+        print("bench.py measures one GPU; --gpus %d is not supported "
+              "(across GPUs the work would shard by pocket, each GPU building only its pockets' maps)"
+              % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import torch
