@@ -201,3 +201,49 @@ def test_slot_records_at_pass_boundaries(oracle, pv_ctx):
     big = pv.score_grad(pv_ctx, st.grids, st.ligs, big_lig, big_box, big_dof)
     es, eb = out["energy"].cpu().numpy(), big["energy"].cpu().numpy()[:B]
     assert np.all(np.abs(es - eb) <= e_tol(es))
+
+
+def test_max_size_ligand_dock(oracle, pv_ctx, big):
+    """The largest ligand the library takes (128 atoms, 32 torsions: 38
+    tangent components, so the BFGS wave sums span three rows): without BFGS
+    sampled chains replay the oracle; with BFGS the batched and plain
+    launches agree exactly, every chain best re-scores to its energy under the
+    oracle, and local optimisation never ends above its start."""
+    import paper_2506_20043_amd as pv
+    from test_gpu_search import _oparams
+    m = S.tree_ligand(np.random.default_rng(128), 128, 32)
+    assert m.n_tors == 32
+    ligs = pv.Ligands(pv_ctx, [m])
+    L = oracle.Ligand(m.xyz, m.types, m.bonds, m.rotatable)
+    assert L.ndof == 39
+    G = big.og[0]
+    assert pv.launch_info(pv_ctx, ligs, pv.KIND_DOCK, 16)[0] == pv.VARIANT_GATHER2
+    p0 = pv.dock_params(chains=16, steps=12, seed=1281, bfgs_max_iter=0, refine_max_iter=0)
+    res = pv.dock(pv_ctx, big.grids, ligs, [(0, 0)], p0)
+    cbe, ev = res["chain_best_e"].cpu().numpy(), res["chain_evals"].cpu().numpy()
+    same = 0
+    for c in range(0, 16, 2):
+        d, e_ref, ne = oracle.mc_chain(L, G, _oparams(oracle, p0), 0, c)
+        same += int(ne == ev[c] and abs(cbe[c] - e_ref) <= e_tol(e_ref))
+    assert same >= 7, same
+    p = pv.dock_params(chains=16, steps=6, seed=1282, flags=pv.PV_DOCK_GRAPH)
+    plan = pv.Plan(pv_ctx, big.grids, ligs, [(0, 0)], p)
+    bat = {k: v.cpu().numpy().copy() for k, v in plan.run().items()}
+    pla = {k: v.cpu().numpy().copy() for k, v in plan.run(plain=True).items()}
+    plan.close()
+    for k in ("chain_best_e", "chain_evals", "chain_best_dof", "job_best_e"):
+        assert np.array_equal(bat[k], pla[k]), k
+    assert np.all(bat["chain_evals"] >= 1 + p.steps) and np.all(np.isfinite(bat["chain_best_e"]))
+    for c in range(16):
+        r = L.score_grad(G, cpu_dof(bat["chain_best_dof"][c, :L.ndof]))
+        slack = 0.01 if r["min_cut"] < 1e-4 else 0.0
+        assert abs(r["e"] - bat["chain_best_e"][c]) <= e_tol(r["e"]) + slack, (c, r["e"], bat["chain_best_e"][c])
+    lig = np.zeros(8, np.int32)
+    box = np.zeros(8, np.int32)
+    dims, org = big.grids.info(0)
+    g = np.random.default_rng(129)
+    dof = S.poses(g, 8, org + 3.0, org + 0.375 * (dims - 1) - 3.0, 32).astype(np.float32)
+    start = pv.score_grad(pv_ctx, big.grids, ligs, lig, box, dof)["energy"].cpu().numpy()
+    out, e, ne = pv.local_opt(pv_ctx, big.grids, ligs, lig, box, dof, pv.dock_params())
+    e = e.cpu().numpy()
+    assert np.all(np.isfinite(e)) and np.all(e <= start + e_tol(start))
