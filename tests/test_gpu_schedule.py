@@ -162,3 +162,54 @@ def test_largest_first_changes_only_the_order(oracle, pv_ctx):
     assert np.all(outs[1]["job_t_end"] >= outs[1]["job_t_start"])
     with pytest.raises(pv.PvError):
         pv.Plan(pv_ctx, grids, ligs, jobs, pv.dock_params(chains=4, steps=2, seed=1, flags=8))
+
+
+def test_ligands_without_intra_pairs(oracle, pv_ctx, setup):
+    """Ligands of one, two and three atoms have no intra pair (the pair loop
+    runs no pass): under each kernel variant, chains without BFGS replay the
+    oracle and full docks give chain bests that re-score to their energies
+    (the variants sum forces in different orders, so their BFGS chains may
+    part ways)."""
+    import paper_2506_20043_amd as pv
+    from test_gpu_search import _oparams
+    one = S.Molecule(np.zeros((1, 3)), np.array([0], np.int32), np.zeros((0, 2), np.int32), np.zeros(0, np.uint8))
+    two = S.Molecule(np.array([[0.0, 0.0, 0.0], [1.5, 0.0, 0.0]]), np.array([3, 5], np.int32),
+                     np.array([[0, 1]], np.int32), np.zeros(1, np.uint8))
+    three = S.Molecule(np.array([[0.0, 0.0, 0.0], [1.5, 0.0, 0.0], [2.0, 1.4, 0.0]]), np.array([0, 2, 6], np.int32),
+                       np.array([[0, 1], [1, 2]], np.int32), np.zeros(2, np.uint8))
+    mols = [one, two, three]
+    ligs = pv.Ligands(pv_ctx, mols)
+    assert [ligs.info(i)[3] for i in range(3)] == [0, 0, 0]
+    ol = [oracle.Ligand(m.xyz, m.types, m.bonds, m.rotatable) for m in mols]
+    jobs = [(0, 0), (1, 0), (2, 0)]
+    chains = 16
+    p0 = pv.dock_params(chains=chains, steps=15, seed=95, bfgs_max_iter=0, refine_max_iter=0)
+    p = pv.dock_params(chains=chains, steps=8, seed=96)
+    outs = []
+    for variant in (0, 1, 2):
+        plan = pv.Plan(pv_ctx, setup["grids"], ligs, jobs, p0)
+        plan.set_schedule(0, variant, 0)
+        o = {k: v.cpu().numpy().copy() for k, v in plan.run().items()}
+        plan.close()
+        cbe, ev = o["chain_best_e"].reshape(3, chains), o["chain_evals"].reshape(3, chains)
+        same = total = 0
+        for j, (lig, _) in enumerate(jobs):
+            for c in range(0, chains, 4):
+                d, e_ref, ne = oracle.mc_chain(ol[lig], setup["og"], _oparams(oracle, p0), j, c)
+                same += int(ne == ev[j, c] and abs(cbe[j, c] - e_ref) <= e_tol(e_ref))
+                total += 1
+        assert same >= total - 1, (variant, same, total)
+        plan = pv.Plan(pv_ctx, setup["grids"], ligs, jobs, p)
+        plan.set_schedule(0, variant, 0)
+        outs.append({k: v.cpu().numpy().copy() for k, v in plan.run().items()})
+        plan.close()
+    for variant, o in enumerate(outs):
+        assert np.all(o["chain_evals"] >= 1 + p.steps) and np.all(np.isfinite(o["chain_best_e"]))
+        cbd = o["chain_best_dof"].reshape(3, chains, -1)
+        cbe = o["chain_best_e"].reshape(3, chains)
+        for j, (lig, _) in enumerate(jobs):
+            L = ol[lig]
+            for c in range(0, chains, 3):
+                r = L.score_grad(setup["og"], cpu_dof(cbd[j, c, :L.ndof]))
+                slack = 0.01 if r["min_cut"] < 1e-4 else 0.0
+                assert abs(r["e"] - cbe[j, c]) <= e_tol(r["e"]) + slack, (variant, j, c, cbe[j, c], r["e"])
