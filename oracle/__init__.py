@@ -107,6 +107,7 @@ def _declare(L):
     L.or_init_pose.argtypes = [C.c_void_p, C.POINTER(_Grid), C.c_uint64, C.c_int, C.c_int, _dp]
     L.or_mc_chain.argtypes = [C.c_void_p, C.POINTER(_Grid), C.POINTER(McParams), C.c_int,
                               C.c_int, _dp, _dp, _i64p]
+    L.or_mutate.argtypes = [C.c_void_p, C.POINTER(McParams), _u64p, _dp]
     L.or_dock.argtypes = [C.c_int, C.POINTER(C.c_void_p), C.c_int, C.POINTER(_Grid), C.c_int,
                           _ip, C.POINTER(McParams), C.c_int, C.c_int, _dp, _dp, _i64p, _dp, _ip]
     L.or_consistency_passes.argtypes = [C.c_int, _dp, C.c_double, _dp, _dp, C.c_double, _dp, C.c_int, C.c_int]
@@ -389,6 +390,16 @@ def init_pose(lig: Ligand, grid: Grid, seed, job, chain):
     lib().or_init_pose(lig.h, C.byref(grid.struct), int(seed) & 0xFFFFFFFFFFFFFFFF, int(job),
                        int(chain), _p(d, _dp))
     return d
+
+
+def mutate(lig: Ligand, params: McParams, words, x):
+    """One mutation (Eq. qvina_eq_2) of pose x from the step's 8 Philox words."""
+    w = np.ascontiguousarray(words, dtype=np.uint64)
+    assert w.shape == (8,)
+    y = _f64(x).copy()
+    assert len(y) == lig.ndof
+    lib().or_mutate(lig.h, C.byref(params), _p(w, _u64p), _p(y, _dp))
+    return y
 
 
 def mc_chain(lig: Ligand, grid: Grid, params: McParams, job, chain):

@@ -1029,6 +1029,11 @@ static void mutate(const or_ligand* L, const or_mc_params* P, const uint64_t w[8
     }
 }
 
+/* One mutation (Eq. qvina_eq_2 with the readings above) of the pose x
+ * (7 + nt values, changed in place) from the step's 8 Philox words w; for the
+ * tests of its distributions. */
+void or_mutate(const or_ligand* L, const or_mc_params* P, const uint64_t w[8], double* x) { mutate(L, P, w, x); }
+
 /* ---- first-order consistency check ------------------------------------
  * Eqs. qvina_eq_4 and qvina_eq_5 and the check of Supplementary Algorithm
  * 2.  Readings: the neighbouring conformation of the mutated pose is the

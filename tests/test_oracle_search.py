@@ -230,3 +230,61 @@ def test_mc_improves_over_random_poses(oracle, sparse):
     rnd = [L.score_grad(G, oracle.init_pose(L, G, 777, 0, c))["e"] for c in range(200)]
     assert res["job_best_e"][0] < np.percentile(rnd, 1)
     assert res["job_best_e"][0] < 0.0
+
+
+def _qmul(a, b):
+    w1, v1, w2, v2 = a[0], np.asarray(a[1:]), b[0], np.asarray(b[1:])
+    return np.concatenate([[w1 * w2 - v1 @ v2], w1 * v2 + w2 * v1 + np.cross(v1, v2)])
+
+
+def test_mutation_distributions(oracle):
+    """The mutation of a Monte Carlo step (Eq. qvina_eq_2, with the readings
+    of the step): exactly one entity moves, chosen uniformly among the
+    position, the orientation and each torsion; the position by a uniform
+    draw from the 2 A ball (radius CDF (r/2)^3, isotropic direction); the
+    orientation by a left rotation whose rotation vector is uniform in the
+    ball of radius 2 / R_g (angle CDF (theta/theta_max)^3); a torsion is
+    redrawn uniformly on [-pi, pi).  Fed with independent uniform words."""
+    g = np.random.default_rng(31)
+    m = S.tree_ligand(g, 14, 3)
+    L = oracle.Ligand(m.xyz, m.types, m.bonds, m.rotatable)
+    T = L.n_tors
+    assert T == 3
+    P = oracle.mc_params(chains=1, steps=1, seed=0)
+    q0 = g.normal(size=4)
+    q0 /= np.linalg.norm(q0)
+    x0 = np.concatenate([[1.0, -2.0, 3.0], q0, g.uniform(-np.pi, np.pi, T)])
+    N = 24000
+    W = g.integers(0, np.iinfo(np.uint64).max, size=(N, 8), dtype=np.uint64, endpoint=True)
+    counts = np.zeros(2 + T, np.int64)
+    dpos, theta, psi = [], [], []
+    q0c = np.concatenate([[q0[0]], -q0[1:]])
+    for w in W:
+        y = oracle.mutate(L, P, w, x0)
+        moved = [np.any(y[:3] != x0[:3]), np.any(y[3:7] != x0[3:7])] + [y[7 + k] != x0[7 + k] for k in range(T)]
+        assert sum(moved) == 1, moved
+        ent = moved.index(True)
+        counts[ent] += 1
+        if ent == 0:
+            dpos.append(y[:3] - x0[:3])
+        elif ent == 1:
+            assert abs(np.linalg.norm(y[3:7]) - 1.0) < 1e-12
+            dq = _qmul(y[3:7], q0c)
+            theta.append(2.0 * np.arccos(min(1.0, abs(dq[0]))))
+        else:
+            psi.append(y[7 + ent - 2])
+    assert stats.chisquare(counts).pvalue > 1e-3, counts
+    d = np.array(dpos)
+    r = np.linalg.norm(d, axis=1)
+    assert r.max() <= 2.0 * (1 + 1e-12)
+    assert stats.kstest(r, lambda v: np.clip(v / 2.0, 0, 1) ** 3).pvalue > 1e-3
+    u = d / r[:, None]
+    assert stats.kstest(u[:, 2], "uniform", args=(-1, 2)).pvalue > 1e-3   # Archimedes: cos of the polar angle
+    assert np.all(np.abs(u.mean(axis=0)) < 4 / np.sqrt(3 * len(u)))
+    th_max = 2.0 / L.rg()
+    th = np.array(theta)
+    assert th.max() <= th_max * (1 + 1e-9)
+    assert stats.kstest(th, lambda v: np.clip(v / th_max, 0, 1) ** 3).pvalue > 1e-3
+    p = np.array(psi)
+    assert p.min() >= -np.pi and p.max() < np.pi
+    assert stats.kstest(p, "uniform", args=(-np.pi, 2 * np.pi)).pvalue > 1e-3
