@@ -108,6 +108,8 @@ def _declare(L):
     L.or_mc_chain.argtypes = [C.c_void_p, C.POINTER(_Grid), C.POINTER(McParams), C.c_int,
                               C.c_int, _dp, _dp, _i64p]
     L.or_mutate.argtypes = [C.c_void_p, C.POINTER(McParams), _u64p, _dp]
+    L.or_metropolis_accepts.argtypes = [C.c_double, C.c_double, C.c_uint64, C.c_double]
+    L.or_metropolis_accepts.restype = C.c_int
     L.or_dock.argtypes = [C.c_int, C.POINTER(C.c_void_p), C.c_int, C.POINTER(_Grid), C.c_int,
                           _ip, C.POINTER(McParams), C.c_int, C.c_int, _dp, _dp, _i64p, _dp, _ip]
     L.or_consistency_passes.argtypes = [C.c_int, _dp, C.c_double, _dp, _dp, C.c_double, _dp, C.c_int, C.c_int]
@@ -400,6 +402,12 @@ def mutate(lig: Ligand, params: McParams, words, x):
     assert len(y) == lig.ndof
     lib().or_mutate(lig.h, C.byref(params), _p(w, _u64p), _p(y, _dp))
     return y
+
+
+def metropolis_accepts(e_cur, e_new, word, temperature=1.2):
+    """The Monte Carlo step's acceptance decision (Eq. qvina_eq_13)."""
+    return bool(lib().or_metropolis_accepts(float(e_cur), float(e_new), int(word) & 0xFFFFFFFFFFFFFFFF,
+                                            float(temperature)))
 
 
 def mc_chain(lig: Ligand, grid: Grid, params: McParams, job, chain):

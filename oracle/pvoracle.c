@@ -1079,6 +1079,14 @@ int or_consistency_passes(int nt, const double* x, double fx, const double* gx,
     return 0;
 }
 
+/* Eq. qvina_eq_13 (reading 13): the candidate e_o replaces the current e_i
+ * when it is lower, or when the step's uniform u = u01(word) is below
+ * exp((e_i - e_o) / T).  The chain's decision; exported for its tests. */
+int or_metropolis_accepts(double e_cur, double e_o, uint64_t word, double temperature)
+{
+    return e_o < e_cur || u01(word) < exp((e_cur - e_o) / temperature);
+}
+
 int or_mc_chain(const or_ligand* L, const or_grid* G, const or_mc_params* P,
                 int job, int chain, double* best_dof, double* best_e, int64_t* n_evals)
 {
@@ -1117,9 +1125,8 @@ int or_mc_chain(const or_ligand* L, const or_grid* G, const or_mc_params* P,
         }
         double e_o;
         or_bfgs(L, G, &P->bfgs, mut, opt, &e_o, &e1, &it); ne += e1;
-        double um = u01(w[7]);
         int moved = 0;
-        if (e_o < e_cur || um < exp((e_cur - e_o) / P->temperature)) {
+        if (or_metropolis_accepts(e_cur, e_o, w[7], P->temperature)) {
             memcpy(cur, opt, sizeof(double) * nx); e_cur = e_o;
             moved = 1;
         }

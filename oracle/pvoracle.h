@@ -135,6 +135,9 @@ int or_init_pose(const or_ligand* L, const or_grid* G, uint64_t seed,
 /* one mutation (Eq. qvina_eq_2) of pose x (7 + nt values, in place) from the
  * step's 8 Philox words; for the tests of its distributions */
 void or_mutate(const or_ligand* L, const or_mc_params* P, const uint64_t w[8], double* x);
+/* the Metropolis decision of a step (Eq. qvina_eq_13): 1 if e_o replaces
+ * e_cur, with u = u01(word) */
+int or_metropolis_accepts(double e_cur, double e_o, uint64_t word, double temperature);
 int or_mc_chain(const or_ligand* L, const or_grid* G, const or_mc_params* P,
                 int job, int chain, double* best_dof, double* best_e,
                 int64_t* n_evals);

@@ -288,3 +288,19 @@ def test_mutation_distributions(oracle):
     p = np.array(psi)
     assert p.min() >= -np.pi and p.max() < np.pi
     assert stats.kstest(p, "uniform", args=(-np.pi, 2 * np.pi)).pvalue > 1e-3
+
+
+def test_metropolis_acceptance_frequency(oracle):
+    """The Monte Carlo step's decision (Eq. qvina_eq_13, read as
+    exp((e_i - e_o)/1.2)): at a fixed energy rise the acceptance frequency
+    over independent uniform words is exp(-rise/T) within binomial error; a
+    fall or a tie is always accepted (the printed form exp(e_i - e_o)/1.2
+    would accept a tie only 83 % of the time)."""
+    g = np.random.default_rng(41)
+    n = 20000
+    for T, rise in ((1.2, -1.0), (1.2, 0.0), (1.2, 0.3), (1.2, 1.0), (1.2, 2.5), (0.6, 1.0)):
+        words = g.integers(0, np.iinfo(np.uint64).max, size=n, dtype=np.uint64, endpoint=True)
+        acc = sum(oracle.metropolis_accepts(-3.0, -3.0 + rise, int(w), T) for w in words)
+        p = min(1.0, float(np.exp(-rise / T)))
+        sd = np.sqrt(max(p * (1 - p), 1.0 / n) / n)
+        assert abs(acc / n - p) <= 4 * sd, (T, rise, acc / n, p)
