@@ -155,13 +155,32 @@ def _torch():
 
 
 def _stream(stream=None):
+    """The HIP stream of a launch: torch's current stream, or `stream`, which
+    then first waits for the current stream's work (the inputs were prepared
+    there).  Results on `stream` are the caller's to wait for."""
     torch = _torch()
-    s = stream if stream is not None else torch.cuda.current_stream()
-    return C.c_void_p(s.cuda_stream)
+    cur = torch.cuda.current_stream()
+    if stream is None:
+        return C.c_void_p(cur.cuda_stream)
+    if stream.cuda_stream != cur.cuda_stream:
+        stream.wait_stream(cur)
+    return C.c_void_p(stream.cuda_stream)
 
 
 def _ptr(t):
     return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _used_on(stream, *tensors):
+    """Tensors a launch on `stream` reads or writes.  torch's allocator ties a
+    block to the stream current when it was allocated; on another stream the
+    block could be handed out again while the launch still uses it, so it is
+    recorded on that stream too."""
+    if stream is None:
+        return
+    for t in tensors:
+        if t is not None:
+            t.record_stream(stream)
 
 
 def _dev_tensor(a, dtype, device):
@@ -256,6 +275,7 @@ class Grids:
         out = torch.empty((8, int(dims[2]), int(dims[1]), int(dims[0])), dtype=torch.float32,
                           device=self.ctx.torch_device)
         _check(lib().pv_grids_copy(self.h, int(box), _ptr(out), _stream(stream)), "pv_grids_copy")
+        _used_on(stream, out)
         return out
 
     def rebuild(self, stream=None):
@@ -358,6 +378,7 @@ def score_grad(ctx: Context, grids: Grids, ligs: Ligands, lig_of_pose, box_of_po
                                _ptr(ge), _ptr(out["energy"]), _ptr(out.get("e_parts")), _ptr(out.get("grad_dof")),
                                _ptr(out.get("xyz")), _ptr(out.get("grad_xyz")), int(ma), _stream(stream)),
            "pv_score_grad")
+    _used_on(stream, dof, lp, bp, ge, *out.values())
     return out
 
 
@@ -378,6 +399,7 @@ def score_grad_xyz(ctx: Context, grids: Grids, ligs: Ligands, lig_of_pose, box_o
     _check(lib().pv_score_grad_xyz(ctx.h, grids.h, ligs.h, int(B), _ptr(lp), _ptr(bp), _ptr(x), int(stride),
                                    _ptr(ge), _ptr(out["energy"]), _ptr(out.get("e_parts")), _ptr(out["grad_xyz"]),
                                    _stream(stream)), "pv_score_grad_xyz")
+    _used_on(stream, x, lp, bp, ge, *out.values())
     return out
 
 
@@ -489,6 +511,7 @@ class Plan:
         self.outputs()
         fn = lib().pv_dock_run_plain if plain else lib().pv_dock_run
         _check(fn(self.h, C.byref(self._c_out), _stream(stream)), "pv_dock_run")
+        _used_on(stream, *self._out.values())
         return self._out
 
     def groups(self) -> int:
@@ -553,6 +576,7 @@ def local_opt(ctx: Context, grids: Grids, ligs: Ligands, lig_of_pose, box_of_pos
     ne = torch.empty(B, dtype=torch.int64, device=dev)
     _check(lib().pv_local_opt(ctx.h, grids.h, ligs.h, int(B), _ptr(lp), _ptr(bp), _ptr(dof), int(stride),
                               C.byref(p), _ptr(out), _ptr(e), _ptr(ne), _stream(stream)), "pv_local_opt")
+    _used_on(stream, dof, lp, bp, out, e, ne)
     return out, e, ne
 
 
@@ -600,6 +624,7 @@ def output_stage(plan: Plan, chain_best_e, chain_best_dof, params: OutputParams 
                  out["mode_affinity"].data_ptr(), out["mode_dof"].data_ptr(), stride)
     _check(lib().pv_output_stage(plan.h, _ptr(e), _ptr(d), stride, C.byref(p), C.byref(o), _stream(stream)),
            "pv_output_stage")
+    _used_on(stream, e, d, *out.values())
     return out
 
 
@@ -625,6 +650,7 @@ class SurfacePoints:
         xyz = torch.empty((self.n_points, 3), dtype=torch.float32, device=dev)
         atom = torch.empty(self.n_points, dtype=torch.int32, device=dev)
         _check(lib().pv_sas_copy(self.h, _ptr(xyz), _ptr(atom), _stream(stream)), "pv_sas_copy")
+        _used_on(stream, xyz, atom)
         return xyz, atom
 
     def features(self, out=None, stream=None):
@@ -632,6 +658,7 @@ class SurfacePoints:
         f = out if out is not None else torch.empty((self.n_points, 12), dtype=torch.float32,
                                                     device=self.ctx.torch_device)
         _check(lib().pv_sas_features(self.h, _ptr(f), _stream(stream)), "pv_sas_features")
+        _used_on(stream, f)
         return f
 
     def close(self):

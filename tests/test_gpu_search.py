@@ -237,3 +237,33 @@ def test_dock_edge_cases(oracle, pv_ctx, tiny):
     with pytest.raises(pv.PvError, match="4096"):
         pv.output_stage(big, e, d)
     big.close()
+
+
+def test_side_stream_launches(oracle, pv_ctx, tiny):
+    """Launches on a caller's stream (torch's current stream stays the
+    default one): inputs prepared on the current stream are ready before the
+    kernel runs, and the results equal those of the same launches on the
+    current stream."""
+    import torch
+
+    import paper_2506_20043_amd as pv
+    side = torch.cuda.Stream()
+    g = np.random.default_rng(17)
+    L = tiny["ol"]
+    dims, org = tiny["grids"].info(0)
+    dof = S.poses(g, 512, org + 2.0, org + 0.375 * (dims - 1) - 2.0, L.n_tors).astype(np.float32)
+    z = np.zeros(512, np.int32)
+    ref = {k: v.cpu() for k, v in pv.score_grad(pv_ctx, tiny["grids"], tiny["ligs"], z, z, dof).items()}
+    got = pv.score_grad(pv_ctx, tiny["grids"], tiny["ligs"], z, z, dof, stream=side)
+    side.synchronize()
+    for k in ref:
+        assert torch.equal(ref[k], got[k].cpu()), k
+    p = _params(pv, chains=16, steps=10, seed=tiny["seed"] + 9, flags=pv.PV_DOCK_GRAPH)
+    plan = pv.Plan(pv_ctx, tiny["grids"], tiny["ligs"], [(0, 0), (0, 0)], p)
+    a = {k: v.cpu().clone() for k, v in plan.run().items()}
+    plan.run(stream=side)
+    side.synchronize()
+    b = {k: v.cpu().clone() for k, v in plan.outputs().items()}
+    plan.close()
+    for k in ("chain_best_e", "chain_evals", "chain_best_dof", "job_best_e"):
+        assert torch.equal(a[k], b[k]), k
