@@ -74,7 +74,9 @@ void pv_destroy(pv_ctx* ctx);
  * boxes: host [n_boxes]; size > 0, spacing > 0, at most 2048 points per axis.
  * penalty_slope: kcal/mol per A added for each atom coordinate outside a box
  * (its lookups clamp to the box face); must be >= 0.
- * n_rec may be 0 (all maps zero). */
+ * n_rec may be 0 (all maps zero).  Every lattice point sums its receptor
+ * atoms in input order, so a build and every rebuild give the same maps bit
+ * for bit. */
 typedef struct {
     float center[3];
     float size[3];
@@ -248,7 +250,11 @@ typedef struct {
 } pv_dock_out;
 
 /* A dock plan: the job table uploaded once and the parameters checked.
- * jobs: host [n_jobs]; every ligand and box index must exist. */
+ * jobs: host [n_jobs]; every ligand and box index must exist.  A chain's
+ * result depends only on the inputs, the parameters and (job, chain): runs
+ * of a plan, graph replays, the plain form, the schedule's width and the job
+ * order all give the same outputs bit for bit (the kernel variant may sum
+ * forces in another order). */
 typedef struct pv_plan pv_plan;
 pv_status pv_dock_plan(pv_ctx* ctx, const pv_grids* grids, const pv_ligands* ligs, const pv_job* jobs,
                        int32_t n_jobs, const pv_dock_params* params, pv_plan** out);
