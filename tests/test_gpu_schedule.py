@@ -61,6 +61,7 @@ def test_forced_variants_replay_oracle(oracle, pv_ctx, setup, variant):
     plan = pv.Plan(pv_ctx, setup["grids"], setup["ligs"], jobs, p)
     assert plan.groups() == 2
     assert plan.schedule(0)["n_jobs"] == 2 and plan.schedule(1)["n_jobs"] == 1
+    runs = []
     for width in (0, 5):
         plan.set_schedule(0, variant, width)
         sc = plan.schedule(0)
@@ -69,7 +70,11 @@ def test_forced_variants_replay_oracle(oracle, pv_ctx, setup, variant):
         out = {k: v.clone() for k, v in plan.run().items()}
         same, total = _replays(oracle, setup, out, jobs, p, chains)
         assert same >= total - 2, (variant, width, same, total)
+        runs.append(out)
     plan.close()
+    # the width changes which wave runs which chain, never a chain's result
+    for k in ("chain_best_e", "chain_evals", "chain_best_dof", "job_best_e"):
+        assert torch.equal(runs[0][k], runs[1][k]), (variant, k)
 
 
 def test_autotune_chooses_remembers_and_stays_valid(oracle, pv_ctx, setup):
