@@ -74,7 +74,7 @@ def main():
     ap.add_argument("--plain-jobs", type=int, default=20, help="jobs of the uneven batch run one launch each")
     ap.add_argument("--stream-jobs", type=int, default=2048, help="jobs taken from the screening stream")
     ap.add_argument("--sweep-steps", type=int, default=1000, help="MC steps per chain in the box-size sweep")
-    ap.add_argument("--leg", choices=["score", "batching", "screening", "box_sweep", "surface"], default=None,
+    ap.add_argument("--leg", choices=["score", "local_opt", "batching", "screening", "box_sweep", "surface"], default=None,
                     help="run only this secondary leg and print its JSON (for profiling it alone)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device (calibrates the HBM byte counters) and exit")
@@ -104,6 +104,7 @@ def main():
         ctx = pv.Context(0)
         stream = torch.cuda.current_stream()
         legs = {"score": lambda: bench_score(pv, S, ctx, stream),
+                "local_opt": lambda: bench_local_opt(pv, S, ctx, stream),
                 "batching": lambda: bench_batching(pv, S, ctx, stream, args),
                 "screening": lambda: bench_screening(pv, S, ctx, stream, args),
                 "box_sweep": lambda: bench_box_sweep(pv, S, ctx, stream, args),
@@ -224,6 +225,7 @@ def main():
                                                         n_evals, dock_ms, plan.outputs())
     if not args.no_score:
         result["score_grad"] = bench_score(pv, S, ctx, stream)
+        result["local_opt"] = bench_local_opt(pv, S, ctx, stream)
     if not args.no_extra:
         result["batching"] = bench_batching(pv, S, ctx, stream, args)
         result["screening"] = bench_screening(pv, S, ctx, stream, args)
@@ -289,6 +291,39 @@ def bench_score(pv, S, ctx, stream):
     return {"workload": "16,384 poses, 64 ligands of 40 atoms / 10 torsions, one 24 A pocket",
             "ms_per_call": ms, "evals_per_s": cfg.n_poses / (ms * 1e-3), "calls": 5 * reps,
             "ms_per_call_runs": runs}
+
+
+def bench_local_opt(pv, S, ctx, stream):
+    """RILC-BFGS alone (pv_local_opt, at most 30 iterations) from the
+    differentiation workload's 16,384 poses: 5 timed calls, the median."""
+    import torch
+    cfg = S.CONFIGS["differentiation"]
+    rx, rt, bxs = S.make_receptor(cfg)
+    grids = pv.build_grids(ctx, rx, rt, bxs[:1], penalty_slope=10.0)
+    ligs = pv.Ligands(ctx, S.make_ligands(cfg))
+    dims, org = grids.info(0)
+    lo, hi = org.astype(np.float64), org + 0.375 * (dims - 1)
+    dof = torch.tensor(S.poses(S.rng(cfg.index, S.STREAM_POSES), cfg.n_poses, lo, hi, 10), device="cuda")
+    lig = torch.tensor(np.repeat(np.arange(64, dtype=np.int32), 256), device="cuda")
+    box = torch.zeros(cfg.n_poses, dtype=torch.int32, device="cuda")
+    params = pv.dock_params()
+    pv.local_opt(ctx, grids, ligs, lig, box, dof, params)
+    torch.cuda.synchronize()
+    runs = []
+    for _ in range(5):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        _, e, ne = pv.local_opt(ctx, grids, ligs, lig, box, dof, params)
+        b.record(stream)
+        torch.cuda.synchronize()
+        runs.append(a.elapsed_time(b))
+    ms = float(np.median(runs))
+    evals = int(ne.sum().item())
+    e0 = pv.score_grad(ctx, grids, ligs, lig, box, dof, grad=False)["energy"]
+    return {"workload": "BFGS (<= 30 iterations) from 16,384 poses of 64 ligands of 40 atoms / 10 torsions",
+            "ms": ms, "poses_per_s": cfg.n_poses / (ms * 1e-3), "evals": evals,
+            "evals_per_s": evals / (ms * 1e-3), "mean_energy_start": float(e0.mean().item()),
+            "mean_energy_end": float(e.mean().item())}
 
 
 def bench_consistency(pv, ctx, grids, ligs, jobs, args, seed, stream, evals_off, ms_off, out_off):
