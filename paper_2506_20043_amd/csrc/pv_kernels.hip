@@ -854,19 +854,24 @@ __device__ __forceinline__ void retract(const Lds& S, int dst, int src, float d,
     const int l = lane_id();
     const float* x = S.pose + src * kSlot;
     float* o = S.pose + dst * kSlot;
+    const int np = 7 + nt;
+    // one LDS read: lane k holds pose entry k; the quaternion comes from
+    // lanes 3..6 by readlane (dst and src are distinct slots)
+    const float xv = l < np ? x[l] : 0.f;
     const float th0 = lane_f(d, 3) * lam, th1 = lane_f(d, 4) * lam, th2 = lane_f(d, 5) * lam;
-    float dq[4], q[4] = {x[3], x[4], x[5], x[6]}, nq[4];
+    float dq[4], q[4] = {lane_f(xv, 3), lane_f(xv, 4), lane_f(xv, 5), lane_f(xv, 6)}, nq[4];
     rotvec_quat(th0, th1, th2, dq);
     quat_mul(dq, q, nq);
     quat_normalize(nq);
-    // lanes 0..2 write t, 3..6 the quaternion, 6..5+nt the torsion of
-    // tangent lane l at pose entry l + 1 (dst and src are distinct slots)
-    float qv = nq[3];
-    qv = l == 5 ? nq[2] : qv;
-    qv = l == 4 ? nq[1] : qv;
-    qv = l == 3 ? nq[0] : qv;
-    if (l < 7) o[l] = l < 3 ? x[l] + lam * d : qv;
-    if (l >= 6 && l < 6 + nt) o[l + 1] = x[l + 1] + lam * d;
+    // pose entries 0..2 move by tangent lanes 0..2, entry k >= 7 (a torsion)
+    // by tangent lane k - 1, brought over by a whole-wave shift (DPP wave_shr:1)
+    const float dprev = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(d), 0x138, 0xF, 0xF, false));
+    float v = xv + lam * (l < 3 ? d : dprev);
+    v = l == 6 ? nq[3] : v;
+    v = l == 5 ? nq[2] : v;
+    v = l == 4 ? nq[1] : v;
+    v = l == 3 ? nq[0] : v;
+    if (l < np) o[l] = v;
     wave_sync();
 }
 
