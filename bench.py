@@ -231,6 +231,7 @@ def main():
         result["screening"] = bench_screening(pv, S, ctx, stream, args)
         result["box_sweep"] = bench_box_sweep(pv, S, ctx, stream, args)
         result["surface"] = bench_surface(pv, S, ctx, stream)
+    result["measured_peaks"] = measure_peaks(pv, ctx, stream)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(S, cfg, rx, rt, bxs, mols, seed, args)
     print(json.dumps(result), flush=True)
@@ -569,6 +570,46 @@ def cpu_baseline(S, cfg, rx, rt, bxs, mols, seed, args):
             "single_core": {"evals_per_s": int(r1["chain_evals"].sum()) / d1,
                             "docks_per_s": (4 / args.chains) / d1,
                             "sample": "pocket 0, 4 chains x %d MC steps, %.1f s" % (args.mc_steps, d1)}}
+
+
+def measure_peaks(pv, ctx, stream):
+    """The device's FP32 multiply-add rate reached by code built here (16
+    independent FMA chains per thread, packed FP32 off) and a 256 MiB
+    device-to-device copy's bandwidth: measured context for the published
+    peaks the roofline is priced at (best of 10 launches each)."""
+    import torch
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    out = torch.empty(n_cu * 2048, dtype=torch.float32, device="cuda")
+    iters = 4096
+    pv.fma_peak(ctx, iters, out)
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(10):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        flops = pv.fma_peak(ctx, iters, out)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b)
+        best = ms if best is None else min(best, ms)
+    n = 64 << 20
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    cbest = None
+    for _ in range(10):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        dst.copy_(src)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b)
+        cbest = ms if cbest is None else min(cbest, ms)
+    return {"fp32_fma_TFLOPs": flops / (best * 1e-3) / 1e12, "fp32_fma_ms": best,
+            "published_fp32_vector_TFLOPs": PEAK_FP32_VECTOR / 1e12,
+            "copy_GBps": 2 * 4 * n / (cbest * 1e-3) / 1e9, "copy_ms": cbest,
+            "published_hbm_GBps": PEAK_HBM / 1e9}
 
 
 def cpu_model():

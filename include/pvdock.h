@@ -418,6 +418,16 @@ void pv_sas_free(pv_sas* sas);
 pv_status pv_launch_info(pv_ctx* ctx, const pv_ligands* ligs, int32_t kind, int64_t items, int32_t* variant,
                          int32_t* lds_bytes, int32_t* per_cu);
 
+/* Measurement aid (not part of docking): the FP32 VALU issue rate of the
+ * device, for comparing the published vector peak with what hand-written
+ * FP32 code built here can reach.  Launches n_out threads (a positive
+ * multiple of 256) that each run 16 independent multiply-add chains for
+ * `iters` rounds, with no memory traffic but one store of their sum to
+ * dev_out [n_out] (device, caller-owned).  One launch performs
+ * 2 * 16 * iters * n_out floating-point operations; time it on `stream`.
+ * PV_E_INVALID for NULL dev_out, iters < 1 or a bad n_out. */
+pv_status pv_fma_peak(pv_ctx* ctx, int32_t iters, float* dev_out, int32_t n_out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

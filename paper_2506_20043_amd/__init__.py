@@ -121,6 +121,7 @@ SIGNATURES = {
     "pv_sas_free": (None, [_vp]),
     "pv_output_params_default": (None, [C.POINTER(OutputParams)]),
     "pv_output_stage": (C.c_int, [_vp, _vp, _vp, _i32, C.POINTER(OutputParams), C.POINTER(ModesOut), _vp]),
+    "pv_fma_peak": (C.c_int, [_vp, _i32, _vp, _i32, _vp]),
 }
 
 
@@ -578,6 +579,16 @@ def local_opt(ctx: Context, grids: Grids, ligs: Ligands, lig_of_pose, box_of_pos
                               C.byref(p), _ptr(out), _ptr(e), _ptr(ne), _stream(stream)), "pv_local_opt")
     _used_on(stream, dof, lp, bp, out, e, ne)
     return out, e, ne
+
+
+def fma_peak(ctx: Context, iters: int, out, stream=None) -> float:
+    """Launches the FP32 multiply-add throughput kernel over out (a device
+    float32 tensor whose length is a multiple of 256); returns the launch's
+    floating-point operation count."""
+    n = int(out.numel())
+    _check(lib().pv_fma_peak(ctx.h, int(iters), _ptr(out), n, _stream(stream)), "pv_fma_peak")
+    _used_on(stream, out)
+    return 2.0 * 16 * int(iters) * n
 
 
 KIND_DOCK, KIND_SCORE, KIND_LOCAL_OPT = 0, 1, 2

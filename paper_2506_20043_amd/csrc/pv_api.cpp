@@ -1087,6 +1087,18 @@ pv_status pv_dock_autotune(pv_plan* P, int32_t tune_steps, int32_t repeats, void
     return done(PV_OK);
 }
 
+pv_status pv_fma_peak(pv_ctx* ctx, int32_t iters, float* dev_out, int32_t n_out, void* stream)
+{
+    if (!ctx_ok(ctx)) return fail(PV_E_STATE, "invalid context");
+    if (!dev_out) return fail(PV_E_INVALID, "dev_out is NULL");
+    if (iters < 1 || n_out < 256 || n_out % 256 != 0)
+        return fail(PV_E_INVALID, "need iters >= 1 and n_out a positive multiple of 256");
+    pv_status st = set_device(ctx);
+    if (st != PV_OK) return st;
+    HIP_TRY(launch_fma_peak(dev_out, n_out, iters, (hipStream_t)stream), "fma peak launch");
+    return PV_OK;
+}
+
 pv_status pv_dock(pv_ctx* ctx, const pv_grids* grids, const pv_ligands* ligs, const pv_job* jobs, int32_t n_jobs,
                   const pv_dock_params* params, const pv_dock_out* out, void* stream)
 {

@@ -208,6 +208,7 @@ hipError_t launch_shape_variant(int kind, const LigDev& l, int variant, LaunchSh
 hipError_t launch_score(const ScoreArgs& a, int n_cu, hipStream_t s);
 hipError_t launch_dock(const DockArgs& a, const LaunchShape& sh, int32_t workgroups, hipStream_t s);
 hipError_t launch_reset_queue(uint32_t* q, hipStream_t s);
+hipError_t launch_fma_peak(float* out, int n, int iters, hipStream_t s);
 hipError_t launch_job_reduce(const float* chain_best_e, const int64_t* chain_evals, int32_t n_jobs,
                              int32_t chains, float* job_best_e, int32_t* job_best_chain, int64_t* job_evals,
                              int32_t* job_status, hipStream_t s);

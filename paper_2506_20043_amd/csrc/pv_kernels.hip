@@ -1261,6 +1261,27 @@ __global__ __launch_bounds__(64) void dock_kernel(DockArgs a)
 
 __global__ void reset_queue_kernel(uint32_t* q) { if (threadIdx.x == 0) *q = 0u; }
 
+// Measurement aid, the VALU FP32 issue rate: every thread runs 16 independent
+// multiply-add chains for `iters` rounds with no memory traffic and stores
+// their sum once, so the launch is bound by FMA issue alone.
+__global__ __launch_bounds__(256) void fma_peak_kernel(float* out, int iters)
+{
+    const int gid = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    const float a = 0.999999f, b = 1e-7f * (float)(threadIdx.x & 7u);
+    float x[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) x[k] = (float)(gid + k) * 1e-6f;
+#pragma unroll 4
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) x[k] = fmaf(x[k], a, b);
+    }
+    float sum = 0.f;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) sum += x[k];
+    out[gid] = sum;
+}
+
 __global__ void reset_times_kernel(uint64_t* t0, uint64_t* t1, int n)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1904,6 +1925,12 @@ hipError_t launch_dock(const DockArgs& a, const LaunchShape& sh, int32_t workgro
         hipLaunchKernelGGL((dock_kernel<1, false>), dim3(grid), dim3(64), sh.lds, s, a);
     else
         hipLaunchKernelGGL((dock_kernel<2, false>), dim3(grid), dim3(64), sh.lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fma_peak(float* out, int n, int iters, hipStream_t s)
+{
+    hipLaunchKernelGGL(fma_peak_kernel, dim3((unsigned)(n / 256)), dim3(256), 0, s, out, iters);
     return hipGetLastError();
 }
 

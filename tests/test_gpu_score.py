@@ -227,3 +227,21 @@ def test_autograd_backward(oracle, pv_ctx):
     ex.sum().backward()
     ref = pv.score_grad(pv_ctx, st.grids, st.ligs, z, z, dof_np, xyz=True)["grad_xyz"].cpu().numpy()
     np.testing.assert_allclose(xyz.grad.cpu().numpy(), ref[:, :L.n_atoms], rtol=1e-3, atol=1e-3)
+
+
+def test_fma_peak_aid(pv_ctx):
+    """The measurement aid behind the bench's measured FP32 rate: one value
+    per thread, finite and the same on every call; bad arguments rejected."""
+    import torch
+
+    import paper_2506_20043_amd as pv
+    out = torch.empty(4 * 256, dtype=torch.float32, device="cuda")
+    flops = pv.fma_peak(pv_ctx, 8, out)
+    assert flops == 2 * 16 * 8 * 1024
+    a = out.cpu().clone()
+    pv.fma_peak(pv_ctx, 8, out)
+    assert torch.isfinite(a).all() and torch.equal(a, out.cpu())
+    with pytest.raises(pv.PvError):
+        pv.fma_peak(pv_ctx, 0, out)
+    with pytest.raises(pv.PvError):
+        pv.fma_peak(pv_ctx, 8, out[:100])
