@@ -5,9 +5,8 @@ only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import it.  It shares no code with the product package.
 
 Arrays are numpy; coordinates and pose DOFs are binary64.  Receptor
-coordinates are binary32, the interface precision of the receptor, so that
-the map cutoff test can be taken in binary32 exactly as the map kernel takes
-it (see ``or_build_maps`` in pvoracle.c).
+coordinates are binary32, the interface precision of the receptor; every map
+value, including its 8 A cutoff test, is computed from them in binary64.
 """
 from __future__ import annotations
 
@@ -79,9 +78,10 @@ def _declare(L):
     L.or_type_params.argtypes = [C.c_int, _dp, _ip, _ip, _ip]
     L.or_weights.argtypes = [_dp]
     L.or_lattice.argtypes = [_dp, _dp, C.c_double, _ip, _fp]
-    L.or_build_maps.argtypes = [C.c_int, _fp, _ip, _ip, _fp, C.c_float, _dp]
+    L.or_build_maps.argtypes = [C.c_int, _fp, _ip, _ip, _fp, C.c_float, _dp, _dp]
     L.or_map_point.argtypes = [C.c_int, _fp, _ip, _ip, _fp, C.c_float,
-                               C.c_int, C.c_int, C.c_int, _dp]
+                               C.c_int, C.c_int, C.c_int, _dp, _dp]
+    L.or_retract.argtypes = [C.c_int, _dp, _dp, C.c_double, _dp]
     L.or_trilinear.argtypes = [_dp, _ip, _fp, C.c_float, C.c_double, _dp, _dp, _dp]
     L.or_trilinear.restype = C.c_double
     L.or_ligand_build.argtypes = [C.c_int, _dp, _ip, C.c_int, _ip, _u8p, C.POINTER(C.c_void_p)]
@@ -174,30 +174,46 @@ def lattice(center, size, h):
     return dims, org
 
 
-def build_maps(rec_xyz, rec_type, dims, origin, h):
+def build_maps(rec_xyz, rec_type, dims, origin, h, margin=False):
+    """Maps [8][nz][ny][nx]; with margin=True also [nz][ny][nx], per point the
+    smallest |r - 8| over the receptor atoms (inf when none is near)."""
     x = _f32(rec_xyz)
     t = _i32(rec_type)
     d = _i32(dims)
     o = _f32(origin)
     out = np.zeros((8, int(d[2]), int(d[1]), int(d[0])), np.float64)
+    mg = np.zeros(out.shape[1:], np.float64) if margin else None
     rc = lib().or_build_maps(len(t), _p(x, _fp), _p(t, _ip), _p(d, _ip), _p(o, _fp),
-                             float(np.float32(h)), _p(out, _dp))
+                             float(np.float32(h)), _p(out, _dp), _p(mg, _dp) if margin else None)
     if rc != 0:
         raise ValueError("invalid receptor (code %d)" % rc)
-    return out
+    return (out, mg) if margin else out
 
 
-def map_point(rec_xyz, rec_type, dims, origin, h, i, j, k):
+def map_point(rec_xyz, rec_type, dims, origin, h, i, j, k, margin=False):
+    """The 8 map values at lattice point (i, j, k); with margin=True also the
+    smallest |r - 8| over the receptor atoms."""
     x = _f32(rec_xyz)
     t = _i32(rec_type)
     d = _i32(dims)
     o = _f32(origin)
     out = np.zeros(8)
+    mg = C.c_double()
     rc = lib().or_map_point(len(t), _p(x, _fp), _p(t, _ip), _p(d, _ip), _p(o, _fp),
-                            float(np.float32(h)), int(i), int(j), int(k), _p(out, _dp))
+                            float(np.float32(h)), int(i), int(j), int(k), _p(out, _dp), C.byref(mg))
     if rc != 0:
         raise ValueError("invalid point (code %d)" % rc)
-    return out
+    return (out, mg.value) if margin else out
+
+
+def retract(nt, x, d, lam):
+    """x (+) lam d, the pose update of the oracle's BFGS."""
+    xx = _f64(x)
+    dd = _f64(d)
+    assert len(xx) == 7 + nt and len(dd) == 6 + nt
+    o = np.zeros(7 + nt)
+    lib().or_retract(int(nt), _p(xx, _dp), _p(dd, _dp), float(lam), _p(o, _dp))
+    return o
 
 
 class Grid:

@@ -124,21 +124,6 @@ int or_lattice(const double center[3], const double size[3], double h,
     return 0;
 }
 
-/* The 8 A cutoff test for map building, taken on binary32 values in
- * this exact order: g = fma(i, h, origin); dx = g - x; r2 = fma(dx, dx,
- * fma(dy, dy, dz*dz)); inside iff r2 < 64. */
-static int map_cutoff_f32(int i, int j, int k, const float o[3], float h,
-                          const float* x)
-{
-    float gx = fmaf((float)i, h, o[0]);
-    float gy = fmaf((float)j, h, o[1]);
-    float gz = fmaf((float)k, h, o[2]);
-    float dx = gx - x[0], dy = gy - x[1], dz = gz - x[2];
-    float dz2 = dz * dz;
-    float r2 = fmaf(dx, dx, fmaf(dy, dy, dz2));
-    return r2 < 64.0f;
-}
-
 static int types_ok(int n, const int32_t* t)
 {
     for (int i = 0; i < n; ++i)
@@ -146,38 +131,53 @@ static int types_ok(int n, const int32_t* t)
     return 1;
 }
 
-/* Map value of every ligand type at one lattice point: the sum over all
- * receptor atoms within the cutoff, in atom-index order.  (Point-major.) */
+/* Map value of every ligand type at one lattice point: the sum over the
+ * receptor atoms closer than the 8 A cutoff, in atom-index order.  The
+ * lattice point g = origin + h (i, j, k), the distance and the cutoff test
+ * r < 8 are all binary64.  margin (may be NULL): the smallest |r - 8| over
+ * all receptor atoms (infinity with none), so that a test can tell the
+ * points where a binary32 build may decide the cutoff the other way.
+ * (Point-major.) */
 int or_map_point(int n_rec, const float* rec, const int32_t* rtype,
                  const int dims[3], const float origin[3], float h,
-                 int i, int j, int k, double out[8])
+                 int i, int j, int k, double out[8], double* margin)
 {
     if (i < 0 || j < 0 || k < 0 || i >= dims[0] || j >= dims[1] || k >= dims[2]) return -1;
     if (!types_ok(n_rec, rtype)) return -1;
     double g[3] = {(double)origin[0] + (double)h * i, (double)origin[1] + (double)h * j,
                    (double)origin[2] + (double)h * k};
+    double mg = INFINITY;
     for (int t = 0; t < OR_NTYPES; ++t) out[t] = 0.0;
     for (int r = 0; r < n_rec; ++r) {
         const float* x = rec + 3 * r;
-        if (!map_cutoff_f32(i, j, k, origin, h, x)) continue;
         double dx = g[0] - x[0], dy = g[1] - x[1], dz = g[2] - x[2];
         double dist = sqrt(dx * dx + dy * dy + dz * dz);
+        if (fabs(dist - CUTOFF) < mg) mg = fabs(dist - CUTOFF);
+        if (!(dist < CUTOFF)) continue;
         for (int t = 0; t < OR_NTYPES; ++t) out[t] += or_pair(t, rtype[r], dist, NULL);
     }
+    if (margin) *margin = mg;
     return 0;
 }
 
 /* All maps of one box.  Atom-major: every receptor atom adds its terms to
- * the lattice points inside its cutoff sphere.  Per point, the atoms are
- * still summed in index order, so the result equals or_map_point. */
+ * the lattice points inside its cutoff sphere (r < 8 in binary64, as in
+ * or_map_point).  Per point, the atoms are still summed in index order, so
+ * the result equals or_map_point.  margin (may be NULL): [nz][ny][nx], per
+ * point the smallest |r - 8| over the receptor atoms within 8.01 A
+ * (infinity with none), as or_map_point's margin wherever it is below
+ * 0.01. */
 int or_build_maps(int n_rec, const float* rec, const int32_t* rtype,
-                  const int dims[3], const float origin[3], float h, double* maps)
+                  const int dims[3], const float origin[3], float h, double* maps,
+                  double* margin)
 {
     if (!types_ok(n_rec, rtype)) return -1;
     const int nx = dims[0], ny = dims[1], nz = dims[2];
     const size_t plane = (size_t)nx * ny, msz = plane * nz;
     memset(maps, 0, sizeof(double) * msz * OR_NTYPES);
-    const double reach = CUTOFF + 0.01; /* wider than any binary32 rounding */
+    if (margin)
+        for (size_t p = 0; p < msz; ++p) margin[p] = INFINITY;
+    const double reach = CUTOFF + 0.01; /* the lattice range scanned per atom */
 #pragma omp parallel for schedule(dynamic, 1)
     for (int k = 0; k < nz; ++k) {
         double gz = (double)origin[2] + (double)h * k;
@@ -195,11 +195,12 @@ int or_build_maps(int n_rec, const float* rec, const int32_t* rtype,
             for (int j = jlo; j <= jhi; ++j) {
                 double gy = (double)origin[1] + (double)h * j;
                 for (int i = ilo; i <= ihi; ++i) {
-                    if (!map_cutoff_f32(i, j, k, origin, h, x)) continue;
                     double gx = (double)origin[0] + (double)h * i;
                     double dx = gx - x[0], dy = gy - x[1], dz = gz - x[2];
                     double dist = sqrt(dx * dx + dy * dy + dz * dz);
                     size_t idx = (size_t)k * plane + (size_t)j * nx + i;
+                    if (margin && fabs(dist - CUTOFF) < margin[idx]) margin[idx] = fabs(dist - CUTOFF);
+                    if (!(dist < CUTOFF)) continue;
                     for (int t = 0; t < OR_NTYPES; ++t)
                         maps[t * msz + idx] += or_pair(t, rtype[r], dist, NULL);
                 }
@@ -802,6 +803,10 @@ static void retract(int nt, const double* x, const double* d, double lam, double
     for (int a = 0; a < 4; ++a) o[3 + a] = q[a] / qn;
     for (int k = 0; k < nt; ++k) o[7 + k] = x[7 + k] + lam * d[6 + k];
 }
+
+/* x (+) lam d as BFGS moves a pose (7 + nt values) along a tangent
+ * direction d (6 + nt values); exported for the tests of its convention. */
+void or_retract(int nt, const double* x, const double* d, double lam, double* o) { retract(nt, x, d, lam, o); }
 
 static double dot(int n, const double* a, const double* b)
 {

@@ -8,10 +8,10 @@
  * the CPU-baseline leg of the benchmark load it.  It shares no code, header
  * or table with the HIP library.
  *
- * All arithmetic is IEEE binary64, with one documented exception: when a
- * grid map is built, the 8 A cutoff test is taken on binary32 distances
- * (see or_build_maps), so that it is decided in the same precision as the
- * kernel that builds the maps.
+ * All arithmetic is IEEE binary64.  Receptor coordinates and the lattice
+ * origin and spacing are binary32, the precision they have at the interface.
+ * The one decision taken in binary32 is the receptor surface point set
+ * (or_sas_points), which is compared as a set of integers.
  *
  * Return codes: 0 = OK; negative = invalid input (nothing written).
  */
@@ -36,13 +36,14 @@ void   or_weights(double w[5]);
 int or_lattice(const double center[3], const double size[3], double h,
                int dims[3], float origin[3]);
 
-/* ---- grid maps: maps[t][k][j][i], t < 8 (Kernel 1) */
+/* ---- grid maps: maps[t][k][j][i], t < 8 (Kernel 1); cutoff r < 8 in
+ * binary64; margin (may be NULL): per point the smallest |r - 8| */
 int or_build_maps(int n_rec, const float* rec_xyz, const int32_t* rec_type,
                   const int dims[3], const float origin[3], float h,
-                  double* maps);
+                  double* maps, double* margin);
 int or_map_point(int n_rec, const float* rec_xyz, const int32_t* rec_type,
                  const int dims[3], const float origin[3], float h,
-                 int i, int j, int k, double out[8]);
+                 int i, int j, int k, double out[8], double* margin);
 
 /* ---- trilinear lookup with out-of-box penalty */
 double or_trilinear(const double* map, const int dims[3], const float origin[3],
@@ -102,6 +103,10 @@ typedef struct {
 int or_bfgs(const or_ligand* L, const or_grid* G, const or_bfgs_params* P,
             const double* x0, double* xout, double* fout,
             int64_t* n_evals, int32_t* n_iters);
+
+/* x (+) lam d: t + lam d_t, exp(lam d_theta) q (left rotation, renormalised),
+ * psi + lam d_psi; x [7+nt], d [6+nt], o [7+nt] */
+void or_retract(int nt, const double* x, const double* d, double lam, double* o);
 
 /* the same BFGS on a flat R^n objective with an additive update */
 typedef void (*or_eval_fn)(void* user, const double* x, double* f, double* g);

@@ -21,12 +21,28 @@ def _gpu_maps(pv_ctx, rx, rt, boxes):
     return grids, [grids.maps(b).cpu().numpy() for b in range(len(boxes))]
 
 
-def _assert_maps_close(gpu, ref, what):
+# A receptor atom within CUT_BAND of the 8 A cutoff may fall on the other
+# side in the kernel's binary32 test than in the oracle's binary64 one.  Its
+# terms do not vanish there (at 8 A the surface distance is 3.9..4.3 A, where
+# gauss2 still weighs up to 0.0045 kcal/mol), so such points get that much
+# more slack per map value; they are counted and must stay rare.
+CUT_BAND = 1e-4
+CUT_SLACK = 0.005
+
+
+def _assert_maps_close(gpu, ref, margin, what, excused=None):
+    """Every map value within 1e-3 + 1e-4 |ref| of the oracle's; points whose
+    margin to the cutoff is below CUT_BAND also within CUT_SLACK more.
+    `margin` is per point ([nz][ny][nx] for whole maps, a scalar for one)."""
     err = np.abs(gpu.astype(np.float64) - ref)
-    tol = 1e-3 + 1e-4 * np.abs(ref)
+    near = np.asarray(margin) < CUT_BAND
+    tol = 1e-3 + 1e-4 * np.abs(ref) + np.where(near, CUT_SLACK, 0.0)
     bad = err > tol
     assert not bad.any(), "%s: %d of %d values off, worst %.3g at %s" % (
         what, int(bad.sum()), bad.size, float(err.max()), np.unravel_index(np.argmax(err - tol), err.shape))
+    if excused is not None:
+        excused[0] += int(np.sum(near))
+        excused[1] += int(np.asarray(near).size)
 
 
 def test_tiny_config_every_value(oracle, pv_ctx):
@@ -37,9 +53,12 @@ def test_tiny_config_every_value(oracle, pv_ctx):
     odims, oorg = oracle.lattice(bxs[0].center.astype(np.float64), bxs[0].size.astype(np.float64), bxs[0].spacing)
     np.testing.assert_array_equal(dims, odims)
     np.testing.assert_array_equal(org, oorg)
-    ref = oracle.build_maps(rx, rt, dims, org, bxs[0].spacing)
+    ref, margin = oracle.build_maps(rx, rt, dims, org, bxs[0].spacing, margin=True)
     assert maps[0].shape == ref.shape == (8, 55, 55, 55)
-    _assert_maps_close(maps[0], ref, "tiny")
+    exc = [0, 0]
+    _assert_maps_close(maps[0], ref, margin, "tiny", exc)
+    # the band holds about 1 % of the points at this receptor density
+    assert exc[0] <= 0.03 * exc[1], exc
 
 
 def test_five_pockets_sampled(oracle, pv_ctx):
@@ -52,8 +71,8 @@ def test_five_pockets_sampled(oracle, pv_ctx):
         assert list(dims) == [65, 65, 65]
         pts = [(0, 0, 0), (64, 64, 64), (64, 0, 32)] + [tuple(int(v) for v in g.integers(0, 65, 3)) for _ in range(300)]
         for i, j, k in pts:
-            ref = oracle.map_point(rx, rt, dims, org, box.spacing, i, j, k)
-            _assert_maps_close(maps[b][:, k, j, i], ref, "box %d point %s" % (b, (i, j, k)))
+            ref, mg = oracle.map_point(rx, rt, dims, org, box.spacing, i, j, k, margin=True)
+            _assert_maps_close(maps[b][:, k, j, i], ref, mg, "box %d point %s" % (b, (i, j, k)))
 
 
 def test_maps_reproducible_and_docks_repeat(pv_ctx):
@@ -95,8 +114,8 @@ def test_ragged_and_degenerate_boxes(oracle, pv_ctx):
     grids, maps = _gpu_maps(pv_ctx, rx, rt, boxes)
     for b, box in enumerate(boxes):
         dims, org = grids.info(b)
-        ref = oracle.build_maps(rx, rt, dims, org, box.spacing)
-        _assert_maps_close(maps[b], ref, "box %d dims %s" % (b, dims))
+        ref, margin = oracle.build_maps(rx, rt, dims, org, box.spacing, margin=True)
+        _assert_maps_close(maps[b], ref, margin, "box %d dims %s" % (b, dims))
     assert list(grids.info(1)[0]) == [2, 2, 2]
 
 
@@ -146,5 +165,5 @@ def test_box_size_sweep_sampled(oracle, pv_ctx):
         m = n - 1
         pts = [(0, 0, 0), (m, m, m), (m, 0, m // 2)] + [tuple(int(v) for v in g.integers(0, n, 3)) for _ in range(40)]
         for i, j, k in pts:
-            ref = oracle.map_point(rx, rt, dims, org, box.spacing, i, j, k)
-            _assert_maps_close(maps[b][:, k, j, i], ref, "box %d point %s" % (b, (i, j, k)))
+            ref, mg = oracle.map_point(rx, rt, dims, org, box.spacing, i, j, k, margin=True)
+            _assert_maps_close(maps[b][:, k, j, i], ref, mg, "box %d point %s" % (b, (i, j, k)))

@@ -26,16 +26,35 @@ def _small_receptor(seed, n, cube):
 
 
 def test_maps_two_paths_agree(oracle):
-    """Atom-major map build equals the point-major sum at sampled points."""
+    """Atom-major map build equals the point-major sum at sampled points, and
+    both report the same cutoff margin wherever an atom is near the cutoff."""
     rx, rt = _small_receptor(1, 300, 16.0)
     dims, org = oracle.lattice([8.0, 8.0, 8.0], [9.0, 7.5, 8.25], 0.375)
-    maps = oracle.build_maps(rx, rt, dims, org, 0.375)
+    maps, margin = oracle.build_maps(rx, rt, dims, org, 0.375, margin=True)
     g = np.random.default_rng(2)
     pts = [(0, 0, 0), (dims[0] - 1, dims[1] - 1, dims[2] - 1)]
     pts += [tuple(int(g.integers(0, dims[a])) for a in range(3)) for _ in range(60)]
     for i, j, k in pts:
-        ref = oracle.map_point(rx, rt, dims, org, 0.375, i, j, k)
+        ref, mg = oracle.map_point(rx, rt, dims, org, 0.375, i, j, k, margin=True)
         np.testing.assert_array_equal(maps[:, k, j, i], ref)
+        if mg < 0.01:
+            assert margin[k, j, i] == mg
+        else:
+            assert margin[k, j, i] >= 0.01
+
+
+def test_map_cutoff_margin_bruteforce(oracle):
+    """The margin is the smallest |r - 8| over the receptor atoms, r taken
+    from the binary32 receptor and lattice in binary64."""
+    rx, rt = _small_receptor(3, 120, 18.0)
+    dims, org = oracle.lattice([9.0, 9.0, 9.0], [6.0, 6.0, 6.0], 0.375)
+    g = np.random.default_rng(4)
+    for _ in range(40):
+        i, j, k = (int(g.integers(0, dims[a])) for a in range(3))
+        p = org.astype(np.float64) + 0.375 * np.array([i, j, k], np.float64)
+        r = np.sqrt(((p[None, :] - rx.astype(np.float64)) ** 2).sum(axis=1))
+        _, mg = oracle.map_point(rx, rt, dims, org, 0.375, i, j, k, margin=True)
+        assert mg == pytest.approx(np.abs(r - 8.0).min(), abs=1e-12)
 
 
 def test_map_single_atom_bruteforce(oracle):
@@ -50,14 +69,12 @@ def test_map_single_atom_bruteforce(oracle):
         gz = org[2].astype(np.float64) + 0.375 * np.arange(dims[2])
         Z, Y, X = np.meshgrid(gz, gy, gx, indexing="ij")
         r = np.sqrt((X - atom[0, 0]) ** 2 + (Y - atom[0, 1]) ** 2 + (Z - atom[0, 2]) ** 2)
+        # the cutoff is decided on this same binary64 distance, so the set of
+        # non-zero points is exactly the open 8 A ball
         inside = r < 8.0
-        # points within binary32 rounding of the cutoff are decided in binary32;
-        # they are few and left out of this check
-        sure = np.abs(r - 8.0) > 1e-5
-        assert sure.mean() > 0.999
-        assert np.all(maps[:, ~inside & sure] == 0.0)
-        assert np.all(maps[:, inside & sure] != 0.0)
-        sel = np.argwhere(inside & sure)[::97]
+        assert np.all(maps[:, ~inside] == 0.0)
+        assert np.all(maps[:, inside] != 0.0)
+        sel = np.argwhere(inside)[::97]
         for (k, j, i) in sel:
             for t in (0, 3, 5, 7):
                 assert maps[t, k, j, i] == pytest.approx(oracle.pair(t, rtype, r[k, j, i])[0], rel=1e-12)
