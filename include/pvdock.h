@@ -62,8 +62,10 @@ void pv_destroy(pv_ctx* ctx);
  * ligand atom type t, the lattice map
  *     M_t(g) = sum over receptor atoms r with |g - x_r| < 8 A of phi_{t,type_r}(|g - x_r|)
  * where phi is the Vina-form pair energy (gauss1, gauss2, repulsion,
- * hydrophobic, hydrogen bond of the surface distance).  The 8 A test is the
- * binary32 comparison fma(dx,dx,fma(dy,dy,dz*dz)) < 64 with g = fma(i,h,origin).
+ * hydrophobic, hydrogen bond of the surface distance).  The 8 A test is
+ * r < 8 on binary64 values (g = origin + h (i, j, k) and r from the binary32
+ * receptor coordinates, each operation rounded to binary64); the terms
+ * themselves are binary32.
  *
  * Lattice of a box: n = ceil(size/spacing) + 1 points per axis, origin =
  * binary32(center - (n-1) * spacing / 2) rounded once from binary64, points
@@ -154,7 +156,8 @@ pv_status pv_ligand_describe(int32_t n_atoms, const float* ref_xyz, const uint8_
  *   grad_dof [B][dof_stride]: grad_energy * dSF/d(t, q, psi), where the
  *   quaternion part is the derivative with respect to the raw input q;
  *   xyz_out, grad_xyz [B][xyz_stride][3]: atom coordinates and
- *   grad_energy * dSF/dx in the caller's atom order.
+ *   grad_energy * dSF/dx in the caller's atom order; rows past the pose's
+ *   ligand's atoms are 0, and every row of an out-of-range pose is NaN.
  * dof_stride >= 7 + max T; xyz_stride >= max atoms when xyz outputs are used. */
 pv_status pv_score_grad(pv_ctx* ctx, const pv_grids* grids, const pv_ligands* ligs, int32_t n_poses,
                         const int32_t* lig_of_pose, const int32_t* box_of_pose, const float* dof,

@@ -62,6 +62,11 @@ class McParams(C.Structure):
                 ("mut_rot_amp", C.c_double), ("seed", C.c_uint64)]
 
 
+class BfgsMargins(C.Structure):
+    _fields_ = [("armijo", C.c_double), ("wolfe", C.c_double), ("curvature", C.c_double),
+                ("descent", C.c_double), ("pose", C.c_double)]
+
+
 class OutputParams(C.Structure):
     _fields_ = [("modes", C.c_int32), ("refine_max_iter", C.c_int32), ("rmsd_cut", C.c_double),
                 ("affinity_w", C.c_double), ("bfgs", BfgsParams)]
@@ -102,6 +107,8 @@ def _declare(L):
     L.or_philox4x64_10.argtypes = [_u64p, _u64p, _u64p]
     L.or_bfgs.argtypes = [C.c_void_p, C.POINTER(_Grid), C.POINTER(BfgsParams), _dp, _dp, _dp,
                           _i64p, _ip]
+    L.or_bfgs_margins_run.argtypes = [C.c_void_p, C.POINTER(_Grid), C.POINTER(BfgsParams), _dp, _dp, _dp,
+                                      _i64p, _ip, C.POINTER(BfgsMargins)]
     L.or_bfgs_generic.argtypes = [C.c_int, EVAL_FN, C.c_void_p, C.POINTER(BfgsParams), _dp, _dp,
                                   _dp, _i64p, _ip]
     L.or_init_pose.argtypes = [C.c_void_p, C.POINTER(_Grid), C.c_uint64, C.c_int, C.c_int, _dp]
@@ -378,6 +385,21 @@ def bfgs(lig: Ligand, grid: Grid, x0, params: BfgsParams | None = None):
     lib().or_bfgs(lig.h, C.byref(grid.struct), C.byref(P), _p(x, _dp), _p(xo, _dp), C.byref(f),
                   C.byref(ne), C.byref(it))
     return xo, f.value, ne.value, it.value
+
+
+def bfgs_margins(lig: Ligand, grid: Grid, x0, params: BfgsParams | None = None):
+    """or_bfgs plus the margins of its decisions: (x, f, n_evals, n_iters,
+    {armijo, wolfe, curvature, descent, pose})."""
+    P = params if params is not None else bfgs_params()
+    x = _f64(x0)
+    xo = np.zeros(lig.ndof)
+    f = C.c_double()
+    ne = C.c_int64()
+    it = C.c_int32()
+    m = BfgsMargins()
+    lib().or_bfgs_margins_run(lig.h, C.byref(grid.struct), C.byref(P), _p(x, _dp), _p(xo, _dp), C.byref(f),
+                              C.byref(ne), C.byref(it), C.byref(m))
+    return xo, f.value, ne.value, it.value, {k: getattr(m, k) for k, _ in BfgsMargins._fields_}
 
 
 def bfgs_generic(fun, x0, params: BfgsParams | None = None):

@@ -824,9 +824,14 @@ typedef struct {
     int nx, nd;
 } bfgs_problem;
 
+/* How close a run came to deciding otherwise (see or_bfgs_margins). */
+static void margin_min(double* m, double v) { if (m && v < *m) *m = v; }
+
 static int bfgs_core(const bfgs_problem* pb, const or_bfgs_params* P, const double* x0,
-                     double* xout, double* fout, int64_t* n_evals, int32_t* n_iters)
+                     double* xout, double* fout, int64_t* n_evals, int32_t* n_iters,
+                     or_bfgs_margins* mg)
 {
+    if (mg) { mg->armijo = mg->wolfe = mg->curvature = mg->descent = INFINITY; }
     const int nd = pb->nd, nx = pb->nx, m = P->m > 0 ? P->m : 1;
     double *x = malloc(sizeof(double) * nx), *xt = malloc(sizeof(double) * nx),
            *xa = malloc(sizeof(double) * nx);
@@ -861,6 +866,9 @@ static int bfgs_core(const bfgs_problem* pb, const or_bfgs_params* P, const doub
         }
         for (int i = 0; i < nd; ++i) d[i] = -qv[i];
         double gd = dot(nd, g, d);
+        double d1 = 0.0;
+        for (int i = 0; i < nd; ++i) d1 += fabs(d[i]);
+        margin_min(mg ? &mg->descent : NULL, fabs(gd) / (1e-300 + d1 * (1.0 + gn)));
         if (!(gd < 0.0)) break;                    /* not a descent direction */
         /* Lewis-Overton bisection (Eqs. qvina_eq_7 and qvina_eq_8) */
         double a_lo = 0.0, lam = 1.0, lam_ok = -1.0, beta = 0.0;
@@ -868,6 +876,13 @@ static int bfgs_core(const bfgs_problem* pb, const or_bfgs_params* P, const doub
         for (int tr = 0; tr < P->ls_max; ++tr) {
             pb->retract(pb->ctx, x, d, lam, xt);
             pb->eval(pb->ctx, xt, &ft, gt); ++ne;
+            if (mg) {
+                double gmax = 0.0;
+                for (int i = 0; i < nd; ++i) gmax = fmax(gmax, fabs(gt[i]));
+                margin_min(&mg->armijo, fabs(ft - (f + P->rho * lam * gd)) / (1.0 + fabs(ft)));
+                if (!(ft > f + P->rho * lam * gd))
+                    margin_min(&mg->wolfe, fabs(dot(nd, gt, d) - P->sigma * gd) / (1e-300 + d1 * (1.0 + gmax)));
+            }
             if (ft > f + P->rho * lam * gd) {          /* Armijo fails: shrink */
                 beta = lam; beta_inf = 0;
             } else if (dot(nd, gt, d) < P->sigma * gd) { /* Wolfe fails: grow */
@@ -891,6 +906,7 @@ static int bfgs_core(const bfgs_problem* pb, const or_bfgs_params* P, const doub
         double* yv = ga;
         for (int i = 0; i < nd; ++i) { sv[i] = lam_ok * d[i]; yv[i] = gt[i] - g[i]; }
         double ys = dot(nd, yv, sv), ss = dot(nd, sv, sv);
+        margin_min(mg ? &mg->curvature : NULL, fabs(ys / ss - P->eps_c * gn) / (1e-300 + fabs(ys / ss) + P->eps_c * gn));
         if (ys / ss > P->eps_c * gn) {
             if (hn == m) { /* drop the oldest */
                 memmove(S, S + nd, sizeof(double) * (m - 1) * nd);
@@ -916,13 +932,15 @@ static int bfgs_core(const bfgs_problem* pb, const or_bfgs_params* P, const doub
     return 0;
 }
 
-typedef struct { const or_ligand* L; const or_grid* G; } pose_ctx;
+typedef struct { const or_ligand* L; const or_grid* G; double* min_flag; } pose_ctx;
 
 static void pose_eval(void* c, const double* x, double* f, double* g)
 {
     const pose_ctx* pc = (const pose_ctx*)c;
     double e3[3];
-    or_score_grad(pc->L, pc->G, x, e3, NULL, g, NULL, NULL, NULL);
+    or_flags fl;
+    or_score_grad(pc->L, pc->G, x, e3, NULL, g, NULL, NULL, pc->min_flag ? &fl : NULL);
+    if (pc->min_flag) margin_min(pc->min_flag, fmin(fl.min_face, fmin(fl.min_cut, fl.min_kink)));
     *f = e3[0];
 }
 
@@ -934,9 +952,19 @@ static void pose_retract(void* c, const double* x, const double* d, double lam, 
 int or_bfgs(const or_ligand* L, const or_grid* G, const or_bfgs_params* P,
             const double* x0, double* xout, double* fout, int64_t* n_evals, int32_t* n_iters)
 {
-    pose_ctx pc = {L, G};
+    pose_ctx pc = {L, G, NULL};
     bfgs_problem pb = {pose_eval, pose_retract, &pc, 7 + L->nt, 6 + L->nt};
-    return bfgs_core(&pb, P, x0, xout, fout, n_evals, n_iters);
+    return bfgs_core(&pb, P, x0, xout, fout, n_evals, n_iters, NULL);
+}
+
+int or_bfgs_margins_run(const or_ligand* L, const or_grid* G, const or_bfgs_params* P,
+                        const double* x0, double* xout, double* fout, int64_t* n_evals,
+                        int32_t* n_iters, or_bfgs_margins* mg)
+{
+    pose_ctx pc = {L, G, &mg->pose};
+    mg->pose = INFINITY;
+    bfgs_problem pb = {pose_eval, pose_retract, &pc, 7 + L->nt, 6 + L->nt};
+    return bfgs_core(&pb, P, x0, xout, fout, n_evals, n_iters, mg);
 }
 
 typedef struct { or_eval_fn fn; void* user; } flat_ctx;
@@ -966,7 +994,7 @@ int or_bfgs_generic(int n, or_eval_fn fn, void* user, const or_bfgs_params* P,
 {
     flat_ctx_n c = {{fn, user}, n};
     bfgs_problem pb = {flat_eval_n, flat_retract_n, &c, n, n};
-    return bfgs_core(&pb, P, x0, xout, fout, n_evals, n_iters);
+    return bfgs_core(&pb, P, x0, xout, fout, n_evals, n_iters, NULL);
 }
 
 /* ------------------------------------------------------------------ */
@@ -1103,7 +1131,7 @@ int or_mc_chain(const or_ligand* L, const or_grid* G, const or_mc_params* P,
     int32_t it;
     or_init_pose(L, G, P->seed, job, chain, cur);
     double e_cur;
-    pose_ctx pc = {L, G};
+    pose_ctx pc = {L, G, NULL};
     pose_eval(&pc, cur, &e_cur, gt); ++ne;
     double e_best = e_cur;
     memcpy(best_dof, cur, sizeof(double) * nx);

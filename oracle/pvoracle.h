@@ -108,6 +108,22 @@ int or_bfgs(const or_ligand* L, const or_grid* G, const or_bfgs_params* P,
  * psi + lam d_psi; x [7+nt], d [6+nt], o [7+nt] */
 void or_retract(int nt, const double* x, const double* d, double lam, double* o);
 
+/* The same run, reporting how close its decisions came to going the other
+ * way (test infrastructure: a binary32 run may take the other branch of a
+ * decision within its rounding).  Dimensionless margins, the smallest over
+ * the run:
+ *   armijo    |f_t - (f + rho lam g.d)| / (1 + |f_t|) over every trial;
+ *   wolfe     |g_t.d - sigma g.d| / (|d|_1 (1 + |g_t|_inf)) over trials that
+ *             passed Armijo;
+ *   curvature |y.s/s.s - eps_c |g|| / (|y.s/s.s| + eps_c |g|);
+ *   descent   |g.d| / (|d|_1 (1 + |g|));
+ *   pose      the smallest min(min_face, min_cut, min_kink) of any pose
+ *             evaluated (A). */
+typedef struct { double armijo, wolfe, curvature, descent, pose; } or_bfgs_margins;
+int or_bfgs_margins_run(const or_ligand* L, const or_grid* G, const or_bfgs_params* P,
+                        const double* x0, double* xout, double* fout, int64_t* n_evals,
+                        int32_t* n_iters, or_bfgs_margins* margins);
+
 /* the same BFGS on a flat R^n objective with an additive update */
 typedef void (*or_eval_fn)(void* user, const double* x, double* f, double* g);
 int or_bfgs_generic(int n, or_eval_fn fn, void* user, const or_bfgs_params* P,

@@ -1326,6 +1326,10 @@ __global__ __launch_bounds__(64) void score_kernel(ScoreArgs a)
             if (l == 0 && a.energy) a.energy[pose] = nanv;
             if (l < 2 && a.e_parts) a.e_parts[2 * (int64_t)pose + l] = nanv;
             if (a.grad_dof && l < a.dof_stride) a.grad_dof[(int64_t)pose * a.dof_stride + l] = nanv;
+            for (int k = l; k < 3 * a.xyz_stride; k += kWave) {
+                if (a.xyz_out && !a.from_xyz) a.xyz_out[(int64_t)pose * a.xyz_stride * 3 + k] = nanv;
+                if (a.grad_xyz) a.grad_xyz[(int64_t)pose * a.xyz_stride * 3 + k] = nanv;
+            }
             continue;
         }
         if (lig != T.lig) stage_ligand(T, a.l, lig, S);
@@ -1367,6 +1371,11 @@ __global__ __launch_bounds__(64) void score_kernel(ScoreArgs a)
             if (l < a.dof_stride) a.grad_dof[(int64_t)pose * a.dof_stride + l] = l < 7 + T.nt ? v * scale : 0.f;
         }
         if (a.xyz_out || a.grad_xyz) {
+            // rows past the ligand's atoms (a batch of mixed sizes) are zero
+            for (int k = 3 * T.n + l; k < 3 * a.xyz_stride; k += kWave) {
+                if (a.xyz_out && !a.from_xyz) a.xyz_out[(int64_t)pose * a.xyz_stride * 3 + k] = 0.f;
+                if (a.grad_xyz) a.grad_xyz[(int64_t)pose * a.xyz_stride * 3 + k] = 0.f;
+            }
             for (int i = l; i < T.n; i += kWave) {
                 const int64_t o = ((int64_t)pose * a.xyz_stride + perm[i]) * 3;
                 if (a.xyz_out) {
@@ -1602,13 +1611,30 @@ __global__ __launch_bounds__(64) void output_kernel(OutputArgs a)
 
 // ---------------------------------------------------------------- grid maps
 // One workgroup per 16x4x4 tile of one box (a wave writes 16-float = 64 B
-// rows).  Receptor atoms near the box are
+// rows).  A term enters the sum when r < 8 A, decided in binary32 where that
+// is unambiguous and in binary64 near the cutoff.  Receptor atoms near the box are
 // streamed in chunks of 256; those within reach of the tile's bounding box
 // are compacted into LDS in the atoms' order (a ballot per wave, the waves'
 // counts in wave order), so every point sums its terms in the same order on
 // every build and the maps are reproducible bit for bit; every lane adds the
 // candidates' terms to its point's 8 accumulators (one per ligand type).
 constexpr int kGridThreads = kTileX * kTileY * kTileZ;  // 256
+
+// The 8 A cutoff of a map term as r < 8 on binary64 values: the lattice
+// point origin + h i, the differences, squares and sum each rounded on its
+// own (no contraction), then the correctly rounded square root.  Used for
+// the few (point, atom) pairs whose binary32 squared distance lies within
+// 0.01 A^2 of 64, where binary32 rounding could decide the other way.
+__device__ __noinline__ bool within_cutoff_f64(int i, int j, int k, float ox, float oy, float oz, float h, float4 at)
+{
+#pragma clang fp contract(off)
+    const double gx = (double)ox + (double)h * (double)i;
+    const double gy = (double)oy + (double)h * (double)j;
+    const double gz = (double)oz + (double)h * (double)k;
+    const double dx = gx - (double)at.x, dy = gy - (double)at.y, dz = gz - (double)at.z;
+    const double s = dx * dx + dy * dy + dz * dz;
+    return __builtin_sqrt(s) < 8.0;
+}
 
 __global__ __launch_bounds__(256) void gridmap_kernel(GridBuildArgs a)
 {
@@ -1671,7 +1697,8 @@ __global__ __launch_bounds__(256) void gridmap_kernel(GridBuildArgs a)
             const float dx = gx - at.x, dy = gy - at.y, dz = gz - at.z;
             const float dz2 = dz * dz;
             const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz2));
-            if (!(r2 < kCut2)) continue;
+            if (!(r2 < kCut2 + 0.01f)) continue;
+            if (r2 > kCut2 - 0.01f && !within_cutoff_f64(i, j, k, ox, oy, oz, h, at)) continue;
             const float r = __builtin_amdgcn_sqrtf(r2);
             const int rt = __float_as_uint(at.w) & 0xff;
             const float Rr = rt <= 1 ? 1.9f : rt <= 4 ? 1.8f : rt <= 6 ? 1.7f : 2.0f;

@@ -21,28 +21,16 @@ def _gpu_maps(pv_ctx, rx, rt, boxes):
     return grids, [grids.maps(b).cpu().numpy() for b in range(len(boxes))]
 
 
-# A receptor atom within CUT_BAND of the 8 A cutoff may fall on the other
-# side in the kernel's binary32 test than in the oracle's binary64 one.  Its
-# terms do not vanish there (at 8 A the surface distance is 3.9..4.3 A, where
-# gauss2 still weighs up to 0.0045 kcal/mol), so such points get that much
-# more slack per map value; they are counted and must stay rare.
-CUT_BAND = 1e-4
-CUT_SLACK = 0.005
-
-
-def _assert_maps_close(gpu, ref, margin, what, excused=None):
-    """Every map value within 1e-3 + 1e-4 |ref| of the oracle's; points whose
-    margin to the cutoff is below CUT_BAND also within CUT_SLACK more.
-    `margin` is per point ([nz][ny][nx] for whole maps, a scalar for one)."""
+def _assert_maps_close(gpu, ref, what):
+    """Every map value within 1e-3 + 1e-4 |ref| of the oracle's.  Both sides
+    decide the 8 A cutoff as r < 8 in binary64, so a term is in both sums or
+    in neither (a wrong decision would move a value by the term's 8 A value,
+    up to 0.0045 kcal/mol)."""
     err = np.abs(gpu.astype(np.float64) - ref)
-    near = np.asarray(margin) < CUT_BAND
-    tol = 1e-3 + 1e-4 * np.abs(ref) + np.where(near, CUT_SLACK, 0.0)
+    tol = 1e-3 + 1e-4 * np.abs(ref)
     bad = err > tol
     assert not bad.any(), "%s: %d of %d values off, worst %.3g at %s" % (
         what, int(bad.sum()), bad.size, float(err.max()), np.unravel_index(np.argmax(err - tol), err.shape))
-    if excused is not None:
-        excused[0] += int(np.sum(near))
-        excused[1] += int(np.asarray(near).size)
 
 
 def test_tiny_config_every_value(oracle, pv_ctx):
@@ -53,12 +41,9 @@ def test_tiny_config_every_value(oracle, pv_ctx):
     odims, oorg = oracle.lattice(bxs[0].center.astype(np.float64), bxs[0].size.astype(np.float64), bxs[0].spacing)
     np.testing.assert_array_equal(dims, odims)
     np.testing.assert_array_equal(org, oorg)
-    ref, margin = oracle.build_maps(rx, rt, dims, org, bxs[0].spacing, margin=True)
+    ref = oracle.build_maps(rx, rt, dims, org, bxs[0].spacing)
     assert maps[0].shape == ref.shape == (8, 55, 55, 55)
-    exc = [0, 0]
-    _assert_maps_close(maps[0], ref, margin, "tiny", exc)
-    # the band holds about 1 % of the points at this receptor density
-    assert exc[0] <= 0.03 * exc[1], exc
+    _assert_maps_close(maps[0], ref, "tiny")
 
 
 def test_five_pockets_sampled(oracle, pv_ctx):
@@ -71,8 +56,8 @@ def test_five_pockets_sampled(oracle, pv_ctx):
         assert list(dims) == [65, 65, 65]
         pts = [(0, 0, 0), (64, 64, 64), (64, 0, 32)] + [tuple(int(v) for v in g.integers(0, 65, 3)) for _ in range(300)]
         for i, j, k in pts:
-            ref, mg = oracle.map_point(rx, rt, dims, org, box.spacing, i, j, k, margin=True)
-            _assert_maps_close(maps[b][:, k, j, i], ref, mg, "box %d point %s" % (b, (i, j, k)))
+            ref = oracle.map_point(rx, rt, dims, org, box.spacing, i, j, k)
+            _assert_maps_close(maps[b][:, k, j, i], ref, "box %d point %s" % (b, (i, j, k)))
 
 
 def test_maps_reproducible_and_docks_repeat(pv_ctx):
@@ -114,9 +99,57 @@ def test_ragged_and_degenerate_boxes(oracle, pv_ctx):
     grids, maps = _gpu_maps(pv_ctx, rx, rt, boxes)
     for b, box in enumerate(boxes):
         dims, org = grids.info(b)
-        ref, margin = oracle.build_maps(rx, rt, dims, org, box.spacing, margin=True)
-        _assert_maps_close(maps[b], ref, margin, "box %d dims %s" % (b, dims))
+        ref = oracle.build_maps(rx, rt, dims, org, box.spacing)
+        _assert_maps_close(maps[b], ref, "box %d dims %s" % (b, dims))
     assert list(grids.info(1)[0]) == [2, 2, 2]
+
+
+def _straddling_atoms(oracle, n_want, seed):
+    """Receptor atoms (binary32) placed within 3e-6 A of the 8 A cutoff from
+    chosen lattice points of a box whose origin is (0, 0, 0), kept when the
+    binary64 decision and a plain binary32 one (g = fma(i, h, 0), r2 =
+    fma(dx,dx,fma(dy,dy,dz*dz)) < 64) disagree, or, failing enough such, when
+    the atom lies within 1e-6 A of the cutoff.  Returns the atoms and their
+    target points."""
+    g = np.random.default_rng(seed)
+    h = np.float32(0.375)
+    atoms, pts = [], []
+    tries = 0
+    while len(atoms) < n_want and tries < 200000:
+        tries += 1
+        ijk = g.integers(0, 41, 3)
+        p = ijk.astype(np.float64) * 0.375
+        u = g.normal(size=3)
+        u /= np.linalg.norm(u)
+        a = (p + (8.0 + g.uniform(-3e-6, 3e-6)) * u).astype(np.float32)
+        if np.any(a < -10) or np.any(a > 25):
+            continue
+        d64 = np.sqrt(((p - a.astype(np.float64)) ** 2).sum())
+        gx = (ijk.astype(np.float32) * h).astype(np.float32)
+        dd = (gx - a).astype(np.float32)
+        r2 = np.float32(np.float64(dd[0]) * dd[0] + np.float32(np.float64(dd[1]) * dd[1] + np.float32(dd[2] * dd[2])))
+        disagree = (d64 < 8.0) != (r2 < np.float32(64.0))
+        if disagree or (tries > 100000 and abs(d64 - 8.0) < 1e-6):
+            atoms.append(a)
+            pts.append(tuple(int(v) for v in ijk))
+    return np.array(atoms, np.float32), pts
+
+
+def test_map_cutoff_decided_in_binary64(oracle, pv_ctx):
+    """Atoms within a few 1e-6 A of the cutoff from lattice points, chosen
+    where binary32 rounding would decide differently from binary64: the
+    kernel's map values at those points match the oracle's r < 8 decision."""
+    rx, pts = _straddling_atoms(oracle, 24, 5)
+    assert len(rx) >= 12
+    rt = np.array([0, 1, 2, 5, 7, 3] * 4, np.uint8)[:len(rx)]
+    box = S.Box(np.full(3, 7.5, np.float32), np.full(3, 15.0, np.float32), 0.375)
+    grids, maps = _gpu_maps(pv_ctx, rx, rt, [box])
+    dims, org = grids.info(0)
+    assert list(dims) == [41, 41, 41] and np.all(org == 0.0)
+    for i, j, k in pts:
+        ref, mg = oracle.map_point(rx, rt, dims, org, box.spacing, i, j, k, margin=True)
+        assert mg < 5e-6
+        _assert_maps_close(maps[0][:, k, j, i], ref, "point %s" % ((i, j, k),))
 
 
 def test_empty_receptor_gives_zero_maps(pv_ctx):
@@ -165,5 +198,5 @@ def test_box_size_sweep_sampled(oracle, pv_ctx):
         m = n - 1
         pts = [(0, 0, 0), (m, m, m), (m, 0, m // 2)] + [tuple(int(v) for v in g.integers(0, n, 3)) for _ in range(40)]
         for i, j, k in pts:
-            ref, mg = oracle.map_point(rx, rt, dims, org, box.spacing, i, j, k, margin=True)
-            _assert_maps_close(maps[b][:, k, j, i], ref, mg, "box %d point %s" % (b, (i, j, k)))
+            ref = oracle.map_point(rx, rt, dims, org, box.spacing, i, j, k)
+            _assert_maps_close(maps[b][:, k, j, i], ref, "box %d point %s" % (b, (i, j, k)))

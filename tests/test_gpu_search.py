@@ -267,3 +267,113 @@ def test_side_stream_launches(oracle, pv_ctx, tiny):
     plan.close()
     for k in ("chain_best_e", "chain_evals", "chain_best_dof", "job_best_e"):
         assert torch.equal(a[k], b[k]), k
+
+
+# ------------------------------------------------------------------ BFGS on real maps, run by run
+# On the differentiation workload's clash-dominated poses the BFGS iteration
+# is ill-conditioned: the oracle's own result after one or two iterations
+# moves by more than the energy tolerance when its start is perturbed at the
+# level of binary32 rounding (1e-6), because the step length times the
+# landscape's curvature amplifies input differences by 1e4..1e6.  A binary32
+# run cannot be held to such a case.  A case is compared run by run when it
+# is well conditioned: two perturbed oracle runs (tangent perturbations of
+# 1e-6) stay within a quarter of the tolerance of the unperturbed one, no
+# line-search, curvature or descent decision of the run lies within 1e-6
+# (relative) of its threshold, and no pose it evaluates has an atom within
+# 1e-5 A of a lattice plane or an intra pair within 1e-5 A of the cutoff or
+# a term kink (binary32 coordinates are rounded by at most 2e-6 A here).
+# Each excused case is counted.
+COND_EPS, COND_FLAG, COND_DECISION = 1e-6, 1e-5, 1e-6
+
+
+@pytest.fixture(scope="module")
+def c4(oracle, pv_ctx):
+    import paper_2506_20043_amd as pv
+    cfg = S.CONFIGS["differentiation"]
+    rx, rt, bxs = S.make_receptor(cfg)
+    mols = S.make_ligands(cfg)
+    b = bxs[0]
+    g = S.rng(cfg.index, S.STREAM_POSES)
+    og = oracle.Grid.build(rx, rt, b.center.astype(np.float64), b.size.astype(np.float64), b.spacing, kappa=KAPPA)
+    lo, hi = og.origin.astype(np.float64), og.origin + og.h * (og.dims - 1)
+    dof = S.poses(g, cfg.n_poses, lo, hi, 10)
+    lig = np.repeat(np.arange(cfg.n_ligands, dtype=np.int32), cfg.n_poses // cfg.n_ligands)
+    sel = np.sort(np.random.default_rng(2).choice(cfg.n_poses, 160, replace=False))
+    d0 = dof[sel].copy()
+    d0[:, 3:7] /= np.linalg.norm(d0[:, 3:7], axis=1, keepdims=True)
+    return dict(grids=pv.build_grids(pv_ctx, rx, rt, bxs[:1], penalty_slope=KAPPA), ligs=pv.Ligands(pv_ctx, mols),
+                og=og, ol=[oracle.Ligand(m.xyz, m.types, m.bonds, m.rotatable) for m in mols],
+                lig=lig[sel], dof=d0.astype(np.float32))
+
+
+def _well_conditioned(oracle, L, G, x, P, f, margins, tol, rng):
+    if min(margins["armijo"], margins["wolfe"], margins["curvature"], margins["descent"]) < COND_DECISION:
+        return False
+    if margins["pose"] < COND_FLAG:
+        return False
+    for _ in range(2):
+        xp = oracle.retract(L.n_tors, x, rng.normal(size=6 + L.n_tors) * COND_EPS, 1.0)
+        if abs(oracle.bfgs(L, G, xp, P)[1] - f) > 0.25 * tol:
+            return False
+    return True
+
+
+def test_bfgs_first_iterations_match_oracle_c4(oracle, pv_ctx, c4):
+    """From 160 differentiation-workload starts (40 atoms, 10 torsions, real
+    maps), RILC-BFGS capped at one and at two iterations: on every
+    well-conditioned case the GPU takes the same number of evaluations (the
+    same line-search trials) and ends at the oracle's energy within
+    1e-3 + 1e-4 |E|."""
+    import paper_2506_20043_amd as pv
+    rng = np.random.default_rng(9)
+    B = len(c4["lig"])
+    for iters, min_well in ((1, 60), (2, 20)):
+        p = pv.dock_params(bfgs_max_iter=iters)
+        P = oracle.bfgs_params(max_iter=iters)
+        _, e, ne = pv.local_opt(pv_ctx, c4["grids"], c4["ligs"], c4["lig"], np.zeros(B, np.int32), c4["dof"], p)
+        e, ne = e.cpu().numpy(), ne.cpu().numpy()
+        well = 0
+        for b in range(B):
+            L = c4["ol"][c4["lig"][b]]
+            x = cpu_dof(c4["dof"][b, :L.ndof])
+            _, f, n, _, m = oracle.bfgs_margins(L, c4["og"], x, P)
+            if not _well_conditioned(oracle, L, c4["og"], x, P, f, m, e_tol(f), rng):
+                continue
+            well += 1
+            assert ne[b] == n, (iters, b, ne[b], n)
+            assert abs(e[b] - f) <= e_tol(f), (iters, b, e[b], f)
+        print("BFGS capped at %d iteration(s): %d of %d cases well conditioned, all matching" % (iters, well, B))
+        assert well >= min_well, (iters, well)
+
+
+def test_bfgs_from_near_oracle_minimum_c4(oracle, pv_ctx, c4):
+    """Starts 0.01 (tangent units) away from the oracle's 30-iteration end
+    points: on every well-conditioned case (two perturbed oracle runs within
+    2.5e-4 kcal/mol) the GPU's 30-iteration BFGS reaches the oracle's
+    minimum within 1e-3 kcal/mol."""
+    import paper_2506_20043_amd as pv
+    rng = np.random.default_rng(10)
+    B = len(c4["lig"])
+    P = oracle.bfgs_params(max_iter=30)
+    starts = np.zeros_like(c4["dof"])
+    for b in range(B):
+        L = c4["ol"][c4["lig"][b]]
+        xe = oracle.bfgs(L, c4["og"], cpu_dof(c4["dof"][b, :L.ndof]), P)[0]
+        starts[b, :L.ndof] = oracle.retract(L.n_tors, xe, rng.normal(size=6 + L.n_tors) * 0.01, 1.0)
+    _, e, _ = pv.local_opt(pv_ctx, c4["grids"], c4["ligs"], c4["lig"], np.zeros(B, np.int32), starts,
+                           pv.dock_params(bfgs_max_iter=30))
+    e = e.cpu().numpy()
+    well = 0
+    for b in range(B):
+        L = c4["ol"][c4["lig"][b]]
+        x = cpu_dof(starts[b, :L.ndof])
+        _, f, _, _, m = oracle.bfgs_margins(L, c4["og"], x, P)
+        if m["pose"] < COND_FLAG or min(m["armijo"], m["wolfe"], m["curvature"], m["descent"]) < COND_DECISION:
+            continue
+        if any(abs(oracle.bfgs(L, c4["og"], oracle.retract(L.n_tors, x, rng.normal(size=6 + L.n_tors) * COND_EPS,
+                                                                   1.0), P)[1] - f) > 2.5e-4 for _ in range(2)):
+            continue
+        well += 1
+        assert abs(e[b] - f) <= 1e-3, (b, e[b], f)
+    print("BFGS from near the oracle's minima: %d of %d well conditioned, all within 1e-3" % (well, B))
+    assert well >= 50, well
