@@ -324,6 +324,29 @@ pv_status pv_dock_autotune(pv_plan* plan, int32_t tune_steps, int32_t repeats, v
 pv_status pv_dock(pv_ctx* ctx, const pv_grids* grids, const pv_ligands* ligs, const pv_job* jobs,
                   int32_t n_jobs, const pv_dock_params* params, const pv_dock_out* out, void* stream);
 
+/* Allocation-free dock, for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, checks and outputs as pv_dock (host jobs,
+ * device outputs), and the same outputs bit for bit: the jobs are split
+ * into the same size classes, each run by one persistent launch with the
+ * variant and width pv_dock_plan would choose.  It calls no hipMalloc,
+ * hipFree or other allocating routine: the job table, the per-class job
+ * maps, the queue counters and, when chain_best_e or chain_evals is NULL,
+ * those per-chain arrays live in one file-scope device array per GPU
+ * (about 12.8 MB, held from the first pv_create on that GPU until the
+ * process ends).  Limits: n_jobs <= PV_NOALLOC_MAX_JOBS and n_jobs x chains
+ * <= PV_NOALLOC_MAX_CHAINS (PV_E_RANGE otherwise).  Only the
+ * PV_DOCK_TIMESTAMPS flag is accepted (PV_E_INVALID for others).  Every call
+ * on a GPU shares that GPU's array, which keeps the last call's contents:
+ * calls on one device are serialised by a lock in the library and each
+ * returns only after its work has completed on `stream`, so calls from
+ * several host threads of one process do not overlap; anything else that
+ * wrote the array while a call ran would race with it. */
+#define PV_NOALLOC_MAX_JOBS 65536
+#define PV_NOALLOC_MAX_CHAINS 1048576
+pv_status pv_dock_noalloc(pv_ctx* ctx, const pv_grids* grids, const pv_ligands* ligs, const pv_job* jobs,
+                          int32_t n_jobs, const pv_dock_params* params, const pv_dock_out* out, void* stream);
+
 /* Local optimisation only: one BFGS run (the parameters' bfgs_* and ls_*
  * fields) from each of B poses.  dof_in, dof_out: device [B][dof_stride];
  * energy [B]; n_evals [B] (may be NULL).  dof_out quaternions are unit. */

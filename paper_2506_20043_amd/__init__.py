@@ -112,6 +112,8 @@ SIGNATURES = {
     "pv_plan_set_schedule": (C.c_int, [_vp, _i32, _i32, _i32]),
     "pv_dock_autotune": (C.c_int, [_vp, _i32, _i32, _vp, C.POINTER(TuneResult), _i32, _ip]),
     "pv_dock": (C.c_int, [_vp, _vp, _vp, C.POINTER(Job), _i32, C.POINTER(DockParams), C.POINTER(DockOut), _vp]),
+    "pv_dock_noalloc": (C.c_int, [_vp, _vp, _vp, C.POINTER(Job), _i32, C.POINTER(DockParams), C.POINTER(DockOut),
+                                  _vp]),
     "pv_local_opt": (C.c_int, [_vp, _vp, _vp, _i32, _vp, _vp, _vp, _i32, C.POINTER(DockParams), _vp, _vp, _vp, _vp]),
     "pv_launch_info": (C.c_int, [_vp, _vp, _i32, C.c_int64, _ip, _ip, _ip]),
     "pv_sas_build": (C.c_int, [_vp, _i32, _vp, _vp, _i32, _vp, C.c_float, _vp, C.POINTER(C.c_void_p)]),
@@ -559,6 +561,62 @@ def dock(ctx: Context, grids: Grids, ligs: Ligands, jobs, params: DockParams | N
     out = plan.run(plain=plain, stream=stream)
     _torch().cuda.synchronize(ctx.device)
     plan.close()
+    return out
+
+
+NOALLOC_MAX_JOBS, NOALLOC_MAX_CHAINS = 65536, 1 << 20
+
+
+def _job_array(jobs):
+    jobs = np.ascontiguousarray(jobs, np.int32).reshape(-1, 2)
+    arr = (Job * max(len(jobs), 1))()
+    for i, (l, b) in enumerate(jobs):
+        arr[i].ligand, arr[i].box = int(l), int(b)
+    return arr, len(jobs)
+
+
+def _dock_outputs(ctx, ligs, n_jobs, chains, chain_outputs=True):
+    """Device tensors for a dock's outputs and the pv_dock_out that names
+    them; without chain_outputs the per-chain arrays are left out (NULL)."""
+    torch = _torch()
+    dev = ctx.torch_device
+    nc = n_jobs * chains
+    out = dict(job_best_e=torch.empty(n_jobs, dtype=torch.float32, device=dev),
+               job_best_chain=torch.empty(n_jobs, dtype=torch.int32, device=dev),
+               job_evals=torch.empty(n_jobs, dtype=torch.int64, device=dev),
+               job_status=torch.empty(n_jobs, dtype=torch.int32, device=dev))
+    if chain_outputs:
+        out.update(chain_best_e=torch.empty(nc, dtype=torch.float32, device=dev),
+                   chain_best_dof=torch.zeros((nc, ligs.dof_stride), dtype=torch.float32, device=dev),
+                   chain_evals=torch.empty(nc, dtype=torch.int64, device=dev),
+                   chain_pairs=torch.empty(nc, dtype=torch.int64, device=dev),
+                   chain_grads=torch.empty(nc, dtype=torch.int64, device=dev))
+    o = DockOut()
+    for k, v in out.items():
+        setattr(o, k, v.data_ptr())
+    o.dof_stride = ligs.dof_stride
+    return out, o
+
+
+def dock_call(ctx: Context, grids: Grids, ligs: Ligands, jobs, params: DockParams, stream=None):
+    """pv_dock: plan, batched run and release in one call (returns after the
+    dock has completed); returns device tensors."""
+    arr, n = _job_array(jobs)
+    out, o = _dock_outputs(ctx, ligs, n, params.chains)
+    _check(lib().pv_dock(ctx.h, grids.h, ligs.h, arr, n, C.byref(params), C.byref(o), _stream(stream)), "pv_dock")
+    return out
+
+
+def dock_noalloc(ctx: Context, grids: Grids, ligs: Ligands, jobs, params: DockParams, chain_outputs=True,
+                 stream=None):
+    """pv_dock_noalloc: the same dock with no device allocation by the
+    library (its scratch is a static device array); returns the device
+    tensors allocated here for its outputs.  Without chain_outputs only the
+    per-job outputs are asked for."""
+    arr, n = _job_array(jobs)
+    out, o = _dock_outputs(ctx, ligs, n, params.chains, chain_outputs)
+    _check(lib().pv_dock_noalloc(ctx.h, grids.h, ligs.h, arr, n, C.byref(params), C.byref(o), _stream(stream)),
+           "pv_dock_noalloc")
     return out
 
 

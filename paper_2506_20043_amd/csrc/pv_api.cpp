@@ -74,6 +74,8 @@ struct pv_ctx {
     int n_cu;
     int lds_per_block;   // dynamic LDS bytes one workgroup may use
     uint32_t magic;
+    void* scratch;             // the device's allocation-free scratch (device address), or NULL
+    hipError_t scratch_err;    // why it is NULL
     std::mutex tune_mu;
     std::vector<TuneEntry> tune;
 };
@@ -209,6 +211,10 @@ pv_status pv_create(int32_t device, pv_ctx** out)
     c->n_cu = prop.multiProcessorCount;
     c->lds_per_block = (int)prop.sharedMemPerBlock;
     c->magic = 0x70766378u;
+    // the allocation-free entry point's scratch: its address on this device,
+    // taken once here with the device current (a failure is reported by
+    // pv_dock_noalloc, the only call that needs it)
+    c->scratch_err = noalloc_scratch(&c->scratch);
     *out = c;
     return PV_OK;
 }
@@ -1110,6 +1116,105 @@ pv_status pv_dock(pv_ctx* ctx, const pv_grids* grids, const pv_ligands* ligs, co
     pv_plan_free(P);
     if (st != PV_OK) return st;
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return PV_OK;
+}
+
+// ------------------------------------------------------------------ allocation-free dock
+// pv_dock without any allocation: the job table, the per-class job maps, the
+// queue counters and (when the caller takes none) the per-chain best
+// energies and evaluation counts live in the device's scratch array.  The
+// size classes, their LDS limits, variants and widths are those pv_dock_plan
+// gives the same jobs, so the outputs equal pv_dock's bit for bit.
+static std::mutex g_noalloc_mu[64];   // one per device: calls on a device share its scratch
+
+pv_status pv_dock_noalloc(pv_ctx* ctx, const pv_grids* grids, const pv_ligands* ligs, const pv_job* jobs,
+                          int32_t n_jobs, const pv_dock_params* params, const pv_dock_out* out, void* stream)
+{
+    pv_status st = check_pair(ctx, grids, ligs);
+    if (st != PV_OK) return st;
+    if ((st = check_search(params, true)) != PV_OK) return st;
+    if (params->flags & ~PV_DOCK_TIMESTAMPS) return fail(PV_E_INVALID, "only PV_DOCK_TIMESTAMPS is accepted here");
+    if (!out) return fail(PV_E_INVALID, "out is NULL");
+    if (n_jobs < 0) return fail(PV_E_INVALID, "n_jobs < 0");
+    if (n_jobs > 0 && !jobs) return fail(PV_E_INVALID, "jobs is NULL");
+    if (n_jobs > kNoAllocMaxJobs) return fail(PV_E_RANGE, "n_jobs above PV_NOALLOC_MAX_JOBS");
+    if ((int64_t)n_jobs * params->chains > kNoAllocMaxChains)
+        return fail(PV_E_RANGE, "n_jobs * chains above PV_NOALLOC_MAX_CHAINS");
+    if (out->chain_best_dof && (out->dof_stride < 7 + ligs->max_tors || out->dof_stride > 64))
+        return fail(PV_E_INVALID, "dof_stride must be 7 + max torsions .. 64");
+    if ((params->flags & PV_DOCK_TIMESTAMPS) && (!out->job_t_start || !out->job_t_end))
+        return fail(PV_E_INVALID, "timestamps requested without job_t_start / job_t_end");
+    // size classes on the host, as pv_dock_plan forms them: counts and the
+    // LDS limits of each (no allocation)
+    int32_t cnt[2] = {0, 0};
+    LigDev lv[2] = {lig_view(ligs), lig_view(ligs)};
+    for (int g = 0; g < 2; ++g) lv[g].max_atoms = lv[g].max_pairs = lv[g].max_tors = lv[g].max_ell = 0;
+    for (int32_t j = 0; j < n_jobs; ++j) {
+        if (jobs[j].ligand < 0 || jobs[j].ligand >= ligs->n_lig) return fail(PV_E_INVALID, "job names an unknown ligand");
+        if (jobs[j].box < 0 || jobs[j].box >= grids->n_boxes) return fail(PV_E_INVALID, "job names an unknown box");
+        const auto& in = (*ligs->info)[jobs[j].ligand];
+        LigDev& v = lv[in[0] > 64 ? 1 : 0];
+        ++cnt[in[0] > 64 ? 1 : 0];
+        v.max_atoms = std::max(v.max_atoms, in[0]);
+        v.max_tors = std::max(v.max_tors, in[2]);
+        v.max_pairs = std::max(v.max_pairs, in[3]);
+        v.max_ell = std::max(v.max_ell, in[8]);
+    }
+    if ((st = set_device(ctx)) != PV_OK) return st;
+    if (!ctx->scratch) return hip_fail(ctx->scratch_err, "scratch address (hipGetSymbolAddress)");
+    if (ctx->device < 0 || ctx->device >= 64) return fail(PV_E_RANGE, "device index above 63");
+    LaunchShape sh[2];
+    int32_t width[2] = {0, 0};
+    for (int g = 0; g < 2; ++g) {
+        if (!cnt[g]) continue;
+        const int64_t items = (int64_t)cnt[g] * params->chains;
+        hipError_t e = launch_shape(kKindDock, lv[g], items, ctx->n_cu, &sh[g]);
+        if (e != hipSuccess) return hip_fail(e, "dock launch shape");
+        const int64_t wg = params->workgroups > 0 ? params->workgroups : (int64_t)sh[g].per_cu * ctx->n_cu;
+        width[g] = (int32_t)std::min<int64_t>(wg, std::max<int64_t>(items, 1));
+    }
+    std::lock_guard<std::mutex> lk(g_noalloc_mu[ctx->device]);
+    const NoAllocLayout W = noalloc_layout(ctx->scratch);
+    hipStream_t s = (hipStream_t)stream;
+    float* cbe = out->chain_best_e ? out->chain_best_e : W.best;
+    int64_t* cev = out->chain_evals ? out->chain_evals : W.evals;
+    if (n_jobs > 0) {
+        static_assert(sizeof(pv_job) == sizeof(int2), "pv_job is two int32");
+        HIP_TRY(hipMemcpyAsync(W.jobs, jobs, (size_t)n_jobs * sizeof(int2), hipMemcpyHostToDevice, s), "job table copy");
+        HIP_TRY(launch_class_map(W.jobs, n_jobs, ligs->ligs, cnt[0], W.map, W.queues, s), "class map");
+    }
+    if (params->flags & PV_DOCK_TIMESTAMPS)
+        HIP_TRY(launch_reset_times(out->job_t_start, out->job_t_end, n_jobs, s), "reset");
+    for (int g = 0; g < 2; ++g) {
+        if (!cnt[g]) continue;
+        DockArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.g = grid_view(grids);
+        a.l = lv[g];
+        a.sp = to_sp(params);
+        a.jobs = W.jobs;
+        a.n_jobs = n_jobs;
+        a.queue = W.queues + g;
+        a.job_map = W.map + (g ? cnt[0] : 0);
+        a.n_items = (int64_t)cnt[g] * params->chains;
+        a.persistent = 1;
+        a.chain_best_e = cbe;
+        a.chain_best_dof = out->chain_best_dof;
+        a.chain_evals = cev;
+        a.chain_pairs = out->chain_pairs;
+        a.chain_grads = out->chain_grads;
+        a.job_t_start = out->job_t_start;
+        a.job_t_end = out->job_t_end;
+        a.dof_stride = out->dof_stride;
+        HIP_TRY(launch_dock(a, sh[g], width[g], s), "dock launch");
+    }
+    if (out->job_best_e || out->job_best_chain || out->job_evals || out->job_status)
+        HIP_TRY(launch_job_reduce(cbe, cev, n_jobs, params->chains, out->job_best_e, out->job_best_chain,
+                                  out->job_evals, out->job_status, s),
+                "job reduce");
+    // the scratch is reused by the next call on this device: return only
+    // once this call's work (and the read of the caller's host jobs) is done
+    HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
     return PV_OK;
 }
 

@@ -224,6 +224,39 @@ int sas_block_size();
 int output_lds_bytes(const LigDev& l, int chains, int modes);
 hipError_t launch_reset_times(uint64_t* t0, uint64_t* t1, int n, hipStream_t s);
 
+// Scratch of the allocation-free dock entry point, one file-scope device
+// array per GPU (see noalloc_scratch): the queue counters of the two size
+// classes, the job table, the per-class job maps and, for callers that take
+// no per-chain outputs, the chains' best energies and evaluation counts.
+constexpr int64_t kNoAllocMaxJobs = 65536;
+constexpr int64_t kNoAllocMaxChains = 1 << 20;   // jobs x chains
+struct NoAllocLayout {
+    uint32_t* queues;   // [2]
+    int2* jobs;         // [kNoAllocMaxJobs]
+    int32_t* map;       // [kNoAllocMaxJobs]: class 0 jobs, then class 1 jobs
+    float* best;        // [kNoAllocMaxChains]
+    int64_t* evals;     // [kNoAllocMaxChains]
+};
+constexpr size_t kNoAllocOffJobs = 256;
+constexpr size_t kNoAllocOffMap = kNoAllocOffJobs + 8 * kNoAllocMaxJobs;
+constexpr size_t kNoAllocOffBest = kNoAllocOffMap + 4 * kNoAllocMaxJobs;
+constexpr size_t kNoAllocOffEvals = kNoAllocOffBest + 4 * kNoAllocMaxChains;
+constexpr size_t kNoAllocBytes = kNoAllocOffEvals + 8 * kNoAllocMaxChains;
+inline NoAllocLayout noalloc_layout(void* base)
+{
+    char* b = (char*)base;
+    return {(uint32_t*)b, (int2*)(b + kNoAllocOffJobs), (int32_t*)(b + kNoAllocOffMap),
+            (float*)(b + kNoAllocOffBest), (int64_t*)(b + kNoAllocOffEvals)};
+}
+// Device address of the current device's scratch array, looked up once per
+// device (hipGetSymbolAddress with that device current) and kept.
+hipError_t noalloc_scratch(void** out);
+// Fills the per-class job maps in job order (ligands of at most 64 atoms
+// first, from map[0]; larger ones from map[n_small]) and zeroes both queue
+// counters.  One workgroup.
+hipError_t launch_class_map(const int2* jobs, int32_t n_jobs, const DevLig* ligs, int32_t n_small, int32_t* map,
+                            uint32_t* queues, hipStream_t s);
+
 // Tiles of the grid-map kernel.
 constexpr int kTileX = 16, kTileY = 4, kTileZ = 4;
 

@@ -18,6 +18,8 @@
 // Every workgroup is one wave of 64 lanes; all arithmetic is binary32.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "pv_internal.h"
 
 namespace pv {
@@ -1861,6 +1863,80 @@ __global__ __launch_bounds__(kSasThreads) void sas_features_kernel(const float4*
     if (valid)
 #pragma unroll
         for (int k = 0; k < 12; ++k) feat[(int64_t)p * 12 + k] = f[k];
+}
+
+// ---------------------------------------------------------------- allocation-free scratch
+// The allocation-free dock entry point keeps its scratch (kNoAllocBytes,
+// laid out by noalloc_layout) in this array.  Each GPU the library runs on
+// holds its own copy until the process ends.  Host code never passes the
+// array's name to a kernel: it takes the device address that
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+hipError_t noalloc_scratch(void** out)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    *out = nullptr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return hipSuccess;
+}
+
+// Stable split of the jobs into the two size classes, in chunks of 1024:
+// a ballot per wave ranks the members of each class inside the wave, and
+// the waves' counts, added in wave order, place them after the earlier
+// chunks.  Also zeroes the classes' queue counters.
+__global__ __launch_bounds__(1024) void class_map_kernel(const int2* jobs, int n_jobs, const DevLig* ligs,
+                                                         int n_small, int32_t* map, uint32_t* queues)
+{
+    __shared__ int wn0[16], wn1[16];
+    const int t = threadIdx.x, w = t / kWave;
+    if (t < 2) queues[t] = 0u;
+    int base0 = 0, base1 = n_small;
+    for (int c = 0; c < n_jobs; c += 1024) {
+        const int j = c + t;
+        const bool valid = j < n_jobs;
+        const bool big = valid && ligs[jobs[j].x].n_atoms > 64;
+        const bool small = valid && !big;
+        const uint64_t ms = __ballot(small), mb = __ballot(big);
+        if ((t & (kWave - 1)) == 0) { wn0[w] = __popcll(ms); wn1[w] = __popcll(mb); }
+        __syncthreads();
+        int off0 = 0, off1 = 0, tot0 = 0, tot1 = 0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int a = wn0[q], b = wn1[q];
+            off0 += q < w ? a : 0;
+            off1 += q < w ? b : 0;
+            tot0 += a;
+            tot1 += b;
+        }
+        const int r0 = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(ms >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ms, 0u));
+        const int r1 = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mb, 0u));
+        if (small) map[base0 + off0 + r0] = j;
+        if (big) map[base1 + off1 + r1] = j;
+        base0 += tot0;
+        base1 += tot1;
+        __syncthreads();   // every wave has read wn0 / wn1 before the next chunk writes them
+    }
+}
+
+hipError_t launch_class_map(const int2* jobs, int32_t n_jobs, const DevLig* ligs, int32_t n_small, int32_t* map,
+                            uint32_t* queues, hipStream_t s)
+{
+    hipLaunchKernelGGL(class_map_kernel, dim3(1), dim3(1024), 0, s, jobs, n_jobs, ligs, n_small, map, queues);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- launchers
