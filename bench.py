@@ -1,15 +1,21 @@
 #!/usr/bin/env python
 """Benchmark of the docking hot path on one MI355X.
 
-One step = one pass of the whole hot path over the multi-pocket workload:
-grid maps of 5 pockets rebuilt (the grid-map kernel), then Monte Carlo +
-RILC-BFGS docking of one 35-atom, 8-torsion ligand into every pocket, 256
-chains x 1,000 MC steps each, as one persistent hipGraph-replayed launch.
-Inputs are seeded and synthetic and stay resident in HBM.
+Headline: the screening stream -- 100,000 (ligand, pocket) jobs in seeded
+random order over the 16 pockets (20..30 A boxes, all maps resident in HBM)
+of an 8,000-atom receptor; ligands of 8..80 atoms and 0..20 torsions; 16
+Monte Carlo chains x 300 steps per job, every step a RILC-BFGS local
+optimisation (<= 30 iterations).  One bench step is 1/--steps of the stream
+(a contiguous slice of the seeded order) docked by the batched persistent
+launches (one per ligand size class, hipGraph-replayed), so --steps steps
+cover the whole stream; warm-up steps replay the first slices before the
+timed region.  Inputs are seeded and synthetic and stay resident in HBM.
 
-Prints one JSON line: docks/s (value), score+grad evaluations/s, the plain
-per-job launch path, the roofline of the dominant kernel (measured with HIP
-events on the stream the kernels run on) and the oracle timed on the host.
+Prints one JSON line: docks/s of the whole stream (value), score+grad
+evaluations/s, the per-job service time p50/p99, the roofline of the dominant
+kernel (HIP events on the stream the kernels run on), the oracle timed on the
+host on the first 64 jobs of the stream, and the secondary legs (the other
+workloads, the plain per-job launch path, the differentiation form).
 """
 import argparse
 import json
@@ -25,56 +31,72 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_VECTOR = 157.3e12   # MI355X vector FP32, FLOP/s
 PEAK_HBM = 8.0e12             # MI355X HBM3E, B/s
 MAP_BYTES_PER_ATOM = 32       # 8 trilinear corners x 4 B, per atom and evaluation
+METRIC = "ligand-pocket docks/s and score+grad evals/s, batched vs plain on 1 MI355X"
 
-# Algorithmic work of one evaluation, counted from the operations the method
-# needs, energy part and gradient part: per intra pair tested (difference,
-# squared distance); per pair inside the cutoff, the terms (20) and with the
-# gradient the derivative and the force on both atoms (16); per atom, the
-# frame transform and the trilinear value (48) and with the gradient the
-# trilinear gradient and the force/torque accumulation (43); per torsion, the
-# local rotation and the frame composition (109) and with the gradient the
+# Algorithmic work of one score+grad evaluation, the planning count of the
+# method's operations: 70 flops per intra pair (distance, the five terms and
+# their derivative, the forces on both atoms), 90 per atom (frame transform,
+# trilinear value and gradient, force and torque accumulation) and 60 per
+# torsion (local rotation, frame composition, torsion derivative); its
+# transcendentals count as one flop each.  Every evaluation counts in full.
+FLOP_PAIR, FLOP_ATOM, FLOP_TORS = 70, 90, 60
+
+
+def log(msg):
+    """Progress on stderr (stdout carries the one JSON line)."""
+    print("[bench %7.1fs] %s" % (time.perf_counter() - _T0, msg), file=sys.stderr, flush=True)
+
+
+_T0 = time.perf_counter()
+
+
+def flops_per_eval(n_pairs, n_atoms, n_tors):
+    return FLOP_PAIR * np.asarray(n_pairs, np.float64) + FLOP_ATOM * np.asarray(n_atoms, np.float64) + \
+        FLOP_TORS * np.asarray(n_tors, np.float64)
+
+
+# A lighter count, from the operations the kernel must perform once the
+# method is fixed: per intra pair tested 8 flops, per pair inside the cutoff
+# the terms (20) and with the gradient the derivative and both forces (16);
+# per atom the frame transform and trilinear value (48) and with the gradient
+# the trilinear gradient and force/torque accumulation (43); per torsion the
+# local rotation and frame composition (109) and with the gradient the
 # torsion derivative (32); per evaluation the root frame and the BFGS vector
 # work.  A line-search trial above the sufficient-decrease bound needs only
-# the energy (the kernel stops there), so the gradient part counts once per
-# evaluation that computed it.
-FLOP_PAIR_TEST = 8
-FLOP_PAIR_IN, FLOP_PAIR_IN_GRAD = 20, 16
-FLOP_ATOM, FLOP_ATOM_GRAD = 48, 43
-FLOP_TORS, FLOP_TORS_GRAD = 109, 32
-FLOP_EVAL = 50
-
-
-def flops_per_launch(n_evals, n_grads, pairs_in, n_atoms, n_tors, n_pairs, m=5):
-    energy = FLOP_PAIR_TEST * n_pairs + FLOP_ATOM * n_atoms + FLOP_TORS * n_tors + FLOP_EVAL
-    energy += (4 * m + 10) * (6 + n_tors)
-    grad = FLOP_ATOM_GRAD * n_atoms + FLOP_TORS_GRAD * n_tors
-    # pairs inside the cutoff are counted over all evaluations; their gradient
-    # share follows the share of evaluations with a gradient
-    share = n_grads / n_evals if n_evals else 0.0
-    return (float(n_evals) * energy + float(n_grads) * grad +
-            float(pairs_in) * (FLOP_PAIR_IN + share * FLOP_PAIR_IN_GRAD))
+# the energy, so the gradient part counts once per evaluation that computed
+# it.  Reported beside the headline count.
+def flops_light(n_evals, n_grads, pairs_in, n_atoms, n_tors, n_pairs, m=5):
+    n_evals = np.asarray(n_evals, np.float64)
+    n_grads = np.asarray(n_grads, np.float64)
+    energy = 8 * n_pairs + 48 * n_atoms + 109 * n_tors + 50 + (4 * m + 10) * (6 + n_tors)
+    grad = 43 * n_atoms + 32 * n_tors
+    share = np.where(n_evals > 0, n_grads / np.maximum(n_evals, 1), 0.0)
+    return float(np.sum(n_evals * energy + n_grads * grad + np.asarray(pairs_in, np.float64) * (20 + share * 16)))
 
 
 def main():
-    ap = argparse.ArgumentParser(description=__doc__)
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--chains", type=int, default=256)
-    ap.add_argument("--mc-steps", type=int, default=1000)
+    ap.add_argument("--steps", type=int, default=4, help="timed steps; each docks 1/steps of the stream")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed steps (replays of the first slices)")
+    ap.add_argument("--stream-jobs", type=int, default=100000, help="jobs of the screening stream (a prefix)")
+    ap.add_argument("--workers", type=int, default=16, help="processes generating the synthetic ligands")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-score", action="store_true")
-    ap.add_argument("--cpu-chains", type=int, default=128)
-    ap.add_argument("--workgroups", type=int, default=0)
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the uneven-batch (batched vs plain) and screening-stream legs")
-    ap.add_argument("--batch-ligands", type=int, default=256,
+                    help="skip every secondary leg (the headline, its oracle and the peaks only)")
+    ap.add_argument("--batch-ligands", type=int, default=4096,
                     help="ligands of the uneven batch (x 5 pockets = jobs)")
     ap.add_argument("--plain-jobs", type=int, default=20, help="jobs of the uneven batch run one launch each")
-    ap.add_argument("--stream-jobs", type=int, default=2048, help="jobs taken from the screening stream")
+    ap.add_argument("--stream-plain-jobs", type=int, default=48,
+                    help="jobs of the stream run one launch each (and batched) for the plain comparison")
+    ap.add_argument("--cpu-jobs", type=int, default=64, help="stream jobs the oracle docks on all host cores")
+    ap.add_argument("--chains", type=int, default=256, help="chains per pocket of the multi-pocket leg")
+    ap.add_argument("--mc-steps", type=int, default=1000, help="MC steps of the multi-pocket leg")
     ap.add_argument("--sweep-steps", type=int, default=1000, help="MC steps per chain in the box-size sweep")
-    ap.add_argument("--leg", choices=["score", "local_opt", "batching", "screening", "box_sweep", "surface"], default=None,
+    ap.add_argument("--leg", choices=["tiny", "multi_pocket", "score", "local_opt", "batching", "stream_plain",
+                                      "box_sweep", "surface"], default=None,
                     help="run only this secondary leg and print its JSON (for profiling it alone)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device (calibrates the HBM byte counters) and exit")
@@ -83,6 +105,9 @@ def main():
         print("bench.py measures one GPU; --gpus %d is not supported "
               "(across GPUs the work would shard by pocket, each GPU building only its pockets' maps)"
               % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    if args.steps < 1 or args.warmup < 0:
+        print("--steps must be >= 1 and --warmup >= 0", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -97,151 +122,236 @@ def main():
         print(json.dumps({"copy_calib_bytes": 4 * n}), flush=True)
         return
 
-    import paper_2506_20043_amd as pv
     from paper_2506_20043_amd import synth as S
+    workers = max(1, min(args.workers, len(os.sched_getaffinity(0))))
+    # synthetic inputs first, with forked workers, before the GPU is touched
+    need_batch = args.leg == "batching" or (args.leg is None and not args.no_extra)
+    need_stream = args.leg in (None, "stream_plain")
+    cfg5 = S.CONFIGS["screening"]
+    inputs = {}
+    t_gen = time.perf_counter()
+    if need_stream:
+        jobs5 = S.make_jobs(cfg5)[:args.stream_jobs]
+        used = np.unique(jobs5[:, 0])
+        mols5 = S.make_ligands_parallel("screening", int(used.max()) + 1, 0, workers)
+        inputs["stream"] = (S.make_receptor(cfg5), mols5, jobs5)
+    if need_batch:
+        inputs["batch"] = S.make_ligands_parallel("uneven_batch", args.batch_ligands, 0, workers)
+    gen_s = time.perf_counter() - t_gen
+    log("synthetic inputs generated in %.1f s" % gen_s)
 
+    import paper_2506_20043_amd as pv
+
+    ctx = pv.Context(0)
+    stream = torch.cuda.current_stream()
     if args.leg:
-        ctx = pv.Context(0)
-        stream = torch.cuda.current_stream()
-        legs = {"score": lambda: bench_score(pv, S, ctx, stream),
+        legs = {"tiny": lambda: bench_tiny(pv, S, ctx, stream, args),
+                "multi_pocket": lambda: bench_multi_pocket(pv, S, ctx, stream, args),
+                "score": lambda: bench_score(pv, S, ctx, stream),
                 "local_opt": lambda: bench_local_opt(pv, S, ctx, stream),
-                "batching": lambda: bench_batching(pv, S, ctx, stream, args),
-                "screening": lambda: bench_screening(pv, S, ctx, stream, args),
+                "batching": lambda: bench_batching(pv, S, ctx, stream, args, inputs["batch"]),
+                "stream_plain": lambda: bench_stream_plain(pv, S, ctx, stream, args, inputs["stream"]),
                 "box_sweep": lambda: bench_box_sweep(pv, S, ctx, stream, args),
                 "surface": lambda: bench_surface(pv, S, ctx, stream)}
         print(json.dumps({"leg": args.leg, "result": legs[args.leg]()}), flush=True)
         return
 
-    cfg = S.CONFIGS["multi_pocket"]
-    rx, rt, bxs = S.make_receptor(cfg)
-    mols = S.make_ligands(cfg)
-    seed = S.philox_seed(cfg)
-    ctx = pv.Context(0)
-    stream = torch.cuda.current_stream()
+    log("headline: screening stream, %d jobs in %d steps after %d warm-up steps"
+        % (len(inputs["stream"][2]), args.steps, args.warmup))
+    result, head = bench_stream(pv, S, ctx, stream, args, inputs["stream"])
+    log("headline: %.1f docks/s" % result["value"])
+    result["input_generation_s"] = gen_s
+
+    def leg(name, fn):
+        log("leg %s" % name)
+        return fn()
+
+    if not args.no_extra:
+        result["stream_plain"] = leg("stream_plain", lambda: bench_stream_plain(pv, S, ctx, stream, args,
+                                                                                inputs["stream"]))
+        result["batched_over_plain"] = result["value"] / result["stream_plain"]["plain"]["docks_per_s"]
+        result["tiny"] = leg("tiny", lambda: bench_tiny(pv, S, ctx, stream, args))
+        result["multi_pocket"] = leg("multi_pocket", lambda: bench_multi_pocket(pv, S, ctx, stream, args))
+        result["batching"] = leg("batching", lambda: bench_batching(pv, S, ctx, stream, args, inputs["batch"]))
+        if not args.no_score:
+            result["score_grad"] = leg("score", lambda: bench_score(pv, S, ctx, stream))
+            result["local_opt"] = leg("local_opt", lambda: bench_local_opt(pv, S, ctx, stream))
+        result["box_sweep"] = leg("box_sweep", lambda: bench_box_sweep(pv, S, ctx, stream, args))
+        result["surface"] = leg("surface", lambda: bench_surface(pv, S, ctx, stream))
+    result["measured_peaks"] = leg("measured_peaks", lambda: measure_peaks(pv, ctx, stream))
+    if not args.no_cpu:
+        result["cpu_baseline"] = leg("cpu_baseline (oracle)", lambda: cpu_baseline_stream(S, inputs["stream"], head,
+                                                                                         args))
+        if not args.no_extra:
+            result["tiny"]["oracle"] = leg("tiny oracle", lambda: cpu_oracle_tiny(S, args))
+            result["batching"]["oracle"] = leg("batch oracle", lambda: cpu_oracle_batch(S, inputs["batch"], args))
+    log("done")
+    print(json.dumps(result), flush=True)
+
+
+def _jobs_info(ligs, jobs):
+    """Per job: atoms, torsions and intra pairs of its ligand."""
+    inf = ligs.infos[np.asarray(jobs)[:, 0]]
+    return inf[:, 0].astype(np.int64), inf[:, 2].astype(np.int64), inf[:, 3].astype(np.int64)
+
+
+def bench_stream(pv, S, ctx, stream, args, inp):
+    """The headline: the screening stream in --steps slices of its seeded
+    order, each docked by one persistent launch per ligand size class
+    (ligands of at most 64 atoms, larger ones) with device timestamps."""
+    import torch
+    (rx, rt, bxs), mols, jobs = inp
+    cfg = S.CONFIGS["screening"]
+    n = len(jobs)
     grids = pv.build_grids(ctx, rx, rt, bxs, penalty_slope=10.0)
+    torch.cuda.synchronize()
+    grid_ms = min(_timed(stream, grids.rebuild) for _ in range(3))
     ligs = pv.Ligands(ctx, mols)
-    n_atoms, n_frag, n_tors, n_pairs = ligs.info(0)[:4]
-    jobs = [(0, b) for b in range(len(bxs))]
-    params = pv.dock_params(chains=args.chains, steps=args.mc_steps, seed=seed,
-                            flags=pv.PV_DOCK_GRAPH, workgroups=args.workgroups)
-    plan = pv.Plan(ctx, grids, ligs, jobs, params)
-    tuning = tune(plan, stream)
-    torch.cuda.synchronize()
+    N, T, P = _jobs_info(ligs, jobs)
+    big = N > 64
+    params = pv.dock_params(chains=cfg.chains, steps=cfg.steps, seed=S.philox_seed(cfg),
+                            flags=pv.PV_DOCK_GRAPH | pv.PV_DOCK_TIMESTAMPS)
+    K = args.steps
+    bounds = np.linspace(0, n, K + 1).astype(np.int64)
+    steps = []
+    for k in range(K):
+        sl = np.arange(bounds[k], bounds[k + 1])
+        cls = []
+        for c in (0, 1):
+            idx = sl[big[sl] == bool(c)]
+            cls.append((pv.Plan(ctx, grids, ligs, jobs[idx], params), idx) if len(idx) else None)
+        steps.append(cls)
 
-    def step():
-        grids.rebuild()
-        plan.run()
+    def run_step(k, evs=None):
+        for c in (0, 1):
+            if evs is not None:
+                evs[c].record(stream)
+            if steps[k][c] is not None:
+                steps[k][c][0].run()
+        if evs is not None:
+            evs[2].record(stream)
 
-    for _ in range(args.warmup):
-        step()
+    for w in range(args.warmup):
+        run_step(w % K)
     torch.cuda.synchronize()
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(args.steps):
-        ev[k][0].record(stream)
-        grids.rebuild()
-        ev[k][1].record(stream)
-        plan.run()
-        ev[k][2].record(stream)
+    for k in range(K):
+        run_step(k, evs[k])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    out = plan.outputs()
-    n_evals = int(out["job_evals"].sum().item())
-    pairs_in = int(out["chain_pairs"].sum().item())
-    n_grads = int(out["chain_grads"].sum().item())
-    grid_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
-    dock_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
-    ms_per_step = wall * 1e3 / args.steps
-    docks = len(jobs) * args.steps
-    docks_per_s = docks / wall
-    evals_per_s = n_evals * args.steps / wall
-    flops = flops_per_launch(n_evals, n_grads, pairs_in, n_atoms, n_tors, n_pairs)
-    achieved = flops / (dock_ms * 1e-3)
+    # outputs per job, in stream order
+    ev = np.zeros(n, np.int64)
+    grads = np.zeros(n, np.int64)
+    pin = np.zeros(n, np.int64)
+    tstart = np.zeros(n, np.int64)
+    tend = np.zeros(n, np.int64)
+    status = np.zeros(n, np.int32)
+    best = np.zeros(n, np.float32)
+    ms_cls = np.zeros((K, 2))
+    sched = [None, None]
+    for k in range(K):
+        for c in (0, 1):
+            ms_cls[k, c] = evs[k][c].elapsed_time(evs[k][c + 1])
+            if steps[k][c] is None:
+                continue
+            plan, idx = steps[k][c]
+            o = plan.outputs()
+            ch = plan.params.chains
+            ev[idx] = o["job_evals"].cpu().numpy()
+            grads[idx] = o["chain_grads"].cpu().numpy().reshape(-1, ch).sum(axis=1)
+            pin[idx] = o["chain_pairs"].cpu().numpy().reshape(-1, ch).sum(axis=1)
+            tstart[idx] = o["job_t_start"].cpu().numpy()
+            tend[idx] = o["job_t_end"].cpu().numpy()
+            status[idx] = o["job_status"].cpu().numpy()
+            best[idx] = o["job_best_e"].cpu().numpy()
+            if sched[c] is None:
+                sc = plan.schedule(0)
+                sched[c] = {"variant": VARIANTS[sc["variant"]], "workgroups": sc["workgroups"],
+                            "lds_bytes": sc["lds_bytes"], "per_cu": sc["per_cu"]}
+            plan.close()
+    svc = (tend - tstart) / 100.0                 # device clock, 100 MHz -> us
+    fl = ev * flops_per_eval(P, N, T)
+    dock_ms = float(ms_cls.sum())
+    cls_stats = []
+    for c in (0, 1):
+        m = big == bool(c)
+        ms_c = float(ms_cls[:, c].sum())
+        launches = int(sum(1 for k in range(K) if steps[k][c] is not None))
+        cls_stats.append({
+            "class": "ligands of at most 64 atoms" if c == 0 else "ligands of more than 64 atoms",
+            "kernel": "dock_kernel<%d, false>" % (1 if c == 0 else 2), "schedule": sched[c],
+            "jobs": int(m.sum()), "launches": launches, "launch_ms_mean": ms_c / max(launches, 1),
+            "evals": int(ev[m].sum()), "evals_per_s": float(ev[m].sum() / (ms_c * 1e-3)) if ms_c else 0.0,
+            "tflops": float(fl[m].sum() / (ms_c * 1e-3) / 1e12) if ms_c else 0.0})
+    dom = cls_stats[0]
+    dom_fl = float(fl[~big].sum())
+    achieved = dom_fl / (float(ms_cls[:, 0].sum()) * 1e-3)
+    light = flops_light(ev[~big], grads[~big], pin[~big], N[~big], T[~big], P[~big])
+    gather_b = float((ev * MAP_BYTES_PER_ATOM * N)[~big].sum())
+    map_mb = sum(8 * int(np.prod(grids.info(b)[0])) * 4 for b in range(len(bxs))) / 1e6
     result = {
-        "metric": "ligand-pocket docks/s and score+grad evals/s, batched vs plain on 1 MI355X",
-        "value": docks_per_s,
+        "metric": METRIC,
+        "value": n / wall,
         "unit": "docks/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": K,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": wall * 1e3 / K,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "data": "synthetic (seeded receptor, pockets and ligand; no datasets)",
+        "data": "synthetic (seeded receptor, pockets, ligands and job order; no datasets)",
         "config": {
-            "workload": "multi-pocket single ligand: 5,000-atom receptor in a 50 A cube, 5 pockets of 24 A "
-                        "at 0.375 A (65^3 x 8 FP32 maps each), one %d-atom ligand with %d torsions "
-                        "(%d intra pairs), %d chains x %d MC steps per pocket, BFGS <= 30 iterations; "
-                        "step = grid-map rebuild + batched persistent dock (hipGraph)"
-                        % (n_atoms, n_tors, n_pairs, args.chains, args.mc_steps),
-            "jobs": len(jobs), "chains": args.chains, "mc_steps": args.mc_steps,
-            "parallelism": "single GPU",
+            "workload": "screening stream: %d (ligand, pocket) jobs in seeded random order; 8,000-atom receptor "
+                        "in a 60 A cube, 16 pockets of 20..30 A at 0.375 A (%.0f MB of FP32 maps resident in HBM); "
+                        "%d ligands of 8..80 atoms / 0..20 torsions; 16 chains x 300 MC steps per job, BFGS <= 30 "
+                        "iterations; batched persistent launches (hipGraph), one per ligand size class; "
+                        "step = 1/%d of the stream" % (n, map_mb, len(mols), K),
+            "jobs": n, "chains": cfg.chains, "mc_steps": cfg.steps, "parallelism": "single GPU",
         },
-        "evals_per_s": evals_per_s,
-        "evals_per_step": n_evals,
-        "gradient_evals_per_step": n_grads,
-        "grid_ms": grid_ms,
+        "evals_per_s": float(ev.sum() / wall),
+        "evals": int(ev.sum()),
         "dock_ms": dock_ms,
-        "docks_per_s_without_grid_build": len(jobs) / (dock_ms * 1e-3),
-        "workgroups": plan_workgroups(plan),
-        "autotune": tuning,
+        "docks_per_s_with_grid_build": n / (wall + grid_ms * 1e-3),
+        "grid_build_ms_16_pockets": grid_ms,
+        "service_us_p50": float(np.percentile(svc, 50)),
+        "service_us_p99": float(np.percentile(svc, 99)),
+        "service_us_max": float(svc.max()),
+        "jobs_status_nonzero": int(np.sum(status != 0)),
+        "best_e_median": float(np.median(best)),
+        "classes": cls_stats,
+        "roofline": {
+            "bound": "alu",
+            "kernel": dom["kernel"] + " (persistent MC + BFGS, ligands of at most 64 atoms)",
+            "achieved": achieved / 1e12,
+            "peak": PEAK_FP32_VECTOR / 1e12,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_VECTOR,
+            "traffic": recorded_traffic(),
+            "flops_per_launch": dom_fl / max(dom["launches"], 1),
+            "flops_per_eval_mean": dom_fl / max(dom["evals"], 1),
+            "launch_ms": dom["launch_ms_mean"],
+            "flops_light": {"tflops": light / (float(ms_cls[:, 0].sum()) * 1e-3) / 1e12,
+                            "frac": light / (float(ms_cls[:, 0].sum()) * 1e-3) / PEAK_FP32_VECTOR},
+            "map_gather": {"bytes_per_launch": gather_b / max(dom["launches"], 1),
+                           "achieved_GBps": gather_b / (float(ms_cls[:, 0].sum()) * 1e-3) / 1e9,
+                           "peak_GBps": PEAK_HBM / 1e9,
+                           "frac": gather_b / (float(ms_cls[:, 0].sum()) * 1e-3) / PEAK_HBM},
+        },
     }
-    # plain path: one launch per job, same kernel and draws
-    if not args.no_plain:
-        plan.run(plain=True)
-        torch.cuda.synchronize()
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        plan.run(plain=True)
-        b.record(stream)
-        torch.cuda.synchronize()
-        plain_ms = a.elapsed_time(b)
-        result["plain"] = {"docks_per_s": len(jobs) / (plain_ms * 1e-3),
-                           "evals_per_s": n_evals / (plain_ms * 1e-3), "dock_ms": plain_ms}
-        result["batched_over_plain"] = plain_ms / dock_ms
-    result["roofline"] = {
-        "bound": "alu",
-        "kernel": "dock_kernel (persistent MC + BFGS)",
-        "achieved": achieved / 1e12,
-        "peak": PEAK_FP32_VECTOR / 1e12,
-        "unit": "TFLOP/s",
-        "frac": achieved / PEAK_FP32_VECTOR,
-        "traffic": recorded_traffic(),
-        "flops_per_launch": flops,
-        "launch_ms": dock_ms,
-        # the second ceiling: every evaluation reads 8 corners x 4 B per atom
-        # from the maps (L2 / Infinity Cache hits mostly), priced at HBM's peak
-        "map_gather": {"bytes_per_launch": MAP_BYTES_PER_ATOM * n_atoms * n_evals,
-                       "achieved_GBps": MAP_BYTES_PER_ATOM * n_atoms * n_evals / (dock_ms * 1e-3) / 1e9,
-                       "peak_GBps": PEAK_HBM / 1e9,
-                       "frac": MAP_BYTES_PER_ATOM * n_atoms * n_evals / (dock_ms * 1e-3) / PEAK_HBM},
-    }
-    result["output_stage"] = bench_output(pv, plan, stream)
-    if not args.no_extra:
-        result["consistency_check"] = bench_consistency(pv, ctx, grids, ligs, jobs, args, seed, stream,
-                                                        n_evals, dock_ms, plan.outputs())
-    if not args.no_score:
-        result["score_grad"] = bench_score(pv, S, ctx, stream)
-        result["local_opt"] = bench_local_opt(pv, S, ctx, stream)
-    if not args.no_extra:
-        result["batching"] = bench_batching(pv, S, ctx, stream, args)
-        result["screening"] = bench_screening(pv, S, ctx, stream, args)
-        result["box_sweep"] = bench_box_sweep(pv, S, ctx, stream, args)
-        result["surface"] = bench_surface(pv, S, ctx, stream)
-    result["measured_peaks"] = measure_peaks(pv, ctx, stream)
-    if not args.no_cpu:
-        result["cpu_baseline"] = cpu_baseline(S, cfg, rx, rt, bxs, mols, seed, args)
-    print(json.dumps(result), flush=True)
+    head = {"jobs": jobs, "ev": ev, "wall": wall, "n": n}
+    return result, head
 
 
 def recorded_traffic():
-    """HBM bytes per dock launch from the committed rocprofv3 counter record,
-    or None when the kernel sources changed since the counters were taken."""
+    """HBM bytes per launch of the dominant dock kernel from the committed
+    rocprofv3 counter record, or None when the kernel sources changed since
+    the counters were taken."""
     import hashlib
-    prof = os.path.join(ROOT, "profiles", "dock_kernel_multipocket.md")
+    prof = os.path.join(ROOT, "profiles", "dock_kernel_screening_stream.md")
     if not os.path.exists(prof):
         return None
     rec = None
@@ -259,6 +369,80 @@ def recorded_traffic():
 
 def plan_workgroups(plan):
     return int(plan.params.workgroups) if plan.params.workgroups else None
+
+
+def bench_multi_pocket(pv, S, ctx, stream, args):
+    """The multi-pocket single ligand: 5,000-atom receptor, 5 pockets of
+    24 A, one 35-atom / 8-torsion ligand, --chains chains x --mc-steps MC
+    steps per pocket as one persistent hipGraph launch (schedule from the
+    autotuner), against the plain path (one launch per pocket); then the
+    same dock gated by the consistency check, and the output stage."""
+    import torch
+    cfg = S.CONFIGS["multi_pocket"]
+    rx, rt, bxs = S.make_receptor(cfg)
+    mols = S.make_ligands(cfg)
+    seed = S.philox_seed(cfg)
+    grids = pv.build_grids(ctx, rx, rt, bxs, penalty_slope=10.0)
+    torch.cuda.synchronize()
+    grid_ms = min(_timed(stream, grids.rebuild) for _ in range(3))
+    ligs = pv.Ligands(ctx, mols)
+    n_atoms, n_frag, n_tors, n_pairs = ligs.info(0)[:4]
+    jobs = [(0, b) for b in range(len(bxs))]
+    params = pv.dock_params(chains=args.chains, steps=args.mc_steps, seed=seed, flags=pv.PV_DOCK_GRAPH)
+    plan = pv.Plan(ctx, grids, ligs, jobs, params)
+    tuning = tune(plan, stream)
+    plan.run()
+    torch.cuda.synchronize()
+    ms = min(_timed(stream, plan.run) for _ in range(2))
+    out = plan.outputs()
+    n_evals = int(out["job_evals"].sum().item())
+    fl = float(n_evals * flops_per_eval(n_pairs, n_atoms, n_tors))
+    res = {"workload": "multi-pocket single ligand: 5,000-atom receptor in a 50 A cube, 5 pockets of 24 A "
+                       "(65^3 x 8 FP32 maps each), one %d-atom ligand with %d torsions (%d intra pairs), %d chains "
+                       "x %d MC steps per pocket" % (n_atoms, n_tors, n_pairs, args.chains, args.mc_steps),
+           "dock_ms": ms, "docks_per_s": len(jobs) / (ms * 1e-3), "evals_per_s": n_evals / (ms * 1e-3),
+           "evals": n_evals, "grid_ms": grid_ms,
+           "docks_per_s_with_grid_build": len(jobs) / ((ms + grid_ms) * 1e-3),
+           "tflops": fl / (ms * 1e-3) / 1e12, "frac_fp32": fl / (ms * 1e-3) / PEAK_FP32_VECTOR,
+           "autotune": tuning}
+    if not args.no_plain:
+        plan.run(plain=True)
+        torch.cuda.synchronize()
+        plain_ms = _timed(stream, lambda: plan.run(plain=True))
+        res["plain"] = {"docks_per_s": len(jobs) / (plain_ms * 1e-3), "evals_per_s": n_evals / (plain_ms * 1e-3),
+                        "dock_ms": plain_ms}
+        res["batched_over_plain"] = plain_ms / ms
+    res["output_stage"] = bench_output(pv, plan, stream)
+    res["consistency_check"] = bench_consistency(pv, ctx, grids, ligs, jobs, args, seed, stream, n_evals, ms,
+                                                 plan.outputs())
+    plan.close()
+    return res
+
+
+def bench_tiny(pv, S, ctx, stream, args):
+    """The tiny configuration: 2,000-atom receptor, one 20 A pocket, one
+    20-atom / 4-torsion ligand, 8 chains x 200 MC steps, batched and plain."""
+    import torch
+    cfg = S.CONFIGS["tiny"]
+    rx, rt, bxs = S.make_receptor(cfg)
+    grids = pv.build_grids(ctx, rx, rt, bxs, penalty_slope=10.0)
+    torch.cuda.synchronize()
+    grid_ms = min(_timed(stream, grids.rebuild) for _ in range(3))
+    ligs = pv.Ligands(ctx, S.make_ligands(cfg))
+    params = pv.dock_params(chains=cfg.chains, steps=cfg.steps, seed=S.philox_seed(cfg), flags=pv.PV_DOCK_GRAPH)
+    plan = pv.Plan(ctx, grids, ligs, [(0, 0)], params)
+    plan.run()
+    torch.cuda.synchronize()
+    ms = min(_timed(stream, plan.run) for _ in range(3))
+    ms_plain = min(_timed(stream, lambda: plan.run(plain=True)) for _ in range(3))
+    out = plan.outputs()
+    ev = int(out["job_evals"].sum().item())
+    best = float(out["job_best_e"][0].item())
+    plan.close()
+    return {"workload": "tiny: 2,000-atom receptor in a 30 A cube, one 20 A pocket (55^3 x 8 maps), one 20-atom "
+                        "ligand with 4 torsions, 8 chains x 200 MC steps",
+            "grid_ms": grid_ms, "dock_ms": ms, "docks_per_s": 1.0 / (ms * 1e-3), "evals": ev,
+            "evals_per_s": ev / (ms * 1e-3), "plain_dock_ms": ms_plain, "job_best_e": best}
 
 
 def bench_score(pv, S, ctx, stream):
@@ -395,29 +579,30 @@ def _timed(stream, fn):
     return a.elapsed_time(b)
 
 
-def bench_batching(pv, S, ctx, stream, args):
-    """Batched vs plain on the uneven batch: ligands of 10..60 atoms and
-    0..15 torsions, each docked into the 5 pockets of the multi-pocket
-    receptor, 32 chains x 500 MC steps per job.  The batched form runs the
-    first --batch-ligands x 5 jobs as one persistent hipGraph launch, handing
-    out the most costly ligands' chains first (PV_DOCK_LARGEST_FIRST); the
-    plain form runs the first --plain-jobs jobs one launch each, and the same
-    jobs are also run batched."""
+def bench_batching(pv, S, ctx, stream, args, mols):
+    """Batched vs plain on the uneven batch: --batch-ligands ligands of
+    10..60 atoms and 0..15 torsions (4,096: the whole batch), each docked into
+    the 5 pockets of the multi-pocket receptor, 32 chains x 500 MC steps per
+    job, as one persistent hipGraph launch whose schedule the autotuner
+    picks, handing out the most costly ligands' chains first; the plain form
+    runs the first --plain-jobs jobs one launch each, and the same jobs are
+    also run batched."""
     import torch
     cfg = S.CONFIGS["uneven_batch"]
     rx, rt, bxs = S.make_receptor(cfg)
-    mols = S.make_ligands(cfg, args.batch_ligands)
     grids = pv.build_grids(ctx, rx, rt, bxs, penalty_slope=10.0)
     ligs = pv.Ligands(ctx, mols)
-    jobs = S.make_jobs(cfg)[:args.batch_ligands * len(bxs)]
+    jobs = S.make_jobs(cfg)[:len(mols) * len(bxs)]
     params = pv.dock_params(chains=cfg.chains, steps=cfg.steps, seed=S.philox_seed(cfg),
                             flags=pv.PV_DOCK_GRAPH | pv.PV_DOCK_LARGEST_FIRST)
     plan = pv.Plan(ctx, grids, ligs, jobs, params)
     tuning = tune(plan, stream, steps=10)
-    plan.run()
     torch.cuda.synchronize()
     ms = _timed(stream, plan.run)
-    ev = int(plan.outputs()["job_evals"].sum().item())
+    out = plan.outputs()
+    ev = int(out["job_evals"].sum().item())
+    N, T, P = _jobs_info(ligs, jobs)
+    fl = float((out["job_evals"].cpu().numpy() * flops_per_eval(P, N, T)).sum())
     variant = plan.schedule(0)["variant"]
     output = bench_output(pv, plan, stream)
     plan.close()
@@ -429,12 +614,12 @@ def bench_batching(pv, S, ctx, stream, args):
     ms_plain = _timed(stream, lambda: pplan.run(plain=True))
     ev_plain = int(pplan.outputs()["job_evals"].sum().item())
     pplan.close()
-    names = ["slots", "gather", "gather2"]
     return {
-        "workload": "uneven batch: ligands of 10..60 atoms / 0..15 torsions x 5 pockets of 24 A, "
-                    "32 chains x 500 MC steps per job",
+        "workload": "uneven batch: %d ligands of 10..60 atoms / 0..15 torsions x 5 pockets of 24 A (%d jobs), "
+                    "32 chains x 500 MC steps per job" % (len(mols), len(jobs)),
         "batched": {"jobs": len(jobs), "docks_per_s": len(jobs) / (ms * 1e-3), "evals_per_s": ev / (ms * 1e-3),
-                    "ms": ms, "variant": names[variant], "autotune": tuning},
+                    "ms": ms, "variant": VARIANTS[variant], "tflops": fl / (ms * 1e-3) / 1e12,
+                    "frac_fp32": fl / (ms * 1e-3) / PEAK_FP32_VECTOR, "autotune": tuning},
         "plain": {"jobs": len(few), "docks_per_s": len(few) / (ms_plain * 1e-3),
                   "evals_per_s": ev_plain / (ms_plain * 1e-3), "ms": ms_plain},
         "batched_same_jobs": {"jobs": len(few), "docks_per_s": len(few) / (ms_same * 1e-3), "ms": ms_same},
@@ -443,47 +628,30 @@ def bench_batching(pv, S, ctx, stream, args):
     }
 
 
-def bench_screening(pv, S, ctx, stream, args):
-    """The screening stream: an 8,000-atom receptor with 16 pockets of
-    20..30 A (all maps resident), ligands of 8..80 atoms / 0..20 torsions,
-    16 chains x 300 MC steps per job, jobs in the stream's seeded order.  The
-    first --stream-jobs jobs run as one persistent launch with per-job device
-    timestamps: service time = last chain done - first chain dequeued."""
+def bench_stream_plain(pv, S, ctx, stream, args, inp):
+    """Plain against batched on the same jobs of the screening stream: its
+    first --stream-plain-jobs jobs, one launch per job in order (the
+    per-ligand loop of the paper's engine), then as one batched launch."""
     import torch
+    (rx, rt, bxs), mols, jobs = inp
     cfg = S.CONFIGS["screening"]
-    rx, rt, bxs = S.make_receptor(cfg)
-    jobs = S.make_jobs(cfg)[:args.stream_jobs]
-    uniq, local = np.unique(jobs[:, 0], return_inverse=True)
-    mols = [S.make_ligands(cfg, 1, int(i))[0] for i in uniq]
+    few = jobs[:args.stream_plain_jobs]
     grids = pv.build_grids(ctx, rx, rt, bxs, penalty_slope=10.0)
-    torch.cuda.synchronize()
-    grid_ms = _timed(stream, grids.rebuild)
-    ligs = pv.Ligands(ctx, mols)
-    jl = np.stack([local.astype(np.int32), jobs[:, 1]], axis=1)
-    params = pv.dock_params(chains=cfg.chains, steps=cfg.steps, seed=S.philox_seed(cfg),
-                            flags=pv.PV_DOCK_GRAPH | pv.PV_DOCK_TIMESTAMPS)
+    ligs = pv.Ligands(ctx, [mols[i] for i in few[:, 0]])
+    jl = np.stack([np.arange(len(few), dtype=np.int32), few[:, 1]], axis=1)
+    params = pv.dock_params(chains=cfg.chains, steps=cfg.steps, seed=S.philox_seed(cfg), flags=pv.PV_DOCK_GRAPH)
     plan = pv.Plan(ctx, grids, ligs, jl, params)
-    tuning = tune(plan, stream, steps=10)
     plan.run()
     torch.cuda.synchronize()
     ms = _timed(stream, plan.run)
-    out = plan.outputs()
-    t0 = out["job_t_start"].cpu().numpy().astype(np.int64)
-    t1 = out["job_t_end"].cpu().numpy().astype(np.int64)
-    ev = int(out["job_evals"].sum().item())
+    ms_plain = _timed(stream, lambda: plan.run(plain=True))
+    ev = int(plan.outputs()["job_evals"].sum().item())
     plan.close()
-    svc = (t1 - t0) / 100.0          # device clock ticks at 100 MHz -> us
-    span = (t1.max() - t0.min()) / 100.0
-    map_mb = sum(8 * int(np.prod(grids.info(b)[0])) * 4 for b in range(len(bxs))) / 1e6
-    return {
-        "workload": "screening stream: 8,000-atom receptor, 16 pockets of 20..30 A (%.0f MB of maps), "
-                    "ligands of 8..80 atoms / 0..20 torsions, 16 chains x 300 MC steps, first %d jobs "
-                    "of the seeded order" % (map_mb, len(jobs)),
-        "jobs": len(jobs), "ms": ms, "docks_per_s": len(jobs) / (ms * 1e-3), "evals_per_s": ev / (ms * 1e-3),
-        "service_us_p50": float(np.percentile(svc, 50)), "service_us_p99": float(np.percentile(svc, 99)),
-        "service_us_max": float(svc.max()), "makespan_us": float(span), "grid_build_ms_16_pockets": grid_ms,
-        "autotune": tuning,
-    }
+    return {"workload": "screening stream, its first %d jobs" % len(few),
+            "batched": {"docks_per_s": len(few) / (ms * 1e-3), "evals_per_s": ev / (ms * 1e-3), "ms": ms},
+            "plain": {"docks_per_s": len(few) / (ms_plain * 1e-3), "evals_per_s": ev / (ms_plain * 1e-3),
+                      "ms": ms_plain},
+            "batched_over_plain_same_jobs": ms_plain / ms}
 
 
 def bench_box_sweep(pv, S, ctx, stream, args):
@@ -543,33 +711,71 @@ def bench_surface(pv, S, ctx, stream):
             "features_ms": feat_ms, "point_atom_pairs_per_s": n * len(rt) / (feat_ms * 1e-3)}
 
 
-def cpu_baseline(S, cfg, rx, rt, bxs, mols, seed, args):
-    """The FP64 oracle on the host: a bounded sample of the same dock (the
-    first --cpu-chains chains of pocket 0, all MC steps), scaled to docks/s."""
-    import oracle as O
-    b = bxs[0]
-    G = O.Grid.build(rx, rt, b.center.astype(np.float64), b.size.astype(np.float64), b.spacing, kappa=10.0)
-    m = mols[0]
-    L = O.Ligand(m.xyz, m.types, m.bonds, m.rotatable)
-    P = O.mc_params(args.cpu_chains, args.mc_steps, seed)
-    threads = len(os.sched_getaffinity(0))
+def _oracle_grids(O, rx, rt, bxs, which):
+    return {int(b): O.Grid.build(rx, rt, bxs[b].center.astype(np.float64), bxs[b].size.astype(np.float64),
+                                 bxs[b].spacing, kappa=10.0) for b in which}
+
+
+def _oracle_dock(O, mols, grids, jobs, cfg, seed, threads):
+    """The oracle's dock of jobs (ligand, box); returns (seconds,
+    evaluations)."""
+    ligs = {}
+    for l in np.unique(jobs[:, 0]):
+        m = mols[l]
+        ligs[int(l)] = O.Ligand(m.xyz, m.types, m.bonds, m.rotatable)
+    lk = sorted(ligs)
+    gk = sorted(grids)
+    oj = [(lk.index(int(l)), gk.index(int(b))) for l, b in jobs]
+    P = O.mc_params(cfg.chains, cfg.steps, seed)
     t0 = time.perf_counter()
-    res = O.dock([L], [G], [(0, 0)], P, n_threads=threads)
-    dt = time.perf_counter() - t0
-    evals = int(res["chain_evals"].sum())
-    frac = args.cpu_chains / args.chains
-    # one core: the first 4 chains of the same sample
-    P1 = O.mc_params(4, args.mc_steps, seed)
-    t1 = time.perf_counter()
-    r1 = O.dock([L], [G], [(0, 0)], P1, n_threads=1)
-    d1 = time.perf_counter() - t1
-    return {"value": frac / dt, "unit": "docks/s", "cores": threads, "kind": "oracle",
-            "sample": "pocket 0, %d of %d chains x %d MC steps (%.3f of one dock), %.1f s wall"
-                      % (args.cpu_chains, args.chains, args.mc_steps, frac, dt),
-            "evals_per_s": evals / dt, "cpu": cpu_model(),
-            "single_core": {"evals_per_s": int(r1["chain_evals"].sum()) / d1,
-                            "docks_per_s": (4 / args.chains) / d1,
-                            "sample": "pocket 0, 4 chains x %d MC steps, %.1f s" % (args.mc_steps, d1)}}
+    res = O.dock([ligs[k] for k in lk], [grids[k] for k in gk], oj, P, n_threads=threads)
+    return time.perf_counter() - t0, int(res["chain_evals"].sum())
+
+
+def cpu_baseline_stream(S, inp, head, args):
+    """The FP64 oracle on the host, on the first --cpu-jobs jobs of the
+    screening stream (all host cores, OpenMP over chains), and on the first
+    job alone on one core; both scaled to docks/s."""
+    import oracle as O
+    (rx, rt, bxs), mols, jobs = inp
+    cfg = S.CONFIGS["screening"]
+    seed = S.philox_seed(cfg)
+    few = jobs[:args.cpu_jobs]
+    grids = _oracle_grids(O, rx, rt, bxs, np.unique(few[:, 1]))
+    threads = len(os.sched_getaffinity(0))
+    dt, ev = _oracle_dock(O, mols, grids, few, cfg, seed, threads)
+    d1, ev1 = _oracle_dock(O, mols, grids, few[:1], cfg, seed, 1)
+    return {"value": len(few) / dt, "unit": "docks/s", "cores": threads, "kind": "oracle",
+            "sample": "screening stream, its first %d jobs (16 chains x 300 MC steps each), %.1f s wall"
+                      % (len(few), dt),
+            "evals_per_s": ev / dt, "evals": ev, "cpu": cpu_model(),
+            "single_core": {"docks_per_s": 1.0 / d1, "evals_per_s": ev1 / d1,
+                            "sample": "the stream's first job on one core, %.1f s" % d1}}
+
+
+def cpu_oracle_tiny(S, args):
+    """The oracle docking the whole tiny configuration on all host cores."""
+    import oracle as O
+    cfg = S.CONFIGS["tiny"]
+    rx, rt, bxs = S.make_receptor(cfg)
+    mols = S.make_ligands(cfg)
+    grids = _oracle_grids(O, rx, rt, bxs, [0])
+    threads = len(os.sched_getaffinity(0))
+    dt, ev = _oracle_dock(O, mols, grids, np.array([[0, 0]]), cfg, S.philox_seed(cfg), threads)
+    return {"docks_per_s": 1.0 / dt, "evals_per_s": ev / dt, "s": dt, "cores": threads, "sample": "in full"}
+
+
+def cpu_oracle_batch(S, mols, args):
+    """The oracle on the first 16 jobs of the uneven batch (all host cores)."""
+    import oracle as O
+    cfg = S.CONFIGS["uneven_batch"]
+    rx, rt, bxs = S.make_receptor(cfg)
+    jobs = S.make_jobs(cfg)[:16]
+    grids = _oracle_grids(O, rx, rt, bxs, np.unique(jobs[:, 1]))
+    threads = len(os.sched_getaffinity(0))
+    dt, ev = _oracle_dock(O, mols, grids, jobs, cfg, S.philox_seed(cfg), threads)
+    return {"docks_per_s": len(jobs) / dt, "evals_per_s": ev / dt, "s": dt, "cores": threads,
+            "sample": "the first %d jobs of the batch" % len(jobs)}
 
 
 def measure_peaks(pv, ctx, stream):

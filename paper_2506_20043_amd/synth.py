@@ -112,13 +112,14 @@ def tree_ligand(g: np.random.Generator, n_atoms: int, n_tors: int, bond: float =
             placed = False
             for _ in range(400):
                 cand = np.nonzero(deg[:a] < max_degree)[0]
-                p = int(g.choice(cand))
+                p = int(cand[g.integers(0, len(cand))])   # the draw Generator.choice(cand) makes
                 v = g.normal(size=3)
-                v /= np.linalg.norm(v)
+                v /= np.sqrt(v.dot(v))
                 x = xyz[p] + bond * v
-                d = np.linalg.norm(xyz[:a] - x, axis=1)
-                d[p] = np.inf
-                if d.min() >= min_sep:
+                diff = xyz[:a] - x
+                d2 = np.einsum("ij,ij->i", diff, diff)
+                d2[p] = np.inf
+                if np.sqrt(d2.min()) >= min_sep:
                     xyz[a] = x
                     deg[p] += 1
                     deg[a] += 1
@@ -209,6 +210,27 @@ def make_ligands(cfg: Config, count: int | None = None, first: int = 0):
         nt = int(g.integers(cfg.lig_tors[0], cfg.lig_tors[1] + 1))
         out.append(tree_ligand(g, na, nt))
     return out
+
+
+def _ligand_slice(args):
+    name, count, first = args
+    return make_ligands(CONFIGS[name], count, first)
+
+
+def make_ligands_parallel(key: str, count: int | None = None, first: int = 0, workers: int = 1):
+    """make_ligands(CONFIGS[key], count, first) split over `workers` forked
+    processes (the same ligands: each has its own sub-stream).  Call it
+    before the process initialises a GPU."""
+    cfg = CONFIGS[key]
+    n = cfg.n_ligands if count is None else count
+    if workers <= 1 or n < 64:
+        return make_ligands(cfg, n, first)
+    import multiprocessing as mp
+    step = (n + 4 * workers - 1) // (4 * workers)
+    parts = [(key, min(step, n - s), first + s) for s in range(0, n, step)]
+    with mp.get_context("fork").Pool(workers) as pool:
+        out = pool.map(_ligand_slice, parts)
+    return [m for part in out for m in part]
 
 
 def make_jobs(cfg: Config):

@@ -22,5 +22,5 @@ def test_more_than_one_gpu_is_refused():
 def test_help_lists_the_legs():
     r = _run("--help")
     assert r.returncode == 0
-    for leg in ("score", "local_opt", "batching", "screening", "box_sweep", "surface"):
+    for leg in ("tiny", "multi_pocket", "score", "local_opt", "batching", "stream_plain", "box_sweep", "surface"):
         assert leg in r.stdout
