@@ -47,7 +47,7 @@ struct alignas(16) DevFrag {
 // pslot (same index as the pair list): the slot the pair occupies in the
 // row of its first atom | in the row of its second atom << 16 (force-slot
 // layout: slot s of atom a at s * (n | 1) + a, slots below ell_w).
-// Atom -> pair table (ELL, [ell_w][n] words): entry k of atom i is
+// Atom -> pair table (ELL, [n][ell_w] words, rows 16-byte aligned): entry k of atom i is
 // p | j << 16, the k-th pair p (index into the pair list) that holds atom i
 // and its partner j; rows shorter than ell_w are padded with p = n_pairs
 // (a zero coefficient) and j = i.
@@ -61,7 +61,7 @@ struct LigModel {
     std::vector<int> tors_frag;     // torsion k -> fragment
     std::vector<uint32_t> pairs;    // i | j << 8 | rk << 16 | class << 19 (radius sum 3.4 + 0.1 rk;
                                     // class 0 plain, 1 hydrophobic, 2 hydrogen bond), grouped by class
-    std::vector<uint32_t> ell;      // [ell_w][n]
+    std::vector<uint32_t> ell;      // [n][ell_w]
     std::vector<uint32_t> pslot;    // per pair: slot in row i | slot in row j << 16
     int ell_w = 0;
     float anchor[3] = {0, 0, 0};

@@ -261,15 +261,16 @@ enum { SLOT_X = 0, SLOT_XT = 1, SLOT_XA = 2, SLOT_CUR = 3, SLOT_BEST = 4, kNSlot
 struct Lds {
     char* base;        // start of the workgroup's dynamic LDS
     float* pose;       // [kNSlots][kSlot]
-    float* frame;      // [kMaxFrag][12] frames, then [kMaxFrag] ancestor links
-    float4* pos;       // [ma + 1]; entry ma: a point far outside every box (LDS-table path)
-    float4* frc;       // [max_atoms]
+    float* frame;      // [kMaxFrag][12] frames, then [kMaxFrag] ancestor links / torsion derivatives
+                       // (without the frames: the [kMaxFrag] torsion derivatives only)
+    float4* pos;       // [ma + 1]; entry ma: a point far outside every box
+    float4* frc;       // [max_atoms] dE/dx per atom, or NULL when nothing reads it back
     float* pre;        // [6][max_atoms]
-    uint4* pairs;      // [max_pairs rounded up to kPairPass] pair records, LDS-table path (see stage_ligand)
-    float* cp;         // [max_pairs + 1] per-pair force coefficient (last = 0), global-table path
-    uint32_t* ell;     // unused in LDS (the global-table path reads the table from memory)
+    uint4* pairs;      // [max_pairs rounded up to kPairPass] pair records, slot layout (see stage_ligand)
+    float* cp;         // [max_pairs rounded up to kWave] per-pair force coefficient, gather layout
+    uint32_t* pw;      // [max_pairs rounded up to kWave] pair words, gather layout (padding: the far point)
     float4* fs;        // [max_ell + 1] pair forces in slot rows of n | 1 atoms (slot-major), then one
-                       // write-only slot for the padding records, LDS-table path
+                       // write-only slot for the padding records, slot layout
     int ma;
 };
 
@@ -300,41 +301,69 @@ __host__ __device__ inline int lds_atoms(int max_atoms) { return round_up(max_at
 // atoms, one atom per lane): the pair list sits in LDS, packed with the slots
 // each pair owns in its two atoms' rows, beside the per-slot pair forces, so
 // an atom's intra force is a stream of independent LDS reads.  Gather: the
-// pair list and the atom -> pair table are read from global memory and only
-// the per-pair coefficients live in LDS (a small footprint, for large
-// ligands or launches that need many resident waves).
-__host__ __device__ inline int lds_bytes(int max_atoms, int max_pairs, int max_ell, bool slots)
+// pair words and the per-pair coefficients live in LDS and the atom -> pair
+// table is read from global memory (a small footprint, for large ligands or
+// launches that need many resident waves).
+//
+// Optional regions: the per-atom forces (read back only by the score
+// kernel's coordinate gradient) and the fragment frames (needed when atoms
+// take their frames from LDS: two atoms per lane, and the output stage's
+// pose positions; with one atom per lane the frames travel by ds_bpermute
+// and only the torsion derivatives use the area).
+struct LdsNeeds {
+    bool slots, frc, frames;
+    bool pw;   // gather layout: the pair words in LDS too (one atom per lane), else read from global memory
+};
+
+__host__ __device__ inline int lds_bytes(int max_atoms, int max_pairs, int max_ell, LdsNeeds nd)
 {
-    int ma = lds_atoms(max_atoms);
-    int b = kNSlots * kSlot * 4 + kMaxFrag * 13 * 4 + 12 + (ma + 1) * 16 + ma * 16 + 6 * ma * 4;
-    if (slots) b += round_up(max_pairs < 1 ? 1 : max_pairs, kPairPass) * 16 + (max_ell + 1) * 16;
-    else b += round_up(max_pairs + 1, 4) * 4;
+    const int ma = lds_atoms(max_atoms);
+    int b = kNSlots * kSlot * 4 + (ma + 1) * 16 + 6 * ma * 4;
+    b += nd.frames ? kMaxFrag * 13 * 4 + 12 : round_up(kMaxFrag, 4) * 4;
+    if (nd.frc) b += ma * 16;
+    if (nd.slots) b += round_up(max_pairs < 1 ? 1 : max_pairs, kPairPass) * 16 + (max_ell + 1) * 16;
+    else b += (nd.pw ? 2 : 1) * round_up(max_pairs + 1, kWave) * 4;
     return b;
 }
 
-__device__ __forceinline__ Lds carve(char* base, int max_atoms, int max_pairs, int max_ell, bool slots)
+__device__ __forceinline__ Lds carve(char* base, int max_atoms, int max_pairs, int max_ell, LdsNeeds nd)
 {
     Lds s;
-    int ma = lds_atoms(max_atoms);
+    const int ma = lds_atoms(max_atoms);
     char* p = base;
     s.base = base;
     s.pos = (float4*)p; p += (ma + 1) * 16;
-    s.frc = (float4*)p; p += ma * 16;
     s.pose = (float*)p; p += kNSlots * kSlot * 4;
-    s.frame = (float*)p; p += kMaxFrag * 13 * 4 + 12;
     s.pre = (float*)p; p += 6 * ma * 4;
-    s.ell = nullptr;
-    if (slots) {
+    s.frc = nullptr;
+    if (nd.frc) { s.frc = (float4*)p; p += ma * 16; }
+    s.frame = (float*)p; p += nd.frames ? kMaxFrag * 13 * 4 + 12 : round_up(kMaxFrag, 4) * 4;
+    s.pairs = nullptr; s.fs = nullptr; s.cp = nullptr; s.pw = nullptr;
+    if (nd.slots) {
         s.pairs = (uint4*)p; p += round_up(max_pairs < 1 ? 1 : max_pairs, kPairPass) * 16;
         s.fs = (float4*)p;
-        s.cp = nullptr;
     } else {
-        s.cp = (float*)p;
-        s.pairs = nullptr;
-        s.fs = nullptr;
+        const int pp = round_up(max_pairs + 1, kWave);
+        s.cp = (float*)p; p += pp * 4;
+        if (nd.pw) s.pw = (uint32_t*)p;
     }
     s.ma = ma;
     return s;
+}
+
+// Torsion derivatives in LDS: after the frames (and their links) when the
+// frames are stored, else at the start of the frame area.
+__device__ __forceinline__ float* dpsi_area(const Lds& S, bool frames) { return frames ? S.frame + 12 * kMaxFrag : S.frame; }
+
+// The regions a kernel's LDS holds: per-atom forces for the score kernel's
+// coordinate gradient; frames for two atoms per lane and the output stage;
+// the pair words for one atom per lane on the gather layout (with two atoms
+// per lane the pair lists are long and the words stay in global memory, so
+// that LDS does not cut the resident waves).
+constexpr int kKindOutput = 3;
+__host__ __device__ inline LdsNeeds kernel_needs(int kind, int A, bool slots)
+{
+    return LdsNeeds{slots, kind == kKindScore, A > 1 || kind == kKindOutput, !slots && A == 1};
 }
 
 // ---------------------------------------------------------------- staged ligand
@@ -382,8 +411,8 @@ __device__ void stage_ligand(Topo<A, SL>& T, const LigDev& L, int lig, const Lds
     T.dof_frag = (l >= 6 && l < 6 + T.nt) ? (int)L.tors_frag[d.tors_base + l - 6] : 0;
     T.gpairs = L.pairs + d.pair_base;
     T.gell = L.ell + d.ell_base;
+    if (l == 0) S.pos[S.ma] = make_float4(1e18f, 1e18f, 1e18f, 0.f);
     if (SL) {
-        if (l == 0) S.pos[S.ma] = make_float4(1e18f, 1e18f, 1e18f, 0.f);
         // Pair record, everything the pair loop needs without decoding:
         //   x: LDS byte addresses of both positions (i | j << 16; S.pos opens
         //      the LDS, so both fit) | class << 30
@@ -416,7 +445,14 @@ __device__ void stage_ligand(Topo<A, SL>& T, const LigDev& L, int lig, const Lds
         }
         for (int k = l; k < nfs; k += kWave) S.fs[k] = make_float4(0.f, 0.f, 0.f, 0.f);   // padding stays zero
     } else {
-        if (l == 0) S.cp[T.np] = 0.f;
+        // one atom per lane: pair words up to a whole pass of 64 in LDS; the padding pairs join the far
+        // point to atom 0, so they fall outside the cutoff and store c = 0
+        // (which also serves the atom -> pair table's padding entries, p = np)
+        if (A == 1) {
+            const int npad = round_up(T.np + 1, kWave);
+            for (int p = l; p < npad; p += kWave) S.pw[p] = p < T.np ? T.gpairs[p] : (uint32_t)S.ma;
+        }
+        if (l == 0) S.cp[T.np] = 0.f;   // not written by the pair loop when np is a multiple of 64
     }
     wave_sync();
 }
@@ -507,94 +543,133 @@ __device__ __forceinline__ void frames(const Topo<A, SL>& T, const Lds& S, const
 typedef float f3v __attribute__((ext_vector_type(3)));
 constexpr float kLog2e = 1.4426950408889634f;
 
+// One pass of U pairs per lane starting at pair p0 (this lane's first);
+// adds this lane's energy to e and its pairs inside the cutoff to cnt.
+template <int A, bool SL, int U>
+__device__ __forceinline__ void pair_pass(const Topo<A, SL>& T, const Lds& S, int p0, float& e, int& cnt)
+{
+    const uint32_t pos0 = lds_addr(S.pos);
+    // position addresses; slot addresses; radius sum bits (slots) or
+    // radius-sum code | class << 3 (gather)
+    uint32_t ai[U], aj[U], ya[U], za[U], rc[U];
+    bool v[U];
+    float4 xi[U], xj[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int p = p0 + u * kWave;
+        if (SL) {
+            const uint4 w = S.pairs[p];
+            ai[u] = w.x & 0xffffu; aj[u] = w.x >> 16;   // the class sits above bit 29: kept for the test
+            ya[u] = w.y; za[u] = w.z; rc[u] = w.w;
+            v[u] = true;
+        } else {
+            // LDS pair words are padded to whole passes of 64 with far-point
+            // pairs; from global memory, a lane past the end reads pair 0
+            // (np >= 1 here) and discards it (an unconditional load, so all
+            // of a pass's loads stay in flight together)
+            uint32_t g;
+            if (A == 1) {
+                g = S.pw[p];
+                v[u] = true;
+            } else {
+                v[u] = p < T.np;
+                g = T.gpairs[v[u] ? p : 0];
+            }
+            ai[u] = pos0 + ((g & 0xffu) << 4); aj[u] = pos0 + (((g >> 8) & 0xffu) << 4);
+            rc[u] = g >> 16;
+            ya[u] = za[u] = 0u;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        xi[u] = *(const float4*)lds_ptr<const float4>(ai[u]);
+        xj[u] = *(const float4*)lds_ptr<const float4>(aj[u] & 0x3fffu);
+    }
+    float dx[U], dy[U], dz[U], d[U], en[U], de[U], rinv[U];
+    bool in[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        dx[u] = xi[u].x - xj[u].x; dy[u] = xi[u].y - xj[u].y; dz[u] = xi[u].z - xj[u].z;
+        const float r2 = dx[u] * dx[u] + dy[u] * dy[u] + dz[u] * dz[u];
+        in[u] = v[u] && r2 < kCut2;
+        // one v_rsq_f32: r = r2 / sqrt(r2) and c = de / r = de * rsq; a
+        // zero distance gets a tiny finite r and its zero direction
+        // zeroes the force
+        const float r2c = fmaxf(r2, 1e-12f);
+        rinv[u] = __builtin_amdgcn_rsqf(r2c);
+        const float rs = SL ? __uint_as_float(rc[u]) : fmaf((float)(rc[u] & 7u), 0.1f, 3.4f);
+        const float dd = r2c * rinv[u] - rs;
+        d[u] = dd;
+        const float g1 = __builtin_amdgcn_exp2f(dd * dd * (-4.f * kLog2e));          // exp(-(d/0.5)^2)
+        const float dm3 = dd - 3.f;
+        const float g2 = __builtin_amdgcn_exp2f(dm3 * dm3 * (-0.25f * kLog2e));      // exp(-((d-3)/2)^2)
+        const float dn = fminf(dd, 0.f);                                             // repulsion d^2, d < 0
+        en[u] = fmaf(kW1, g1, fmaf(kW2, g2, kW3 * (dn * dn)));
+        de[u] = fmaf(g1, dd * (-8.f * kW1), fmaf(g2, dm3 * (-0.5f * kW2), dn * (2.f * kW3)));
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        // class 1 (both hydrophobic) adds the hydrophobic term, class 2
+        // (donor with acceptor) the hydrogen-bond term
+        const uint32_t cls = SL ? aj[u] >> 14 : rc[u] >> 3;
+        if (__ballot(cls != 0u)) {
+            const float wy = cls == 1u ? kW4 : 0.f, wz = cls == 2u ? kW5 : 0.f;
+            const float dd = d[u];
+            const float hv = fminf(fmaxf(1.5f - dd, 0.f), 1.f);            // 1 below 0.5, 0 above 1.5
+            const float bv = fminf(fmaxf(dd * -(1.f / 0.7f), 0.f), 1.f);   // 1 below -0.7, 0 above 0
+            en[u] = fmaf(wy, hv, fmaf(wz, bv, en[u]));
+            const float hs = (dd >= 0.5f && dd < 1.5f) ? -wy : 0.f;
+            const float bs = (dd >= -0.7f && dd < 0.f) ? wz * -(1.f / 0.7f) : 0.f;
+            de[u] += hs + bs;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        e += in[u] ? en[u] : 0.f;
+        cnt += in[u] ? 1 : 0;
+        const float c = in[u] ? de[u] * rinv[u] : 0.f;
+        if (SL) {
+            // 12-byte writes (ds_write_b96) into the 16-byte slots; the
+            // gather reads x, y, z
+            const float fx = c * dx[u], fy = c * dy[u], fz = c * dz[u];
+            *(f3v*)lds_ptr<f3v>(ya[u]) = f3v{fx, fy, fz};
+            *(f3v*)lds_ptr<f3v>(za[u]) = f3v{-fx, -fy, -fz};
+        } else if (v[u]) {
+            S.cp[p0 + u * kWave] = c;
+        }
+    }
+}
+
+// Intra pairs, lanes over pairs: whole passes of kPairUnroll pairs per lane
+// (every load of a pass issued before any of its arithmetic, so the LDS
+// latency is paid once per pass), then, on the gather layout, passes of one
+// pair per lane over the rest, so at most 63 padding pairs are evaluated.
+// Per pair, with d the surface distance and inside 8 A: the gauss,
+// repulsion, hydrophobic and hydrogen-bond terms of the Vina form and the
+// force coefficient c = (dphi/dr) / r.  Pairs are grouped by interaction
+// class, so a whole 64-pair chunk usually has no hydrophobic or
+// hydrogen-bond weight and skips those terms on a wave-uniform branch.  With
+// the slot layout each pair writes +f / -f into its slots of the two atoms'
+// rows (records padded to whole passes, no per-lane guard); otherwise it
+// stores c for the table gather.  No atomics either way.  Returns this
+// lane's energy; adds this lane's pairs inside the cutoff to cnt.
 template <int A, bool SL>
 __device__ __forceinline__ float pair_loop(const Topo<A, SL>& T, const Lds& S, int& cnt)
 {
-    constexpr int U = kPairUnroll;
     const int l = lane_id();
     const int np = T.np;
-    const uint32_t pos0 = lds_addr(S.pos);
     float e = 0.f;
-    for (int p0 = l; p0 - l < np; p0 += kPairPass) {
-        // position addresses; slot addresses; radius sum bits (slots) or
-        // radius-sum code | class << 3 (gather)
-        uint32_t ai[U], aj[U], ya[U], za[U], rc[U];
-        bool v[U];
-        float4 xi[U], xj[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int p = p0 + u * kWave;
-            if (SL) {
-                const uint4 w = S.pairs[p];
-                ai[u] = w.x & 0xffffu; aj[u] = w.x >> 16;   // the class sits above bit 29: kept for the test
-                ya[u] = w.y; za[u] = w.z; rc[u] = w.w;
-                v[u] = true;
-            } else {
-                // a lane past the end reads pair 0 (np >= 1 here) and discards it
-                v[u] = p < np;
-                const uint32_t g = T.gpairs[v[u] ? p : 0];
-                ai[u] = pos0 + ((g & 0xffu) << 4); aj[u] = pos0 + (((g >> 8) & 0xffu) << 4);
-                rc[u] = g >> 16;
-                ya[u] = za[u] = 0u;
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            xi[u] = *(const float4*)lds_ptr<const float4>(ai[u]);
-            xj[u] = *(const float4*)lds_ptr<const float4>(aj[u] & 0x3fffu);
-        }
-        float dx[U], dy[U], dz[U], d[U], en[U], de[U], rinv[U];
-        bool in[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            dx[u] = xi[u].x - xj[u].x; dy[u] = xi[u].y - xj[u].y; dz[u] = xi[u].z - xj[u].z;
-            const float r2 = dx[u] * dx[u] + dy[u] * dy[u] + dz[u] * dz[u];
-            in[u] = v[u] && r2 < kCut2;
-            // one v_rsq_f32: r = r2 / sqrt(r2) and c = de / r = de * rsq; a
-            // zero distance gets a tiny finite r and its zero direction
-            // zeroes the force
-            const float r2c = fmaxf(r2, 1e-12f);
-            rinv[u] = __builtin_amdgcn_rsqf(r2c);
-            const float rs = SL ? __uint_as_float(rc[u]) : fmaf((float)(rc[u] & 7u), 0.1f, 3.4f);
-            const float dd = r2c * rinv[u] - rs;
-            d[u] = dd;
-            const float g1 = __builtin_amdgcn_exp2f(dd * dd * (-4.f * kLog2e));          // exp(-(d/0.5)^2)
-            const float dm3 = dd - 3.f;
-            const float g2 = __builtin_amdgcn_exp2f(dm3 * dm3 * (-0.25f * kLog2e));      // exp(-((d-3)/2)^2)
-            const float dn = fminf(dd, 0.f);                                             // repulsion d^2, d < 0
-            en[u] = fmaf(kW1, g1, fmaf(kW2, g2, kW3 * (dn * dn)));
-            de[u] = fmaf(g1, dd * (-8.f * kW1), fmaf(g2, dm3 * (-0.5f * kW2), dn * (2.f * kW3)));
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            // class 1 (both hydrophobic) adds the hydrophobic term, class 2
-            // (donor with acceptor) the hydrogen-bond term
-            const uint32_t cls = SL ? aj[u] >> 14 : rc[u] >> 3;
-            if (__ballot(cls != 0u)) {
-                const float wy = cls == 1u ? kW4 : 0.f, wz = cls == 2u ? kW5 : 0.f;
-                const float dd = d[u];
-                const float hv = fminf(fmaxf(1.5f - dd, 0.f), 1.f);            // 1 below 0.5, 0 above 1.5
-                const float bv = fminf(fmaxf(dd * -(1.f / 0.7f), 0.f), 1.f);   // 1 below -0.7, 0 above 0
-                en[u] = fmaf(wy, hv, fmaf(wz, bv, en[u]));
-                const float hs = (dd >= 0.5f && dd < 1.5f) ? -wy : 0.f;
-                const float bs = (dd >= -0.7f && dd < 0.f) ? wz * -(1.f / 0.7f) : 0.f;
-                de[u] += hs + bs;
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            e += in[u] ? en[u] : 0.f;
-            cnt += in[u] ? 1 : 0;
-            const float c = in[u] ? de[u] * rinv[u] : 0.f;
-            if (SL) {
-                // 12-byte writes (ds_write_b96) into the 16-byte slots; the
-                // gather reads x, y, z
-                const float fx = c * dx[u], fy = c * dy[u], fz = c * dz[u];
-                *(f3v*)lds_ptr<f3v>(ya[u]) = f3v{fx, fy, fz};
-                *(f3v*)lds_ptr<f3v>(za[u]) = f3v{-fx, -fy, -fz};
-            } else if (v[u]) {
-                S.cp[p0 + u * kWave] = c;
-            }
+    int p0 = l;
+    if (SL) {
+        for (; p0 - l < np; p0 += kPairPass) pair_pass<A, SL, kPairUnroll>(T, S, p0, e, cnt);
+    } else {
+        if (A > 1) {
+            // two atoms per lane (ligands of 65 to 128 atoms, long pair
+            // lists): whole passes only, over pair words padded to them
+            for (; p0 - l < np; p0 += kPairPass) pair_pass<A, SL, kPairUnroll>(T, S, p0, e, cnt);
+        } else {
+            for (; p0 - l + kPairPass <= np; p0 += kPairPass) pair_pass<A, SL, kPairUnroll>(T, S, p0, e, cnt);
+            for (; p0 - l < np; p0 += kWave) pair_pass<A, SL, 1>(T, S, p0, e, cnt);
         }
     }
     return e;
@@ -607,7 +682,6 @@ template <int A, bool SL>
 __device__ __forceinline__ void gather_pair_forces(const Topo<A, SL>& T, const Lds& S, int i, float4 xi, float& gx,
                                                    float& gy, float& gz)
 {
-    const int n = T.n;
     if (SL) {
         // eight independent reads in flight per group (rows are padded to a
         // multiple of four, so at most one group of four is left)
@@ -630,13 +704,13 @@ __device__ __forceinline__ void gather_pair_forces(const Topo<A, SL>& T, const L
         }
         return;
     }
-    // unsigned 32-bit offsets from the table's base let the loads use a
-    // scalar base plus one vector offset
+    // the atom's row is contiguous ([n][ell_w], ell_w a multiple of four):
+    // one 16-byte load per four entries, at an unsigned 32-bit offset from
+    // the table's base (a scalar base plus one vector offset)
+    const char* row = (const char*)T.gell + (uint32_t)(i * T.ell_w * 4);
     for (int k = 0; k < T.ell_w; k += 4) {
-        uint32_t e[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-            e[u] = *(const uint32_t*)((const char*)T.gell + (uint32_t)(((k + u) * n + i) * 4));
+        const uint4 e4 = *(const uint4*)(row + (uint32_t)(k * 4));
+        const uint32_t e[4] = {e4.x, e4.y, e4.z, e4.w};
         float c[4];
         float4 xj[4];
 #pragma unroll
@@ -676,6 +750,11 @@ __device__ Eval evaluate(const Topo<A, SL>& T, const BoxView& B, const Lds& S, c
     Eval out;
     float R[9], b[3];
     frames(T, S, pose, R, b);
+    // the world axis of this fragment lane's torsion, the one use of the
+    // frame after the atom positions (so R and b need not stay live)
+    const float awx = R[0] * T.ax + R[1] * T.ay + R[2] * T.az;
+    const float awy = R[3] * T.ax + R[4] * T.ay + R[5] * T.az;
+    const float awz = R[6] * T.ax + R[7] * T.ay + R[8] * T.az;
     if (A > 1) {
         if (l < T.nf) {
             float* fr = S.frame + 12 * l;
@@ -715,23 +794,30 @@ __device__ Eval evaluate(const Topo<A, SL>& T, const BoxView& B, const Lds& S, c
             X4[a] = make_float4(0.f, 0.f, 0.f, 0.f);
             G[a][0] = G[a][1] = G[a][2] = 0.f;
             if (i < T.n) {
-                const int ty = __float_as_uint(T.ref[a].w) & 0xff;
                 X4[a] = atom_position(T.ref[a], S);
                 S.pos[i] = X4[a];
-                tri_issue(B, ty, X4[a].x, X4[a].y, X4[a].z, TL[a]);
             }
         }
     }
     wave_sync();
     int cnt = 0;
-    const float e_ia = pair_loop(T, S, cnt);   // hides the map loads
+    const float e_ia = pair_loop(T, S, cnt);   // hides the map loads (one atom per lane)
     // the energy sums start here, so their cross-lane steps overlap the
     // force gather and the scans below
     out.e_intra = wsum(e_ia);
     wave_sync();
+    if (A > 1) {
+        // two atoms per lane: the map loads start only now, since holding
+        // both lookups across the pair loop would cost a resident wave
+#pragma unroll
+        for (int a = 0; a < A; ++a)
+            if (l * A + a < T.n)
+                tri_issue(B, __float_as_uint(T.ref[a].w) & 0xff, X4[a].x, X4[a].y, X4[a].z, TL[a]);
+    }
 #pragma unroll
     for (int a = 0; a < A; ++a)
-        if (l * A + a < T.n) e_in += tri_finish(B, TL[a], G[a][0], G[a][1], G[a][2]);
+        if (l * A + a < T.n)
+            e_in += tri_finish(B, TL[a], G[a][0], G[a][1], G[a][2]);
     out.e_inter = wsum(e_in);
     out.e = out.e_inter + out.e_intra;
     out.pairs_in = cnt;
@@ -752,7 +838,7 @@ __device__ Eval evaluate(const Topo<A, SL>& T, const BoxView& B, const Lds& S, c
         const int i = l * A + a;
         float rx = 0, ry = 0, rz = 0;
         if (i < T.n) {
-            S.frc[i] = make_float4(G[a][0], G[a][1], G[a][2], 0.f);
+            if (S.frc) S.frc[i] = make_float4(G[a][0], G[a][1], G[a][2], 0.f);
             rx = X4[a].x - tx; ry = X4[a].y - ty; rz = X4[a].z - tz;
         }
         run[0] += G[a][0]; run[1] += G[a][1]; run[2] += G[a][2];
@@ -793,12 +879,9 @@ __device__ Eval evaluate(const Topo<A, SL>& T, const BoxView& B, const Lds& S, c
         const float mx = Sg[3] - (cy * Sg[2] - cz * Sg[1]);
         const float my = Sg[4] - (cz * Sg[0] - cx * Sg[2]);
         const float mz = Sg[5] - (cx * Sg[1] - cy * Sg[0]);
-        const float awx = R[0] * T.ax + R[1] * T.ay + R[2] * T.az;
-        const float awy = R[3] * T.ax + R[4] * T.ay + R[5] * T.az;
-        const float awz = R[6] * T.ax + R[7] * T.ay + R[8] * T.az;
         dpsi = awx * mx + awy * my + awz * mz;
     }
-    float* dps = S.frame + 12 * kMaxFrag;   // reuse the link area
+    float* dps = dpsi_area(S, A > 1);
     if (l >= 1 && l < T.nf) dps[l] = dpsi;
     wave_sync();
     const int last = T.n - 1;
@@ -829,7 +912,7 @@ __device__ Eval evaluate_xyz(const Topo<A, SL>& T, const BoxView& B, const Lds& 
             float gx, gy, gz;
             e_in += trilinear(B, ty, p.x, p.y, p.z, gx, gy, gz);
             gather_pair_forces(T, S, i, p, gx, gy, gz);
-            S.frc[i] = make_float4(gx, gy, gz, 0.f);
+            if (S.frc) S.frc[i] = make_float4(gx, gy, gz, 0.f);
         }
     }
     wave_sync();
@@ -1219,7 +1302,7 @@ template <int A, bool SL>
 __global__ __launch_bounds__(64) void dock_kernel(DockArgs a)
 {
     extern __shared__ __align__(16) char smem[];
-    const Lds S = carve(smem, a.l.max_atoms, a.l.max_pairs, a.l.max_ell, SL);
+    const Lds S = carve(smem, a.l.max_atoms, a.l.max_pairs, a.l.max_ell, kernel_needs(kKindDock, A, SL));
     const int l = lane_id();
     Topo<A, SL> T;
     T.lig = -1;
@@ -1313,7 +1396,7 @@ template <int A, bool SL>
 __global__ __launch_bounds__(64) void score_kernel(ScoreArgs a)
 {
     extern __shared__ __align__(16) char smem[];
-    const Lds S = carve(smem, a.l.max_atoms, a.l.max_pairs, a.l.max_ell, SL);
+    const Lds S = carve(smem, a.l.max_atoms, a.l.max_pairs, a.l.max_ell, kernel_needs(kKindScore, A, SL));
     const int l = lane_id();
     Topo<A, SL> T;
     T.lig = -1;
@@ -1398,7 +1481,7 @@ template <int A, bool SL>
 __global__ __launch_bounds__(64) void local_opt_kernel(OptArgs a)
 {
     extern __shared__ __align__(16) char smem[];
-    const Lds S = carve(smem, a.l.max_atoms, a.l.max_pairs, a.l.max_ell, SL);
+    const Lds S = carve(smem, a.l.max_atoms, a.l.max_pairs, a.l.max_ell, kernel_needs(kKindOpt, A, SL));
     const int l = lane_id();
     Topo<A, SL> T;
     T.lig = -1;
@@ -1489,8 +1572,8 @@ template <int A>
 __global__ __launch_bounds__(64) void output_kernel(OutputArgs a)
 {
     extern __shared__ __align__(16) char smem[];
-    const Lds S = carve(smem, a.l.max_atoms, a.l.max_pairs, a.l.max_ell, false);
-    char* ext = smem + lds_bytes(a.l.max_atoms, a.l.max_pairs, a.l.max_ell, false);
+    const Lds S = carve(smem, a.l.max_atoms, a.l.max_pairs, a.l.max_ell, kernel_needs(kKindOutput, A, false));
+    char* ext = smem + lds_bytes(a.l.max_atoms, a.l.max_pairs, a.l.max_ell, kernel_needs(kKindOutput, A, false));
     const int ma = S.ma, M = a.modes, C = a.chains;
     int* order = (int*)ext;     ext += round_up(C, 4) * 4;
     float4* rep = (float4*)ext; ext += M * ma * 16;
@@ -1971,12 +2054,12 @@ hipError_t launch_shape(int kind, const LigDev& l, int64_t items, int n_cu, Laun
 {
     const int64_t cus = n_cu > 0 ? n_cu : 1;
     if (l.max_atoms > 64) {
-        const int lds = lds_bytes(l.max_atoms, l.max_pairs, l.max_ell, false);
+        const int lds = lds_bytes(l.max_atoms, l.max_pairs, l.max_ell, kernel_needs(kind, 2, false));
         *out = {2, lds, kind_occupancy<2, false>(kind, lds)};
         return out->per_cu > 0 ? hipSuccess : hipErrorInvalidConfiguration;
     }
-    const int lds_s = lds_bytes(l.max_atoms, l.max_pairs, l.max_ell, true);
-    const int lds_g = lds_bytes(l.max_atoms, l.max_pairs, l.max_ell, false);
+    const int lds_s = lds_bytes(l.max_atoms, l.max_pairs, l.max_ell, kernel_needs(kind, 1, true));
+    const int lds_g = lds_bytes(l.max_atoms, l.max_pairs, l.max_ell, kernel_needs(kind, 1, false));
     const int occ_s = kind_occupancy<1, true>(kind, lds_s);
     const int occ_g = kind_occupancy<1, false>(kind, lds_g);
     const int64_t need = std::min<int64_t>(items > 0 ? items : 1, (int64_t)occ_g * cus);
@@ -1991,7 +2074,7 @@ hipError_t launch_shape_variant(int kind, const LigDev& l, int variant, LaunchSh
 {
     *out = {variant, 0, 0};
     if (variant < 0 || variant > 2 || (variant < 2 && l.max_atoms > 64)) return hipErrorInvalidValue;
-    const int lds = lds_bytes(l.max_atoms, l.max_pairs, l.max_ell, variant == 0);
+    const int lds = lds_bytes(l.max_atoms, l.max_pairs, l.max_ell, kernel_needs(kind, variant == 2 ? 2 : 1, variant == 0));
     int occ;
     if (variant == 0) occ = kind_occupancy<1, true>(kind, lds);
     else if (variant == 1) occ = kind_occupancy<1, false>(kind, lds);
@@ -2089,7 +2172,8 @@ hipError_t launch_output(const OutputArgs& a, hipStream_t s)
 int output_lds_bytes(const LigDev& l, int chains, int modes)
 {
     const int ma = lds_atoms(l.max_atoms);
-    return lds_bytes(l.max_atoms, l.max_pairs, l.max_ell, false) + round_up(chains, 4) * 4 + modes * ma * 16 +
+    return lds_bytes(l.max_atoms, l.max_pairs, l.max_ell, kernel_needs(kKindOutput, l.max_atoms > 64 ? 2 : 1, false)) +
+           round_up(chains, 4) * 4 + modes * ma * 16 +
            modes * kSlot * 4 + 5 * round_up(modes, 4) * 4;
 }
 

@@ -276,10 +276,14 @@ int build_ligand_model(int n, const float* xyz, const uint8_t* type, int nb, con
             }
         }
     }
+    // row-major ([n][w], w a multiple of four): a lane reads four of its
+    // atom's entries with one 16-byte load (measured faster than entry-major
+    // [w][n] with one load per entry, and than groups of four side by side)
     M.ell.assign((size_t)w * n, 0u);
     for (int i = 0; i < n; ++i)
         for (int k = 0; k < w; ++k)
-            M.ell[(size_t)k * n + i] = k < (int)rows[i].size() ? rows[i][k] : ((uint32_t)P | ((uint32_t)i << 16));
+            M.ell[(size_t)i * w + k] =
+                k < (int)rows[i].size() ? rows[i][k] : ((uint32_t)P | ((uint32_t)i << 16));
     return PV_OK;
 }
 
