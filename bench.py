@@ -320,7 +320,8 @@ def bench_stream(pv, S, ctx, stream, args, inp):
         "service_us_p50": float(np.percentile(svc, 50)),
         "service_us_p99": float(np.percentile(svc, 99)),
         "service_us_max": float(svc.max()),
-        "jobs_status_nonzero": int(np.sum(status != 0)),
+        "jobs_status": {"nonfinite": int(np.sum((status & 1) != 0)), "budget": int(np.sum((status & 2) != 0)),
+                        "best_pose_outside_box": int(np.sum((status & 4) != 0))},
         "best_e_median": float(np.median(best)),
         "classes": cls_stats,
         "roofline": {

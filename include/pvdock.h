@@ -208,7 +208,16 @@ typedef struct {
     uint64_t seed;
     int32_t workgroups;      /* persistent launch width; 0 = chosen by the library */
     int32_t consistency;     /* 0: every step runs BFGS (default); 1: the consistency check gates it */
+    int64_t max_evals;       /* evaluation budget per chain, >= 0; 0 = none.  A chain whose count
+                                reaches it after a step stops there (status PV_JOB_BUDGET) */
 } pv_dock_params;
+
+/* Per-chain and per-job status bits of a dock (0 = ok).  Failures never stop
+ * the other chains or jobs. */
+#define PV_JOB_NONFINITE 1u   /* job: the best energy is not finite */
+#define PV_JOB_BUDGET 2u      /* chain: stopped at max_evals; job: some chain did */
+#define PV_JOB_OUTSIDE 4u     /* chain: its best pose has an atom outside the box (its energy carries
+                                 the out-of-box penalty); job: the best chain's pose does */
 
 #define PV_DOCK_TIMESTAMPS 1u /* write per-job device timestamps */
 #define PV_DOCK_GRAPH 2u      /* pv_dock_run captures its launches in a hipGraph once and replays it */
@@ -232,11 +241,14 @@ typedef struct { int32_t ligand, box; } pv_job;
  *   and refinements included), chain_pairs [jobs*chains] (intra pairs
  *   evaluated inside the cutoff, for the roofline),
  *   job_best_e [jobs], job_best_chain [jobs] (ties: lowest chain),
- *   job_evals [jobs], job_status [jobs] (0 ok, 1 non-finite best energy),
+ *   job_evals [jobs], job_status [jobs] (PV_JOB_* bits, 0 = ok),
  *   job_t_start, job_t_end [jobs] (device clock, 100 MHz; with
  *   PV_DOCK_TIMESTAMPS), chain_grads [jobs*chains] (the evaluations that
  *   computed the gradient: a line-search trial above the sufficient-decrease
- *   bound stops after its energy, since no step reads its gradient). */
+ *   bound stops after its energy, since no step reads its gradient),
+ *   chain_status [jobs*chains] (PV_JOB_BUDGET, PV_JOB_OUTSIDE bits).  The
+ *   outside test re-evaluates each chain's best pose once at its end; that
+ *   evaluation is not counted in chain_evals. */
 typedef struct {
     float* chain_best_e;
     float* chain_best_dof;
@@ -250,6 +262,7 @@ typedef struct {
     uint64_t* job_t_end;
     int32_t dof_stride;
     int64_t* chain_grads;
+    int32_t* chain_status;
 } pv_dock_out;
 
 /* A dock plan: the job table uploaded once and the parameters checked.

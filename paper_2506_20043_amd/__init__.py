@@ -27,6 +27,7 @@ _lib = None
 PV_DOCK_TIMESTAMPS = 1
 PV_DOCK_GRAPH = 2
 PV_DOCK_LARGEST_FIRST = 4
+PV_JOB_NONFINITE, PV_JOB_BUDGET, PV_JOB_OUTSIDE = 1, 2, 4
 MAX_ATOMS, MAX_TORS = 128, 32
 
 
@@ -44,7 +45,7 @@ class DockParams(C.Structure):
                 ("ls_rho", C.c_float), ("ls_sigma", C.c_float), ("eps_grad", C.c_float),
                 ("eps_curv", C.c_float), ("temperature", C.c_float), ("mut_pos_amp", C.c_float),
                 ("mut_rot_amp", C.c_float), ("flags", C.c_uint32), ("seed", C.c_uint64),
-                ("workgroups", C.c_int32), ("consistency", C.c_int32)]
+                ("workgroups", C.c_int32), ("consistency", C.c_int32), ("max_evals", C.c_int64)]
 
 
 class Job(C.Structure):
@@ -57,7 +58,7 @@ class DockOut(C.Structure):
                 ("job_best_e", C.c_void_p), ("job_best_chain", C.c_void_p),
                 ("job_evals", C.c_void_p), ("job_status", C.c_void_p),
                 ("job_t_start", C.c_void_p), ("job_t_end", C.c_void_p), ("dof_stride", C.c_int32),
-                ("chain_grads", C.c_void_p)]
+                ("chain_grads", C.c_void_p), ("chain_status", C.c_void_p)]
 
 
 class OutputParams(C.Structure):
@@ -496,6 +497,7 @@ class Plan:
                 chain_evals=torch.empty(nj * ch, dtype=torch.int64, device=dev),
                 chain_pairs=torch.empty(nj * ch, dtype=torch.int64, device=dev),
                 chain_grads=torch.empty(nj * ch, dtype=torch.int64, device=dev),
+                chain_status=torch.empty(nj * ch, dtype=torch.int32, device=dev),
                 job_best_e=torch.empty(nj, dtype=torch.float32, device=dev),
                 job_best_chain=torch.empty(nj, dtype=torch.int32, device=dev),
                 job_evals=torch.empty(nj, dtype=torch.int64, device=dev),
@@ -590,7 +592,8 @@ def _dock_outputs(ctx, ligs, n_jobs, chains, chain_outputs=True):
                    chain_best_dof=torch.zeros((nc, ligs.dof_stride), dtype=torch.float32, device=dev),
                    chain_evals=torch.empty(nc, dtype=torch.int64, device=dev),
                    chain_pairs=torch.empty(nc, dtype=torch.int64, device=dev),
-                   chain_grads=torch.empty(nc, dtype=torch.int64, device=dev))
+                   chain_grads=torch.empty(nc, dtype=torch.int64, device=dev),
+                   chain_status=torch.empty(nc, dtype=torch.int32, device=dev))
     o = DockOut()
     for k, v in out.items():
         setattr(o, k, v.data_ptr())

@@ -133,6 +133,7 @@ struct pv_plan {
     uint32_t* queue;
     float* scratch_best;      // chain_best_e when the caller does not want it
     int64_t* scratch_evals;   // chain_evals when only job_evals is wanted
+    int32_t* scratch_status;  // chain_status when the caller does not want it
     // Jobs in size classes (ligands of at most 64 atoms, larger ones), each
     // with its own LDS limits, kernel variant and persistent launch; jobs
     // keep their indices through a per-group job map.
@@ -192,7 +193,7 @@ extern "C" {
 
 const char* pv_last_error(void) { return g_err.c_str(); }
 
-int32_t pv_version(void) { return 100; }
+int32_t pv_version(void) { return 101; }
 
 pv_status pv_create(int32_t device, pv_ctx** out)
 {
@@ -655,6 +656,7 @@ static pv_status check_search(const pv_dock_params* p, bool mc)
     if (mc && !(p->temperature > 0.f)) return fail(PV_E_INVALID, "temperature must be > 0");
     if (mc && (!(p->mut_pos_amp >= 0.f) || !(p->mut_rot_amp >= 0.f))) return fail(PV_E_INVALID, "amplitudes must be >= 0");
     if (p->consistency != 0 && p->consistency != 1) return fail(PV_E_INVALID, "consistency must be 0 or 1");
+    if (p->max_evals < 0) return fail(PV_E_INVALID, "max_evals must be >= 0");
     return PV_OK;
 }
 
@@ -677,6 +679,7 @@ static SearchParams to_sp(const pv_dock_params* p)
     s.flags = p->flags;
     s.consistency = p->consistency;
     s.seed = p->seed;
+    s.max_evals = p->max_evals;
     return s;
 }
 
@@ -712,7 +715,8 @@ pv_status pv_dock_plan(pv_ctx* ctx, const pv_grids* grids, const pv_ligands* lig
     if ((st = upload(&P->jobs, hj.data(), hj.size(), "job table")) != PV_OK ||
         (st = upload(&P->queue, (const uint32_t*)nullptr, 2, "queue")) != PV_OK ||
         (st = upload(&P->scratch_best, (const float*)nullptr, nchain, "scratch")) != PV_OK ||
-        (st = upload(&P->scratch_evals, (const int64_t*)nullptr, nchain, "scratch")) != PV_OK) {
+        (st = upload(&P->scratch_evals, (const int64_t*)nullptr, nchain, "scratch")) != PV_OK ||
+        (st = upload(&P->scratch_status, (const int32_t*)nullptr, nchain, "scratch")) != PV_OK) {
         pv_plan_free(P);
         return st;
     }
@@ -774,7 +778,7 @@ struct pv_sas {
     float4* pts;     // (x, y, z, atom index bits)
 };
 
-static DockArgs dock_args(pv_plan* P, const pv_dock_out* o, float* cbe, int64_t* cev)
+static DockArgs dock_args(pv_plan* P, const pv_dock_out* o, float* cbe, int64_t* cev, int32_t* cst)
 {
     DockArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -789,6 +793,7 @@ static DockArgs dock_args(pv_plan* P, const pv_dock_out* o, float* cbe, int64_t*
     a.chain_evals = cev;
     a.chain_pairs = o->chain_pairs;
     a.chain_grads = o->chain_grads;
+    a.chain_status = cst;
     a.job_t_start = o->job_t_start;
     a.job_t_end = o->job_t_end;
     a.dof_stride = o->dof_stride;
@@ -809,6 +814,7 @@ static hipError_t enqueue_batched(pv_plan* P, const pv_dock_out* o, hipStream_t 
 {
     float* cbe = o->chain_best_e ? o->chain_best_e : P->scratch_best;
     int64_t* cev = o->chain_evals ? o->chain_evals : P->scratch_evals;
+    int32_t* cst = o->chain_status ? o->chain_status : P->scratch_status;
     hipError_t e = hipSuccess;
     if (P->sp.flags & PV_DOCK_TIMESTAMPS) {
         e = launch_reset_times(o->job_t_start, o->job_t_end, P->n_jobs, s);
@@ -816,7 +822,7 @@ static hipError_t enqueue_batched(pv_plan* P, const pv_dock_out* o, hipStream_t 
     }
     for (size_t g = 0; g < P->groups.size(); ++g) {
         const DockGroup& G = P->groups[g];
-        DockArgs a = dock_args(P, o, cbe, cev);
+        DockArgs a = dock_args(P, o, cbe, cev, cst);
         a.l = G.lv;
         a.job_map = G.job_map;
         a.queue = P->queue + g;
@@ -828,7 +834,7 @@ static hipError_t enqueue_batched(pv_plan* P, const pv_dock_out* o, hipStream_t 
         if (e != hipSuccess) return e;
     }
     if (o->job_best_e || o->job_best_chain || o->job_evals || o->job_status)
-        e = launch_job_reduce(cbe, cev, P->n_jobs, P->sp.chains, o->job_best_e, o->job_best_chain, o->job_evals,
+        e = launch_job_reduce(cbe, cev, cst, P->n_jobs, P->sp.chains, o->job_best_e, o->job_best_chain, o->job_evals,
                               o->job_status, s);
     return e;
 }
@@ -878,10 +884,11 @@ pv_status pv_dock_run_plain(pv_plan* P, const pv_dock_out* o, void* stream)
     hipStream_t s = (hipStream_t)stream;
     float* cbe = o->chain_best_e ? o->chain_best_e : P->scratch_best;
     int64_t* cev = o->chain_evals ? o->chain_evals : P->scratch_evals;
+    int32_t* cst = o->chain_status ? o->chain_status : P->scratch_status;
     if (P->sp.flags & PV_DOCK_TIMESTAMPS) HIP_TRY(launch_reset_times(o->job_t_start, o->job_t_end, P->n_jobs, s), "reset");
     for (int32_t j = 0; j < P->n_jobs; ++j) {
         const DockGroup& G = P->groups[P->job_group[j]];
-        DockArgs a = dock_args(P, o, cbe, cev);
+        DockArgs a = dock_args(P, o, cbe, cev, cst);
         a.l = G.lv;
         a.job_begin = j;
         a.n_items = P->sp.chains;
@@ -889,8 +896,8 @@ pv_status pv_dock_run_plain(pv_plan* P, const pv_dock_out* o, void* stream)
         HIP_TRY(launch_dock(a, G.plain_shape, 0, s), "dock launch");
     }
     if (o->job_best_e || o->job_best_chain || o->job_evals || o->job_status)
-        HIP_TRY(launch_job_reduce(cbe, cev, P->n_jobs, P->sp.chains, o->job_best_e, o->job_best_chain, o->job_evals,
-                                  o->job_status, s),
+        HIP_TRY(launch_job_reduce(cbe, cev, cst, P->n_jobs, P->sp.chains, o->job_best_e, o->job_best_chain,
+                                  o->job_evals, o->job_status, s),
                 "job reduce");
     return PV_OK;
 }
@@ -904,7 +911,7 @@ void pv_plan_free(pv_plan* P)
         (void)hipGraphDestroy(P->graph);
     }
     if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
-    dfree(P->jobs); dfree(P->queue); dfree(P->scratch_best); dfree(P->scratch_evals);
+    dfree(P->jobs); dfree(P->queue); dfree(P->scratch_best); dfree(P->scratch_evals); dfree(P->scratch_status);
     for (DockGroup& G : P->groups) dfree(G.job_map);
     delete P;
 }
@@ -1050,7 +1057,7 @@ pv_status pv_dock_autotune(pv_plan* P, int32_t tune_steps, int32_t repeats, void
         double best_rate = -1.0;
         std::vector<int32_t> slot(cand.size(), -1);
         for (size_t k = 0; k < cand.size(); ++k) {
-            DockArgs a = dock_args(P, &none, P->scratch_best, P->scratch_evals);
+            DockArgs a = dock_args(P, &none, P->scratch_best, P->scratch_evals, P->scratch_status);
             a.sp.steps = tune_steps;
             a.sp.flags &= ~PV_DOCK_TIMESTAMPS;
             a.l = G.lv;
@@ -1178,6 +1185,7 @@ pv_status pv_dock_noalloc(pv_ctx* ctx, const pv_grids* grids, const pv_ligands* 
     hipStream_t s = (hipStream_t)stream;
     float* cbe = out->chain_best_e ? out->chain_best_e : W.best;
     int64_t* cev = out->chain_evals ? out->chain_evals : W.evals;
+    int32_t* cst = out->chain_status ? out->chain_status : W.status;
     if (n_jobs > 0) {
         static_assert(sizeof(pv_job) == sizeof(int2), "pv_job is two int32");
         HIP_TRY(hipMemcpyAsync(W.jobs, jobs, (size_t)n_jobs * sizeof(int2), hipMemcpyHostToDevice, s), "job table copy");
@@ -1203,13 +1211,14 @@ pv_status pv_dock_noalloc(pv_ctx* ctx, const pv_grids* grids, const pv_ligands* 
         a.chain_evals = cev;
         a.chain_pairs = out->chain_pairs;
         a.chain_grads = out->chain_grads;
+        a.chain_status = cst;
         a.job_t_start = out->job_t_start;
         a.job_t_end = out->job_t_end;
         a.dof_stride = out->dof_stride;
         HIP_TRY(launch_dock(a, sh[g], width[g], s), "dock launch");
     }
     if (out->job_best_e || out->job_best_chain || out->job_evals || out->job_status)
-        HIP_TRY(launch_job_reduce(cbe, cev, n_jobs, params->chains, out->job_best_e, out->job_best_chain,
+        HIP_TRY(launch_job_reduce(cbe, cev, cst, n_jobs, params->chains, out->job_best_e, out->job_best_chain,
                                   out->job_evals, out->job_status, s),
                 "job reduce");
     // the scratch is reused by the next call on this device: return only

@@ -121,6 +121,7 @@ struct SearchParams {
     uint32_t flags;
     int32_t consistency;   // 1: the first-order consistency check gates the step's BFGS
     uint64_t seed;
+    int64_t max_evals;     // evaluation budget per chain (0: none)
 };
 
 struct DockArgs {
@@ -140,6 +141,7 @@ struct DockArgs {
     int64_t* chain_evals;
     int64_t* chain_pairs;
     int64_t* chain_grads;     // evaluations that computed the gradient
+    int32_t* chain_status;    // PV_JOB_BUDGET / PV_JOB_OUTSIDE bits per chain (never NULL)
     uint64_t* job_t_start;
     uint64_t* job_t_end;
     int32_t dof_stride;
@@ -209,9 +211,9 @@ hipError_t launch_score(const ScoreArgs& a, int n_cu, hipStream_t s);
 hipError_t launch_dock(const DockArgs& a, const LaunchShape& sh, int32_t workgroups, hipStream_t s);
 hipError_t launch_reset_queue(uint32_t* q, hipStream_t s);
 hipError_t launch_fma_peak(float* out, int n, int iters, hipStream_t s);
-hipError_t launch_job_reduce(const float* chain_best_e, const int64_t* chain_evals, int32_t n_jobs,
-                             int32_t chains, float* job_best_e, int32_t* job_best_chain, int64_t* job_evals,
-                             int32_t* job_status, hipStream_t s);
+hipError_t launch_job_reduce(const float* chain_best_e, const int64_t* chain_evals, const int32_t* chain_status,
+                             int32_t n_jobs, int32_t chains, float* job_best_e, int32_t* job_best_chain,
+                             int64_t* job_evals, int32_t* job_status, hipStream_t s);
 hipError_t launch_local_opt(const OptArgs& a, int n_cu, hipStream_t s);
 hipError_t launch_output(const OutputArgs& a, hipStream_t s);
 hipError_t launch_sas_candidates(const float4* atoms, int n_rec, const float* dirs, int n_dirs, float probe,
@@ -227,7 +229,8 @@ hipError_t launch_reset_times(uint64_t* t0, uint64_t* t1, int n, hipStream_t s);
 // Scratch of the allocation-free dock entry point, one file-scope device
 // array per GPU (see noalloc_scratch): the queue counters of the two size
 // classes, the job table, the per-class job maps and, for callers that take
-// no per-chain outputs, the chains' best energies and evaluation counts.
+// no per-chain outputs, the chains' best energies, evaluation counts and
+// statuses.
 constexpr int64_t kNoAllocMaxJobs = 65536;
 constexpr int64_t kNoAllocMaxChains = 1 << 20;   // jobs x chains
 struct NoAllocLayout {
@@ -236,17 +239,19 @@ struct NoAllocLayout {
     int32_t* map;       // [kNoAllocMaxJobs]: class 0 jobs, then class 1 jobs
     float* best;        // [kNoAllocMaxChains]
     int64_t* evals;     // [kNoAllocMaxChains]
+    int32_t* status;    // [kNoAllocMaxChains]
 };
 constexpr size_t kNoAllocOffJobs = 256;
 constexpr size_t kNoAllocOffMap = kNoAllocOffJobs + 8 * kNoAllocMaxJobs;
 constexpr size_t kNoAllocOffBest = kNoAllocOffMap + 4 * kNoAllocMaxJobs;
 constexpr size_t kNoAllocOffEvals = kNoAllocOffBest + 4 * kNoAllocMaxChains;
-constexpr size_t kNoAllocBytes = kNoAllocOffEvals + 8 * kNoAllocMaxChains;
+constexpr size_t kNoAllocOffStatus = kNoAllocOffEvals + 8 * kNoAllocMaxChains;
+constexpr size_t kNoAllocBytes = kNoAllocOffStatus + 4 * kNoAllocMaxChains;
 inline NoAllocLayout noalloc_layout(void* base)
 {
     char* b = (char*)base;
     return {(uint32_t*)b, (int2*)(b + kNoAllocOffJobs), (int32_t*)(b + kNoAllocOffMap),
-            (float*)(b + kNoAllocOffBest), (int64_t*)(b + kNoAllocOffEvals)};
+            (float*)(b + kNoAllocOffBest), (int64_t*)(b + kNoAllocOffEvals), (int32_t*)(b + kNoAllocOffStatus)};
 }
 // Device address of the current device's scratch array, looked up once per
 // device (hipGetSymbolAddress with that device current) and kept.

@@ -462,6 +462,7 @@ struct Eval {
     float e, e_inter, e_intra;
     float g;          // this lane's tangent component (lane < 6 + T)
     int pairs_in;     // this lane's intra pairs inside the cutoff
+    bool outside;     // some atom lies outside the box (its lookup was clamped)
 };
 
 // Frame of every fragment: x = R X + b on reference coordinates.  Lane f
@@ -814,10 +815,14 @@ __device__ Eval evaluate(const Topo<A, SL>& T, const BoxView& B, const Lds& S, c
             if (l * A + a < T.n)
                 tri_issue(B, __float_as_uint(T.ref[a].w) & 0xff, X4[a].x, X4[a].y, X4[a].z, TL[a]);
     }
+    bool outl = false;
 #pragma unroll
     for (int a = 0; a < A; ++a)
-        if (l * A + a < T.n)
+        if (l * A + a < T.n) {
             e_in += tri_finish(B, TL[a], G[a][0], G[a][1], G[a][2]);
+            outl = outl || TL[a].cx || TL[a].cy || TL[a].cz;
+        }
+    out.outside = __ballot(outl) != 0;
     out.e_inter = wsum(e_in);
     out.e = out.e_inter + out.e_intra;
     out.pairs_in = cnt;
@@ -917,6 +922,7 @@ __device__ Eval evaluate_xyz(const Topo<A, SL>& T, const BoxView& B, const Lds& 
     }
     wave_sync();
     out.g = 0.f;
+    out.outside = false;
     out.e_inter = wsum(e_in);
     out.e_intra = wsum(e_ia);
     out.e = out.e_inter + out.e_intra;
@@ -970,6 +976,7 @@ struct BfgsOut {
     int grads;        // evaluations that computed the gradient
     int64_t pairs;    // this lane's share of the intra pairs inside the cutoff
     bool skipped;     // the consistency check ended the run after its first evaluation
+    bool outside0;    // the start pose has an atom outside the box
 };
 
 // The neighbour of a mutated pose for the first-order consistency check:
@@ -1030,6 +1037,7 @@ __device__ BfgsOut bfgs(const Topo<A, SL>& T, const BoxView& B, const Lds& S, co
     out.grads = 0;
     out.pairs = 0;
     out.skipped = false;
+    out.outside0 = false;
     float Sh[kMaxM], Yh[kMaxM], rh[kMaxM];
 #pragma unroll
     for (int h = 0; h < kMaxM; ++h) { Sh[h] = 0.f; Yh[h] = 0.f; rh[h] = 0.f; }
@@ -1049,6 +1057,7 @@ __device__ BfgsOut bfgs(const Topo<A, SL>& T, const BoxView& B, const Lds& S, co
         bool begin = false;
         if (initial) {
             f = ft; g = gt; initial = false; begin = true;
+            out.outside0 = ev.outside;
             if (check && !consistency_passes(S, S.pose + SLOT_X * kSlot, ft, gt, ck)) {
                 out.skipped = true;
                 break;
@@ -1142,7 +1151,10 @@ __device__ BfgsOut bfgs(const Topo<A, SL>& T, const BoxView& B, const Lds& S, co
 struct ChainOut {
     float best_e;
     int64_t evals, grads, pairs;   // pairs: this lane's share
+    int status;                    // PV_JOB_BUDGET | PV_JOB_OUTSIDE bits
 };
+
+constexpr int kStatusBudget = 2, kStatusOutside = 4;   // the PV_JOB_* bits of the ABI
 
 template <int A, bool SL>
 __device__ void init_pose(const Topo<A, SL>& T, const BoxView& B, const Lds& S, int slot, uint64_t seed, int job,
@@ -1233,16 +1245,23 @@ __device__ ChainOut mc_chain(const Topo<A, SL>& T, const BoxView& B, const Lds& 
     out.evals = 0;
     out.grads = 0;
     out.pairs = 0;
+    out.status = 0;
     init_pose(T, B, S, SLOT_X, P.seed, job, chain);
     float e_cur = 0.f, e_best = 0.f, um = 0.f;
     CheckIn ck;            // the current pose as the consistency check's neighbour
     ck.g = 0.f;
     ck.p_lo = ck.p_hi = 0;
-    int s = 0, mode = 0;   // 0 initial pose, 1 step optimisation, 2 refinement
+    // 0 initial pose, 1 step optimisation, 2 refinement, 3 the closing
+    // look at the best pose (one uncounted evaluation: is it inside the box?)
+    int s = 0, mode = 0;
     while (true) {
-        const int iters = mode == 0 ? 0 : (mode == 1 ? P.max_iter : P.refine_max_iter);
+        const int iters = mode == 0 || mode == 3 ? 0 : (mode == 1 ? P.max_iter : P.refine_max_iter);
         ck.f = e_cur;
         const BfgsOut bo = bfgs(T, B, S, P, iters, mode == 1 && P.consistency, ck);
+        if (mode == 3) {
+            if (bo.outside0) out.status |= kStatusOutside;
+            break;
+        }
         out.evals += bo.evals;
         out.grads += bo.grads;
         out.pairs += bo.pairs;
@@ -1270,7 +1289,13 @@ __device__ ChainOut mc_chain(const Topo<A, SL>& T, const BoxView& B, const Lds& 
             ck.g = bo.g;
         }
         if (!next) continue;
-        if (s >= P.steps) break;
+        const bool spent = P.max_evals > 0 && out.evals >= P.max_evals;
+        if (spent) out.status |= kStatusBudget;
+        if (s >= P.steps || spent) {
+            slot_copy(S, SLOT_X, SLOT_BEST, 7 + T.nt);
+            mode = 3;
+            continue;
+        }
         // the 8 draws of step s + 1: lanes 0-3 compute block 0, lanes 4-7 block 1
         const uint64_t mine = philox_word(P.seed, job, chain, (uint64_t)s + 1, (uint64_t)((l >> 2) & 1), l & 3);
         uint64_t w[8];
@@ -1333,6 +1358,7 @@ __global__ __launch_bounds__(64) void dock_kernel(DockArgs a)
             if (a.chain_evals) a.chain_evals[ci] = co.evals;
             if (a.chain_pairs) a.chain_pairs[ci] = pairs;
             if (a.chain_grads) a.chain_grads[ci] = co.grads;
+            a.chain_status[ci] = co.status;
             if (a.sp.flags & 1u) {
                 const uint64_t t1 = wall_clock64();
                 atomicMin((unsigned long long*)&a.job_t_start[job], (unsigned long long)t0);
@@ -1373,23 +1399,28 @@ __global__ void reset_times_kernel(uint64_t* t0, uint64_t* t1, int n)
     if (i < n) { t0[i] = ~0ull; t1[i] = 0ull; }
 }
 
-__global__ void job_reduce_kernel(const float* cbe, const int64_t* cev, int n_jobs, int chains, float* jbe,
-                                  int32_t* jbc, int64_t* jev, int32_t* jst)
+// Per job: the best chain (lowest energy, ties to the lower chain, a number
+// before NaN), the evaluation total and the status bits: not finite, some
+// chain stopped at its budget, the best chain's pose outside the box.
+__global__ void job_reduce_kernel(const float* cbe, const int64_t* cev, const int32_t* cst, int n_jobs, int chains,
+                                  float* jbe, int32_t* jbc, int64_t* jev, int32_t* jst)
 {
     int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n_jobs) return;
     int bc = 0;
     float be = cbe[(int64_t)j * chains];
     int64_t ev = cev ? cev[(int64_t)j * chains] : 0;
+    int budget = cst[(int64_t)j * chains] & kStatusBudget;
     for (int c = 1; c < chains; ++c) {
         const float e = cbe[(int64_t)j * chains + c];
         if (e < be || (be != be && e == e)) { be = e; bc = c; }
         if (cev) ev += cev[(int64_t)j * chains + c];
+        budget |= cst[(int64_t)j * chains + c] & kStatusBudget;
     }
     if (jbe) jbe[j] = be;
     if (jbc) jbc[j] = bc;
     if (jev) jev[j] = ev;
-    if (jst) jst[j] = isfinite(be) ? 0 : 1;
+    if (jst) jst[j] = (isfinite(be) ? 0 : 1) | budget | (cst[(int64_t)j * chains + bc] & kStatusOutside);
 }
 
 template <int A, bool SL>
@@ -2133,11 +2164,11 @@ hipError_t launch_reset_times(uint64_t* t0, uint64_t* t1, int n, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_job_reduce(const float* cbe, const int64_t* cev, int32_t n_jobs, int32_t chains, float* jbe,
-                             int32_t* jbc, int64_t* jev, int32_t* jst, hipStream_t s)
+hipError_t launch_job_reduce(const float* cbe, const int64_t* cev, const int32_t* cst, int32_t n_jobs,
+                             int32_t chains, float* jbe, int32_t* jbc, int64_t* jev, int32_t* jst, hipStream_t s)
 {
     if (n_jobs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(job_reduce_kernel, dim3((n_jobs + 255) / 256), dim3(256), 0, s, cbe, cev, n_jobs, chains,
+    hipLaunchKernelGGL(job_reduce_kernel, dim3((n_jobs + 255) / 256), dim3(256), 0, s, cbe, cev, cst, n_jobs, chains,
                        jbe, jbc, jev, jst);
     return hipGetLastError();
 }

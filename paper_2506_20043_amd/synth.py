@@ -142,6 +142,97 @@ def tree_ligand(g: np.random.Generator, n_atoms: int, n_tors: int, bond: float =
     return Molecule(xyz, _types(g, n_atoms), bonds, rot, int(k))
 
 
+def ring_ligand(g: np.random.Generator, n_atoms: int, n_tors: int, n_rings: int = 1, bond: float = 1.5,
+                min_sep: float = 2.3, max_degree: int = 4) -> Molecule:
+    """Random ligand with `n_rings` planar six-membered rings (bond length
+    `bond`, so 1,3 and 1,4 ring distances are 2.6 and 3.0 A), each ring after
+    the first joined by a single bond to an atom of the one before, then
+    grown into a tree as tree_ligand does.  Ring bonds are never rotatable (a
+    rotatable bond must be a bridge); `n_tors` bridges with two non-terminal
+    ends are marked rotatable (clamped)."""
+    assert n_atoms >= 6 * n_rings
+    hexagon = np.array([[np.cos(k * np.pi / 3), np.sin(k * np.pi / 3), 0.0] for k in range(6)]) * bond
+    while True:
+        xyz = np.zeros((n_atoms, 3))
+        deg = np.zeros(n_atoms, np.int32)
+        bonds, in_ring = [], []
+        ok = True
+        a = 0
+        for r in range(n_rings):
+            w, x, y, z = random_quaternions(g, 1)[0]
+            R = np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                          [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                          [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+            ring = hexagon @ R.T
+            anchor = -1
+            if r > 0:
+                # ring r starts one bond out from a random atom of ring r - 1,
+                # pointing away from that ring's centre, its own centre
+                # further out along the same line
+                anchor = a - 6 + int(g.integers(0, 6))
+                out = xyz[anchor] - xyz[a - 6:a].mean(axis=0)
+                out /= np.linalg.norm(out)
+                first = xyz[anchor] + bond * out
+                centre = first + bond * out
+                ring = ring - ring.mean(axis=0)
+                k0 = int(np.argmin(((ring + centre - first) ** 2).sum(axis=1)))
+                ring = np.roll(ring, -k0, axis=0) + centre
+                ring += first - ring[0]
+            if a > 0:
+                diff = ring[:, None, :] - xyz[None, :a, :]
+                d = np.sqrt((diff ** 2).sum(axis=2))
+                d[0, anchor] = np.inf
+                if d.min() < min_sep:
+                    ok = False
+                    break
+            xyz[a:a + 6] = ring
+            for k in range(6):
+                bonds.append((a + k, a + (k + 1) % 6))
+                in_ring.append(True)
+            deg[a:a + 6] += 2
+            if anchor >= 0:
+                bonds.append((anchor, a))
+                in_ring.append(False)
+                deg[anchor] += 1
+                deg[a] += 1
+            a += 6
+        if not ok:
+            continue
+        for b in range(a, n_atoms):
+            placed = False
+            for _ in range(400):
+                cand = np.nonzero(deg[:b] < max_degree)[0]
+                p = int(cand[g.integers(0, len(cand))])
+                v = g.normal(size=3)
+                v /= np.sqrt(v.dot(v))
+                x = xyz[p] + bond * v
+                diff = xyz[:b] - x
+                d2 = np.einsum("ij,ij->i", diff, diff)
+                d2[p] = np.inf
+                if np.sqrt(d2.min()) >= min_sep:
+                    xyz[b] = x
+                    deg[p] += 1
+                    deg[b] += 1
+                    bonds.append((p, b))
+                    in_ring.append(False)
+                    placed = True
+                    break
+            if not placed:
+                ok = False
+                break
+        if ok:
+            break
+    bonds = np.array(bonds, np.int32).reshape(-1, 2)
+    inner = [k for k in range(len(bonds)) if not in_ring[k] and deg[bonds[k, 0]] >= 2 and deg[bonds[k, 1]] >= 2]
+    k = min(n_tors, len(inner))
+    rot = np.zeros(len(bonds), np.uint8)
+    if k > 0:
+        rot[g.choice(inner, size=k, replace=False)] = 1
+    xyz -= xyz.mean(axis=0)
+    xyz = xyz.astype(np.float32).astype(np.float64)
+    return Molecule(xyz, _types(g, n_atoms), bonds, rot, int(k))
+
+
 def random_quaternions(g: np.random.Generator, n: int) -> np.ndarray:
     q = g.normal(size=(n, 4))
     return q / np.linalg.norm(q, axis=1, keepdims=True)

@@ -31,7 +31,7 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_version_and_defaults():
-    assert pv.lib().pv_version() == 100
+    assert pv.lib().pv_version() == 101
     p = pv.dock_params()
     assert (p.bfgs_max_iter, p.bfgs_m, p.ls_max_trials) == (30, 5, 10)
     assert p.ls_rho == pytest.approx(1e-4) and p.ls_sigma == pytest.approx(0.1)
@@ -99,6 +99,44 @@ def test_ligand_model_matches_oracle(oracle, cfg):
     n = {"tiny": 1, "multi_pocket": 1, "uneven_batch": 40, "differentiation": 8, "screening": 40}[cfg]
     for m in S.make_ligands(c, count=n):
         _check_same_model(oracle, m)
+
+
+def _bond_distances(n, bonds):
+    """All-pairs bond-graph distances by breadth-first search."""
+    adj = [[] for _ in range(n)]
+    for a, b in bonds:
+        adj[a].append(b)
+        adj[b].append(a)
+    dist = np.full((n, n), -1, np.int64)
+    for s0 in range(n):
+        dist[s0, s0] = 0
+        todo = [s0]
+        while todo:
+            u = todo.pop(0)
+            for v in adj[u]:
+                if dist[s0, v] < 0:
+                    dist[s0, v] = dist[s0, u] + 1
+                    todo.append(v)
+    return dist
+
+
+def test_ligand_model_with_rings_matches_oracle(oracle):
+    """Ligands with rigid six-membered rings (rings inside fragments, torsions
+    on bridges elsewhere): the library's host model equals the oracle's, every
+    ring lies inside one fragment, and the intra pairs are exactly the atom
+    pairs in different fragments at least four bonds apart along the
+    shortest path of the cyclic bond graph."""
+    g = np.random.default_rng(17)
+    for n, t, r in ((12, 2, 1), (20, 4, 2), (33, 7, 2), (40, 8, 3), (64, 12, 4), (90, 16, 3)):
+        m = S.ring_ligand(g, n, t, r)
+        assert len(m.bonds) == n - 1 + r
+        _check_same_model(oracle, m)
+        info, pairs, frag = pv.describe_ligand(m.xyz, m.types, m.bonds, m.rotatable)
+        for k in range(r):
+            assert len(set(frag[6 * k:6 * k + 6].tolist())) == 1
+        dist = _bond_distances(n, m.bonds)
+        want = {(i, j) for i in range(n) for j in range(i + 1, n) if frag[i] != frag[j] and dist[i, j] >= 4}
+        assert {tuple(p) for p in pairs.tolist()} == want
 
 
 def test_ligand_model_extremes(oracle):

@@ -35,7 +35,9 @@ def _check(oracle, out, jobs, chains, steps, seed, lig_of, grid_of, sample):
     assert np.array_equal(out["job_best_e"], cbe.min(axis=1))
     assert np.array_equal(out["job_best_chain"], np.argmin(cbe, axis=1))
     assert np.array_equal(out["job_evals"], cev.sum(axis=1))
-    assert np.all(out["job_status"] == 0)
+    # finite bests, no budget set; a best pose may leave the box (its energy
+    # carries the out-of-box penalty), which the status reports
+    assert np.all((out["job_status"] & ~4) == 0)
     assert np.all(cev >= 1 + steps)          # one evaluation of the start, then one or more per step
     # the start and every step's first evaluation compute the gradient; a
     # line-search trial above the sufficient-decrease bound stops at its energy

@@ -90,6 +90,38 @@ def test_mc_without_bfgs_replays_oracle(oracle, pv_ctx, tiny):
     assert same >= 58, same
 
 
+def test_ring_ligand_mc_replays_oracle(oracle, pv_ctx, tiny):
+    """A ligand with two rigid rings docked without BFGS (mutation +
+    Metropolis only): the same Philox draws give the oracle's trajectory,
+    chain by chain, except for Metropolis tests within rounding of their
+    threshold; with BFGS the chain bests re-score to their energies."""
+    import paper_2506_20043_amd as pv
+    g = np.random.default_rng(29)
+    m = S.ring_ligand(g, 24, 5, 2)
+    ligs = pv.Ligands(pv_ctx, [m])
+    L = oracle.Ligand(m.xyz, m.types, m.bonds, m.rotatable)
+    G = tiny["og"]
+    p = _params(pv, chains=64, steps=40, seed=tiny["seed"] + 5, bfgs_max_iter=0, refine_max_iter=0)
+    res = pv.dock(pv_ctx, tiny["grids"], ligs, [(0, 0)], p)
+    cbd = res["chain_best_dof"].cpu().numpy()
+    cbe = res["chain_best_e"].cpu().numpy()
+    ev = res["chain_evals"].cpu().numpy()
+    same = 0
+    for c in range(64):
+        d, e, ne = oracle.mc_chain(L, G, _oparams(oracle, p), 0, c)
+        if ne == ev[c] and abs(cbe[c] - e) <= e_tol(e) and np.abs(cbd[c, :3] - d[:3]).max() < 1e-3:
+            same += 1
+    assert same >= 58, same
+    p2 = _params(pv, chains=16, steps=20, seed=tiny["seed"] + 6)
+    res = pv.dock(pv_ctx, tiny["grids"], ligs, [(0, 0)], p2)
+    cbd = res["chain_best_dof"].cpu().numpy()
+    cbe = res["chain_best_e"].cpu().numpy()
+    for c in range(16):
+        r = L.score_grad(G, cpu_dof(cbd[c, :L.ndof]))
+        slack = 0.01 if r["min_cut"] < 1e-4 else 0.0
+        assert abs(cbe[c] - r["e"]) <= e_tol(r["e"]) + slack, (c, cbe[c], r["e"])
+
+
 def test_local_opt_matches_oracle_on_smooth_objective(oracle, pv_ctx):
     """Intra-only objective (no receptor), C_P atoms and ligands at most 5
     bonds across, so it is smooth: from the same starts the GPU's FP32 BFGS

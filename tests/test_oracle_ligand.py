@@ -280,3 +280,40 @@ def test_score_grad_consistent_with_xyz(oracle, c1_grid):
         b = L.score_xyz(c1_grid, a["xyz"])
         assert a["e"] == b["e"]
         np.testing.assert_array_equal(a["grad_xyz"], b["grad_xyz"])
+
+
+def test_ring_ligand_fk_and_gradient(oracle, c1_grid):
+    """A ligand with rigid rings: forward kinematics keeps every bond length,
+    every ring's shape and every fragment rigid, and the analytic gradient
+    equals central differences on every DOF away from non-smooth points (the
+    torsion tree's subtrees are found through the cyclic bond graph)."""
+    G = c1_grid
+    g = np.random.default_rng(21)
+    m = S.ring_ligand(g, 30, 6, 2)
+    L = oracle.Ligand(m.xyz, m.types, m.bonds, m.rotatable)
+    assert L.n_tors == 6
+    frag = L.frag()
+    lo, hi = G.origin.astype(np.float64), G.origin + G.h * (G.dims - 1)
+    checked = 0
+    for _ in range(30):
+        dof = np.concatenate([g.uniform(lo + 3, hi - 3), g.normal(size=4), g.uniform(-np.pi, np.pi, L.n_tors)])
+        x = L.fk(dof)
+        for a, b in m.bonds:
+            assert np.linalg.norm(x[a] - x[b]) == pytest.approx(np.linalg.norm(m.xyz[a] - m.xyz[b]), abs=1e-12)
+        for f in range(L.n_frag):
+            idx = np.nonzero(frag == f)[0]
+            d0 = np.linalg.norm(m.xyz[idx, None] - m.xyz[None, idx], axis=-1)
+            d1 = np.linalg.norm(x[idx, None] - x[None, idx], axis=-1)
+            np.testing.assert_allclose(d1, d0, atol=1e-12)
+        r = L.score_grad(G, dof)
+        if min(r["min_face"], r["min_cut"], r["min_kink"]) < 1e-4:
+            continue
+        h = 1e-6
+        for i in range(L.ndof):
+            dp, dm = dof.copy(), dof.copy()
+            dp[i] += h
+            dm[i] -= h
+            fd = (L.score_grad(G, dp)["e"] - L.score_grad(G, dm)["e"]) / (2 * h)
+            assert r["grad_dof"][i] == pytest.approx(fd, rel=1e-5, abs=1e-5 * (1 + abs(r["e"]))), i
+        checked += 1
+    assert checked >= 20, checked
