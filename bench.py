@@ -81,6 +81,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1, help="untimed steps (replays of the first slices)")
     ap.add_argument("--stream-jobs", type=int, default=100000, help="jobs of the screening stream (a prefix)")
     ap.add_argument("--workers", type=int, default=16, help="processes generating the synthetic ligands")
+    ap.add_argument("--job-order", choices=["stream", "box"], default="box",
+                    help="order in which a batched launch hands out the slice's jobs: the stream's, or grouped "
+                         "by pocket (outputs are identical)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-score", action="store_true")
@@ -209,8 +212,9 @@ def bench_stream(pv, S, ctx, stream, args, inp):
     ligs = pv.Ligands(ctx, mols)
     N, T, P = _jobs_info(ligs, jobs)
     big = N > 64
+    order = pv.PV_DOCK_BOX_ORDER if args.job_order == "box" else 0
     params = pv.dock_params(chains=cfg.chains, steps=cfg.steps, seed=S.philox_seed(cfg),
-                            flags=pv.PV_DOCK_GRAPH | pv.PV_DOCK_TIMESTAMPS)
+                            flags=pv.PV_DOCK_GRAPH | pv.PV_DOCK_TIMESTAMPS | order)
     K = args.steps
     bounds = np.linspace(0, n, K + 1).astype(np.int64)
     steps = []
@@ -310,7 +314,8 @@ def bench_stream(pv, S, ctx, stream, args, inp):
                         "%d ligands of 8..80 atoms / 0..20 torsions; 16 chains x 300 MC steps per job, BFGS <= 30 "
                         "iterations; batched persistent launches (hipGraph), one per ligand size class; "
                         "step = 1/%d of the stream" % (n, map_mb, len(mols), K),
-            "jobs": n, "chains": cfg.chains, "mc_steps": cfg.steps, "parallelism": "single GPU",
+            "jobs": n, "chains": cfg.chains, "mc_steps": cfg.steps, "job_order": args.job_order,
+            "parallelism": "single GPU",
         },
         "evals_per_s": float(ev.sum() / wall),
         "evals": int(ev.sum()),
@@ -331,7 +336,7 @@ def bench_stream(pv, S, ctx, stream, args, inp):
             "peak": PEAK_FP32_VECTOR / 1e12,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_VECTOR,
-            "traffic": recorded_traffic(),
+            "traffic": recorded_traffic(args.job_order),
             "flops_per_launch": dom_fl / max(dom["launches"], 1),
             "flops_per_eval_mean": dom_fl / max(dom["evals"], 1),
             "launch_ms": dom["launch_ms_mean"],
@@ -347,11 +352,22 @@ def bench_stream(pv, S, ctx, stream, args, inp):
     return result, head
 
 
-def recorded_traffic():
-    """HBM bytes per launch of the dominant dock kernel from the committed
-    rocprofv3 counter record, or None when the kernel sources changed since
-    the counters were taken."""
+def native_source_hash():
+    """SHA-256 of the native sources (kernels, launch planning, ligand
+    layout), in file-name order."""
     import hashlib
+    csrc = os.path.join(ROOT, "paper_2506_20043_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".cpp", ".h")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()
+
+
+def recorded_traffic(job_order):
+    """HBM bytes per launch of the dominant dock kernel from the committed
+    rocprofv3 counter record, or None when the native sources changed since
+    the counters were taken or they were taken under another job order."""
     prof = os.path.join(ROOT, "profiles", "dock_kernel_screening_stream.md")
     if not os.path.exists(prof):
         return None
@@ -359,11 +375,9 @@ def recorded_traffic():
     for line in open(prof):
         if line.startswith("traffic_record: "):
             rec = json.loads(line[len("traffic_record: "):])
-    if rec is None:
+    if rec is None or rec.get("job_order") != job_order:
         return None
-    csrc = os.path.join(ROOT, "paper_2506_20043_amd", "csrc")
-    src = b"".join(open(os.path.join(csrc, f), "rb").read() for f in ("pv_kernels.hip", "pv_internal.h"))
-    if hashlib.sha256(src).hexdigest() != rec["kernel_source_sha256"]:
+    if native_source_hash() != rec.get("native_source_sha256"):
         return None
     return rec["dock_traffic_bytes_per_launch"]
 

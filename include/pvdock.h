@@ -225,9 +225,16 @@ typedef struct {
  * energy work: 8 x pairs + 48 x atoms + 109 x torsions; ties keep the job
  * order), so that short chains fill the end of the launch.  Only the order in
  * which chains start changes: every chain's result depends on (seed, job,
- * chain) alone, so the outputs are identical bit for bit.  Other flag bits are
- * rejected (PV_E_INVALID). */
+ * chain) alone, so the outputs are identical bit for bit. */
 #define PV_DOCK_LARGEST_FIRST 4u
+/* hand out each size class's jobs grouped by box (ascending box index; inside
+ * a box, the job order, or the PV_DOCK_LARGEST_FIRST order when that flag is
+ * set too), so that the chains in flight at any time read one or two boxes'
+ * maps and the L2 caches hold those instead of every box's.  As with
+ * PV_DOCK_LARGEST_FIRST only the start order changes: outputs are identical
+ * bit for bit. */
+#define PV_DOCK_BOX_ORDER 8u
+/* other flag bits are rejected (PV_E_INVALID) */
 
 /* fills the defaults: 30 BFGS iterations, m = 5, 10 trials, rho 1e-4,
  * sigma 0.1, eps_grad 1e-3, eps_curv 1e-6, temperature 1.2, amplitudes 2 A */

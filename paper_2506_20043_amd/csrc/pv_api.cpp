@@ -691,7 +691,7 @@ pv_status pv_dock_plan(pv_ctx* ctx, const pv_grids* grids, const pv_ligands* lig
     pv_status st = check_pair(ctx, grids, ligs);
     if (st != PV_OK) return st;
     if ((st = check_search(params, true)) != PV_OK) return st;
-    if (params->flags & ~(PV_DOCK_TIMESTAMPS | PV_DOCK_GRAPH | PV_DOCK_LARGEST_FIRST))
+    if (params->flags & ~(PV_DOCK_TIMESTAMPS | PV_DOCK_GRAPH | PV_DOCK_LARGEST_FIRST | PV_DOCK_BOX_ORDER))
         return fail(PV_E_INVALID, "unknown dock flag");
     if (n_jobs < 0) return fail(PV_E_INVALID, "n_jobs < 0");
     if (n_jobs > 0 && !jobs) return fail(PV_E_INVALID, "jobs is NULL");
@@ -734,6 +734,12 @@ pv_status pv_dock_plan(pv_ctx* ctx, const pv_grids* grids, const pv_ligands* lig
         };
         for (auto& m : members)
             std::stable_sort(m.begin(), m.end(), [&](int32_t a, int32_t b) { return cost(a) > cost(b); });
+    }
+    if (params->flags & PV_DOCK_BOX_ORDER) {
+        // one or two boxes' maps in flight at a time: each XCD's L2 holds
+        // those rather than a slice of every box's
+        for (auto& m : members)
+            std::stable_sort(m.begin(), m.end(), [&](int32_t a, int32_t b) { return hj[a].y < hj[b].y; });
     }
     hipError_t e = hipSuccess;
     for (int g = 0; g < 2 && e == hipSuccess; ++g) {

@@ -140,11 +140,12 @@ def test_schedule_rejects(pv_ctx, setup):
     plan.close()
 
 
-def test_largest_first_changes_only_the_order(oracle, pv_ctx):
+def test_job_orders_change_only_the_order(oracle, pv_ctx):
     """PV_DOCK_LARGEST_FIRST hands out each size class's jobs most costly
-    ligand first; every chain still depends on (seed, job, chain) alone, so
-    all outputs equal the job-order plan's bit for bit.  Unknown flag bits
-    are rejected."""
+    ligand first and PV_DOCK_BOX_ORDER groups them by box; every chain still
+    depends on (seed, job, chain) alone, so all outputs equal the job-order
+    plan's bit for bit, alone and combined.  Unknown flag bits are
+    rejected."""
     import paper_2506_20043_amd as pv
     cfg = S.CONFIGS["multi_pocket"]
     rx, rt, bxs = S.make_receptor(cfg)
@@ -152,21 +153,22 @@ def test_largest_first_changes_only_the_order(oracle, pv_ctx):
     mols = [S.tree_ligand(g, n, t) for n, t in ((12, 2), (50, 7), (30, 4), (100, 12), (80, 9), (20, 3))]
     grids = pv.build_grids(pv_ctx, rx, rt, bxs[:2], penalty_slope=KAPPA)
     ligs = pv.Ligands(pv_ctx, mols)
-    jobs = [(i % len(mols), i % 2) for i in range(14)]
+    jobs = [(i % len(mols), (i // 3) % 2) for i in range(14)]
     outs = []
-    for flag in (0, pv.PV_DOCK_LARGEST_FIRST):
+    for flag in (0, pv.PV_DOCK_LARGEST_FIRST, pv.PV_DOCK_BOX_ORDER, pv.PV_DOCK_LARGEST_FIRST | pv.PV_DOCK_BOX_ORDER):
         p = pv.dock_params(chains=16, steps=15, seed=94, flags=pv.PV_DOCK_GRAPH | pv.PV_DOCK_TIMESTAMPS | flag)
         plan = pv.Plan(pv_ctx, grids, ligs, jobs, p)
         assert plan.groups() == 2
         outs.append({k: v.cpu().numpy().copy() for k, v in plan.run().items()})
         plan.close()
-    for k in outs[0]:
-        if k in ("job_t_start", "job_t_end"):
-            continue
-        assert np.array_equal(outs[0][k], outs[1][k]), k
-    assert np.all(outs[1]["job_t_end"] >= outs[1]["job_t_start"])
+    for o in outs[1:]:
+        for k in outs[0]:
+            if k in ("job_t_start", "job_t_end"):
+                continue
+            assert np.array_equal(outs[0][k], o[k]), k
+        assert np.all(o["job_t_end"] >= o["job_t_start"])
     with pytest.raises(pv.PvError):
-        pv.Plan(pv_ctx, grids, ligs, jobs, pv.dock_params(chains=4, steps=2, seed=1, flags=8))
+        pv.Plan(pv_ctx, grids, ligs, jobs, pv.dock_params(chains=4, steps=2, seed=1, flags=16))
 
 
 def test_ligands_without_intra_pairs(oracle, pv_ctx, setup):
