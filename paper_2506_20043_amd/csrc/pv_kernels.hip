@@ -547,7 +547,8 @@ constexpr float kLog2e = 1.4426950408889634f;
 // One pass of U pairs per lane starting at pair p0 (this lane's first);
 // adds this lane's energy to e and its pairs inside the cutoff to cnt.
 template <int A, bool SL, int U>
-__device__ __forceinline__ void pair_pass(const Topo<A, SL>& T, const Lds& S, int p0, float& e, int& cnt)
+__device__ __forceinline__ void pair_pass(const Topo<A, SL>& T, const Lds& S, int p0, float& e, int& cnt,
+                                          const uint32_t* words = nullptr)
 {
     const uint32_t pos0 = lds_addr(S.pos);
     // position addresses; slot addresses; radius sum bits (slots) or
@@ -565,16 +566,16 @@ __device__ __forceinline__ void pair_pass(const Topo<A, SL>& T, const Lds& S, in
             v[u] = true;
         } else {
             // LDS pair words are padded to whole passes of 64 with far-point
-            // pairs; from global memory, a lane past the end reads pair 0
-            // (np >= 1 here) and discards it (an unconditional load, so all
-            // of a pass's loads stay in flight together)
+            // pairs; with two atoms per lane the caller brings the words
+            // from global memory (a lane past the end holds pair 0 and
+            // discards it)
             uint32_t g;
             if (A == 1) {
                 g = S.pw[p];
                 v[u] = true;
             } else {
                 v[u] = p < T.np;
-                g = T.gpairs[v[u] ? p : 0];
+                g = words[u];
             }
             ai[u] = pos0 + ((g & 0xffu) << 4); aj[u] = pos0 + (((g >> 8) & 0xffu) << 4);
             rc[u] = g >> 16;
@@ -666,8 +667,27 @@ __device__ __forceinline__ float pair_loop(const Topo<A, SL>& T, const Lds& S, i
     } else {
         if (A > 1) {
             // two atoms per lane (ligands of 65 to 128 atoms, long pair
-            // lists): whole passes only, over pair words padded to them
-            for (; p0 - l < np; p0 += kPairPass) pair_pass<A, SL, kPairUnroll>(T, S, p0, e, cnt);
+            // lists): whole passes only; the pair words come from global
+            // memory, each pass's loaded during the pass before (a lane past
+            // the end reads pair 0, np >= 1 here, and discards it)
+            uint32_t w[kPairUnroll], nw[kPairUnroll];
+            if (np > 0) {
+#pragma unroll
+                for (int u = 0; u < kPairUnroll; ++u) {
+                    const int p = p0 + u * kWave;
+                    w[u] = T.gpairs[p < np ? p : 0];
+                }
+            }
+            for (; p0 - l < np; p0 += kPairPass) {
+#pragma unroll
+                for (int u = 0; u < kPairUnroll; ++u) {
+                    const int p = p0 + kPairPass + u * kWave;
+                    nw[u] = T.gpairs[p < np ? p : 0];
+                }
+                pair_pass<A, SL, kPairUnroll>(T, S, p0, e, cnt, w);
+#pragma unroll
+                for (int u = 0; u < kPairUnroll; ++u) w[u] = nw[u];
+            }
         } else {
             for (; p0 - l + kPairPass <= np; p0 += kPairPass) pair_pass<A, SL, kPairUnroll>(T, S, p0, e, cnt);
             for (; p0 - l < np; p0 += kWave) pair_pass<A, SL, 1>(T, S, p0, e, cnt);
