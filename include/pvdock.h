@@ -318,8 +318,10 @@ pv_status pv_plan_set_schedule(pv_plan* plan, int32_t group, int32_t variant, in
  * candidate schedule -- every variant legal for the class, at widths of 1,
  * 3/4 and 1/2 of the workgroups the CUs hold (capped by the class's work) --
  * on a short run of the class's launch (tune_steps >= 1 Monte Carlo steps per
- * chain, outputs to the plan's own scratch, no timestamps), keeps the best of
- * `repeats` >= 1 timings (HIP events on `stream`) and sets the candidate
+ * chain, outputs to the plan's own scratch, no timestamps) over the class's
+ * first jobs in the order the launch hands them out (enough chains to fill
+ * the widest candidate 8 times, or the whole class when it has fewer), keeps
+ * the best of `repeats` >= 1 timings (HIP events on `stream`) and sets the candidate
  * with the most evaluations per second; on a tie the earlier candidate (the
  * model's schedule comes first) wins.  The choice is remembered by the
  * context, keyed by the class's ligand limits, work items, tune_steps and

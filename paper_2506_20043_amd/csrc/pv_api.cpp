@@ -68,6 +68,7 @@ struct TuneEntry {
 };
 
 constexpr size_t kTuneMemory = 256;   // autotuner choices a context remembers
+constexpr int64_t kTuneFill = 8;      // a tuning run's chains: this many times the widest candidate's workgroups
 
 struct pv_ctx {
     int device;
@@ -138,6 +139,7 @@ struct pv_plan {
     // with its own LDS limits, kernel variant and persistent launch; jobs
     // keep their indices through a per-group job map.
     std::vector<DockGroup> groups;
+    std::vector<std::vector<int32_t>> group_jobs;   // per group: its plan jobs in job-map order
     std::vector<int32_t> job_group;   // per job: index into groups
     hipStream_t cap_stream;
     hipGraph_t graph;
@@ -768,6 +770,7 @@ pv_status pv_dock_plan(pv_ctx* ctx, const pv_grids* grids, const pv_ligands* lig
         }
         for (int32_t j : members[g]) P->job_group[j] = (int32_t)P->groups.size();
         P->groups.push_back(G);
+        P->group_jobs.push_back(members[g]);
     }
     if (e != hipSuccess) { pv_plan_free(P); return hip_fail(e, "dock launch shape"); }
     e = hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking);
@@ -1059,6 +1062,14 @@ pv_status pv_dock_autotune(pv_plan* P, int32_t tune_steps, int32_t repeats, void
                 if (!seen) cand.push_back({sh, wg});
             }
         }
+        // every candidate runs on the class's first jobs in job-map order:
+        // enough chains to fill the widest candidate kTuneFill times (all of
+        // the class when it is smaller), so the tuning cost does not grow
+        // with the batch
+        int64_t widest = 1;
+        for (const auto& c : cand) widest = std::max<int64_t>(widest, c.second);
+        const int64_t t_items = std::min<int64_t>(items, (kTuneFill * widest + chains - 1) / chains * chains);
+        const int32_t t_jobs = (int32_t)(t_items / chains);
         size_t best = 0;
         double best_rate = -1.0;
         std::vector<int32_t> slot(cand.size(), -1);
@@ -1070,7 +1081,7 @@ pv_status pv_dock_autotune(pv_plan* P, int32_t tune_steps, int32_t repeats, void
             a.job_map = G.job_map;
             a.queue = P->queue + g;
             a.job_begin = 0;
-            a.n_items = items;
+            a.n_items = t_items;
             a.persistent = 1;
             float best_ms = 0.f;
             for (int r = 0; r < repeats; ++r) {
@@ -1087,9 +1098,10 @@ pv_status pv_dock_autotune(pv_plan* P, int32_t tune_steps, int32_t repeats, void
             e = hipMemcpy(hev.data(), P->scratch_evals, hev.size() * sizeof(int64_t), hipMemcpyDeviceToHost);
             if (e != hipSuccess) return done(hip_fail(e, "autotune evaluation counts"));
             int64_t ev = 0;
-            for (int32_t j = 0; j < P->n_jobs; ++j)
-                if (P->job_group[j] == (int32_t)g)
-                    for (int32_t c = 0; c < chains; ++c) ev += hev[(size_t)j * chains + c];
+            for (int32_t q = 0; q < t_jobs; ++q) {
+                const int32_t j = P->group_jobs[g][q];
+                for (int32_t c = 0; c < chains; ++c) ev += hev[(size_t)j * chains + c];
+            }
             const double rate = best_ms > 0.f ? (double)ev / (best_ms * 1e-3) : 0.0;
             slot[k] = put(pv_tune_result{(int32_t)g, cand[k].first.variant, cand[k].second, 0, 0, best_ms, rate});
             if (rate > best_rate) { best_rate = rate; best = k; }
