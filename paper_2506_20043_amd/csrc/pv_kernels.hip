@@ -644,8 +644,9 @@ __device__ __forceinline__ void pair_pass(const Topo<A, SL>& T, const Lds& S, in
 
 // Intra pairs, lanes over pairs: whole passes of kPairUnroll pairs per lane
 // (every load of a pass issued before any of its arithmetic, so the LDS
-// latency is paid once per pass), then, on the gather layout, passes of one
-// pair per lane over the rest, so at most 63 padding pairs are evaluated.
+// latency is paid once per pass), then, on the gather layout with one atom
+// per lane, whole passes of two pairs per lane and passes of one over the
+// rest, so at most 63 padding pairs are evaluated.
 // Per pair, with d the surface distance and inside 8 A: the gauss,
 // repulsion, hydrophobic and hydrogen-bond terms of the Vina form and the
 // force coefficient c = (dphi/dr) / r.  Pairs are grouped by interaction
@@ -690,6 +691,7 @@ __device__ __forceinline__ float pair_loop(const Topo<A, SL>& T, const Lds& S, i
             }
         } else {
             for (; p0 - l + kPairPass <= np; p0 += kPairPass) pair_pass<A, SL, kPairUnroll>(T, S, p0, e, cnt);
+            for (; p0 - l + 2 * kWave <= np; p0 += 2 * kWave) pair_pass<A, SL, 2>(T, S, p0, e, cnt);
             for (; p0 - l < np; p0 += kWave) pair_pass<A, SL, 1>(T, S, p0, e, cnt);
         }
     }
