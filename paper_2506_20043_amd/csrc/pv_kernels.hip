@@ -375,6 +375,8 @@ struct Topo {
     float anc_x, anc_y, anc_z, rot_scale;
     float4 ref[A];
     int f_parent, f_tors, f_child, f_a0, f_end;
+    uint64_t links;   // the ancestor a fragment lane composes with in each pointer-doubling round, 6 bits per
+                      // round (63: none): fragments 0..32 and up to 6 rounds
     float ax, ay, az, cx, cy, cz;
     int dof_frag;
     const uint32_t* gpairs;   // pair list and atom -> pair table in global
@@ -409,6 +411,18 @@ __device__ void stage_ligand(Topo<A, SL>& T, const LigDev& L, int lig, const Lds
         T.ax = T.ay = T.az = T.cx = T.cy = T.cz = 0.f;
     }
     T.dof_frag = (l >= 6 && l < 6 + T.nt) ? (int)L.tors_frag[d.tors_base + l - 6] : 0;
+    {
+        // the links do not depend on the pose: jumped once here (a lane
+        // with an ancestor takes that ancestor's link after each round)
+        static_assert(kMaxFrag <= 63, "a link holds a fragment index below 63");
+        int anc = (l >= 1 && l < T.nf) ? T.f_parent : -1;
+        T.links = 0;
+        for (int r = 0; r < T.rounds; ++r) {
+            T.links |= (uint64_t)(anc >= 0 ? anc : 63) << (6 * r);
+            const int panc = __builtin_amdgcn_ds_bpermute((anc >= 0 ? anc : l) << 2, anc);
+            if (anc >= 0) anc = panc;
+        }
+    }
     T.gpairs = L.pairs + d.pair_base;
     T.gell = L.ell + d.ell_base;
     if (l == 0) S.pos[S.ma] = make_float4(1e18f, 1e18f, 1e18f, 0.f);
@@ -497,21 +511,20 @@ __device__ __forceinline__ void frames(const Topo<A, SL>& T, const Lds& S, const
     b[0] = px - (R[0] * ax + R[1] * ay + R[2] * az);
     b[1] = py - (R[3] * ax + R[4] * ay + R[5] * az);
     b[2] = pz - (R[6] * ax + R[7] * ay + R[8] * az);
-    int anc = (!root && l < T.nf) ? T.f_parent : -1;
     // pointer doubling across lanes: every round each fragment fetches the
-    // partial frame and ancestor link of its current ancestor straight from
-    // that lane's registers (ds_bpermute, all lanes taking part), then
-    // composes; a lane without an ancestor fetches its own values and keeps
-    // its frame
+    // partial frame of its ancestor of that round (links jumped at staging)
+    // straight from that lane's registers (ds_bpermute, all lanes taking
+    // part), then composes; a lane without an ancestor fetches its own
+    // values and keeps its frame
     for (int r = 0; r < T.rounds; ++r) {
-        const int src = (anc >= 0 ? anc : l) << 2;
+        const int anc = (int)(T.links >> (6 * r)) & 63;
+        const int src = (anc != 63 ? anc : l) << 2;
         float P[9], pb[3];
 #pragma unroll
         for (int k = 0; k < 9; ++k) P[k] = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(R[k])));
 #pragma unroll
         for (int k = 0; k < 3; ++k) pb[k] = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(b[k])));
-        const int panc = __builtin_amdgcn_ds_bpermute(src, anc);
-        if (anc >= 0) {
+        if (anc != 63) {
             float N[9], nb[3];
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
@@ -524,7 +537,6 @@ __device__ __forceinline__ void frames(const Topo<A, SL>& T, const Lds& S, const
             for (int k = 0; k < 9; ++k) R[k] = N[k];
 #pragma unroll
             for (int k = 0; k < 3; ++k) b[k] = nb[k];
-            anc = panc;
         }
     }
 }
@@ -1081,6 +1093,7 @@ __device__ BfgsOut bfgs(const Topo<A, SL>& T, const BoxView& B, const Lds& S, co
     const int m = P.m;
     float f = 0.f, g = 0.f, d = 0.f, gd = 0.f, gn = 0.f;
     float lo = 0.f, lam = 1.f, beta = 0.f, fa = 0.f, ga = 0.f;
+    float sy_new = 0.f, yy_new = 1.f;   // s.y and y.y of the newest stored pair (the H0 scale)
     bool beta_inf = true, initial = true;
     while (true) {
         // a trial above the sufficient-decrease bound needs no gradient
@@ -1125,8 +1138,10 @@ __device__ BfgsOut bfgs(const Topo<A, SL>& T, const BoxView& B, const Lds& S, co
             }
             // s = lam d, y = g+ - g; cautious update (Eqs. qvina_eq_10, qvina_eq_11)
             const float sv = lam_ok * d, yv = gnw - g;
-            const float ys = wsum_n(yv * sv, nd), ss = wsum_n(sv * sv, nd);
+            const float ys = wsum_n(yv * sv, nd), ss = wsum_n(sv * sv, nd), yy = wsum_n(yv * yv, nd);
             if (ys * __builtin_amdgcn_rcpf(ss) > P.eps_c * gn) {
+                sy_new = ys;
+                yy_new = yy;
                 if (hn == m) {
 #pragma unroll
                     for (int h = 0; h < kMaxM - 1; ++h) { Sh[h] = Sh[h + 1]; Yh[h] = Yh[h + 1]; rh[h] = rh[h + 1]; }
@@ -1157,13 +1172,7 @@ __device__ BfgsOut bfgs(const Topo<A, SL>& T, const BoxView& B, const Lds& S, co
                     q -= al[h] * Yh[h];
                 }
             }
-            if (hn > 0) {
-                float sy = 0.f, yy = 0.f;
-#pragma unroll
-                for (int h = 0; h < kMaxM; ++h)
-                    if (h == hn - 1) { sy = Sh[h] * Yh[h]; yy = Yh[h] * Yh[h]; }
-                q *= wsum_n(sy, nd) * __builtin_amdgcn_rcpf(wsum_n(yy, nd));
-            }
+            if (hn > 0) q *= sy_new * __builtin_amdgcn_rcpf(yy_new);
 #pragma unroll
             for (int h = 0; h < kMaxM; ++h) {
                 if (h < hn) {
