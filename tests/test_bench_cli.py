@@ -1,6 +1,7 @@
 """The benchmark's command line on the CPU: it measures one GPU, so more
 than one is refused with a message and a non-zero status before any device
-work; --help lists the legs."""
+work; --help lists the legs; the recorded HBM traffic is used only where it
+still describes the code."""
 import os
 import subprocess
 import sys
@@ -24,3 +25,24 @@ def test_help_lists_the_legs():
     assert r.returncode == 0
     for leg in ("tiny", "multi_pocket", "score", "local_opt", "batching", "stream_plain", "box_sweep", "surface"):
         assert leg in r.stdout
+
+
+def test_recorded_traffic_only_for_matching_sources_and_order():
+    """The HBM traffic in the bench line comes from the committed counter
+    record only while every native source hashes to the recorded value and
+    the job order is the recorded one; otherwise it is null."""
+    import json
+    sys.path.insert(0, ROOT)
+    import bench
+    rec = None
+    for line in open(os.path.join(ROOT, "profiles", "dock_kernel_screening_stream.md")):
+        if line.startswith("traffic_record: "):
+            rec = json.loads(line[len("traffic_record: "):])
+    assert rec is not None and rec["job_order"] in ("stream", "box")
+    other = "stream" if rec["job_order"] == "box" else "box"
+    assert bench.recorded_traffic(other) is None
+    got = bench.recorded_traffic(rec["job_order"])
+    if bench.native_source_hash() == rec["native_source_sha256"]:
+        assert got == rec["dock_traffic_bytes_per_launch"]
+    else:
+        assert got is None
