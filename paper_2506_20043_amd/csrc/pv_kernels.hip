@@ -463,8 +463,19 @@ __device__ void stage_ligand(Topo<A, SL>& T, const LigDev& L, int lig, const Lds
         // point to atom 0, so they fall outside the cutoff and store c = 0
         // (which also serves the atom -> pair table's padding entries, p = np)
         if (A == 1) {
+            // eight loads per lane in flight before their stores
             const int npad = round_up(T.np + 1, kWave);
-            for (int p = l; p < npad; p += kWave) S.pw[p] = p < T.np ? T.gpairs[p] : (uint32_t)S.ma;
+            for (int p0 = l; p0 < npad; p0 += 8 * kWave) {
+                uint32_t w[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int p = p0 + q * kWave;
+                    w[q] = p < T.np ? T.gpairs[p] : (uint32_t)S.ma;
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (p0 + q * kWave < npad) S.pw[p0 + q * kWave] = w[q];
+            }
         }
         if (l == 0) S.cp[T.np] = 0.f;   // not written by the pair loop when np is a multiple of 64
     }
@@ -1483,8 +1494,24 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(A == 1 && !S
     // once), the runs' lengths differing by at most one so no wave idles
     const int p_begin = (int)(((int64_t)blockIdx.x * a.n_poses) / (int64_t)gridDim.x);
     const int p_end = (int)(((int64_t)(blockIdx.x + 1) * a.n_poses) / (int64_t)gridDim.x);
+    // the next pose's indices and pose vector are loaded while this one is
+    // evaluated (lane l holds pose entry l)
+    const bool dof_in = !a.from_xyz;
+    int n_lig = 0, n_box = 0;
+    float n_dof = 0.f;
+    if (p_begin < p_end) {
+        n_lig = a.lig_of_pose[p_begin];
+        n_box = a.box_of_pose[p_begin];
+        if (dof_in && l < a.dof_stride) n_dof = a.dof[(int64_t)p_begin * a.dof_stride + l];
+    }
     for (int pose = p_begin; pose < p_end; ++pose) {
-        const int lig = a.lig_of_pose[pose], box = a.box_of_pose[pose];
+        const int lig = n_lig, box = n_box;
+        const float dof_l = n_dof;
+        if (pose + 1 < p_end) {
+            n_lig = a.lig_of_pose[pose + 1];
+            n_box = a.box_of_pose[pose + 1];
+            if (dof_in && l < a.dof_stride) n_dof = a.dof[(int64_t)(pose + 1) * a.dof_stride + l];
+        }
         if (lig < 0 || lig >= a.l.n_lig || box < 0 || box >= a.g.n_boxes) {
             if (l == 0 && a.energy) a.energy[pose] = nanv;
             if (l < 2 && a.e_parts) a.e_parts[2 * (int64_t)pose + l] = nanv;
@@ -1501,7 +1528,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(A == 1 && !S
         const int16_t* perm = a.l.perm + a.l.ligs[lig].atom_base;
         Eval ev;
         if (!a.from_xyz) {
-            if (l < 7 + T.nt) S.pose[SLOT_X * kSlot + l] = a.dof[(int64_t)pose * a.dof_stride + l];
+            if (l < 7 + T.nt) S.pose[SLOT_X * kSlot + l] = dof_l;
             wave_sync();
             ev = evaluate(T, B, S, S.pose + SLOT_X * kSlot);
         } else {
