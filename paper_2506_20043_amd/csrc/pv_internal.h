@@ -42,7 +42,8 @@ struct alignas(16) DevFrag {
     float xc[4];         // reference position of the child-side atom
 };
 
-// Intra pair packed as i | j << 8 | rk << 16 | class << 19 (new atom order).
+// Intra pair packed as i | j << 8 | rk << 16 | class << 24 (new atom order; the
+// radius-sum code fills byte 2 alone, so the kernel converts it in one step).
 // Atom record: x, y, z and w = bits(type | fragment << 8).
 // pslot (same index as the pair list): the slot the pair occupies in the
 // row of its first atom | in the row of its second atom << 16 (force-slot
@@ -59,7 +60,7 @@ struct LigModel {
     std::vector<float> ref;         // [n][4] new order: x, y, z, w-bits
     std::vector<DevFrag> frags;     // preorder
     std::vector<int> tors_frag;     // torsion k -> fragment
-    std::vector<uint32_t> pairs;    // i | j << 8 | rk << 16 | class << 19 (radius sum 3.4 + 0.1 rk;
+    std::vector<uint32_t> pairs;    // i | j << 8 | rk << 16 | class << 24 (radius sum 3.4 + 0.1 rk;
                                     // class 0 plain, 1 hydrophobic, 2 hydrogen bond), grouped by class
     std::vector<uint32_t> ell;      // [n][ell_w]
     std::vector<uint32_t> pslot;    // per pair: slot in row i | slot in row j << 16

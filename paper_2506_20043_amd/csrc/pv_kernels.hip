@@ -446,7 +446,7 @@ __device__ void stage_ligand(Topo<A, SL>& T, const LigDev& L, int lig, const Lds
             if (p < T.np) {
                 const uint32_t pk = T.gpairs[p], sl = ps[p];
                 const uint32_t i = pk & 0xff, j = (pk >> 8) & 0xff;
-                r.x = (pos0 + (i << 4)) | (pos0 + (j << 4)) << 16 | ((pk >> 19) << 30);
+                r.x = (pos0 + (i << 4)) | (pos0 + (j << 4)) << 16 | ((pk >> 24) << 30);
                 r.y = fs0 + (((sl & 0xffff) * ns + i) << 4);
                 r.z = fs0 + (((sl >> 16) * ns + j) << 4);
                 r.w = __float_as_uint(fmaf((float)((pk >> 16) & 7u), 0.1f, 3.4f));
@@ -575,7 +575,7 @@ __device__ __forceinline__ void pair_pass(const Topo<A, SL>& T, const Lds& S, in
 {
     const uint32_t pos0 = lds_addr(S.pos);
     // position addresses; slot addresses; radius sum bits (slots) or
-    // radius-sum code | class << 3 (gather)
+    // the pair word's upper half, radius-sum code | class << 8 (gather)
     uint32_t ai[U], aj[U], ya[U], za[U], rc[U];
     bool v[U];
     float4 xi[U], xj[U];
@@ -608,7 +608,7 @@ __device__ __forceinline__ void pair_pass(const Topo<A, SL>& T, const Lds& S, in
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         xi[u] = *(const float4*)lds_ptr<const float4>(ai[u]);
-        xj[u] = *(const float4*)lds_ptr<const float4>(aj[u] & 0x3fffu);
+        xj[u] = *(const float4*)lds_ptr<const float4>(SL ? aj[u] & 0x3fffu : aj[u]);
     }
     float dx[U], dy[U], dz[U], d[U], en[U], de[U], rinv[U];
     bool in[U];
@@ -622,7 +622,7 @@ __device__ __forceinline__ void pair_pass(const Topo<A, SL>& T, const Lds& S, in
         // zeroes the force
         const float r2c = fmaxf(r2, 1e-12f);
         rinv[u] = __builtin_amdgcn_rsqf(r2c);
-        const float rs = SL ? __uint_as_float(rc[u]) : fmaf((float)(rc[u] & 7u), 0.1f, 3.4f);
+        const float rs = SL ? __uint_as_float(rc[u]) : fmaf((float)(rc[u] & 0xffu), 0.1f, 3.4f);
         const float dd = r2c * rinv[u] - rs;
         d[u] = dd;
         const float g1 = __builtin_amdgcn_exp2f(dd * dd * (-4.f * kLog2e));          // exp(-(d/0.5)^2)
@@ -636,7 +636,7 @@ __device__ __forceinline__ void pair_pass(const Topo<A, SL>& T, const Lds& S, in
     for (int u = 0; u < U; ++u) {
         // class 1 (both hydrophobic) adds the hydrophobic term, class 2
         // (donor with acceptor) the hydrogen-bond term
-        const uint32_t cls = SL ? aj[u] >> 14 : rc[u] >> 3;
+        const uint32_t cls = SL ? aj[u] >> 14 : rc[u] >> 8;
         if (__ballot(cls != 0u)) {
             const float wy = cls == 1u ? kW4 : 0.f, wz = cls == 2u ? kW5 : 0.f;
             const float dd = d[u];

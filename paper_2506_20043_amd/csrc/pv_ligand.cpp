@@ -233,7 +233,7 @@ int build_ligand_model(int n, const float* xyz, const uint8_t* type, int nb, con
         const int ta = type[perm[i]], tb = type[perm[j]];
         const int rk = (int)std::lround((kRadius[ta] + kRadius[tb] - 3.4) * 10.0);
         M.pairs.push_back((uint32_t)i | ((uint32_t)j << 8) | ((uint32_t)rk << 16) |
-                          ((uint32_t)cls(pl[idx]) << 19));
+                          ((uint32_t)cls(pl[idx]) << 24));
     }
     // atom -> pair rows (partners in ascending pair order), padded to the longest
     std::vector<std::vector<uint32_t>> rows(n);
