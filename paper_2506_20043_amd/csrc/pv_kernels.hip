@@ -625,12 +625,16 @@ __device__ __forceinline__ void pair_pass(const Topo<A, SL>& T, const Lds& S, in
         const float rs = SL ? __uint_as_float(rc[u]) : fmaf((float)(rc[u] & 0xffu), 0.1f, 3.4f);
         const float dd = r2c * rinv[u] - rs;
         d[u] = dd;
-        const float g1 = __builtin_amdgcn_exp2f(dd * dd * (-4.f * kLog2e));          // exp(-(d/0.5)^2)
-        const float dm3 = dd - 3.f;
-        const float g2 = __builtin_amdgcn_exp2f(dm3 * dm3 * (-0.25f * kLog2e));      // exp(-((d-3)/2)^2)
+        // exp(-(d/0.5)^2) and exp(-((d-3)/2)^2), the second exponent
+        // expanded around d^2 so both share it: c (d-3)^2 = c d^2 - 6c d + 9c
+        const float d2 = dd * dd;
+        const float g1 = __builtin_amdgcn_exp2f(d2 * (-4.f * kLog2e));
+        constexpr float c2 = -0.25f * kLog2e;
+        const float g2 = __builtin_amdgcn_exp2f(fmaf(d2, c2, fmaf(dd, -6.f * c2, 9.f * c2)));
         const float dn = fminf(dd, 0.f);                                             // repulsion d^2, d < 0
         en[u] = fmaf(kW1, g1, fmaf(kW2, g2, kW3 * (dn * dn)));
-        de[u] = fmaf(g1, dd * (-8.f * kW1), fmaf(g2, dm3 * (-0.5f * kW2), dn * (2.f * kW3)));
+        constexpr float k2 = -0.5f * kW2;                                            // d/dd of the second: k2 (d-3)
+        de[u] = fmaf(g1, dd * (-8.f * kW1), fmaf(g2, fmaf(dd, k2, -3.f * k2), dn * (2.f * kW3)));
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {

@@ -122,6 +122,37 @@ def test_autotune_chooses_remembers_and_stays_valid(oracle, pv_ctx, setup):
     plan2.close()
 
 
+def test_autotune_on_a_prefix_of_a_large_class(pv_ctx, setup):
+    """A class with more chains than 8 times the widest candidate is tuned
+    on its first jobs only; the tuner still reports every candidate with a
+    timing and a rate, sets the fastest, and the tuned run equals a run of
+    a fresh plan given the same schedule by hand."""
+    import paper_2506_20043_amd as pv
+    import torch
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    chains = 16
+    n_jobs = (8 * 8 * n_cu) // chains + 76   # more chains than 8 x (8 waves per CU x the CUs)
+    jobs = [(0, 0)] * n_jobs
+    p = pv.dock_params(chains=chains, steps=1, seed=97, flags=pv.PV_DOCK_GRAPH)
+    plan = pv.Plan(pv_ctx, setup["grids"], setup["ligs"], jobs, p)
+    assert plan.groups() == 1
+    res = plan.autotune(steps=1, repeats=1)
+    assert len(res) >= 2 and all(r["cached"] == 0 and r["ms"] > 0 and r["evals_per_s"] > 0 for r in res)
+    chosen = [r for r in res if r["chosen"]]
+    assert len(chosen) == 1 and chosen[0]["evals_per_s"] == max(r["evals_per_s"] for r in res)
+    sc = plan.schedule(0)
+    assert (sc["variant"], sc["workgroups"]) == (chosen[0]["variant"], chosen[0]["workgroups"])
+    out = {k: v.cpu().numpy().copy() for k, v in plan.run().items()}
+    plan.close()
+    assert np.all(np.isfinite(out["job_best_e"])) and np.all(out["job_evals"] > 0)
+    ref = pv.Plan(pv_ctx, setup["grids"], setup["ligs"], jobs, p)
+    ref.set_schedule(0, sc["variant"], sc["workgroups"])
+    o2 = {k: v.cpu().numpy().copy() for k, v in ref.run().items()}
+    ref.close()
+    for k in ("chain_best_e", "chain_evals", "job_best_e", "job_evals"):
+        assert np.array_equal(out[k], o2[k]), k
+
+
 def test_schedule_rejects(pv_ctx, setup):
     import paper_2506_20043_amd as pv
     p = pv.dock_params(chains=8, steps=5, seed=93)
