@@ -73,7 +73,9 @@ void pv_destroy(pv_ctx* ctx);
  * resident in device memory and owned by the handle.
  *
  * rec_xyz: host [n_rec][3]; rec_type: host [n_rec], values < 8.
- * boxes: host [n_boxes]; size > 0, spacing > 0, at most 2048 points per axis.
+ * boxes: host [n_boxes]; size > 0, spacing > 0, at most 2048 points per axis
+ * and fewer than 2^24 points per box (a cube of 255 points: edges up to 95 A at
+ * 0.375 A), else PV_E_RANGE.
  * penalty_slope: kcal/mol per A added for each atom coordinate outside a box
  * (its lookups clamp to the box face); must be >= 0.
  * n_rec may be 0 (all maps zero).  Every lattice point sums its receptor

@@ -287,6 +287,7 @@ pv_status pv_build_grids(pv_ctx* ctx, int32_t n_rec, const float* rec_xyz, const
             geom[8 * b + 5 + a] = e3[a];
             msz *= (int64_t)d3[a];
         }
+        if (msz >= ((int64_t)1 << 24)) return fail(PV_E_RANGE, "a box's lattice has 2^24 points or more");
         dims[4 * b + 3] = 0;
         geom[8 * b + 3] = B.spacing;
         geom[8 * b + 4] = (float)(1.0 / h);

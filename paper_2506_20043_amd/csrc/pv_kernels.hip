@@ -186,11 +186,15 @@ __device__ __forceinline__ BoxView box_view(const GridDev& g, int box)
 __device__ __forceinline__ void axis_setup(float x, float o, float inv_h, float ext, int n, float kappa,
                                            int& i0, float& u, float& pen, float& dpen, bool& clamped)
 {
-    float rel = x - o;
-    float f = rel * inv_h;
-    pen = 0.f; dpen = 0.f; clamped = false;
-    if (x < o) { pen = kappa * (o - x); dpen = -kappa; f = 0.f; clamped = true; }
-    else if (rel > ext) { pen = kappa * (rel - ext); dpen = kappa; f = (float)(n - 1); clamped = true; }
+    // no branches: at most one side is out (ext >= 0), so the penalty is the
+    // sum of both sides' excess; a NaN coordinate is on neither side and
+    // keeps its NaN in f
+    const float rel = x - o;
+    const bool lo = x < o, hi = rel > ext;
+    pen = kappa * (fmaxf(o - x, 0.f) + fmaxf(rel - ext, 0.f));
+    dpen = lo ? -kappa : (hi ? kappa : 0.f);
+    const float f = lo ? 0.f : (hi ? (float)(n - 1) : rel * inv_h);
+    clamped = lo || hi;
     int c = (int)floorf(f);
     c = max(0, min(c, n - 2));  // also keeps a NaN coordinate inside the map
     i0 = c;
@@ -214,13 +218,22 @@ __device__ __forceinline__ void tri_issue(const BoxView& B, int t, float x, floa
     axis_setup(y, B.oy, B.inv_h, B.ey, B.ny, B.kappa, iy, L.uy, py, L.dy, L.cy);
     axis_setup(z, B.oz, B.inv_h, B.ez, B.nz, B.kappa, iz, L.uz, pz, L.dz, L.cz);
     L.pen = px + py + pz;
-    const float* m = B.maps + (int64_t)t * B.msz + ((int64_t)iz * B.ny + iy) * B.nx + ix;
-    const int sy = B.nx;
-    const int64_t sz = (int64_t)B.nx * B.ny;
-    L.m[0] = m[0]; L.m[1] = m[1];
-    L.m[2] = m[sy]; L.m[3] = m[sy + 1];
-    L.m[4] = m[sz]; L.m[5] = m[sz + 1];
-    L.m[6] = m[sz + sy]; L.m[7] = m[sz + sy + 1];
+    // a box's 8 maps hold fewer than 8 x 2^24 points (checked when the grids
+    // are built), so the corner offsets are 32-bit byte offsets from the
+    // maps' base, formed with 24-bit multiplies
+    const uint32_t nx = (uint32_t)B.nx, ny = (uint32_t)B.ny;
+    const uint32_t e = __umul24((uint32_t)t, (uint32_t)B.msz) + __umul24(__umul24((uint32_t)iz, ny) + (uint32_t)iy, nx) +
+                       (uint32_t)ix;
+    const uint32_t o0 = e << 2, oy = nx << 2, oz = __umul24(nx, ny) << 2;
+    const char* mb = (const char*)B.maps;
+    const float* r0 = (const float*)(mb + o0);
+    const float* r1 = (const float*)(mb + (o0 + oy));
+    const float* r2 = (const float*)(mb + (o0 + oz));
+    const float* r3 = (const float*)(mb + (o0 + oz + oy));
+    L.m[0] = r0[0]; L.m[1] = r0[1];
+    L.m[2] = r1[0]; L.m[3] = r1[1];
+    L.m[4] = r2[0]; L.m[5] = r2[1];
+    L.m[6] = r3[0]; L.m[7] = r3[1];
 }
 
 __device__ __forceinline__ float tri_finish(const BoxView& B, const TriLoad& L, float& gx, float& gy, float& gz)
@@ -1383,8 +1396,11 @@ __device__ ChainOut mc_chain(const Topo<A, SL>& T, const BoxView& B, const Lds& 
 
 // ---------------------------------------------------------------- kernels
 
+// Two waves per SIMD for the slot form: without the bound it took 8 AGPRs
+// above its 252 VGPRs and fell to one (it holds 253 VGPRs with 4 spilled).
+// The gather forms fit two waves by themselves and are faster without it.
 template <int A, bool SL>
-__global__ __launch_bounds__(64) void dock_kernel(DockArgs a)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SL ? 2 : 1))) void dock_kernel(DockArgs a)
 {
     extern __shared__ __align__(16) char smem[];
     const Lds S = carve(smem, a.l.max_atoms, a.l.max_pairs, a.l.max_ell, kernel_needs(kKindDock, A, SL));

@@ -176,6 +176,12 @@ def test_build_grids_rejects(pv_ctx):
     bad = S.Box(np.zeros(3, np.float32), np.array([5.0, 0.0, 5.0], np.float32), 0.375)
     with pytest.raises(pv.PvError, match="size"):
         pv.build_grids(pv_ctx, rx, np.array([0], np.uint8), [bad])
+    # 268^3 points: beyond the 2^24 points a box's 32-bit map offsets allow
+    huge = S.Box(np.zeros(3, np.float32), np.full(3, 100.0, np.float32), 0.375)
+    with pytest.raises(pv.PvError, match="2\\^24"):
+        pv.build_grids(pv_ctx, rx, np.array([0], np.uint8), [huge])
+    edge = S.Box(np.zeros(3, np.float32), np.full(3, 94.875, np.float32), 0.375)   # 254^3 points: accepted
+    assert pv.build_grids(pv_ctx, rx, np.array([0], np.uint8), [edge]).info(0)[0].tolist() == [254, 254, 254]
 
 
 def test_box_size_sweep_sampled(oracle, pv_ctx):
