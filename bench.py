@@ -285,7 +285,7 @@ def bench_stream(pv, S, ctx, stream, args, inp):
         launches = int(sum(1 for k in range(K) if steps[k][c] is not None))
         cls_stats.append({
             "class": "ligands of at most 64 atoms" if c == 0 else "ligands of more than 64 atoms",
-            "kernel": "dock_kernel<%d, false>" % (1 if c == 0 else 2), "schedule": sched[c],
+            "kernel": kernel_name(sched[c]["variant"], params.bfgs_m) if sched[c] else None, "schedule": sched[c],
             "jobs": int(m.sum()), "launches": launches, "launch_ms_mean": ms_c / max(launches, 1),
             "evals": int(ev[m].sum()), "evals_per_s": float(ev[m].sum() / (ms_c * 1e-3)) if ms_c else 0.0,
             "tflops": float(fl[m].sum() / (ms_c * 1e-3) / 1e12) if ms_c else 0.0})
@@ -362,6 +362,13 @@ def native_source_hash():
         if f.endswith((".hip", ".cpp", ".h")):
             h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()
+
+
+def kernel_name(variant, m):
+    """The dock kernel instantiation a schedule runs: its variant's atoms per
+    lane and slot layout, and the history capacity the search's m selects."""
+    a, sl = {"slots": (1, "true"), "gather": (1, "false"), "gather2": (2, "false")}[variant]
+    return "dock_kernel<%d, %s, %d>" % (a, sl, 5 if m <= 5 else 8)
 
 
 def recorded_traffic(job_order):

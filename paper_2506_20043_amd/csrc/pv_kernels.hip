@@ -1043,7 +1043,9 @@ __device__ __forceinline__ void retract(const Lds& S, int dst, int src, float d,
 }
 
 // ---------------------------------------------------------------- RILC-BFGS
-constexpr int kMaxM = 8;
+constexpr int kMaxM = 8;     // the most history pairs a search may keep (bfgs_m)
+constexpr int kShortM = 5;   // the dock kernel is also built for at most this many (the default m): the history
+                             // lives in registers, and room for 8 pairs cost the shift and copies of 3 more
 
 struct BfgsOut {
     float f;
@@ -1101,10 +1103,11 @@ __device__ __forceinline__ bool consistency_passes(const Lds& S, const float* x,
 // Minimises from the pose in SLOT_X; the result is left in SLOT_X.  Written
 // as one loop around a single evaluation (the first at x0, then one per
 // line-search trial) so the kernel carries one copy of the evaluation code.
-template <int A, bool SL>
+template <int A, bool SL, int MM = kMaxM>
 __device__ BfgsOut bfgs(const Topo<A, SL>& T, const BoxView& B, const Lds& S, const SearchParams& P, int max_iter,
                         bool check = false, CheckIn ck = CheckIn{0.f, 0.f, 0, 0})
 {
+    static_assert(MM >= 1 && MM <= kMaxM, "history capacity");
     const int l = lane_id();
     const int nd = 6 + T.nt;
     const bool act = l < nd;
@@ -1114,9 +1117,9 @@ __device__ BfgsOut bfgs(const Topo<A, SL>& T, const BoxView& B, const Lds& S, co
     out.pairs = 0;
     out.skipped = false;
     out.outside0 = false;
-    float Sh[kMaxM], Yh[kMaxM], rh[kMaxM];
+    float Sh[MM], Yh[MM], rh[MM];
 #pragma unroll
-    for (int h = 0; h < kMaxM; ++h) { Sh[h] = 0.f; Yh[h] = 0.f; rh[h] = 0.f; }
+    for (int h = 0; h < MM; ++h) { Sh[h] = 0.f; Yh[h] = 0.f; rh[h] = 0.f; }
     int hn = 0, it = 0, tr = 0;
     const int m = P.m;
     float f = 0.f, g = 0.f, d = 0.f, gd = 0.f, gn = 0.f;
@@ -1172,11 +1175,11 @@ __device__ BfgsOut bfgs(const Topo<A, SL>& T, const BoxView& B, const Lds& S, co
                 yy_new = yy;
                 if (hn == m) {
 #pragma unroll
-                    for (int h = 0; h < kMaxM - 1; ++h) { Sh[h] = Sh[h + 1]; Yh[h] = Yh[h + 1]; rh[h] = rh[h + 1]; }
+                    for (int h = 0; h < MM - 1; ++h) { Sh[h] = Sh[h + 1]; Yh[h] = Yh[h + 1]; rh[h] = rh[h + 1]; }
                     --hn;
                 }
 #pragma unroll
-                for (int h = 0; h < kMaxM; ++h)
+                for (int h = 0; h < MM; ++h)
                     if (h == hn) { Sh[h] = sv; Yh[h] = yv; rh[h] = __builtin_amdgcn_rcpf(ys); }
                 ++hn;
             }
@@ -1191,9 +1194,9 @@ __device__ BfgsOut bfgs(const Topo<A, SL>& T, const BoxView& B, const Lds& S, co
             gn = __builtin_amdgcn_sqrtf(wsum_n(g * g, nd));
             if (gn <= P.eps_g) break;                 // Eq. qvina_eq_12
             // two-loop recursion: d = -H g (d = -g with no pairs, Eq. qvina_eq_6)
-            float q = g, al[kMaxM];
+            float q = g, al[MM];
 #pragma unroll
-            for (int h = kMaxM - 1; h >= 0; --h) {
+            for (int h = MM - 1; h >= 0; --h) {
                 al[h] = 0.f;
                 if (h < hn) {
                     al[h] = rh[h] * wsum_n(Sh[h] * q, nd);
@@ -1202,7 +1205,7 @@ __device__ BfgsOut bfgs(const Topo<A, SL>& T, const BoxView& B, const Lds& S, co
             }
             if (hn > 0) q *= sy_new * __builtin_amdgcn_rcpf(yy_new);
 #pragma unroll
-            for (int h = 0; h < kMaxM; ++h) {
+            for (int h = 0; h < MM; ++h) {
                 if (h < hn) {
                     const float bb = rh[h] * wsum_n(Yh[h] * q, nd);
                     q += Sh[h] * (al[h] - bb);
@@ -1309,7 +1312,7 @@ __device__ __forceinline__ void chain_priority(int64_t evals, int s, int steps)
     else __builtin_amdgcn_s_setprio(0);
 }
 
-template <int A, bool SL>
+template <int A, bool SL, int MM = kMaxM>
 __device__ ChainOut mc_chain(const Topo<A, SL>& T, const BoxView& B, const Lds& S, const SearchParams& P, int job,
                              int chain)
 {
@@ -1330,7 +1333,7 @@ __device__ ChainOut mc_chain(const Topo<A, SL>& T, const BoxView& B, const Lds& 
     while (true) {
         const int iters = mode == 0 || mode == 3 ? 0 : (mode == 1 ? P.max_iter : P.refine_max_iter);
         ck.f = e_cur;
-        const BfgsOut bo = bfgs(T, B, S, P, iters, mode == 1 && P.consistency, ck);
+        const BfgsOut bo = bfgs<A, SL, MM>(T, B, S, P, iters, mode == 1 && P.consistency, ck);
         if (mode == 3) {
             if (bo.outside0) out.status |= kStatusOutside;
             break;
@@ -1399,7 +1402,7 @@ __device__ ChainOut mc_chain(const Topo<A, SL>& T, const BoxView& B, const Lds& 
 // Two waves per SIMD for the slot form: without the bound it took 8 AGPRs
 // above its 252 VGPRs and fell to one (it holds 253 VGPRs with 4 spilled).
 // The gather forms fit two waves by themselves and are faster without it.
-template <int A, bool SL>
+template <int A, bool SL, int MM>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SL ? 2 : 1))) void dock_kernel(DockArgs a)
 {
     extern __shared__ __align__(16) char smem[];
@@ -1424,7 +1427,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SL ? 2 : 1))
         const BoxView B = box_view(a.g, jb.y);
         uint64_t t0 = 0;
         if (a.sp.flags & 1u) t0 = wall_clock64();
-        ChainOut co = mc_chain(T, B, S, a.sp, job, chain);
+        ChainOut co = mc_chain<A, SL, MM>(T, B, S, a.sp, job, chain);
         const int64_t pairs = wsum_i64(co.pairs);
         const int64_t ci = (int64_t)job * chains + chain;
         if (a.chain_best_dof && l < a.dof_stride)
@@ -2166,7 +2169,8 @@ static int occupancy(K kernel, int lds)
 template <int A, bool SL>
 static int kind_occupancy(int kind, int lds)
 {
-    if (kind == kKindDock) return occupancy(dock_kernel<A, SL>, lds);
+    if (kind == kKindDock)   // the fewer of the two history capacities' resident blocks
+        return std::min(occupancy(dock_kernel<A, SL, kShortM>, lds), occupancy(dock_kernel<A, SL, kMaxM>, lds));
     if (kind == kKindScore) return occupancy(score_kernel<A, SL>, lds);
     return occupancy(local_opt_kernel<A, SL>, lds);
 }
@@ -2230,12 +2234,17 @@ hipError_t launch_dock(const DockArgs& a, const LaunchShape& sh, int32_t workgro
 {
     if (a.n_items <= 0) return hipSuccess;
     const unsigned grid = a.persistent ? (unsigned)workgroups : (unsigned)a.n_items;
-    if (sh.variant == 0)
-        hipLaunchKernelGGL((dock_kernel<1, true>), dim3(grid), dim3(64), sh.lds, s, a);
-    else if (sh.variant == 1)
-        hipLaunchKernelGGL((dock_kernel<1, false>), dim3(grid), dim3(64), sh.lds, s, a);
-    else
-        hipLaunchKernelGGL((dock_kernel<2, false>), dim3(grid), dim3(64), sh.lds, s, a);
+    const bool short_m = a.sp.m <= kShortM;
+    if (sh.variant == 0) {
+        if (short_m) hipLaunchKernelGGL((dock_kernel<1, true, kShortM>), dim3(grid), dim3(64), sh.lds, s, a);
+        else hipLaunchKernelGGL((dock_kernel<1, true, kMaxM>), dim3(grid), dim3(64), sh.lds, s, a);
+    } else if (sh.variant == 1) {
+        if (short_m) hipLaunchKernelGGL((dock_kernel<1, false, kShortM>), dim3(grid), dim3(64), sh.lds, s, a);
+        else hipLaunchKernelGGL((dock_kernel<1, false, kMaxM>), dim3(grid), dim3(64), sh.lds, s, a);
+    } else {
+        if (short_m) hipLaunchKernelGGL((dock_kernel<2, false, kShortM>), dim3(grid), dim3(64), sh.lds, s, a);
+        else hipLaunchKernelGGL((dock_kernel<2, false, kMaxM>), dim3(grid), dim3(64), sh.lds, s, a);
+    }
     return hipGetLastError();
 }
 

@@ -183,13 +183,15 @@ def test_local_opt_decreases_and_is_valid(oracle, pv_ctx, tiny):
     assert ks.pvalue > 0.01, (ks, np.median(e), np.median(fo))
 
 
-def test_dock_valid_and_statistically_like_oracle(oracle, pv_ctx, tiny):
+@pytest.mark.parametrize("m", [5, 8, 3])
+def test_dock_valid_and_statistically_like_oracle(oracle, pv_ctx, tiny, m):
     """Full MC + BFGS on the tiny configuration with 64 chains: every GPU
     chain best re-scores to its reported energy under the oracle, never
     exceeds its initial energy, and the distribution of chain bests matches
-    the oracle's run on the same Philox streams."""
+    the oracle's run on the same Philox streams.  m = 5 and 3 run the dock
+    kernel built for at most 5 history pairs, m = 8 the one for 8."""
     import paper_2506_20043_amd as pv
-    p = _params(pv, chains=64, steps=200, seed=tiny["seed"])
+    p = _params(pv, chains=64, steps=200, seed=tiny["seed"], bfgs_m=m)
     res = pv.dock(pv_ctx, tiny["grids"], tiny["ligs"], [(0, 0)], p)
     cbd = res["chain_best_dof"].cpu().numpy()
     cbe = res["chain_best_e"].cpu().numpy()
