@@ -1502,8 +1502,9 @@ __global__ void job_reduce_kernel(const float* cbe, const int64_t* cev, const in
     if (jst) jst[j] = (isfinite(be) ? 0 : 1) | budget | (cst[(int64_t)j * chains + bc] & kStatusOutside);
 }
 
-// The one-atom gather form fits three waves per SIMD in 168 VGPRs with no
-// spill (measured 10% faster than two); the other forms need more.
+// The one-atom gather form fits three waves per SIMD in 168 VGPRs (4 of them
+// spilled to scratch; three waves measured 10% faster than two); the other
+// forms need more.
 template <int A, bool SL>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(A == 1 && !SL ? 3 : 1))) void score_kernel(ScoreArgs a)
 {
