@@ -38,7 +38,9 @@ METRIC = "ligand-pocket docks/s and score+grad evals/s, batched vs plain on 1 MI
 # their derivative, the forces on both atoms), 90 per atom (frame transform,
 # trilinear value and gradient, force and torque accumulation) and 60 per
 # torsion (local rotation, frame composition, torsion derivative); its
-# transcendentals count as one flop each.  Every evaluation counts in full.
+# transcendentals count as one flop each.  Every evaluation counts in full,
+# except a line-search trial the kernel decides from its map energy and the
+# intra lower bound: it counts its atom and torsion work, no pair work.
 FLOP_PAIR, FLOP_ATOM, FLOP_TORS = 70, 90, 60
 
 
@@ -55,6 +57,14 @@ def flops_per_eval(n_pairs, n_atoms, n_tors):
         FLOP_TORS * np.asarray(n_tors, np.float64)
 
 
+def flops_of(n_evals, n_bounded, n_pairs, n_atoms, n_tors):
+    """Planning-count flops of evaluations, n_bounded of them decided by the
+    intra bound (no pair work); per job, or summed over arrays of jobs."""
+    n_evals = np.asarray(n_evals, np.float64)
+    n_bounded = np.asarray(n_bounded, np.float64)
+    return n_evals * flops_per_eval(n_pairs, n_atoms, n_tors) - n_bounded * FLOP_PAIR * np.asarray(n_pairs, np.float64)
+
+
 # A lighter count, from the operations the kernel must perform once the
 # method is fixed: per intra pair tested 8 flops, per pair inside the cutoff
 # the terms (20) and with the gradient the derivative and both forces (16);
@@ -65,13 +75,15 @@ def flops_per_eval(n_pairs, n_atoms, n_tors):
 # work.  A line-search trial above the sufficient-decrease bound needs only
 # the energy, so the gradient part counts once per evaluation that computed
 # it.  Reported beside the headline count.
-def flops_light(n_evals, n_grads, pairs_in, n_atoms, n_tors, n_pairs, m=5):
+def flops_light(n_evals, n_grads, pairs_in, n_atoms, n_tors, n_pairs, n_bounded=0, m=5):
     n_evals = np.asarray(n_evals, np.float64)
     n_grads = np.asarray(n_grads, np.float64)
     energy = 8 * n_pairs + 48 * n_atoms + 109 * n_tors + 50 + (4 * m + 10) * (6 + n_tors)
     grad = 43 * n_atoms + 32 * n_tors
     share = np.where(n_evals > 0, n_grads / np.maximum(n_evals, 1), 0.0)
-    return float(np.sum(n_evals * energy + n_grads * grad + np.asarray(pairs_in, np.float64) * (20 + share * 16)))
+    pair_test = 8 * np.asarray(n_bounded, np.float64) * n_pairs   # trials decided by the bound test no pair
+    return float(np.sum(n_evals * energy - pair_test + n_grads * grad +
+                        np.asarray(pairs_in, np.float64) * (20 + share * 16)))
 
 
 def main():
@@ -248,6 +260,7 @@ def bench_stream(pv, S, ctx, stream, args, inp):
     # outputs per job, in stream order
     ev = np.zeros(n, np.int64)
     grads = np.zeros(n, np.int64)
+    bnd = np.zeros(n, np.int64)
     pin = np.zeros(n, np.int64)
     tstart = np.zeros(n, np.int64)
     tend = np.zeros(n, np.int64)
@@ -265,6 +278,7 @@ def bench_stream(pv, S, ctx, stream, args, inp):
             ch = plan.params.chains
             ev[idx] = o["job_evals"].cpu().numpy()
             grads[idx] = o["chain_grads"].cpu().numpy().reshape(-1, ch).sum(axis=1)
+            bnd[idx] = o["chain_bounded"].cpu().numpy().reshape(-1, ch).sum(axis=1)
             pin[idx] = o["chain_pairs"].cpu().numpy().reshape(-1, ch).sum(axis=1)
             tstart[idx] = o["job_t_start"].cpu().numpy()
             tend[idx] = o["job_t_end"].cpu().numpy()
@@ -276,7 +290,7 @@ def bench_stream(pv, S, ctx, stream, args, inp):
                             "lds_bytes": sc["lds_bytes"], "per_cu": sc["per_cu"]}
             plan.close()
     svc = (tend - tstart) / 100.0                 # device clock, 100 MHz -> us
-    fl = ev * flops_per_eval(P, N, T)
+    fl = flops_of(ev, bnd, P, N, T)
     dock_ms = float(ms_cls.sum())
     cls_stats = []
     for c in (0, 1):
@@ -292,7 +306,7 @@ def bench_stream(pv, S, ctx, stream, args, inp):
     dom = cls_stats[0]
     dom_fl = float(fl[~big].sum())
     achieved = dom_fl / (float(ms_cls[:, 0].sum()) * 1e-3)
-    light = flops_light(ev[~big], grads[~big], pin[~big], N[~big], T[~big], P[~big])
+    light = flops_light(ev[~big], grads[~big], pin[~big], N[~big], T[~big], P[~big], bnd[~big])
     gather_b = float((ev * MAP_BYTES_PER_ATOM * N)[~big].sum())
     map_mb = sum(8 * int(np.prod(grids.info(b)[0])) * 4 for b in range(len(bxs))) / 1e6
     result = {
@@ -319,6 +333,7 @@ def bench_stream(pv, S, ctx, stream, args, inp):
         },
         "evals_per_s": float(ev.sum() / wall),
         "evals": int(ev.sum()),
+        "evals_decided_by_bound": int(bnd.sum()),
         "dock_ms": dock_ms,
         "docks_per_s_with_grid_build": n / (wall + grid_ms * 1e-3),
         "grid_build_ms_16_pockets": grid_ms,
@@ -425,7 +440,8 @@ def bench_multi_pocket(pv, S, ctx, stream, args):
     ms = min(_timed(stream, plan.run) for _ in range(2))
     out = plan.outputs()
     n_evals = int(out["job_evals"].sum().item())
-    fl = float(n_evals * flops_per_eval(n_pairs, n_atoms, n_tors))
+    n_bnd = int(out["chain_bounded"].sum().item())
+    fl = float(flops_of(n_evals, n_bnd, n_pairs, n_atoms, n_tors))
     res = {"workload": "multi-pocket single ligand: 5,000-atom receptor in a 50 A cube, 5 pockets of 24 A "
                        "(65^3 x 8 FP32 maps each), one %d-atom ligand with %d torsions (%d intra pairs), %d chains "
                        "x %d MC steps per pocket" % (n_atoms, n_tors, n_pairs, args.chains, args.mc_steps),
@@ -631,7 +647,8 @@ def bench_batching(pv, S, ctx, stream, args, mols):
     out = plan.outputs()
     ev = int(out["job_evals"].sum().item())
     N, T, P = _jobs_info(ligs, jobs)
-    fl = float((out["job_evals"].cpu().numpy() * flops_per_eval(P, N, T)).sum())
+    bnd_j = out["chain_bounded"].cpu().numpy().reshape(len(jobs), -1).sum(axis=1)
+    fl = float(flops_of(out["job_evals"].cpu().numpy(), bnd_j, P, N, T).sum())
     variant = plan.schedule(0)["variant"]
     output = bench_output(pv, plan, stream)
     plan.close()

@@ -248,16 +248,22 @@ typedef struct { int32_t ligand, box; } pv_job;
  *   chain_best_e [jobs*chains], chain_best_dof [jobs*chains][dof_stride],
  *   chain_evals [jobs*chains] (score+grad evaluations, line-search trials
  *   and refinements included), chain_pairs [jobs*chains] (intra pairs
- *   evaluated inside the cutoff, for the roofline),
+ *   evaluated inside the cutoff, summed over the evaluations that ran the
+ *   pair loop),
  *   job_best_e [jobs], job_best_chain [jobs] (ties: lowest chain),
  *   job_evals [jobs], job_status [jobs] (PV_JOB_* bits, 0 = ok),
  *   job_t_start, job_t_end [jobs] (device clock, 100 MHz; with
  *   PV_DOCK_TIMESTAMPS), chain_grads [jobs*chains] (the evaluations that
  *   computed the gradient: a line-search trial above the sufficient-decrease
  *   bound stops after its energy, since no step reads its gradient),
- *   chain_status [jobs*chains] (PV_JOB_BUDGET, PV_JOB_OUTSIDE bits).  The
- *   outside test re-evaluates each chain's best pose once at its end; that
- *   evaluation is not counted in chain_evals. */
+ *   chain_status [jobs*chains] (PV_JOB_BUDGET, PV_JOB_OUTSIDE bits),
+ *   chain_bounded [jobs*chains] (line-search trials decided before the pair
+ *   loop: their map energy plus a lower bound of the intra energy -- each
+ *   pair's class's least pair energy, summed -- is already above the
+ *   sufficient-decrease bound, so the full energy is too; they are counted
+ *   in chain_evals, not in chain_grads, and add no pairs).  The outside test
+ *   re-evaluates each chain's best pose once at its end; that evaluation is
+ *   not counted in chain_evals. */
 typedef struct {
     float* chain_best_e;
     float* chain_best_dof;
@@ -272,6 +278,7 @@ typedef struct {
     int32_t dof_stride;
     int64_t* chain_grads;
     int32_t* chain_status;
+    int64_t* chain_bounded;
 } pv_dock_out;
 
 /* A dock plan: the job table uploaded once and the parameters checked.

@@ -59,7 +59,7 @@ class DockOut(C.Structure):
                 ("job_best_e", C.c_void_p), ("job_best_chain", C.c_void_p),
                 ("job_evals", C.c_void_p), ("job_status", C.c_void_p),
                 ("job_t_start", C.c_void_p), ("job_t_end", C.c_void_p), ("dof_stride", C.c_int32),
-                ("chain_grads", C.c_void_p), ("chain_status", C.c_void_p)]
+                ("chain_grads", C.c_void_p), ("chain_status", C.c_void_p), ("chain_bounded", C.c_void_p)]
 
 
 class OutputParams(C.Structure):
@@ -499,6 +499,7 @@ class Plan:
                 chain_pairs=torch.empty(nj * ch, dtype=torch.int64, device=dev),
                 chain_grads=torch.empty(nj * ch, dtype=torch.int64, device=dev),
                 chain_status=torch.empty(nj * ch, dtype=torch.int32, device=dev),
+                chain_bounded=torch.empty(nj * ch, dtype=torch.int64, device=dev),
                 job_best_e=torch.empty(nj, dtype=torch.float32, device=dev),
                 job_best_chain=torch.empty(nj, dtype=torch.int32, device=dev),
                 job_evals=torch.empty(nj, dtype=torch.int64, device=dev),
@@ -594,7 +595,8 @@ def _dock_outputs(ctx, ligs, n_jobs, chains, chain_outputs=True):
                    chain_evals=torch.empty(nc, dtype=torch.int64, device=dev),
                    chain_pairs=torch.empty(nc, dtype=torch.int64, device=dev),
                    chain_grads=torch.empty(nc, dtype=torch.int64, device=dev),
-                   chain_status=torch.empty(nc, dtype=torch.int32, device=dev))
+                   chain_status=torch.empty(nc, dtype=torch.int32, device=dev),
+                   chain_bounded=torch.empty(nc, dtype=torch.int64, device=dev))
     o = DockOut()
     for k, v in out.items():
         setattr(o, k, v.data_ptr())

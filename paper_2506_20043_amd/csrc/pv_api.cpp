@@ -195,7 +195,7 @@ extern "C" {
 
 const char* pv_last_error(void) { return g_err.c_str(); }
 
-int32_t pv_version(void) { return 101; }
+int32_t pv_version(void) { return 102; }
 
 pv_status pv_create(int32_t device, pv_ctx** out)
 {
@@ -803,6 +803,7 @@ static DockArgs dock_args(pv_plan* P, const pv_dock_out* o, float* cbe, int64_t*
     a.chain_evals = cev;
     a.chain_pairs = o->chain_pairs;
     a.chain_grads = o->chain_grads;
+    a.chain_bounded = o->chain_bounded;
     a.chain_status = cst;
     a.job_t_start = o->job_t_start;
     a.job_t_end = o->job_t_end;
@@ -1230,6 +1231,7 @@ pv_status pv_dock_noalloc(pv_ctx* ctx, const pv_grids* grids, const pv_ligands* 
         a.chain_evals = cev;
         a.chain_pairs = out->chain_pairs;
         a.chain_grads = out->chain_grads;
+        a.chain_bounded = out->chain_bounded;
         a.chain_status = cst;
         a.job_t_start = out->job_t_start;
         a.job_t_end = out->job_t_end;

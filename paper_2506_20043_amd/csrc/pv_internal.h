@@ -142,6 +142,7 @@ struct DockArgs {
     int64_t* chain_evals;
     int64_t* chain_pairs;
     int64_t* chain_grads;     // evaluations that computed the gradient
+    int64_t* chain_bounded;   // trials decided by their map energy and the intra lower bound
     int32_t* chain_status;    // PV_JOB_BUDGET / PV_JOB_OUTSIDE bits per chain (never NULL)
     uint64_t* job_t_start;
     uint64_t* job_t_end;

@@ -379,6 +379,11 @@ __host__ __device__ inline LdsNeeds kernel_needs(int kind, int A, bool slots)
     return LdsNeeds{slots, kind == kKindScore, A > 1 || kind == kKindOutput, !slots && A == 1};
 }
 
+// Least value over all surface distances of a pair's energy, by class (the
+// Vina terms above: plain at d = 0.003, hydrophobic at d = 0.003, hydrogen
+// bond at d = -0.466), rounded down in the fourth digit.
+constexpr float kPairMin0 = -0.03615f, kPairMin1 = -0.07125f, kPairMin2 = -0.22356f;
+
 // ---------------------------------------------------------------- staged ligand
 // Topology lives in registers: atoms blocked A per lane (atom = lane*A + a),
 // fragments one per lane, and for lane 6+k the fragment of torsion k.
@@ -392,6 +397,7 @@ struct Topo {
                       // round (63: none): fragments 0..32 and up to 6 rounds
     float ax, ay, az, cx, cy, cz;
     int dof_frag;
+    float lb;   // a lower bound of the intra energy: the sum over the pairs of their class's least pair energy
     const uint32_t* gpairs;   // pair list and atom -> pair table in global
     const uint32_t* gell;     // memory (read from there when A > 1)
 };
@@ -438,6 +444,17 @@ __device__ void stage_ligand(Topo<A, SL>& T, const LigDev& L, int lig, const Lds
     }
     T.gpairs = L.pairs + d.pair_base;
     T.gell = L.ell + d.ell_base;
+    {
+        // least pair energy of each class (plain, hydrophobic, hydrogen
+        // bond) over all distances, rounded down; a pair past the cutoff
+        // adds 0, which is above them
+        float lbl = 0.f;
+        for (int p = l; p < T.np; p += kWave) {
+            const uint32_t c = T.gpairs[p] >> 24;
+            lbl += c == 0 ? kPairMin0 : (c == 1 ? kPairMin1 : kPairMin2);
+        }
+        T.lb = wsum(lbl);
+    }
     if (l == 0) S.pos[S.ma] = make_float4(1e18f, 1e18f, 1e18f, 0.f);
     if (SL) {
         // Pair record, everything the pair loop needs without decoding:
@@ -501,6 +518,7 @@ struct Eval {
     float g;          // this lane's tangent component (lane < 6 + T)
     int pairs_in;     // this lane's intra pairs inside the cutoff
     bool outside;     // some atom lies outside the box (its lookup was clamped)
+    bool bounded;     // a trial decided by its map energy and the intra bound (no pair loop)
 };
 
 // Frame of every fragment: x = R X + b on reference coordinates.  Lane f
@@ -877,29 +895,75 @@ __device__ Eval evaluate(const Topo<A, SL>& T, const BoxView& B, const Lds& S, c
         }
     }
     wave_sync();
+    // A line-search trial whose map energy plus the intra lower bound is
+    // already above its sufficient-decrease bound is rejected by the full
+    // energy too: it stops before the pair loop (a margin covers rounding)
+    const bool bound = e_limit < 3.0e38f;   // wave-uniform
+    bool outl = false, map_done = false;
+    if (bound) {
+        if (A > 1) {
+#pragma unroll
+            for (int a = 0; a < A; ++a)
+                if (l * A + a < T.n)
+                    tri_issue(B, __float_as_uint(T.ref[a].w) & 0xff, X4[a].x, X4[a].y, X4[a].z, TL[a]);
+        }
+#pragma unroll
+        for (int a = 0; a < A; ++a)
+            if (l * A + a < T.n) {
+                e_in += tri_finish(B, TL[a], G[a][0], G[a][1], G[a][2]);
+                outl = outl || TL[a].cx || TL[a].cy || TL[a].cz;
+            }
+        out.e_inter = wsum(e_in);
+        map_done = true;
+        if (out.e_inter + T.lb > e_limit + 1e-3f + 1e-4f * (fabsf(out.e_inter) + fabsf(T.lb))) {
+            out.e_intra = T.lb;
+            out.e = out.e_inter + T.lb;
+            out.pairs_in = 0;
+            out.outside = __ballot(outl) != 0;
+            out.bounded = true;
+            out.g = 0.f;
+            wave_sync();
+            return out;
+        }
+        // the map forces wait in the scan area (unused until the scans), so
+        // no registers are held across the pair loop
+#pragma unroll
+        for (int a = 0; a < A; ++a) {
+            const int i = l * A + a;
+            if (i < T.n) { S.pre[i] = G[a][0]; S.pre[S.ma + i] = G[a][1]; S.pre[2 * S.ma + i] = G[a][2]; }
+        }
+    }
     int cnt = 0;
     const float e_ia = pair_loop(T, S, cnt);   // hides the map loads (one atom per lane)
     // the energy sums start here, so their cross-lane steps overlap the
     // force gather and the scans below
     out.e_intra = wsum(e_ia);
     wave_sync();
-    if (A > 1) {
-        // two atoms per lane: the map loads start only now, since holding
-        // both lookups across the pair loop would cost a resident wave
+    if (!map_done) {
+        if (A > 1) {
+            // two atoms per lane: the map loads start only now, since holding
+            // both lookups across the pair loop would cost a resident wave
+#pragma unroll
+            for (int a = 0; a < A; ++a)
+                if (l * A + a < T.n)
+                    tri_issue(B, __float_as_uint(T.ref[a].w) & 0xff, X4[a].x, X4[a].y, X4[a].z, TL[a]);
+        }
 #pragma unroll
         for (int a = 0; a < A; ++a)
-            if (l * A + a < T.n)
-                tri_issue(B, __float_as_uint(T.ref[a].w) & 0xff, X4[a].x, X4[a].y, X4[a].z, TL[a]);
-    }
-    bool outl = false;
+            if (l * A + a < T.n) {
+                e_in += tri_finish(B, TL[a], G[a][0], G[a][1], G[a][2]);
+                outl = outl || TL[a].cx || TL[a].cy || TL[a].cz;
+            }
+        out.e_inter = wsum(e_in);
+    } else {
 #pragma unroll
-    for (int a = 0; a < A; ++a)
-        if (l * A + a < T.n) {
-            e_in += tri_finish(B, TL[a], G[a][0], G[a][1], G[a][2]);
-            outl = outl || TL[a].cx || TL[a].cy || TL[a].cz;
+        for (int a = 0; a < A; ++a) {
+            const int i = l * A + a;
+            if (i < T.n) { G[a][0] = S.pre[i]; G[a][1] = S.pre[S.ma + i]; G[a][2] = S.pre[2 * S.ma + i]; }
         }
+    }
     out.outside = __ballot(outl) != 0;
-    out.e_inter = wsum(e_in);
+    out.bounded = false;
     out.e = out.e_inter + out.e_intra;
     out.pairs_in = cnt;
     if (out.e > e_limit) {    // wave-uniform
@@ -999,6 +1063,7 @@ __device__ Eval evaluate_xyz(const Topo<A, SL>& T, const BoxView& B, const Lds& 
     wave_sync();
     out.g = 0.f;
     out.outside = false;
+    out.bounded = false;
     out.e_inter = wsum(e_in);
     out.e_intra = wsum(e_ia);
     out.e = out.e_inter + out.e_intra;
@@ -1052,6 +1117,7 @@ struct BfgsOut {
     float g;          // this lane's tangent gradient component at the result
     int evals;
     int grads;        // evaluations that computed the gradient
+    int bounded;      // evaluations decided by the intra lower bound (no pair loop)
     int64_t pairs;    // this lane's share of the intra pairs inside the cutoff
     bool skipped;     // the consistency check ended the run after its first evaluation
     bool outside0;    // the start pose has an atom outside the box
@@ -1114,6 +1180,7 @@ __device__ BfgsOut bfgs(const Topo<A, SL>& T, const BoxView& B, const Lds& S, co
     BfgsOut out;
     out.evals = 0;
     out.grads = 0;
+    out.bounded = 0;
     out.pairs = 0;
     out.skipped = false;
     out.outside0 = false;
@@ -1132,6 +1199,7 @@ __device__ BfgsOut bfgs(const Topo<A, SL>& T, const BoxView& B, const Lds& S, co
         const Eval ev = evaluate(T, B, S, S.pose + (initial ? SLOT_X : SLOT_XT) * kSlot, armijo);
         ++out.evals;
         out.grads += ev.e > armijo ? 0 : 1;
+        out.bounded += ev.bounded ? 1 : 0;
         out.pairs += ev.pairs_in;
         const float ft = ev.e, gt = act ? ev.g : 0.f;
         bool begin = false;
@@ -1226,7 +1294,7 @@ __device__ BfgsOut bfgs(const Topo<A, SL>& T, const BoxView& B, const Lds& S, co
 // ---------------------------------------------------------------- Monte Carlo
 struct ChainOut {
     float best_e;
-    int64_t evals, grads, pairs;   // pairs: this lane's share
+    int64_t evals, grads, bounded, pairs;   // pairs: this lane's share
     int status;                    // PV_JOB_BUDGET | PV_JOB_OUTSIDE bits
 };
 
@@ -1320,6 +1388,7 @@ __device__ ChainOut mc_chain(const Topo<A, SL>& T, const BoxView& B, const Lds& 
     ChainOut out;
     out.evals = 0;
     out.grads = 0;
+    out.bounded = 0;
     out.pairs = 0;
     out.status = 0;
     init_pose(T, B, S, SLOT_X, P.seed, job, chain);
@@ -1340,6 +1409,7 @@ __device__ ChainOut mc_chain(const Topo<A, SL>& T, const BoxView& B, const Lds& 
         }
         out.evals += bo.evals;
         out.grads += bo.grads;
+        out.bounded += bo.bounded;
         out.pairs += bo.pairs;
         bool next = true;
         if (mode == 0) {
@@ -1403,7 +1473,7 @@ __device__ ChainOut mc_chain(const Topo<A, SL>& T, const BoxView& B, const Lds& 
 // above its 252 VGPRs and fell to one (it holds 253 VGPRs with 4 spilled).
 // The gather forms fit two waves by themselves and are faster without it.
 template <int A, bool SL, int MM>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SL ? 2 : 1))) void dock_kernel(DockArgs a)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SL || A > 1 ? 2 : 1))) void dock_kernel(DockArgs a)
 {
     extern __shared__ __align__(16) char smem[];
     const Lds S = carve(smem, a.l.max_atoms, a.l.max_pairs, a.l.max_ell, kernel_needs(kKindDock, A, SL));
@@ -1437,6 +1507,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SL ? 2 : 1))
             if (a.chain_evals) a.chain_evals[ci] = co.evals;
             if (a.chain_pairs) a.chain_pairs[ci] = pairs;
             if (a.chain_grads) a.chain_grads[ci] = co.grads;
+            if (a.chain_bounded) a.chain_bounded[ci] = co.bounded;
             a.chain_status[ci] = co.status;
             if (a.sp.flags & 1u) {
                 const uint64_t t1 = wall_clock64();
@@ -1607,7 +1678,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(A == 1 && !S
 }
 
 template <int A, bool SL>
-__global__ __launch_bounds__(64) void local_opt_kernel(OptArgs a)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SL || A > 1 ? 2 : 1))) void local_opt_kernel(OptArgs a)
 {
     extern __shared__ __align__(16) char smem[];
     const Lds S = carve(smem, a.l.max_atoms, a.l.max_pairs, a.l.max_ell, kernel_needs(kKindOpt, A, SL));
@@ -2171,8 +2242,7 @@ template <int A, bool SL>
 static int kind_occupancy(int kind, int lds)
 {
     if (kind == kKindDock) {   // the fewer of the history capacities' resident blocks
-        if constexpr (A > 1) return occupancy(dock_kernel<A, SL, kMaxM>, lds);
-        else return std::min(occupancy(dock_kernel<A, SL, kShortM>, lds), occupancy(dock_kernel<A, SL, kMaxM>, lds));
+        return std::min(occupancy(dock_kernel<A, SL, kShortM>, lds), occupancy(dock_kernel<A, SL, kMaxM>, lds));
     }
     if (kind == kKindScore) return occupancy(score_kernel<A, SL>, lds);
     return occupancy(local_opt_kernel<A, SL>, lds);
@@ -2245,8 +2315,8 @@ hipError_t launch_dock(const DockArgs& a, const LaunchShape& sh, int32_t workgro
         if (short_m) hipLaunchKernelGGL((dock_kernel<1, false, kShortM>), dim3(grid), dim3(64), sh.lds, s, a);
         else hipLaunchKernelGGL((dock_kernel<1, false, kMaxM>), dim3(grid), dim3(64), sh.lds, s, a);
     } else {
-        // two atoms per lane: the 5-pair build measured 1 % slower here
-        hipLaunchKernelGGL((dock_kernel<2, false, kMaxM>), dim3(grid), dim3(64), sh.lds, s, a);
+        if (short_m) hipLaunchKernelGGL((dock_kernel<2, false, kShortM>), dim3(grid), dim3(64), sh.lds, s, a);
+        else hipLaunchKernelGGL((dock_kernel<2, false, kMaxM>), dim3(grid), dim3(64), sh.lds, s, a);
     }
     return hipGetLastError();
 }

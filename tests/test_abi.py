@@ -31,7 +31,7 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_version_and_defaults():
-    assert pv.lib().pv_version() == 101
+    assert pv.lib().pv_version() == 102
     p = pv.dock_params()
     assert (p.bfgs_max_iter, p.bfgs_m, p.ls_max_trials) == (30, 5, 10)
     assert p.ls_rho == pytest.approx(1e-4) and p.ls_sigma == pytest.approx(0.1)

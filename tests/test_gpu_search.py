@@ -208,6 +208,25 @@ def test_dock_valid_and_statistically_like_oracle(oracle, pv_ctx, tiny, m):
     assert res["job_best_chain"].cpu().numpy()[0] == int(np.argmin(cbe))
 
 
+def test_trials_decided_by_the_intra_bound(pv_ctx, tiny):
+    """chain_bounded counts the line-search trials rejected before the pair
+    loop (map energy + the intra lower bound above the sufficient-decrease
+    bound): never more than the evaluations without a gradient, none without
+    BFGS, and on the tiny configuration's clash-heavy chains a good share."""
+    import paper_2506_20043_amd as pv
+    p = _params(pv, chains=64, steps=60, seed=tiny["seed"] + 11)
+    plan = pv.Plan(pv_ctx, tiny["grids"], tiny["ligs"], [(0, 0)], p)
+    o = {k: v.cpu().numpy() for k, v in plan.run().items()}
+    plan.close()
+    b, ev, gr = o["chain_bounded"], o["chain_evals"], o["chain_grads"]
+    assert np.all(b >= 0) and np.all(b <= ev - gr)
+    assert b.sum() > 0.05 * ev.sum(), (b.sum(), ev.sum())
+    p0 = _params(pv, chains=16, steps=20, seed=tiny["seed"] + 12, bfgs_max_iter=0, refine_max_iter=0)
+    plan = pv.Plan(pv_ctx, tiny["grids"], tiny["ligs"], [(0, 0)], p0)
+    assert plan.run()["chain_bounded"].sum().item() == 0
+    plan.close()
+
+
 def test_batched_plain_graph_agree(pv_ctx, tiny):
     import torch
 
