@@ -387,10 +387,9 @@ def native_source_hash():
 
 def kernel_name(variant, m):
     """The dock kernel instantiation a schedule runs: its variant's atoms per
-    lane and slot layout, and the history capacity (5 when m <= 5 with one
-    atom per lane, else 8)."""
+    lane and slot layout, and the history capacity (5 when m <= 5, else 8)."""
     a, sl = {"slots": (1, "true"), "gather": (1, "false"), "gather2": (2, "false")}[variant]
-    return "dock_kernel<%d, %s, %d>" % (a, sl, 5 if m <= 5 and a == 1 else 8)
+    return "dock_kernel<%d, %s, %d>" % (a, sl, 5 if m <= 5 else 8)
 
 
 def recorded_traffic(job_order):
