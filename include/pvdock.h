@@ -261,7 +261,9 @@ typedef struct { int32_t ligand, box; } pv_job;
  *   loop: their map energy plus a lower bound of the intra energy -- each
  *   pair's class's least pair energy, summed -- is already above the
  *   sufficient-decrease bound, so the full energy is too; they are counted
- *   in chain_evals, not in chain_grads, and add no pairs).  The outside test
+ *   in chain_evals, not in chain_grads, and add no pairs; the gather
+ *   variants only: the slot variant always runs the pair loop and leaves
+ *   zeros).  The outside test
  *   re-evaluates each chain's best pose once at its end; that evaluation is
  *   not counted in chain_evals. */
 typedef struct {

@@ -897,8 +897,11 @@ __device__ Eval evaluate(const Topo<A, SL>& T, const BoxView& B, const Lds& S, c
     wave_sync();
     // A line-search trial whose map energy plus the intra lower bound is
     // already above its sufficient-decrease bound is rejected by the full
-    // energy too: it stops before the pair loop (a margin covers rounding)
-    const bool bound = e_limit < 3.0e38f;   // wave-uniform
+    // energy too: it stops before the pair loop (a margin covers rounding).
+    // The slot form runs few waves per SIMD, where ending the map loads before
+    // the pair loop costs more latency than the skipped trials save: it
+    // always runs both.
+    const bool bound = !SL && e_limit < 3.0e38f;   // wave-uniform
     bool outl = false, map_done = false;
     if (bound) {
         if (A > 1) {

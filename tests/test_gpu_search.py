@@ -211,16 +211,23 @@ def test_dock_valid_and_statistically_like_oracle(oracle, pv_ctx, tiny, m):
 def test_trials_decided_by_the_intra_bound(pv_ctx, tiny):
     """chain_bounded counts the line-search trials rejected before the pair
     loop (map energy + the intra lower bound above the sufficient-decrease
-    bound): never more than the evaluations without a gradient, none without
-    BFGS, and on the tiny configuration's clash-heavy chains a good share."""
+    bound): under the gather variants never more than the evaluations without
+    a gradient and on the tiny configuration's clash-heavy chains a good
+    share; none under the slot variant, which always runs the pair loop, and
+    none without BFGS."""
     import paper_2506_20043_amd as pv
     p = _params(pv, chains=64, steps=60, seed=tiny["seed"] + 11)
-    plan = pv.Plan(pv_ctx, tiny["grids"], tiny["ligs"], [(0, 0)], p)
-    o = {k: v.cpu().numpy() for k, v in plan.run().items()}
-    plan.close()
-    b, ev, gr = o["chain_bounded"], o["chain_evals"], o["chain_grads"]
-    assert np.all(b >= 0) and np.all(b <= ev - gr)
-    assert b.sum() > 0.05 * ev.sum(), (b.sum(), ev.sum())
+    for variant in (0, 1, 2):
+        plan = pv.Plan(pv_ctx, tiny["grids"], tiny["ligs"], [(0, 0)], p)
+        plan.set_schedule(0, variant, 0)
+        o = {k: v.cpu().numpy() for k, v in plan.run().items()}
+        plan.close()
+        b, ev, gr = o["chain_bounded"], o["chain_evals"], o["chain_grads"]
+        if variant == 0:
+            assert np.all(b == 0)
+            continue
+        assert np.all(b >= 0) and np.all(b <= ev - gr), variant
+        assert b.sum() > 0.05 * ev.sum(), (variant, b.sum(), ev.sum())
     p0 = _params(pv, chains=16, steps=20, seed=tiny["seed"] + 12, bfgs_max_iter=0, refine_max_iter=0)
     plan = pv.Plan(pv_ctx, tiny["grids"], tiny["ligs"], [(0, 0)], p0)
     assert plan.run()["chain_bounded"].sum().item() == 0
