@@ -307,6 +307,7 @@ def bench_stream(pv, S, ctx, stream, args, inp):
     dom_fl = float(fl[~big].sum())
     achieved = dom_fl / (float(ms_cls[:, 0].sum()) * 1e-3)
     light = flops_light(ev[~big], grads[~big], pin[~big], N[~big], T[~big], P[~big], bnd[~big])
+    full = float(flops_of(ev, 0, P, N, T)[~big].sum())
     gather_b = float((ev * MAP_BYTES_PER_ATOM * N)[~big].sum())
     map_mb = sum(8 * int(np.prod(grids.info(b)[0])) * 4 for b in range(len(bxs))) / 1e6
     result = {
@@ -355,6 +356,10 @@ def bench_stream(pv, S, ctx, stream, args, inp):
             "flops_per_launch": dom_fl / max(dom["launches"], 1),
             "flops_per_eval_mean": dom_fl / max(dom["evals"], 1),
             "launch_ms": dom["launch_ms_mean"],
+            # the same count with every line-search trial's pair work included,
+            # as if no trial were decided by the intra bound
+            "every_trial_in_full": {"tflops": full / (float(ms_cls[:, 0].sum()) * 1e-3) / 1e12,
+                                    "frac": full / (float(ms_cls[:, 0].sum()) * 1e-3) / PEAK_FP32_VECTOR},
             "flops_light": {"tflops": light / (float(ms_cls[:, 0].sum()) * 1e-3) / 1e12,
                             "frac": light / (float(ms_cls[:, 0].sum()) * 1e-3) / PEAK_FP32_VECTOR},
             "map_gather": {"bytes_per_launch": gather_b / max(dom["launches"], 1),

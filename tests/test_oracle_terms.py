@@ -88,3 +88,37 @@ def test_cutoff_on_map(oracle):
             assert out[t] == pytest.approx(want, rel=1e-12, abs=1e-300)
         if inside:
             assert np.all(out != 0.0)
+
+
+def test_intra_bound_class_minima(oracle):
+    """The dock kernel rejects a line-search trial early when its map energy
+    plus a lower bound of its intra energy (each pair's class minimum, summed)
+    is above the sufficient-decrease bound.  Each class minimum the kernel
+    holds must be at most the oracle's least pair energy of every type pair
+    of that class (a bound), and within 2e-4 of the least one (so a wrong
+    digit fails).  The pair energy depends on r only through the surface
+    distance, so a dense scan of r per type pair, refined around its best
+    sample, gives the minimum."""
+    import re
+
+    from scipy.optimize import minimize_scalar
+    src = os.path.join(os.path.dirname(__file__), "..", "paper_2506_20043_amd", "csrc", "pv_kernels.hip")
+    text = open(src).read()
+    consts = [float(re.search(r"kPairMin%d = (-?[0-9.]+)f" % c, text).group(1)) for c in range(3)]
+    least = [math.inf] * 3
+    nt = len(XS_NAMES)
+    for ta in range(nt):
+        ra, ha, da, aa = oracle.type_params(ta)
+        for tb in range(ta, nt):
+            rb, hb, db, ab = oracle.type_params(tb)
+            cls = 1 if (ha and hb) else (2 if (da and ab) or (aa and db) else 0)
+            rs = np.arange(0.05, 8.0, 0.002)
+            es = np.array([oracle.pair(ta, tb, r)[0] for r in rs])
+            k = int(np.argmin(es))
+            res = minimize_scalar(lambda r: oracle.pair(ta, tb, r)[0], bounds=(rs[max(k - 1, 0)], rs[min(k + 1, len(rs) - 1)]),
+                                  method="bounded", options={"xatol": 1e-9})
+            e_min = min(float(es[k]), float(res.fun))
+            assert e_min >= consts[cls], (XS_NAMES[ta], XS_NAMES[tb], cls, e_min, consts[cls])
+            least[cls] = min(least[cls], e_min)
+    for c in range(3):
+        assert least[c] - consts[c] < 2e-4, (c, least[c], consts[c])
