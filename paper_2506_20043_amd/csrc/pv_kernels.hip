@@ -836,10 +836,11 @@ __device__ __forceinline__ float4 atom_position(float4 ref, const Lds& S)
 // atom positions in S.pos and dE/dx in S.frc.  When the energy exceeds
 // e_limit (a line-search trial that fails the sufficient-decrease test,
 // whose gradient nobody reads) it returns after the energy, with g = 0 and
-// S.frc not written.
+// S.frc not written.  use_bound lets such a trial try the intra lower bound
+// before its pair loop.
 template <int A, bool SL>
 __device__ Eval evaluate(const Topo<A, SL>& T, const BoxView& B, const Lds& S, const float* pose,
-                         float e_limit = __builtin_inff())
+                         float e_limit = __builtin_inff(), bool use_bound = true)
 {
     const int l = lane_id();
     Eval out;
@@ -901,7 +902,7 @@ __device__ Eval evaluate(const Topo<A, SL>& T, const BoxView& B, const Lds& S, c
     // The slot form runs few waves per SIMD, where ending the map loads before
     // the pair loop costs more latency than the skipped trials save: it
     // always runs both.
-    const bool bound = !SL && e_limit < 3.0e38f;   // wave-uniform
+    const bool bound = !SL && use_bound && e_limit < 3.0e38f;   // wave-uniform
     bool outl = false, map_done = false;
     if (bound) {
         if (A > 1) {
@@ -1197,9 +1198,13 @@ __device__ BfgsOut bfgs(const Topo<A, SL>& T, const BoxView& B, const Lds& S, co
     float sy_new = 0.f, yy_new = 1.f;   // s.y and y.y of the newest stored pair (the H0 scale)
     bool beta_inf = true, initial = true;
     while (true) {
-        // a trial above the sufficient-decrease bound needs no gradient
+        // a trial above the sufficient-decrease bound needs no gradient.  The
+        // intra bound decides an iteration's first trial (the full step) less
+        // often than the later ones, and with one atom per lane trying it costs
+        // the corner loads their cover by the pair loop: that form tries it
+        // only once a trial of the iteration has failed
         const float armijo = initial ? __builtin_inff() : f + P.rho * lam * gd;
-        const Eval ev = evaluate(T, B, S, S.pose + (initial ? SLOT_X : SLOT_XT) * kSlot, armijo);
+        const Eval ev = evaluate(T, B, S, S.pose + (initial ? SLOT_X : SLOT_XT) * kSlot, armijo, A > 1 || tr > 0);
         ++out.evals;
         out.grads += ev.e > armijo ? 0 : 1;
         out.bounded += ev.bounded ? 1 : 0;
