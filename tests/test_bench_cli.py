@@ -46,3 +46,20 @@ def test_recorded_traffic_only_for_matching_sources_and_order():
         assert got == rec["dock_traffic_bytes_per_launch"]
     else:
         assert got is None
+
+
+def test_flop_counts():
+    """The roofline's count is F = 70 P + 90 N + 60 T per evaluation, every
+    evaluation in full; the work performed takes out 70 P for each trial the
+    intra bound decides, and nothing else."""
+    sys.path.insert(0, ROOT)
+    import numpy as np
+
+    import bench
+    assert bench.flops_of(3, 100, 20, 5) == 3 * (70 * 100 + 90 * 20 + 60 * 5)
+    ev, bnd = np.array([10, 7, 0]), np.array([4, 0, 0])
+    P, N, T = np.array([100, 50, 10]), np.array([20, 12, 8]), np.array([5, 0, 1])
+    full = bench.flops_of(ev, P, N, T)
+    done = bench.flops_performed(ev, bnd, P, N, T)
+    assert np.array_equal(full - done, bnd * 70 * P)
+    assert np.array_equal(bench.flops_performed(ev, 0, P, N, T), full)
