@@ -1202,9 +1202,11 @@ __device__ BfgsOut bfgs(const Topo<A, SL>& T, const BoxView& B, const Lds& S, co
         // intra bound decides an iteration's first trial (the full step) less
         // often than the later ones, and with one atom per lane trying it costs
         // the corner loads their cover by the pair loop: that form tries it
-        // only once a trial of the iteration has failed
+        // once a trial of the iteration has failed, and while no history pair
+        // is stored, when the full step is the unscaled gradient step
         const float armijo = initial ? __builtin_inff() : f + P.rho * lam * gd;
-        const Eval ev = evaluate(T, B, S, S.pose + (initial ? SLOT_X : SLOT_XT) * kSlot, armijo, A > 1 || tr > 0);
+        const Eval ev = evaluate(T, B, S, S.pose + (initial ? SLOT_X : SLOT_XT) * kSlot, armijo,
+                                 A > 1 || tr > 0 || hn == 0);
         ++out.evals;
         out.grads += ev.e > armijo ? 0 : 1;
         out.bounded += ev.bounded ? 1 : 0;
