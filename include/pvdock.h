@@ -236,6 +236,12 @@ typedef struct {
  * PV_DOCK_LARGEST_FIRST only the start order changes: outputs are identical
  * bit for bit. */
 #define PV_DOCK_BOX_ORDER 8u
+/* every line-search trial runs its pair loop: the intra lower-bound check
+ * (see chain_bounded) is off.  The check only ever rejects trials the full
+ * energy rejects, so the searches, energies, poses and evaluation counts are
+ * identical bit for bit; chain_bounded is zero and chain_pairs counts every
+ * trial's pairs.  For checking that claim and timing the check. */
+#define PV_DOCK_NO_INTRA_BOUND 16u
 /* other flag bits are rejected (PV_E_INVALID) */
 
 /* fills the defaults: 30 BFGS iterations, m = 5, 10 trials, rho 1e-4,

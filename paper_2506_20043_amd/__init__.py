@@ -28,6 +28,7 @@ PV_DOCK_TIMESTAMPS = 1
 PV_DOCK_GRAPH = 2
 PV_DOCK_LARGEST_FIRST = 4
 PV_DOCK_BOX_ORDER = 8
+PV_DOCK_NO_INTRA_BOUND = 16
 PV_JOB_NONFINITE, PV_JOB_BUDGET, PV_JOB_OUTSIDE = 1, 2, 4
 MAX_ATOMS, MAX_TORS = 128, 32
 

@@ -694,7 +694,9 @@ pv_status pv_dock_plan(pv_ctx* ctx, const pv_grids* grids, const pv_ligands* lig
     pv_status st = check_pair(ctx, grids, ligs);
     if (st != PV_OK) return st;
     if ((st = check_search(params, true)) != PV_OK) return st;
-    if (params->flags & ~(PV_DOCK_TIMESTAMPS | PV_DOCK_GRAPH | PV_DOCK_LARGEST_FIRST | PV_DOCK_BOX_ORDER))
+    static_assert(PV_DOCK_NO_INTRA_BOUND == kDockNoIntraBound, "the kernels' copy of the flag bit");
+    if (params->flags & ~(PV_DOCK_TIMESTAMPS | PV_DOCK_GRAPH | PV_DOCK_LARGEST_FIRST | PV_DOCK_BOX_ORDER |
+                          PV_DOCK_NO_INTRA_BOUND))
         return fail(PV_E_INVALID, "unknown dock flag");
     if (n_jobs < 0) return fail(PV_E_INVALID, "n_jobs < 0");
     if (n_jobs > 0 && !jobs) return fail(PV_E_INVALID, "jobs is NULL");

@@ -116,6 +116,9 @@ struct ScoreArgs {
     int32_t xyz_stride;
 };
 
+// the PV_DOCK_NO_INTRA_BOUND bit of the ABI's dock flags (SearchParams::flags)
+constexpr uint32_t kDockNoIntraBound = 16u;
+
 struct SearchParams {
     int32_t chains, steps, max_iter, m, ls_max, refine_max_iter;
     float rho, sigma, eps_g, eps_c, temperature, pos_amp, rot_amp;

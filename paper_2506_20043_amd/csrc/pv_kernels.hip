@@ -1206,7 +1206,7 @@ __device__ BfgsOut bfgs(const Topo<A, SL>& T, const BoxView& B, const Lds& S, co
         // is stored, when the full step is the unscaled gradient step
         const float armijo = initial ? __builtin_inff() : f + P.rho * lam * gd;
         const Eval ev = evaluate(T, B, S, S.pose + (initial ? SLOT_X : SLOT_XT) * kSlot, armijo,
-                                 A > 1 || tr > 0 || hn == 0);
+                                 !(P.flags & kDockNoIntraBound) && (A > 1 || tr > 0 || hn == 0));
         ++out.evals;
         out.grads += ev.e > armijo ? 0 : 1;
         out.bounded += ev.bounded ? 1 : 0;

@@ -199,7 +199,7 @@ def test_job_orders_change_only_the_order(oracle, pv_ctx):
             assert np.array_equal(outs[0][k], o[k]), k
         assert np.all(o["job_t_end"] >= o["job_t_start"])
     with pytest.raises(pv.PvError):
-        pv.Plan(pv_ctx, grids, ligs, jobs, pv.dock_params(chains=4, steps=2, seed=1, flags=16))
+        pv.Plan(pv_ctx, grids, ligs, jobs, pv.dock_params(chains=4, steps=2, seed=1, flags=32))
 
 
 def test_ligands_without_intra_pairs(oracle, pv_ctx, setup):

@@ -234,6 +234,29 @@ def test_trials_decided_by_the_intra_bound(pv_ctx, tiny):
     plan.close()
 
 
+def test_intra_bound_changes_no_search(pv_ctx, tiny):
+    """The intra-bound check only rejects trials the full energy rejects: with
+    PV_DOCK_NO_INTRA_BOUND (every trial runs its pair loop) the searches come
+    out identical bit for bit under both gather variants -- best energies and
+    poses, evaluation and gradient counts, statuses -- with no trial counted
+    as bound-decided and at least as many pairs evaluated."""
+    import paper_2506_20043_amd as pv
+    for variant in (1, 2):
+        outs = []
+        for flags in (0, pv.PV_DOCK_NO_INTRA_BOUND):
+            p = _params(pv, chains=64, steps=60, seed=tiny["seed"] + 13, flags=flags)
+            plan = pv.Plan(pv_ctx, tiny["grids"], tiny["ligs"], [(0, 0), (0, 0)], p)
+            plan.set_schedule(0, variant, 0)
+            outs.append({k: v.cpu().numpy() for k, v in plan.run().items()})
+            plan.close()
+        a, b = outs
+        for k in ("chain_best_e", "chain_best_dof", "chain_evals", "chain_grads", "chain_status", "job_best_e",
+                  "job_best_chain"):
+            assert np.array_equal(a[k], b[k]), (variant, k)
+        assert a["chain_bounded"].sum() > 0 and b["chain_bounded"].sum() == 0, variant
+        assert np.all(b["chain_pairs"] >= a["chain_pairs"]) and b["chain_pairs"].sum() > a["chain_pairs"].sum()
+
+
 def test_batched_plain_graph_agree(pv_ctx, tiny):
     import torch
 
