@@ -30,6 +30,18 @@ def test_every_declared_symbol_is_exported():
     assert sorted(pv.SIGNATURES) == names
 
 
+def test_binding_constants_match_the_header():
+    """Every PV_* integer constant the Python binding defines has the value the
+    header gives it (flag and status bits, limits, kinds, variants)."""
+    text = open(HEADER).read()
+    defs = {m.group(1): int(m.group(2)) for m in re.finditer(r"^#define (PV_[A-Z0-9_]+) (\d+)u?\b", text, re.M)}
+    assert "PV_DOCK_NO_INTRA_BOUND" in defs and len(defs) >= 15
+    mirrored = [n for n in dir(pv) if n.startswith("PV_") and isinstance(getattr(pv, n), int)]
+    assert len(mirrored) >= 8
+    for n in mirrored:
+        assert n in defs and getattr(pv, n) == defs[n], n
+
+
 def test_version_and_defaults():
     assert pv.lib().pv_version() == 102
     p = pv.dock_params()
