@@ -1481,7 +1481,7 @@ __device__ ChainOut mc_chain(const Topo<A, SL>& T, const BoxView& B, const Lds& 
 
 // Two waves per SIMD for the slot form and the two-atom form: without the
 // hint they take AGPRs above 256 VGPRs and fall to one wave (with it the slot
-// form holds 247 VGPRs, the two-atom form 256 with 30 spilled).  The one-atom
+// form holds 247 VGPRs, the two-atom form 256 with 28 spilled).  The one-atom
 // gather form fits two waves by itself and is faster without the hint.
 template <int A, bool SL, int MM>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SL || A > 1 ? 2 : 1))) void dock_kernel(DockArgs a)
