@@ -758,7 +758,8 @@ __device__ __forceinline__ float pair_loop(const Topo<A, SL>& T, const Lds& S, i
 
 // dE/dx_i of the intra term.  LDS tables: the sum of atom i's row of pair
 // forces (independent reads, rows padded to a multiple of four with zeros).
-// Global tables: sum over the pairs holding atom i of c_p (x_i - x_j).
+// Global tables: sum over the pairs holding atom i of c_p (x_i - x_j); an
+// entry holds p in its low half and j's byte offset in S.pos in its high half.
 // row loads of the global atom -> pair table issued together by the gather:
 // the table sits in L2, so a row walked one load at a time pays one L2
 // round trip per four entries
@@ -808,7 +809,10 @@ __device__ __forceinline__ void gather_pair_forces(const Topo<A, SL>& T, const L
             float c[4];
             float4 xj[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) { c[u] = S.cp[e[u] & 0xffff]; xj[u] = S.pos[e[u] >> 16]; }
+            for (int u = 0; u < 4; ++u) {
+                c[u] = S.cp[e[u] & 0xffff];
+                xj[u] = *(const float4*)((const char*)S.pos + (e[u] >> 16));
+            }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 gx += c[u] * (xi.x - xj[u].x);

@@ -235,12 +235,14 @@ int build_ligand_model(int n, const float* xyz, const uint8_t* type, int nb, con
         M.pairs.push_back((uint32_t)i | ((uint32_t)j << 8) | ((uint32_t)rk << 16) |
                           ((uint32_t)cls(pl[idx]) << 24));
     }
-    // atom -> pair rows (partners in ascending pair order), padded to the longest
+    // atom -> pair rows (partners in ascending pair order), padded to the longest;
+    // an entry is the pair index | the partner's byte offset in the kernels'
+    // LDS position array (16 B per atom) << 16
     std::vector<std::vector<uint32_t>> rows(n);
     for (int q = 0; q < P; ++q) {
         const uint32_t i = M.pairs[q] & 0xff, j = (M.pairs[q] >> 8) & 0xff;
-        rows[i].push_back((uint32_t)q | (j << 16));
-        rows[j].push_back((uint32_t)q | (i << 16));
+        rows[i].push_back((uint32_t)q | ((j * 16) << 16));
+        rows[j].push_back((uint32_t)q | ((i * 16) << 16));
     }
     int w = 0;
     for (int i = 0; i < n; ++i) w = std::max(w, (int)rows[i].size());
@@ -283,7 +285,7 @@ int build_ligand_model(int n, const float* xyz, const uint8_t* type, int nb, con
     for (int i = 0; i < n; ++i)
         for (int k = 0; k < w; ++k)
             M.ell[(size_t)i * w + k] =
-                k < (int)rows[i].size() ? rows[i][k] : ((uint32_t)P | ((uint32_t)i << 16));
+                k < (int)rows[i].size() ? rows[i][k] : ((uint32_t)P | ((uint32_t)(i * 16) << 16));
     return PV_OK;
 }
 
