@@ -90,6 +90,44 @@ def test_cutoff_on_map(oracle):
             assert np.all(out != 0.0)
 
 
+def _kernel_pair_minima():
+    import re
+    src = os.path.join(os.path.dirname(__file__), "..", "paper_2506_20043_amd", "csrc", "pv_kernels.hip")
+    text = open(src).read()
+    return [float(re.search(r"kPairMin%d = (-?[0-9.]+)f" % c, text).group(1)) for c in range(3)]
+
+
+def _pair_class(oracle, ta, tb):
+    _, ha, da, aa = oracle.type_params(ta)
+    _, hb, db, ab = oracle.type_params(tb)
+    return 1 if (ha and hb) else (2 if (da and ab) or (aa and db) else 0)
+
+
+def test_intra_energy_never_below_the_bound(oracle):
+    """The oracle's intra energy of any pose is at least the sum, over the
+    ligand's intra pairs, of the kernel's class minima: the bound the dock
+    kernel subtracts from a trial's map energy.  Random poses of random tree
+    ligands of the screening stream's sizes, including folded ones (random
+    torsions bring far atoms together)."""
+    from paper_2506_20043_amd import synth as S
+    mins = _kernel_pair_minima()
+    grid = oracle.Grid(np.zeros(8 * 27), (3, 3, 3), (0.0, 0.0, 0.0), 1.0)   # intra only: maps unused
+    g = np.random.default_rng(20043)
+    checked = 0
+    for n, t in ((10, 2), (24, 6), (40, 10), (64, 16), (80, 20)):
+        m = S.tree_ligand(g, n, t)
+        L = oracle.Ligand(m.xyz, m.types, m.bonds, m.rotatable)
+        types = np.asarray(m.types)
+        lb = sum(mins[_pair_class(oracle, types[i], types[j])] for i, j in L.pairs())
+        for _ in range(20):
+            q = g.normal(size=4)
+            dof = np.concatenate([[0.0, 0.0, 0.0], q / np.linalg.norm(q), g.uniform(-np.pi, np.pi, L.n_tors)])
+            e = L.score_grad(grid, dof)["e_intra"]
+            assert e >= lb, (n, t, e, lb)
+            checked += 1
+    assert checked == 100
+
+
 def test_intra_bound_class_minima(oracle):
     """The dock kernel rejects a line-search trial early when its map energy
     plus a lower bound of its intra energy (each pair's class minimum, summed)
@@ -99,19 +137,13 @@ def test_intra_bound_class_minima(oracle):
     digit fails).  The pair energy depends on r only through the surface
     distance, so a dense scan of r per type pair, refined around its best
     sample, gives the minimum."""
-    import re
-
     from scipy.optimize import minimize_scalar
-    src = os.path.join(os.path.dirname(__file__), "..", "paper_2506_20043_amd", "csrc", "pv_kernels.hip")
-    text = open(src).read()
-    consts = [float(re.search(r"kPairMin%d = (-?[0-9.]+)f" % c, text).group(1)) for c in range(3)]
+    consts = _kernel_pair_minima()
     least = [math.inf] * 3
     nt = len(XS_NAMES)
     for ta in range(nt):
-        ra, ha, da, aa = oracle.type_params(ta)
         for tb in range(ta, nt):
-            rb, hb, db, ab = oracle.type_params(tb)
-            cls = 1 if (ha and hb) else (2 if (da and ab) or (aa and db) else 0)
+            cls = _pair_class(oracle, ta, tb)
             rs = np.arange(0.05, 8.0, 0.002)
             es = np.array([oracle.pair(ta, tb, r)[0] for r in rs])
             k = int(np.argmin(es))
